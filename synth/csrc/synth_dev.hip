@@ -1,0 +1,127 @@
+// Seeded synthetic memory images: device fill, device page mutation, and the fp32
+// SAXPY co-runner used to measure overlap.
+//
+// The fill writes the same byte stream as synth_host.c (SplitMix64 output
+// function over a per-region counter); tests cross-check the two. Nothing in
+// this file is part of the checkpoint path.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+__device__ __forceinline__ uint64_t sm64_mix(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+// dst must be 8-byte aligned and `words` 8-byte words long; word i gets
+// counter value base + word_off + i.
+__global__ void synth_fill_kernel(uint64_t* __restrict__ dst, uint64_t words, uint64_t base,
+                                  uint64_t word_off)
+{
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (; i < words; i += stride)
+        dst[i] = sm64_mix(base + word_off + i);
+}
+
+__device__ __forceinline__ uint64_t mut_hash(uint64_t ms, uint64_t region, uint64_t page,
+                                             uint64_t t)
+{
+    return sm64_mix(ms * 0x9E3779B97F4A7C15ULL + region * 0xD1B54A32D192ED03ULL +
+                    page * 0x8CB92BA72F3D8DD7ULL + t);
+}
+
+// One thread per (listed page, patch element): kind 0 has up to 16 word
+// patches per page, kind 1 has 256 byte patches per page. The rule is the one
+// documented in synth_host.c; the host and device versions are cross-checked.
+__global__ void synth_mutate_kernel(uint8_t* __restrict__ region_bytes, uint64_t page_size,
+                                    const int64_t* __restrict__ pages, uint64_t n_pages, int kind,
+                                    uint64_t ms, uint64_t region)
+{
+    const uint64_t per = kind == 0 ? 16 : 256;
+    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= n_pages * per)
+        return;
+    const uint64_t page = (uint64_t)pages[gid / per];
+    const uint64_t t = gid % per;
+    uint8_t* pb = region_bytes + page * page_size;
+    const uint64_t h0 = mut_hash(ms, region, page, 0);
+    if (kind == 0) {
+        const uint64_t W = page_size / 4;
+        const uint64_t k = 1 + (h0 & 15);
+        if (t >= k)
+            return;
+        const uint64_t start = (h0 >> 8) % W;
+        const uint64_t step = ((h0 >> 40) | 1) % W;
+        const uint64_t pos = (start + t * step) % W;
+        const uint32_t m = (uint32_t)(1 + mut_hash(ms, region, page, t + 1) % 0xFFFFFFFFULL);
+        uint32_t* w = (uint32_t*)(pb + 4 * pos);
+        *w ^= m;
+    } else {
+        const uint64_t o = h0 % (page_size - 255);
+        const uint64_t h = mut_hash(ms, region, page, 1 + t / 8);
+        uint8_t m = (uint8_t)(h >> (8 * (t & 7)));
+        if (t == 0)
+            m = (uint8_t)(1 + h % 255);
+        pb[o + t] ^= m;
+    }
+}
+
+// y <- a*x + y, repeated `iters` times over n elements (the co-running
+// compute kernel of the many-allocations workload).
+__global__ void synth_saxpy_loop_kernel(float* __restrict__ y, const float* __restrict__ x,
+                                        float a, uint64_t n, int iters)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (int it = 0; it < iters; ++it) {
+        for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+            y[i] = a * x[i] + y[i];
+    }
+}
+
+extern "C" {
+
+int synth_fill_dev(void* dst, uint64_t nbytes, uint64_t seed, uint64_t region,
+                   uint64_t byte_off, void* stream)
+{
+    if (((uintptr_t)dst & 7) || (nbytes & 7) || (byte_off & 7))
+        return -1;
+    const uint64_t words = nbytes >> 3;
+    if (words == 0)
+        return 0;
+    const uint64_t base = seed * 0x9E3779B97F4A7C15ULL + region * 0xD1B54A32D192ED03ULL;
+    uint64_t blocks = (words + 255) / 256;
+    if (blocks > 65536)
+        blocks = 65536;
+    hipLaunchKernelGGL(synth_fill_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                       (hipStream_t)stream, (uint64_t*)dst, words, base, byte_off >> 3);
+    return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+int synth_mutate_dev(void* region_bytes, uint64_t page_size, const int64_t* d_pages,
+                     uint64_t n_pages, int kind, uint64_t ms, uint64_t region, void* stream)
+{
+    if (n_pages == 0)
+        return 0;
+    if (page_size < 4096 || (page_size & (page_size - 1)) || (kind != 0 && kind != 1))
+        return -1;
+    const uint64_t per = kind == 0 ? 16 : 256;
+    const uint64_t blocks = (n_pages * per + 255) / 256;
+    hipLaunchKernelGGL(synth_mutate_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                       (hipStream_t)stream, (uint8_t*)region_bytes, page_size, d_pages, n_pages,
+                       kind, ms, region);
+    return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+int synth_saxpy_loop(float* y, const float* x, float a, uint64_t n, int iters, int blocks,
+                     void* stream)
+{
+    if (n == 0 || iters <= 0)
+        return 0;
+    hipLaunchKernelGGL(synth_saxpy_loop_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                       y, x, a, n, iters);
+    return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+}  // extern "C"
