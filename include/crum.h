@@ -1,0 +1,164 @@
+/*
+ * crum.h -- C ABI of the incremental GPU snapshot library (gfx950 / MI355X).
+ *
+ * The library implements phase one of a GPU checkpoint: after the application
+ * has quiesced its work (paper section 3.4: synchronise the device, then read
+ * back every active device and managed region), the device memory named by a
+ * region table is drained to host memory.  It is incremental: each region may
+ * come with a shadow copy of its last snapshot in device memory, and only
+ * pages whose bytes differ from the shadow are packed and copied.  A region
+ * without a shadow has every page dirty, as a freshly created shadow region
+ * is all-dirty in the paper's shadow-page scheme (section 3.2, Algorithm 1).
+ * Restore is the inverse (section 3.4, restart: data copied back into the
+ * re-created regions).
+ *
+ * Every buffer argument is caller-owned: regions, shadows, the device staging
+ * buffer, the pinned host image, the status.  The context owns only internal
+ * scratch, CRC tables, one side stream and events.  Device pointers may come
+ * from hipMalloc, hipMallocManaged or a framework allocator; host image and
+ * status pointers must be pinned host memory (hipHostMalloc or equivalent).
+ *
+ * Image layout v1 (little-endian, pad bytes zero):
+ *    0 "CRUMIMG1" | 8 u32 version=1 | 12 u32 page_size | 16 u32 n_regions
+ *   20 u32 flags (bit 0: no region had a shadow) | 24 u64 total_pages G
+ *   32 u64 n_dirty D | 40 u64 seq | 48 u64 data_off | 56 u32 meta_crc
+ *   60 u32 crcs_crc | 64 region table: n_regions x {u64 id, u64 len,
+ *   u64 first_page, u64 0} | 64+32R bitmap: ceil(G/64) u64 words (bit g%64 of
+ *   word g/64 set when global page g is dirty) | zero pad to
+ *   data_off = roundup(64+32R+8W, 4096) | D packed pages in ascending page
+ *   order | D u32 CRC-32C values, one per packed page | zero pad to 8 bytes.
+ *   crcs_crc is the CRC-32C of the CRC array; meta_crc is the CRC-32C of
+ *   bytes [0, 64+32R+8W) with bytes 56..59 read as zero.  Pages are numbered
+ *   globally in table order; page boundaries are relative to each region base.
+ *   CRC-32C: polynomial 0x1EDC6F41 reflected, init and final XOR 0xFFFFFFFF.
+ *
+ * Error conventions.  Argument errors are returned synchronously and nothing
+ * is enqueued (CRUM_EINVAL).  A failing HIP call returns CRUM_EHIP.  Errors
+ * found on the device (ENOSPC, ECRC, EFORMAT) are reported in *h_status, which
+ * is valid once `stream` has passed the call.  A context is not thread-safe;
+ * distinct contexts may be used from distinct threads.  Regions must not be
+ * written while a snapshot of them is in flight.
+ */
+#ifndef CRUM_H
+#define CRUM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct crum_ctx crum_ctx;
+typedef struct crum_plan crum_plan;
+
+/* One snapshotted allocation.  base: device or managed address of the
+ * current bytes; shadow: device address of the baseline copy, or NULL (all
+ * pages dirty); len: bytes, a multiple of the page size (0 allowed); id:
+ * caller tag stored in the image and checked at restore.  base and shadow are
+ * 16-byte aligned; no current or shadow range may overlap another. */
+typedef struct {
+    void* base;
+    void* shadow;
+    uint64_t len;
+    uint64_t id;
+} crum_region;
+
+/* Result of one call, written asynchronously on the call's stream.
+ * code: CRUM_OK or a device-detected error; first_bad: lowest packed-page
+ * slot whose CRC failed (ECRC only); n_dirty: D; total_pages: G;
+ * image_bytes: size of the image (for ENOSPC, the size that was needed). */
+typedef struct {
+    int32_t code;
+    uint32_t first_bad;
+    uint64_t n_dirty;
+    uint64_t total_pages;
+    uint64_t image_bytes;
+} crum_status;
+
+enum {
+    CRUM_OK = 0,
+    CRUM_EINVAL = -1,    /* bad argument; nothing enqueued */
+    CRUM_ENOSPC = -2,    /* image larger than the staging or host capacity */
+    CRUM_ECRC = -3,      /* a packed page failed CRC verification */
+    CRUM_EFORMAT = -4,   /* image header, table, bitmap, pads or checksums invalid */
+    CRUM_EHIP = -5,      /* a HIP runtime call failed */
+    CRUM_EMISMATCH = -6  /* restore table differs from the image (count, len, id) */
+};
+
+enum {
+    CRUM_UPDATE_SHADOW = 1u, /* snapshot: copy each dirty page into its shadow on success;
+                                restore: also write restored pages into the shadows */
+    CRUM_VERIFY = 2u         /* restore: check every page CRC before writing any byte */
+};
+
+/* Create a context on HIP device `device`; builds the CRC tables, the side
+ * stream and events.  Returns CRUM_OK, CRUM_EINVAL (bad device or out==NULL)
+ * or CRUM_EHIP. */
+int crum_ctx_create(int device, crum_ctx** out);
+
+/* Destroy a context (waits for its outstanding work). NULL is ignored. */
+void crum_ctx_destroy(crum_ctx* ctx);
+
+/* Bytes of the image before the first packed page (data_off) for a table of
+ * n_regions regions holding total_pages pages.  Pure host computation. */
+int crum_image_prefix_bytes(uint32_t n_regions, uint64_t total_pages, uint64_t* out);
+
+/* Bytes of an image with the given shape and dirty count. Pure host computation. */
+int crum_image_bytes(uint32_t n_regions, uint64_t total_pages, uint64_t n_dirty,
+                     uint32_t page_size, uint64_t* out);
+
+/* Incremental snapshot (paper section 3.4, checkpoint: quiesce, then read back
+ * every active region; section 3.2: per-page dirty state, all-dirty without a
+ * baseline, dirty cleared after a flush).
+ *
+ * Enqueues on `stream` (a hipStream_t; NULL = the null stream): diff of every
+ * page against its shadow -> dirty bitmap -> prefix sum -> pack of dirty pages
+ * with their CRC-32C -> image header, all built in d_staging in the image
+ * layout above.  The calling thread then waits for the dirty count (one small
+ * device-to-host read), and enqueues the drain of the image to h_image on the
+ * context's side stream, chunked so that copies overlap packing; `stream` is
+ * made to wait for the drain.  With CRUM_UPDATE_SHADOW, every dirty page is
+ * also copied into its shadow, but only when the status is CRUM_OK.
+ *
+ * d_staging: device buffer of staging_bytes, at least data_off bytes, 16-byte
+ * aligned; receives the image.  h_image: pinned host buffer of h_image_bytes,
+ * or NULL to keep the image on the device only.  If the image does not fit
+ * either capacity, status CRUM_ENOSPC: nothing is packed, no shadow changes,
+ * n_dirty/image_bytes and the bitmap (at d_staging + 64 + 32R) are valid.
+ * h_status: pinned host memory, valid after `stream` passes the call.
+ * Returns CRUM_OK (enqueued), CRUM_EINVAL or CRUM_EHIP. */
+int crum_snapshot(crum_ctx* ctx, const crum_region* regions, uint32_t n_regions,
+                  uint32_t page_size, uint32_t flags, uint64_t seq, void* d_staging,
+                  uint64_t staging_bytes, void* h_image, uint64_t h_image_bytes, void* stream,
+                  crum_status* h_status);
+
+/* Restore (paper section 3.4, restart: the re-created regions receive the
+ * saved data).  The image is read from h_image (pinned host, image_bytes
+ * long) into d_staging, or, when h_image is NULL, is taken to be already in
+ * d_staging.  The host checks the header and region table synchronously:
+ * CRUM_EFORMAT or CRUM_EMISMATCH are returned (and written to *h_status) with
+ * nothing enqueued.  On the device: meta_crc, crcs_crc, bitmap and pads are
+ * checked (CRUM_EFORMAT); with CRUM_VERIFY every page CRC is checked
+ * (CRUM_ECRC, first_bad = lowest failing slot); only then is each packed page
+ * scattered to its page (and its shadow with CRUM_UPDATE_SHADOW).  On any
+ * device-detected error no region byte is written.  staging_bytes below
+ * image_bytes returns CRUM_ENOSPC synchronously. */
+int crum_restore(crum_ctx* ctx, const crum_region* regions, uint32_t n_regions,
+                 const void* h_image, uint64_t image_bytes, uint32_t flags, void* d_staging,
+                 uint64_t staging_bytes, void* stream, crum_status* h_status);
+
+/* Per-kernel timing, for measurement.  When enabled, the context brackets
+ * each launch of its kernels and each drain copy with timing events.
+ * crum_ctx_timing returns, for kernel class `which` (0 diff, 1 pack,
+ * 2 drain copies, 3 scan/bitmap/list, 4 header, 5 verify, 6 scatter), the
+ * number of launches and the summed duration in milliseconds since the last
+ * reset; it waits for the recorded events. */
+int crum_ctx_set_timing(crum_ctx* ctx, int enable);
+int crum_ctx_timing(crum_ctx* ctx, int which, uint64_t* launches, double* total_ms);
+int crum_ctx_timing_reset(crum_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CRUM_H */

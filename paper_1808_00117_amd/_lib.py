@@ -1,0 +1,147 @@
+"""ctypes binding of libcrum.so: argument marshalling only.
+
+Every function of ``include/crum.h`` is exposed under the same name with the
+same argument order; pointers are Python ints (for example ``tensor.data_ptr()``
+of a device or pinned tensor) and streams are raw ``hipStream_t`` handles
+(``torch.cuda.current_stream().cuda_stream``).  There is no fallback: when the
+shared library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO = os.path.join(HERE, "libcrum.so")
+
+CRUM_OK, CRUM_EINVAL, CRUM_ENOSPC, CRUM_ECRC = 0, -1, -2, -3
+CRUM_EFORMAT, CRUM_EHIP, CRUM_EMISMATCH = -4, -5, -6
+CRUM_UPDATE_SHADOW, CRUM_VERIFY = 1, 2
+
+CODE_NAMES = {0: "CRUM_OK", -1: "CRUM_EINVAL", -2: "CRUM_ENOSPC", -3: "CRUM_ECRC",
+              -4: "CRUM_EFORMAT", -5: "CRUM_EHIP", -6: "CRUM_EMISMATCH"}
+
+
+class crum_region(ctypes.Structure):
+    _fields_ = [("base", ctypes.c_void_p), ("shadow", ctypes.c_void_p),
+                ("len", ctypes.c_uint64), ("id", ctypes.c_uint64)]
+
+
+class crum_status(ctypes.Structure):
+    _fields_ = [("code", ctypes.c_int32), ("first_bad", ctypes.c_uint32),
+                ("n_dirty", ctypes.c_uint64), ("total_pages", ctypes.c_uint64),
+                ("image_bytes", ctypes.c_uint64)]
+
+
+_P = ctypes.c_void_p
+_U32, _U64, _I = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+_SIGS = {
+    "crum_ctx_create": (_I, [_I, ctypes.POINTER(_P)]),
+    "crum_ctx_destroy": (None, [_P]),
+    "crum_image_prefix_bytes": (_I, [_U32, _U64, ctypes.POINTER(_U64)]),
+    "crum_image_bytes": (_I, [_U32, _U64, _U64, _U32, ctypes.POINTER(_U64)]),
+    "crum_snapshot": (_I, [_P, _P, _U32, _U32, _U32, _U64, _P, _U64, _P, _U64, _P, _P]),
+    "crum_restore": (_I, [_P, _P, _U32, _P, _U64, _U32, _P, _U64, _P, _P]),
+    "crum_ctx_set_timing": (_I, [_P, _I]),
+    "crum_ctx_timing": (_I, [_P, _I, ctypes.POINTER(_U64), ctypes.POINTER(ctypes.c_double)]),
+    "crum_ctx_timing_reset": (_I, [_P]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libcrum.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO):
+            raise RuntimeError(f"{SO} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(SO)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def region_table(regions: Sequence) -> "ctypes.Array":
+    """regions: (base_ptr, shadow_ptr_or_0, len, id) tuples -> crum_region array."""
+    arr = (crum_region * max(1, len(regions)))()
+    for i, (base, shadow, ln, rid) in enumerate(regions):
+        arr[i] = crum_region(base or None, shadow or None, ln, rid)
+    return arr
+
+
+def crum_ctx_create(device: int = 0) -> int:
+    h = _P()
+    rc = lib().crum_ctx_create(device, ctypes.byref(h))
+    if rc != CRUM_OK:
+        raise RuntimeError(f"crum_ctx_create failed: {CODE_NAMES.get(rc, rc)}")
+    return h.value
+
+
+def crum_ctx_destroy(ctx: int) -> None:
+    lib().crum_ctx_destroy(ctx)
+
+
+def crum_image_prefix_bytes(n_regions: int, total_pages: int) -> int:
+    out = _U64()
+    rc = lib().crum_image_prefix_bytes(n_regions, total_pages, ctypes.byref(out))
+    if rc != CRUM_OK:
+        raise ValueError(CODE_NAMES.get(rc, rc))
+    return out.value
+
+
+def crum_image_bytes(n_regions: int, total_pages: int, n_dirty: int, page_size: int) -> int:
+    out = _U64()
+    rc = lib().crum_image_bytes(n_regions, total_pages, n_dirty, page_size, ctypes.byref(out))
+    if rc != CRUM_OK:
+        raise ValueError(CODE_NAMES.get(rc, rc))
+    return out.value
+
+
+def crum_snapshot(ctx: int, regions, page_size: int, flags: int, seq: int, d_staging: int,
+                  staging_bytes: int, h_image: int, h_image_bytes: int, stream: int,
+                  h_status: int) -> int:
+    """regions: sequence of (base, shadow, len, id) or a crum_region array."""
+    arr = regions if isinstance(regions, ctypes.Array) else region_table(regions)
+    n = len(regions)
+    return lib().crum_snapshot(ctx, ctypes.cast(arr, _P) if n else None, n, page_size, flags,
+                               seq, d_staging, staging_bytes, h_image or None, h_image_bytes,
+                               stream or None, h_status)
+
+
+def crum_restore(ctx: int, regions, h_image: int, image_bytes: int, flags: int,
+                 d_staging: int, staging_bytes: int, stream: int, h_status: int) -> int:
+    arr = regions if isinstance(regions, ctypes.Array) else region_table(regions)
+    n = len(regions)
+    return lib().crum_restore(ctx, ctypes.cast(arr, _P) if n else None, n, h_image or None,
+                              image_bytes, flags, d_staging, staging_bytes, stream or None,
+                              h_status)
+
+
+def crum_ctx_set_timing(ctx: int, enable: bool) -> None:
+    lib().crum_ctx_set_timing(ctx, 1 if enable else 0)
+
+
+def crum_ctx_timing(ctx: int, which: int):
+    n, ms = _U64(), ctypes.c_double()
+    rc = lib().crum_ctx_timing(ctx, which, ctypes.byref(n), ctypes.byref(ms))
+    if rc != CRUM_OK:
+        raise RuntimeError(CODE_NAMES.get(rc, rc))
+    return n.value, ms.value
+
+
+def crum_ctx_timing_reset(ctx: int) -> None:
+    rc = lib().crum_ctx_timing_reset(ctx)
+    if rc != CRUM_OK:
+        raise RuntimeError(CODE_NAMES.get(rc, rc))
+
+
+def read_status(addr: int) -> crum_status:
+    """Copy a crum_status out of (pinned) host memory at addr."""
+    st = crum_status()
+    ctypes.memmove(ctypes.byref(st), addr, ctypes.sizeof(st))
+    return st

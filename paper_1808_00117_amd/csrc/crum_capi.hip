@@ -1,0 +1,695 @@
+// Host runtime and C ABI of libcrum: argument validation, flattening of the
+// region table, scratch management, stream/event orchestration of the
+// snapshot and restore pipelines, and the chunked drain.
+#include "crum.h"
+#include "crum_dev.h"
+#include "gf2.h"
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <utility>
+#include <vector>
+
+using namespace crum;
+
+namespace {
+
+constexpr int kTimingClasses = 7;
+enum { kTDiff = 0, kTPack = 1, kTDrain = 2, kTScan = 3, kTHeader = 4, kTVerify = 5, kTScatter = 6 };
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess)
+            prev = -1;
+        if (prev != dev)
+            (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev)
+            (void)hipSetDevice(prev);
+    }
+};
+
+uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+int log2_exact(uint64_t p)
+{
+    int s = 0;
+    while ((1ull << s) < p)
+        ++s;
+    return s;
+}
+
+bool page_size_ok(uint64_t p) { return p >= 4096 && p <= (1ull << 30) && (p & (p - 1)) == 0; }
+
+// Scratch layout of one launch (offsets into ctx->d_scratch).
+struct Layout {
+    size_t regs = 0, reqs = 0, out = 0, glob = 0, upload_end = 0;
+    size_t flags = 0, bitmap = 0, prefix = 0, list = 0, partials = 0, total = 0;
+};
+
+Layout make_layout(uint32_t n_regs, uint32_t n_reqs, uint64_t n_units, uint64_t n_words,
+                   uint64_t list_cap, uint64_t partial_cap)
+{
+    Layout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = round_up(off + bytes, 256);
+        return o;
+    };
+    L.regs = take(64ull * std::max<uint32_t>(1, n_regs));
+    L.reqs = take(64ull * n_reqs);
+    L.out = take(64ull * n_reqs + 64);
+    L.glob = L.out + 64ull * n_reqs;
+    L.upload_end = off;
+    L.flags = take(std::max<uint64_t>(n_units, 1));
+    L.bitmap = take(8 * std::max<uint64_t>(n_words, 1));
+    L.prefix = take(4 * std::max<uint64_t>(n_words, 1));
+    L.list = take(4 * std::max<uint64_t>(list_cap, 1));
+    L.partials = take(4 * std::max<uint64_t>(partial_cap, 1));
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct crum_ctx {
+    int device = 0;
+    int cus = 256;
+    hipStream_t side = nullptr;
+    CrcTables* d_tabs = nullptr;
+    uint8_t* d_scratch = nullptr;
+    size_t scratch_cap = 0;
+    uint8_t* h_pin = nullptr;  // uploads, then readback area
+    size_t pin_cap = 0;
+    hipEvent_t ev_upload = nullptr, ev_count = nullptr, ev_done = nullptr, ev_hdr = nullptr;
+    std::vector<hipEvent_t> ev_chunk;
+    LaunchShape shape{};
+    bool timing = false;
+    std::vector<hipEvent_t> pool;
+    size_t pool_used = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> spans[kTimingClasses];
+};
+
+namespace {
+
+hipEvent_t timing_event(crum_ctx* c)
+{
+    if (c->pool_used == c->pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess)
+            return nullptr;
+        c->pool.push_back(e);
+    }
+    return c->pool[c->pool_used++];
+}
+
+// Brackets launches with timing events when the context measures.
+struct Span {
+    crum_ctx* c;
+    int cls;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    Span(crum_ctx* c_, int cls_, hipStream_t s_) : c(c_), cls(cls_), s(s_)
+    {
+        if (c->timing && (a = timing_event(c)))
+            (void)hipEventRecord(a, s);
+    }
+    void end()
+    {
+        if (!a)
+            return;
+        hipEvent_t b = timing_event(c);
+        if (b && hipEventRecord(b, s) == hipSuccess)
+            c->spans[cls].emplace_back(a, b);
+        a = nullptr;
+    }
+    ~Span() { end(); }
+};
+
+hipError_t ensure_scratch(crum_ctx* c, size_t bytes)
+{
+    if (bytes <= c->scratch_cap)
+        return hipSuccess;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess)
+        return e;
+    if (c->d_scratch)
+        (void)hipFree(c->d_scratch);
+    c->d_scratch = nullptr;
+    c->scratch_cap = 0;
+    const size_t cap = round_up(bytes + bytes / 4, 1 << 20);
+    e = hipMalloc(reinterpret_cast<void**>(&c->d_scratch), cap);
+    if (e == hipSuccess)
+        c->scratch_cap = cap;
+    return e;
+}
+
+hipError_t ensure_pinned(crum_ctx* c, size_t bytes)
+{
+    if (bytes <= c->pin_cap)
+        return hipSuccess;
+    hipError_t e = hipEventSynchronize(c->ev_upload);
+    if (e != hipSuccess)
+        return e;
+    e = hipEventSynchronize(c->ev_done);
+    if (e != hipSuccess)
+        return e;
+    if (c->h_pin)
+        (void)hipHostFree(c->h_pin);
+    c->h_pin = nullptr;
+    c->pin_cap = 0;
+    const size_t cap = round_up(bytes + bytes / 4, 1 << 16);
+    e = hipHostMalloc(reinterpret_cast<void**>(&c->h_pin), cap, 0);
+    if (e == hipSuccess)
+        c->pin_cap = cap;
+    return e;
+}
+
+// Pointer rules shared by snapshot and restore: non-empty regions have a
+// base, every pointer is 16-byte aligned, and no current or shadow range
+// overlaps another.
+int check_ranges(const crum_region* regs, uint32_t n)
+{
+    std::vector<std::pair<uintptr_t, uintptr_t>> iv;
+    iv.reserve(2 * (size_t)n);
+    for (uint32_t i = 0; i < n; ++i) {
+        const crum_region& r = regs[i];
+        if ((reinterpret_cast<uintptr_t>(r.base) & 15u) ||
+            (reinterpret_cast<uintptr_t>(r.shadow) & 15u))
+            return CRUM_EINVAL;
+        if (r.len == 0)
+            continue;
+        if (!r.base)
+            return CRUM_EINVAL;
+        const uintptr_t b = reinterpret_cast<uintptr_t>(r.base);
+        if (b + r.len < b)
+            return CRUM_EINVAL;
+        iv.emplace_back(b, b + r.len);
+        if (r.shadow) {
+            const uintptr_t s = reinterpret_cast<uintptr_t>(r.shadow);
+            if (s + r.len < s)
+                return CRUM_EINVAL;
+            iv.emplace_back(s, s + r.len);
+        }
+    }
+    std::sort(iv.begin(), iv.end());
+    for (size_t i = 1; i < iv.size(); ++i)
+        if (iv[i].first < iv[i - 1].second)
+            return CRUM_EINVAL;
+    return CRUM_OK;
+}
+
+// Flatten one table into DevRegion entries (single request, request 0).
+void flatten(const crum_region* regs, uint32_t n, uint32_t ps, DevRegion* out,
+             uint64_t* n_pages, uint64_t* n_tiles, uint64_t* n_units)
+{
+    uint64_t page = 0, tile = 0, unit = 0;
+    const uint32_t us = std::min<uint32_t>(ps, kTileShift);
+    for (uint32_t i = 0; i < n; ++i) {
+        DevRegion& d = out[i];
+        d.cur = static_cast<const uint8_t*>(regs[i].base);
+        d.shadow = static_cast<uint8_t*>(regs[i].shadow);
+        d.len = regs[i].len;
+        d.first_page = page;
+        d.first_tile = tile;
+        d.first_unit = unit;
+        d.id = regs[i].id;
+        d.page_shift = ps;
+        d.req = 0;
+        page += regs[i].len >> ps;
+        tile += (regs[i].len + kTileBytes - 1) >> kTileShift;
+        unit += regs[i].len >> us;
+    }
+    *n_pages = page;
+    *n_tiles = tile;
+    *n_units = unit;
+}
+
+#define CRUM_TRY(expr)                          \
+    do {                                        \
+        hipError_t e_ = (expr);                 \
+        if (e_ != hipSuccess)                   \
+            return CRUM_EHIP;                   \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int crum_image_prefix_bytes(uint32_t n_regions, uint64_t total_pages, uint64_t* out)
+{
+    if (!out || total_pages > (1ull << 40))
+        return CRUM_EINVAL;
+    *out = round_up(64 + 32ull * n_regions + 8 * ((total_pages + 63) / 64), 4096);
+    return CRUM_OK;
+}
+
+int crum_image_bytes(uint32_t n_regions, uint64_t total_pages, uint64_t n_dirty,
+                     uint32_t page_size, uint64_t* out)
+{
+    uint64_t pre = 0;
+    if (!out || !page_size_ok(page_size) || n_dirty > total_pages ||
+        crum_image_prefix_bytes(n_regions, total_pages, &pre) != CRUM_OK)
+        return CRUM_EINVAL;
+    *out = pre + n_dirty * page_size + round_up(4 * n_dirty, 8);
+    return CRUM_OK;
+}
+
+int crum_ctx_create(int device, crum_ctx** out)
+{
+    if (!out)
+        return CRUM_EINVAL;
+    *out = nullptr;
+    int n_dev = 0;
+    if (hipGetDeviceCount(&n_dev) != hipSuccess)
+        return CRUM_EHIP;
+    if (device < 0 || device >= n_dev)
+        return CRUM_EINVAL;
+    DeviceGuard g(device);
+    crum_ctx* c = new crum_ctx();
+    c->device = device;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+        cus > 0)
+        c->cus = cus;
+    c->shape.diff_blocks = c->cus * 8;
+    c->shape.pack_blocks = c->cus * 4;
+    if (const char* v = std::getenv("CRUM_DIFF_BLOCKS"))
+        c->shape.diff_blocks = std::max(1, std::atoi(v));
+    if (const char* v = std::getenv("CRUM_PACK_BLOCKS"))
+        c->shape.pack_blocks = std::max(1, std::atoi(v));
+    CrcTables host;
+    build_crc_tables(&host);
+    bool ok = hipMalloc(reinterpret_cast<void**>(&c->d_tabs), sizeof(CrcTables)) == hipSuccess &&
+              hipMemcpy(c->d_tabs, &host, sizeof(CrcTables), hipMemcpyHostToDevice) ==
+                  hipSuccess &&
+              hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&c->ev_upload, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&c->ev_count, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&c->ev_hdr, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        crum_ctx_destroy(c);
+        return CRUM_EHIP;
+    }
+    *out = c;
+    return CRUM_OK;
+}
+
+void crum_ctx_destroy(crum_ctx* c)
+{
+    if (!c)
+        return;
+    DeviceGuard g(c->device);
+    (void)hipDeviceSynchronize();
+    for (hipEvent_t e : c->pool)
+        (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->ev_chunk)
+        (void)hipEventDestroy(e);
+    for (hipEvent_t e : {c->ev_upload, c->ev_count, c->ev_done, c->ev_hdr})
+        if (e)
+            (void)hipEventDestroy(e);
+    if (c->side)
+        (void)hipStreamDestroy(c->side);
+    if (c->d_tabs)
+        (void)hipFree(c->d_tabs);
+    if (c->d_scratch)
+        (void)hipFree(c->d_scratch);
+    if (c->h_pin)
+        (void)hipHostFree(c->h_pin);
+    delete c;
+}
+
+int crum_ctx_set_timing(crum_ctx* c, int enable)
+{
+    if (!c)
+        return CRUM_EINVAL;
+    c->timing = enable != 0;
+    return CRUM_OK;
+}
+
+int crum_ctx_timing_reset(crum_ctx* c)
+{
+    if (!c)
+        return CRUM_EINVAL;
+    DeviceGuard g(c->device);
+    for (auto& v : c->spans) {
+        for (auto& p : v)
+            if (hipEventSynchronize(p.second) != hipSuccess)
+                return CRUM_EHIP;
+        v.clear();
+    }
+    c->pool_used = 0;
+    return CRUM_OK;
+}
+
+int crum_ctx_timing(crum_ctx* c, int which, uint64_t* launches, double* total_ms)
+{
+    if (!c || which < 0 || which >= kTimingClasses || !launches || !total_ms)
+        return CRUM_EINVAL;
+    DeviceGuard g(c->device);
+    double tot = 0;
+    for (auto& p : c->spans[which]) {
+        float ms = 0;
+        if (hipEventSynchronize(p.second) != hipSuccess ||
+            hipEventElapsedTime(&ms, p.first, p.second) != hipSuccess)
+            return CRUM_EHIP;
+        tot += ms;
+    }
+    *launches = c->spans[which].size();
+    *total_ms = tot;
+    return CRUM_OK;
+}
+
+int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
+                  uint32_t page_size, uint32_t flags, uint64_t seq, void* d_staging,
+                  uint64_t staging_bytes, void* h_image, uint64_t h_image_bytes, void* stream_,
+                  crum_status* h_status)
+{
+    // ---- synchronous argument checks (nothing enqueued on failure)
+    if (!c || !h_status || (n_regions && !regions) || !d_staging ||
+        (reinterpret_cast<uintptr_t>(d_staging) & 15u) || !page_size_ok(page_size) ||
+        (flags & ~(uint32_t)CRUM_UPDATE_SHADOW))
+        return CRUM_EINVAL;
+    const uint32_t ps = (uint32_t)log2_exact(page_size);
+    for (uint32_t i = 0; i < n_regions; ++i)
+        if (regions[i].len % page_size)
+            return CRUM_EINVAL;
+    if (check_ranges(regions, n_regions) != CRUM_OK)
+        return CRUM_EINVAL;
+    uint64_t G = 0;
+    for (uint32_t i = 0; i < n_regions; ++i)
+        G += regions[i].len >> ps;
+    if (G > 0xFFFFFF00ull)
+        return CRUM_EINVAL;
+    const uint64_t W = (G + 63) / 64;
+    const uint64_t data_off = round_up(64 + 32ull * n_regions + 8 * W, 4096);
+    if (staging_bytes < data_off || (h_image && h_image_bytes < data_off))
+        return CRUM_EINVAL;
+    const uint64_t capacity = h_image ? std::min(staging_bytes, h_image_bytes) : staging_bytes;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    DeviceGuard g(c->device);
+
+    // ---- flatten, scratch, upload
+    const uint32_t np_shift = ps > kPieceShift ? ps - kPieceShift : 0;
+    std::vector<DevRegion> dregs(std::max<uint32_t>(1, n_regions));
+    uint64_t n_pages = 0, n_tiles = 0, n_units = 0;
+    flatten(regions, n_regions, ps, dregs.data(), &n_pages, &n_tiles, &n_units);
+    const Layout L = make_layout(n_regions, 1, n_units, W, W * 64, np_shift ? G << np_shift : 0);
+    CRUM_TRY(ensure_scratch(c, L.total));
+    const size_t rb_off = round_up(L.upload_end, 256);
+    CRUM_TRY(ensure_pinned(c, rb_off + 128));
+    CRUM_TRY(hipEventSynchronize(c->ev_upload));
+    uint8_t* P = c->h_pin;
+    std::memset(P, 0, L.upload_end);
+    std::memcpy(P + L.regs, dregs.data(), sizeof(DevRegion) * n_regions);
+    DevRequest rq{};
+    rq.first_word = 0;
+    rq.n_words = W;
+    rq.n_pages = G;
+    rq.first_region = 0;
+    rq.n_regions = n_regions;
+    rq.data_off = data_off;
+    rq.seq = seq;
+    rq.page_shift = ps;
+    rq.init_fix = crc_init_fix(page_size);
+    std::memcpy(P + L.reqs, &rq, sizeof(rq));
+    DevGlobal gl{};
+    gl.crc_bad = kNoBad;
+    std::memcpy(P + L.glob, &gl, sizeof(gl));
+
+    uint8_t* S = c->d_scratch;
+    const DevRegion* d_regs = reinterpret_cast<const DevRegion*>(S + L.regs);
+    const DevRequest* d_reqs = reinterpret_cast<const DevRequest*>(S + L.reqs);
+    DevReqOut* d_out = reinterpret_cast<DevReqOut*>(S + L.out);
+    DevGlobal* d_glob = reinterpret_cast<DevGlobal*>(S + L.glob);
+    uint8_t* d_flags = S + L.flags;
+    uint64_t* d_bitmap = reinterpret_cast<uint64_t*>(S + L.bitmap);
+    uint32_t* d_prefix = reinterpret_cast<uint32_t*>(S + L.prefix);
+    uint32_t* d_list = reinterpret_cast<uint32_t*>(S + L.list);
+    uint32_t* d_partials = reinterpret_cast<uint32_t*>(S + L.partials);
+    uint8_t* staging = static_cast<uint8_t*>(d_staging);
+
+    // the previous call on this context may still be draining from scratch
+    CRUM_TRY(hipStreamWaitEvent(stream, c->ev_done, 0));
+    CRUM_TRY(hipMemcpyAsync(S, P, L.upload_end, hipMemcpyHostToDevice, stream));
+    CRUM_TRY(hipEventRecord(c->ev_upload, stream));
+
+    // ---- diff, bitmap, scan (device), then the count readback
+    {
+        Span sp(c, kTDiff, stream);
+        CRUM_TRY(launch_diff(d_regs, n_regions, n_tiles, d_flags, c->shape.diff_blocks, stream));
+    }
+    {
+        Span sp(c, kTScan, stream);
+        CRUM_TRY(launch_bitmap(d_regs, n_regions, W, d_flags, d_bitmap, stream));
+        CRUM_TRY(launch_scan(d_bitmap, W, d_prefix, d_reqs, 1, d_out, d_glob, capacity, 0,
+                             stream));
+    }
+    uint8_t* rb = P + rb_off;
+    CRUM_TRY(hipMemcpyAsync(rb, d_out, 128, hipMemcpyDeviceToHost, stream));
+    CRUM_TRY(hipEventRecord(c->ev_count, stream));
+    CRUM_TRY(hipEventSynchronize(c->ev_count));
+    DevReqOut o;
+    std::memcpy(&o, rb, sizeof(o));
+
+    if (o.code != CRUM_OK) {
+        // ENOSPC: header, table and bitmap only; nothing packed or drained
+        Span sp(c, kTHeader, stream);
+        CRUM_TRY(launch_header(d_regs, d_reqs, 1, d_out, d_bitmap, 0, staging, c->d_tabs, stream));
+        sp.end();
+        CRUM_TRY(hipMemcpyAsync(h_status, d_out, sizeof(crum_status), hipMemcpyDeviceToHost,
+                                stream));
+        CRUM_TRY(hipEventRecord(c->ev_done, stream));
+        return CRUM_OK;
+    }
+    const uint64_t D = o.n_dirty;
+    uint8_t* himg = static_cast<uint8_t*>(h_image);
+
+    // ---- compaction list, then pack in chunks with the drain behind it
+    if (D) {
+        Span sp(c, kTScan, stream);
+        CRUM_TRY(launch_list(d_bitmap, d_prefix, W, d_list, stream));
+    }
+    uint64_t k0 = 0;
+    uint64_t chunk_bytes = 8ull << 20;
+    size_t ci = 0;
+    while (k0 < D) {
+        const uint64_t n_slots = std::max<uint64_t>(1, chunk_bytes >> ps);
+        const uint64_t k1 = std::min(D, k0 + n_slots);
+        {
+            Span sp(c, kTPack, stream);
+            CRUM_TRY(launch_pack(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, k0, k1,
+                                 np_shift, staging, (flags & CRUM_UPDATE_SHADOW) ? 1 : 0,
+                                 d_partials, c->d_tabs, d_glob, c->shape.pack_blocks, stream));
+            CRUM_TRY(launch_finalize(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, k0, k1,
+                                     np_shift, d_partials, staging, d_glob, stream));
+        }
+        if (himg) {
+            if (ci == c->ev_chunk.size()) {
+                hipEvent_t e;
+                CRUM_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+                c->ev_chunk.push_back(e);
+            }
+            CRUM_TRY(hipEventRecord(c->ev_chunk[ci], stream));
+            CRUM_TRY(hipStreamWaitEvent(c->side, c->ev_chunk[ci], 0));
+            const uint64_t off = data_off + (k0 << ps);
+            Span sp(c, kTDrain, c->side);
+            CRUM_TRY(hipMemcpyAsync(himg + off, staging + off, (k1 - k0) << ps,
+                                    hipMemcpyDeviceToHost, c->side));
+        }
+        ++ci;
+        k0 = k1;
+        chunk_bytes = std::min<uint64_t>(chunk_bytes * 2, 256ull << 20);
+    }
+    {
+        Span sp(c, kTHeader, stream);
+        CRUM_TRY(launch_header(d_regs, d_reqs, 1, d_out, d_bitmap, 0, staging, c->d_tabs, stream));
+    }
+    if (himg) {
+        CRUM_TRY(hipEventRecord(c->ev_hdr, stream));
+        CRUM_TRY(hipStreamWaitEvent(c->side, c->ev_hdr, 0));
+        const uint64_t tail = data_off + (D << ps);
+        Span sp(c, kTDrain, c->side);
+        CRUM_TRY(hipMemcpyAsync(himg, staging, data_off, hipMemcpyDeviceToHost, c->side));
+        if (o.image_bytes > tail)
+            CRUM_TRY(hipMemcpyAsync(himg + tail, staging + tail, o.image_bytes - tail,
+                                    hipMemcpyDeviceToHost, c->side));
+        sp.end();
+        CRUM_TRY(hipMemcpyAsync(h_status, d_out, sizeof(crum_status), hipMemcpyDeviceToHost,
+                                c->side));
+        CRUM_TRY(hipEventRecord(c->ev_done, c->side));
+        CRUM_TRY(hipStreamWaitEvent(stream, c->ev_done, 0));
+    } else {
+        CRUM_TRY(hipMemcpyAsync(h_status, d_out, sizeof(crum_status), hipMemcpyDeviceToHost,
+                                stream));
+        CRUM_TRY(hipEventRecord(c->ev_done, stream));
+    }
+    return CRUM_OK;
+}
+
+static int restore_fail(crum_status* st, int code, uint64_t D, uint64_t G, uint64_t n)
+{
+    st->code = code;
+    st->first_bad = 0;
+    st->n_dirty = D;
+    st->total_pages = G;
+    st->image_bytes = n;
+    return code;
+}
+
+static uint32_t rd32(const uint8_t* p)
+{
+    uint32_t v;
+    std::memcpy(&v, p, 4);
+    return v;
+}
+
+static uint64_t rd64(const uint8_t* p)
+{
+    uint64_t v;
+    std::memcpy(&v, p, 8);
+    return v;
+}
+
+int crum_restore(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
+                 const void* h_image, uint64_t image_bytes, uint32_t flags, void* d_staging,
+                 uint64_t staging_bytes, void* stream_, crum_status* h_status)
+{
+    if (!c || !h_status || (n_regions && !regions) || !d_staging ||
+        (reinterpret_cast<uintptr_t>(d_staging) & 15u) ||
+        (flags & ~(uint32_t)(CRUM_UPDATE_SHADOW | CRUM_VERIFY)))
+        return CRUM_EINVAL;
+    if (check_ranges(regions, n_regions) != CRUM_OK)
+        return CRUM_EINVAL;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    DeviceGuard g(c->device);
+
+    // ---- host-side header and table checks
+    std::vector<uint8_t> hdr_copy;
+    const uint8_t* h = static_cast<const uint8_t*>(h_image);
+    if (image_bytes < 64)
+        return restore_fail(h_status, CRUM_EFORMAT, 0, 0, image_bytes);
+    if (!h) {
+        const uint64_t want = std::min<uint64_t>(image_bytes, 64 + 32ull * n_regions);
+        hdr_copy.resize(want);
+        CRUM_TRY(hipStreamSynchronize(stream));
+        CRUM_TRY(hipMemcpy(hdr_copy.data(), d_staging, want, hipMemcpyDeviceToHost));
+        h = hdr_copy.data();
+    }
+    if (std::memcmp(h, "CRUMIMG1", 8) != 0 || rd32(h + 8) != 1 || !page_size_ok(rd32(h + 12)) ||
+        (rd32(h + 20) & ~1u))
+        return restore_fail(h_status, CRUM_EFORMAT, 0, 0, image_bytes);
+    const uint32_t page_size = rd32(h + 12);
+    const uint32_t ps = (uint32_t)log2_exact(page_size);
+    const uint64_t R = rd32(h + 16), G = rd64(h + 24), D = rd64(h + 32), seq = rd64(h + 40);
+    const uint64_t data_off = rd64(h + 48);
+    if (G > 0xFFFFFF00ull || D > G)
+        return restore_fail(h_status, CRUM_EFORMAT, D, G, image_bytes);
+    const uint64_t W = (G + 63) / 64;
+    const uint64_t prefix_end = 64 + 32 * R + 8 * W;
+    if (data_off != round_up(prefix_end, 4096) ||
+        data_off + (D << ps) + round_up(4 * D, 8) != image_bytes)
+        return restore_fail(h_status, CRUM_EFORMAT, D, G, image_bytes);
+    if (R != n_regions)
+        return restore_fail(h_status, CRUM_EMISMATCH, D, G, image_bytes);
+    if (hdr_copy.size() && hdr_copy.size() < 64 + 32 * R)
+        return restore_fail(h_status, CRUM_EFORMAT, D, G, image_bytes);
+    uint64_t chain = 0;
+    bool mismatch = false;
+    for (uint64_t i = 0; i < R; ++i) {
+        const uint8_t* e = h + 64 + 32 * i;
+        const uint64_t len = rd64(e + 8);
+        if (rd64(e + 24) != 0 || len % page_size || rd64(e + 16) != chain)
+            return restore_fail(h_status, CRUM_EFORMAT, D, G, image_bytes);
+        chain += len >> ps;
+        if (rd64(e) != regions[i].id || len != regions[i].len)
+            mismatch = true;
+    }
+    if (chain != G)
+        return restore_fail(h_status, CRUM_EFORMAT, D, G, image_bytes);
+    if (mismatch)
+        return restore_fail(h_status, CRUM_EMISMATCH, D, G, image_bytes);
+    if (staging_bytes < image_bytes)
+        return restore_fail(h_status, CRUM_ENOSPC, D, G, image_bytes);
+
+    // ---- device tables
+    const uint32_t np_shift = ps > kPieceShift ? ps - kPieceShift : 0;
+    std::vector<DevRegion> dregs(std::max<uint32_t>(1, n_regions));
+    uint64_t n_pages = 0, n_tiles = 0, n_units = 0;
+    flatten(regions, n_regions, ps, dregs.data(), &n_pages, &n_tiles, &n_units);
+    const Layout L = make_layout(n_regions, 1, 0, W, W * 64, np_shift ? D << np_shift : 0);
+    CRUM_TRY(ensure_scratch(c, L.total));
+    CRUM_TRY(ensure_pinned(c, L.upload_end));
+    CRUM_TRY(hipEventSynchronize(c->ev_upload));
+    uint8_t* P = c->h_pin;
+    std::memset(P, 0, L.upload_end);
+    std::memcpy(P + L.regs, dregs.data(), sizeof(DevRegion) * n_regions);
+    DevRequest rq{};
+    rq.n_words = W;
+    rq.n_pages = G;
+    rq.n_regions = n_regions;
+    rq.data_off = data_off;
+    rq.seq = seq;
+    rq.page_shift = ps;
+    rq.init_fix = crc_init_fix(page_size);
+    std::memcpy(P + L.reqs, &rq, sizeof(rq));
+    DevReqOut o{};
+    o.n_dirty = D;
+    o.total_pages = G;
+    o.image_bytes = image_bytes;
+    std::memcpy(P + L.out, &o, sizeof(o));
+    DevGlobal gl{};
+    gl.crc_bad = kNoBad;
+    std::memcpy(P + L.glob, &gl, sizeof(gl));
+
+    uint8_t* S = c->d_scratch;
+    const DevRegion* d_regs = reinterpret_cast<const DevRegion*>(S + L.regs);
+    const DevRequest* d_reqs = reinterpret_cast<const DevRequest*>(S + L.reqs);
+    DevReqOut* d_out = reinterpret_cast<DevReqOut*>(S + L.out);
+    DevGlobal* d_glob = reinterpret_cast<DevGlobal*>(S + L.glob);
+    uint32_t* d_prefix = reinterpret_cast<uint32_t*>(S + L.prefix);
+    uint32_t* d_list = reinterpret_cast<uint32_t*>(S + L.list);
+    uint32_t* d_partials = reinterpret_cast<uint32_t*>(S + L.partials);
+    uint8_t* staging = static_cast<uint8_t*>(d_staging);
+    const uint64_t* img_bitmap = reinterpret_cast<const uint64_t*>(staging + 64 + 32 * R);
+
+    CRUM_TRY(hipStreamWaitEvent(stream, c->ev_done, 0));
+    CRUM_TRY(hipMemcpyAsync(S, P, L.upload_end, hipMemcpyHostToDevice, stream));
+    CRUM_TRY(hipEventRecord(c->ev_upload, stream));
+    if (h_image)
+        CRUM_TRY(hipMemcpyAsync(staging, h_image, image_bytes, hipMemcpyHostToDevice, stream));
+    {
+        Span sp(c, kTScan, stream);
+        CRUM_TRY(launch_restore_check(d_reqs, 1, d_out, staging, c->d_tabs, d_glob, stream));
+        CRUM_TRY(launch_scan(img_bitmap, W, d_prefix, d_reqs, 1, d_out, d_glob, 0, 1, stream));
+        CRUM_TRY(launch_list(img_bitmap, d_prefix, W, d_list, stream));
+    }
+    if (flags & CRUM_VERIFY) {
+        Span sp(c, kTVerify, stream);
+        CRUM_TRY(launch_pack(kModeVerify, d_regs, n_regions, d_reqs, d_out, d_list, 0, D,
+                             np_shift, staging, 0, d_partials, c->d_tabs, d_glob,
+                             c->shape.pack_blocks, stream));
+        CRUM_TRY(launch_finalize(kModeVerify, d_regs, n_regions, d_reqs, d_out, d_list, 0, D,
+                                 np_shift, d_partials, staging, d_glob, stream));
+    }
+    {
+        Span sp(c, kTScatter, stream);
+        CRUM_TRY(launch_scatter(d_regs, n_regions, d_reqs, d_out, d_list, D, np_shift, staging,
+                                (flags & CRUM_UPDATE_SHADOW) ? 1 : 0, d_glob,
+                                c->shape.pack_blocks, stream));
+    }
+    CRUM_TRY(launch_restore_finish(d_out, 1, d_glob, stream));
+    CRUM_TRY(hipMemcpyAsync(h_status, d_out, sizeof(crum_status), hipMemcpyDeviceToHost, stream));
+    CRUM_TRY(hipEventRecord(c->ev_done, stream));
+    return CRUM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,123 @@
+// Internal device-side structures and kernel launch interface of libcrum.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace crum {
+
+// Diff tile: each wave compares kDiffUnroll * 1 KiB of a region per step
+// (64 lanes x 16 bytes per load, kDiffUnroll loads per array).
+constexpr int kDiffUnroll = 8;
+constexpr uint32_t kTileShift = 13;  // log2(kDiffUnroll * 1024)
+constexpr uint32_t kTileBytes = 1u << kTileShift;
+// CRC piece: pages larger than this are split across waves and combined.
+constexpr uint32_t kPieceShift = 16;  // 64 KiB
+constexpr uint32_t kNoBad = 0xFFFFFFFFu;
+
+// One region of the flattened page space (host-built, uploaded per call).
+// Page indices are global across all requests of a launch; each request
+// starts at a multiple of 64 pages so that bitmap words never straddle
+// requests.
+struct DevRegion {
+    const uint8_t* cur;
+    uint8_t* shadow;     // NULL: no baseline
+    uint64_t len;
+    uint64_t first_page; // global page index of page 0
+    uint64_t first_tile; // global diff-tile index of tile 0
+    uint64_t first_unit; // global flag-unit index of unit 0
+    uint64_t id;
+    uint32_t page_shift; // log2 page size
+    uint32_t req;        // request index
+};
+static_assert(sizeof(DevRegion) == 64, "DevRegion layout");
+
+// One request (one image) of a launch.
+struct DevRequest {
+    uint64_t first_word;   // first bitmap word (global)
+    uint64_t n_words;
+    uint64_t n_pages;      // pages of the request (unpadded G)
+    uint64_t first_region; // index into the region table
+    uint64_t n_regions;
+    uint64_t data_off;     // image prefix bytes
+    uint64_t seq;
+    uint32_t page_shift;
+    uint32_t init_fix;     // CRC constant for one page (see gf2.h)
+};
+static_assert(sizeof(DevRequest) == 64, "DevRequest layout");
+
+// Per-request results written on the device.
+struct DevReqOut {
+    int32_t code;
+    uint32_t first_bad;
+    uint64_t n_dirty;
+    uint64_t total_pages;
+    uint64_t image_bytes;
+    uint64_t slot_base;  // global slot of the request's first packed page
+    uint64_t img_base;   // byte offset of the request's image in staging
+    uint64_t pad[2];
+};
+static_assert(sizeof(DevReqOut) == 64, "DevReqOut layout");
+
+// Launch-wide counters written on the device.
+struct DevGlobal {
+    uint64_t total_dirty;    // sum of D over requests
+    uint64_t staging_used;   // bytes of staging the images occupy
+    int32_t code;            // CRUM_OK or CRUM_ENOSPC (any request) / CRUM_EFORMAT
+    uint32_t fmt_bad;        // restore: image check failed
+    uint32_t crc_bad;        // restore: lowest failing slot, kNoBad if none
+    uint32_t pad0;
+    uint64_t pad[4];
+};
+static_assert(sizeof(DevGlobal) == 64, "DevGlobal layout");
+
+// CRC lookup tables held in device memory and staged into LDS:
+//   t[k][b]    = b * x^(8(k+1))        (slicing-by-16 for one 16-byte word)
+//   z[j][i][b] = (b << 8i) * x^(8 L_j)  (shift of a 32-bit state by L_j bytes)
+// with L_j = 32, 64, 128, 256, 512, 1024 for j = 0..5.
+struct CrcTables {
+    uint32_t t[16][256];
+    uint32_t z[6][4][256];
+};
+
+enum PackMode { kModePack = 0, kModeVerify = 1 };
+
+struct LaunchShape {
+    int diff_blocks;   // persistent grid of the diff kernel (256-thread blocks)
+    int pack_blocks;   // persistent grid of the pack/verify/scatter kernels
+};
+
+// Kernel launchers (crum_kernels.hip).  All enqueue on `s`.
+void build_crc_tables(CrcTables* host);
+hipError_t launch_diff(const DevRegion* regs, uint32_t n_regs, uint64_t n_tiles,
+                       uint8_t* unit_flags, int blocks, hipStream_t s);
+hipError_t launch_bitmap(const DevRegion* regs, uint32_t n_regs, uint64_t n_words,
+                         const uint8_t* unit_flags, uint64_t* bitmap, hipStream_t s);
+hipError_t launch_scan(const uint64_t* bitmap, uint64_t n_words, uint32_t* prefix,
+                       const DevRequest* reqs, uint32_t n_reqs, DevReqOut* out, DevGlobal* glob,
+                       uint64_t capacity, int restore_mode, hipStream_t s);
+hipError_t launch_list(const uint64_t* bitmap, const uint32_t* prefix, uint64_t n_words,
+                       uint32_t* list, hipStream_t s);
+hipError_t launch_pack(int mode, const DevRegion* regs, uint32_t n_regs, const DevRequest* reqs,
+                       const DevReqOut* out, const uint32_t* list, uint64_t slot0,
+                       uint64_t slot1, uint32_t piece_shift, uint8_t* staging, int update_shadow,
+                       uint32_t* partials, const CrcTables* tabs, DevGlobal* glob, int blocks,
+                       hipStream_t s);
+hipError_t launch_finalize(int mode, const DevRegion* regs, uint32_t n_regs,
+                           const DevRequest* reqs, const DevReqOut* out, const uint32_t* list,
+                           uint64_t slot0, uint64_t slot1, uint32_t piece_shift,
+                           const uint32_t* partials, uint8_t* staging, DevGlobal* glob,
+                           hipStream_t s);
+hipError_t launch_header(const DevRegion* regs, const DevRequest* reqs, uint32_t n_reqs,
+                         const DevReqOut* out, const uint64_t* bitmap, uint32_t img_flags_mask,
+                         uint8_t* staging, const CrcTables* tabs, hipStream_t s);
+hipError_t launch_restore_check(const DevRequest* reqs, uint32_t n_reqs, const DevReqOut* out,
+                                const uint8_t* staging, const CrcTables* tabs, DevGlobal* glob,
+                                hipStream_t s);
+hipError_t launch_scatter(const DevRegion* regs, uint32_t n_regs, const DevRequest* reqs,
+                          const DevReqOut* out, const uint32_t* list, uint64_t n_slots,
+                          uint32_t np_shift, const uint8_t* staging, int update_shadow,
+                          const DevGlobal* glob, int blocks, hipStream_t s);
+hipError_t launch_restore_finish(DevReqOut* out, uint32_t n_reqs, DevGlobal* glob,
+                                 hipStream_t s);
+
+}  // namespace crum

@@ -1,0 +1,872 @@
+// HIP kernels of the incremental snapshot (gfx950, wave64).
+//
+// Snapshot pipeline (one launch of each, except pack which runs in chunks):
+//   k_diff    per page: OR over 16-byte words of (cur ^ shadow) != 0, read with
+//             coalesced 128-bit loads; one flag byte per diff unit
+//             (min(page, tile) bytes), reduced across the wave by ballot.
+//   k_bitmap  per 64 pages: OR of each page's unit flags, then one ballot
+//             gives the u64 bitmap word.
+//   k_scan    one workgroup: exclusive prefix sum of popcount(word) -> slot of
+//             each word's first dirty page; per-request dirty counts, image
+//             offsets and the capacity check (ENOSPC before any pack write).
+//   k_list    per word: ballot compaction, lane with bit set writes its page
+//             index at prefix + popcount(bits below the lane).
+//   k_pack    per dirty page (or 64 KiB piece): copy into the image's page
+//             area, optionally into the shadow, and CRC-32C on the way.
+//   k_header  per request: header, region table, bitmap, pads, crcs_crc,
+//             meta_crc.
+// Restore: k_restore_check, k_scan, k_list, k_pack (verify), k_scatter.
+//
+// CRC-32C on the device.  The polynomial arithmetic is in gf2.h.  A wave
+// processes a piece of n = 64*T 16-byte words; lane l takes words l, l+64,
+// ..., so every load is coalesced.  Lane l keeps a Horner accumulator
+//   C_l = sum_t raw(w_{l+64t}) * x^(8*1024*(T-1-t)),
+// stepping with "shift by 1024 bytes" (4 table lookups) plus slicing-by-16 of
+// the new word (16 lookups).  The piece's raw CRC is
+//   sum_l C_l * x^(8*16*(63-l)),
+// formed by a 6-level butterfly over lanes (level k shifts the lower half by
+// 16*2^k bytes).  Pieces of one page combine the same way with a shift by the
+// piece length; the standard CRC adds crc_init_fix(page bytes).
+#include "crum_dev.h"
+#include "gf2.h"
+
+namespace crum {
+
+// ------------------------------------------------------------ CRC tables
+
+void build_crc_tables(CrcTables* h)
+{
+    for (int k = 0; k < 16; ++k) {
+        const uint32_t xk = gf2_xpow8n((uint64_t)k + 1);
+        for (int b = 0; b < 256; ++b)
+            h->t[k][b] = gf2_mulmod((uint32_t)b, xk);
+    }
+    const uint64_t L[6] = {32, 64, 128, 256, 512, 1024};
+    for (int j = 0; j < 6; ++j) {
+        const uint32_t xl = gf2_xpow8n(L[j]);
+        for (int i = 0; i < 4; ++i)
+            for (int b = 0; b < 256; ++b)
+                h->z[j][i][b] = gf2_mulmod((uint32_t)b << (8 * i), xl);
+    }
+}
+
+constexpr int kTabWords = 16 * 256 + 6 * 4 * 256;  // 40 KiB
+constexpr int kSliceWords = 16 * 256;              // 16 KiB
+
+// raw CRC of one 16-byte word (bytes b0..b15, b0 = low byte of w.x)
+__device__ __forceinline__ uint32_t word_crc(const uint32_t* __restrict__ T, uint4 w)
+{
+    return T[15 * 256 + (w.x & 255u)] ^ T[14 * 256 + ((w.x >> 8) & 255u)] ^
+           T[13 * 256 + ((w.x >> 16) & 255u)] ^ T[12 * 256 + (w.x >> 24)] ^
+           T[11 * 256 + (w.y & 255u)] ^ T[10 * 256 + ((w.y >> 8) & 255u)] ^
+           T[9 * 256 + ((w.y >> 16) & 255u)] ^ T[8 * 256 + (w.y >> 24)] ^
+           T[7 * 256 + (w.z & 255u)] ^ T[6 * 256 + ((w.z >> 8) & 255u)] ^
+           T[5 * 256 + ((w.z >> 16) & 255u)] ^ T[4 * 256 + (w.z >> 24)] ^
+           T[3 * 256 + (w.w & 255u)] ^ T[2 * 256 + ((w.w >> 8) & 255u)] ^
+           T[1 * 256 + ((w.w >> 16) & 255u)] ^ T[0 * 256 + (w.w >> 24)];
+}
+
+// state carried through 16 zero bytes: the first four slicing tables
+__device__ __forceinline__ uint32_t shift16(const uint32_t* __restrict__ T, uint32_t s)
+{
+    return T[15 * 256 + (s & 255u)] ^ T[14 * 256 + ((s >> 8) & 255u)] ^
+           T[13 * 256 + ((s >> 16) & 255u)] ^ T[12 * 256 + (s >> 24)];
+}
+
+// state carried through L_j zero bytes (Z points at z[j])
+__device__ __forceinline__ uint32_t shiftz(const uint32_t* __restrict__ Z, uint32_t s)
+{
+    return Z[s & 255u] ^ Z[256 + ((s >> 8) & 255u)] ^ Z[512 + ((s >> 16) & 255u)] ^
+           Z[768 + (s >> 24)];
+}
+
+__device__ __forceinline__ void load_tables(uint32_t* lds, const CrcTables* tabs, int words)
+{
+    const uint32_t* src = &tabs->t[0][0];
+    for (int i = threadIdx.x; i < words; i += blockDim.x)
+        lds[i] = src[i];
+    __syncthreads();
+}
+
+// Butterfly over the 64 lanes: afterwards every lane holds sum_l C_l*x^(128(63-l)).
+__device__ __forceinline__ uint32_t lane_combine(const uint32_t* __restrict__ lds, uint32_t s,
+                                                 uint32_t lane)
+{
+#pragma unroll
+    for (int lvl = 0; lvl < 6; ++lvl) {
+        const uint32_t other = (uint32_t)__shfl_xor((int)s, 1 << lvl);
+        const bool upper = (lane >> lvl) & 1u;
+        const uint32_t left = upper ? other : s;
+        const uint32_t right = upper ? s : other;
+        const uint32_t sh = lvl == 0 ? shift16(lds, left)
+                                     : shiftz(lds + kSliceWords + (lvl - 1) * 1024, left);
+        s = sh ^ right;
+    }
+    return s;
+}
+
+// Raw (zero-initialised) CRC of `steps` KiB at src, copied to dst (and sh)
+// when STORE.  All lanes return the same value.
+template <bool STORE>
+__device__ __forceinline__ uint32_t wave_piece_crc(const uint4* __restrict__ src,
+                                                   uint4* __restrict__ dst,
+                                                   uint4* __restrict__ sh, uint32_t steps,
+                                                   uint32_t lane,
+                                                   const uint32_t* __restrict__ lds)
+{
+    const uint32_t* Z1024 = lds + kSliceWords + 5 * 1024;
+    uint32_t s = 0;
+    uint32_t t = 0;
+    for (; t + 4 <= steps; t += 4) {
+        uint4 w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            w[u] = src[(t + u) * 64 + lane];
+        if (STORE) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                dst[(t + u) * 64 + lane] = w[u];
+            if (sh) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    sh[(t + u) * 64 + lane] = w[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            s = shiftz(Z1024, s) ^ word_crc(lds, w[u]);
+    }
+    for (; t < steps; ++t) {
+        const uint4 w = src[t * 64 + lane];
+        if (STORE) {
+            dst[t * 64 + lane] = w;
+            if (sh)
+                sh[t * 64 + lane] = w;
+        }
+        s = shiftz(Z1024, s) ^ word_crc(lds, w);
+    }
+    return lane_combine(lds, s, lane);
+}
+
+// ------------------------------------------------------------ region lookup
+
+// Last region whose field (3 first_page, 4 first_tile) is <= key.
+template <int FIELD>
+__device__ __forceinline__ uint32_t find_region(const DevRegion* __restrict__ regs, uint32_t n,
+                                                uint64_t key)
+{
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        const uint64_t v = FIELD == 3 ? regs[mid].first_page : regs[mid].first_tile;
+        if (v <= key)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------ k_diff
+
+template <int UNROLL>
+__global__ __launch_bounds__(256) void k_diff(const DevRegion* __restrict__ regs,
+                                              uint32_t n_regs, uint64_t n_tiles,
+                                              uint8_t* __restrict__ unit_flags)
+{
+    static_assert(UNROLL * 1024 == (int)kTileBytes, "tile size");
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t wave = (uint64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t n_waves = (uint64_t)gridDim.x * 4;
+    uint32_t r = 0;
+    uint64_t r_lo = 1, r_hi = 0;
+    for (uint64_t t = wave; t < n_tiles; t += n_waves) {
+        if (t < r_lo || t >= r_hi) {
+            r = find_region<4>(regs, n_regs, t);
+            r_lo = regs[r].first_tile;
+            r_hi = r_lo + ((regs[r].len + kTileBytes - 1) >> kTileShift);
+        }
+        const DevRegion& R = regs[r];
+        const uint64_t off = (t - R.first_tile) << kTileShift;
+        const uint64_t rem = R.len - off;
+        const uint32_t us = R.page_shift < kTileShift ? R.page_shift : kTileShift;
+        const uint64_t ubase = R.first_unit + (off >> us);
+        const uint32_t nbytes = rem < kTileBytes ? (uint32_t)rem : kTileBytes;
+        const uint32_t n_units = nbytes >> us;
+        uint64_t dirty_units = 0;
+        if (R.shadow == nullptr) {
+            dirty_units = ~0ull;
+        } else {
+            const uint4* a = reinterpret_cast<const uint4*>(R.cur + off) + lane;
+            const uint4* b = reinterpret_cast<const uint4*>(R.shadow + off) + lane;
+            uint32_t x[UNROLL];
+            if (nbytes == kTileBytes) {
+                uint4 va[UNROLL], vb[UNROLL];
+#pragma unroll
+                for (int j = 0; j < UNROLL; ++j) {
+                    va[j] = a[j * 64];
+                    vb[j] = b[j * 64];
+                }
+#pragma unroll
+                for (int j = 0; j < UNROLL; ++j)
+                    x[j] = (va[j].x ^ vb[j].x) | (va[j].y ^ vb[j].y) | (va[j].z ^ vb[j].z) |
+                           (va[j].w ^ vb[j].w);
+            } else {
+#pragma unroll
+                for (int j = 0; j < UNROLL; ++j) {
+                    x[j] = 0;
+                    if ((uint32_t)j * 1024u < nbytes) {
+                        const uint4 va = a[j * 64], vb = b[j * 64];
+                        x[j] = (va.x ^ vb.x) | (va.y ^ vb.y) | (va.z ^ vb.z) | (va.w ^ vb.w);
+                    }
+                }
+            }
+            const uint32_t lpu_shift = us - 10;  // log2(loads per unit)
+#pragma unroll
+            for (int j = 0; j < UNROLL; ++j) {
+                const uint64_t m = __ballot(x[j] != 0);
+                if (m)
+                    dirty_units |= 1ull << ((uint32_t)j >> lpu_shift);
+            }
+        }
+        if (lane < n_units)
+            unit_flags[ubase + lane] = (uint8_t)((dirty_units >> lane) & 1u);
+    }
+}
+
+hipError_t launch_diff(const DevRegion* regs, uint32_t n_regs, uint64_t n_tiles,
+                       uint8_t* unit_flags, int blocks, hipStream_t s)
+{
+    if (n_tiles == 0)
+        return hipSuccess;
+    const uint64_t need = (n_tiles + 3) / 4;
+    const uint64_t nb = need < (uint64_t)blocks ? need : (uint64_t)blocks;
+    hipLaunchKernelGGL(k_diff<kDiffUnroll>, dim3((unsigned)nb), dim3(256), 0, s, regs, n_regs,
+                       n_tiles, unit_flags);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ k_bitmap
+
+__global__ __launch_bounds__(256) void k_bitmap(const DevRegion* __restrict__ regs,
+                                                uint32_t n_regs, uint64_t n_words,
+                                                const uint8_t* __restrict__ unit_flags,
+                                                uint64_t* __restrict__ bitmap)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t w = (uint64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (w >= n_words)
+        return;
+    const uint64_t g = w * 64 + lane;
+    const uint32_t r = find_region<3>(regs, n_regs, g);
+    const DevRegion& R = regs[r];
+    bool dirty = false;
+    const uint64_t np = R.len >> R.page_shift;
+    if (g >= R.first_page && g - R.first_page < np) {
+        const uint64_t pi = g - R.first_page;
+        const uint32_t us = R.page_shift < kTileShift ? R.page_shift : kTileShift;
+        const uint32_t upp_shift = R.page_shift - us;
+        const uint8_t* f = unit_flags + R.first_unit + (pi << upp_shift);
+        uint32_t acc = 0;
+        for (uint32_t i = 0; i < (1u << upp_shift); ++i)
+            acc |= f[i];
+        dirty = acc != 0;
+    }
+    const uint64_t m = __ballot(dirty);
+    if (lane == 0)
+        bitmap[w] = m;
+}
+
+hipError_t launch_bitmap(const DevRegion* regs, uint32_t n_regs, uint64_t n_words,
+                         const uint8_t* unit_flags, uint64_t* bitmap, hipStream_t s)
+{
+    if (n_words == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_bitmap, dim3((unsigned)((n_words + 3) / 4)), dim3(256), 0, s, regs,
+                       n_regs, n_words, unit_flags, bitmap);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ k_scan
+
+__global__ __launch_bounds__(1024) void k_scan(const uint64_t* __restrict__ bitmap,
+                                               uint64_t n_words, uint32_t* __restrict__ prefix,
+                                               const DevRequest* __restrict__ reqs,
+                                               uint32_t n_reqs, DevReqOut* __restrict__ out,
+                                               DevGlobal* __restrict__ glob, uint64_t capacity,
+                                               int restore_mode)
+{
+    constexpr int V = 4;  // words per thread per pass
+    __shared__ uint32_t wave_tot[16];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    uint32_t carry = 0;
+    for (uint64_t base = 0; base < n_words; base += 1024 * V) {
+        uint32_t c[V];
+        uint32_t local = 0;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const uint64_t w = base + (uint64_t)tid * V + v;
+            c[v] = w < n_words ? (uint32_t)__popcll(bitmap[w]) : 0u;
+            local += c[v];
+        }
+        uint32_t incl = local;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = (uint32_t)__shfl_up((int)incl, d);
+            if (lane >= (uint32_t)d)
+                incl += y;
+        }
+        if (lane == 63)
+            wave_tot[wv] = incl;
+        __syncthreads();
+        uint32_t woff = 0, blk = 0;
+        for (uint32_t i = 0; i < 16; ++i) {
+            if (i < wv)
+                woff += wave_tot[i];
+            blk += wave_tot[i];
+        }
+        uint32_t excl = carry + woff + incl - local;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const uint64_t w = base + (uint64_t)tid * V + v;
+            if (w < n_words)
+                prefix[w] = excl;
+            excl += c[v];
+        }
+        carry += blk;
+        __syncthreads();
+    }
+    __threadfence_block();
+    __syncthreads();
+    if (tid != 0)
+        return;
+    // per-request results, images laid out back to back (4 KiB aligned)
+    uint64_t img = 0, used = 0;
+    for (uint32_t q = 0; q < n_reqs; ++q) {
+        const DevRequest& Q = reqs[q];
+        const uint64_t w0 = Q.first_word, w1 = Q.first_word + Q.n_words;
+        const uint64_t p0 = w0 < n_words ? prefix[w0] : carry;
+        const uint64_t p1 = w1 < n_words ? prefix[w1] : carry;
+        const uint64_t D = p1 - p0;
+        DevReqOut& O = out[q];
+        O.n_dirty = D;
+        O.total_pages = Q.n_pages;
+        O.slot_base = p0;
+        if (!restore_mode) {
+            const uint64_t ib = Q.data_off + (D << Q.page_shift) + ((4 * D + 7) & ~7ull);
+            O.code = 0;
+            O.first_bad = 0;
+            O.image_bytes = ib;
+            O.img_base = img;
+            used = img + ib;
+            img = (used + 4095) & ~4095ull;
+        }
+    }
+    glob->total_dirty = carry;
+    if (!restore_mode) {
+        glob->staging_used = used;
+        const int32_t code = used > capacity ? -2 /* CRUM_ENOSPC */ : 0;
+        glob->code = code;
+        if (code)
+            for (uint32_t q = 0; q < n_reqs; ++q)
+                out[q].code = code;
+    }
+}
+
+hipError_t launch_scan(const uint64_t* bitmap, uint64_t n_words, uint32_t* prefix,
+                       const DevRequest* reqs, uint32_t n_reqs, DevReqOut* out, DevGlobal* glob,
+                       uint64_t capacity, int restore_mode, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, bitmap, n_words, prefix, reqs, n_reqs,
+                       out, glob, capacity, restore_mode);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ k_list
+
+__global__ __launch_bounds__(256) void k_list(const uint64_t* __restrict__ bitmap,
+                                              const uint32_t* __restrict__ prefix,
+                                              uint64_t n_words, uint32_t* __restrict__ list)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t w = (uint64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (w >= n_words)
+        return;
+    const uint64_t m = bitmap[w];
+    if (m == 0)
+        return;
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    if ((m >> lane) & 1u)
+        list[prefix[w] + below] = (uint32_t)(w * 64 + lane);
+}
+
+hipError_t launch_list(const uint64_t* bitmap, const uint32_t* prefix, uint64_t n_words,
+                       uint32_t* list, hipStream_t s)
+{
+    if (n_words == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_list, dim3((unsigned)((n_words + 3) / 4)), dim3(256), 0, s, bitmap,
+                       prefix, n_words, list);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ k_pack / verify
+
+// Work item = (slot, piece); pieces per slot = 2^np_shift for the launch.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs, uint32_t n_regs,
+                                              const DevRequest* __restrict__ reqs,
+                                              const DevReqOut* __restrict__ out,
+                                              const uint32_t* __restrict__ list, uint64_t slot0,
+                                              uint64_t n_items, uint32_t np_shift,
+                                              uint8_t* __restrict__ staging, int update_shadow,
+                                              uint32_t* __restrict__ partials,
+                                              const CrcTables* __restrict__ tabs,
+                                              DevGlobal* __restrict__ glob)
+{
+    __shared__ uint32_t lds[kTabWords];
+    if (MODE == kModeVerify && glob->fmt_bad)
+        return;
+    load_tables(lds, tabs, kTabWords);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t wave = (uint64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t n_waves = (uint64_t)gridDim.x * 4;
+    uint32_t r = 0;
+    uint64_t r_lo = 1, r_hi = 0;
+    for (uint64_t item = wave; item < n_items; item += n_waves) {
+        const uint64_t k = slot0 + (item >> np_shift);
+        const uint32_t piece = (uint32_t)(item & ((1ull << np_shift) - 1));
+        const uint64_t g = list[k];
+        if (g < r_lo || g >= r_hi) {
+            r = find_region<3>(regs, n_regs, g);
+            r_lo = regs[r].first_page;
+            r_hi = r_lo + (regs[r].len >> regs[r].page_shift);
+        }
+        const DevRegion& R = regs[r];
+        if (g < r_lo || g >= r_hi)
+            continue;  // only reachable for a corrupt restore bitmap (gated above)
+        const DevRequest& Q = reqs[R.req];
+        const DevReqOut& O = out[R.req];
+        const uint32_t ps = R.page_shift;
+        const uint32_t pb_shift = ps < kPieceShift ? ps : kPieceShift;
+        if (piece >= (1u << (ps - pb_shift)))
+            continue;
+        const uint64_t local = k - O.slot_base;
+        const uint64_t page_off = (g - R.first_page) << ps;
+        const uint64_t piece_off = (uint64_t)piece << pb_shift;
+        uint8_t* img = staging + O.img_base;
+        uint8_t* slot_ptr = img + Q.data_off + (local << ps) + piece_off;
+        const uint32_t steps = 1u << (pb_shift - 10);
+        uint32_t raw;
+        if (MODE == kModePack) {
+            const uint4* src = reinterpret_cast<const uint4*>(R.cur + page_off + piece_off);
+            uint4* sh = (update_shadow && R.shadow)
+                            ? reinterpret_cast<uint4*>(R.shadow + page_off + piece_off)
+                            : nullptr;
+            raw = wave_piece_crc<true>(src, reinterpret_cast<uint4*>(slot_ptr), sh, steps, lane,
+                                       lds);
+        } else {
+            raw = wave_piece_crc<false>(reinterpret_cast<const uint4*>(slot_ptr), nullptr,
+                                        nullptr, steps, lane, lds);
+        }
+        if (lane != 0)
+            continue;
+        if (ps > pb_shift) {
+            partials[item] = raw;
+            continue;
+        }
+        uint32_t* crc_ptr =
+            reinterpret_cast<uint32_t*>(img + Q.data_off + (O.n_dirty << ps)) + local;
+        const uint32_t crc = raw ^ Q.init_fix;
+        if (MODE == kModePack)
+            *crc_ptr = crc;
+        else if (crc != *crc_ptr)
+            atomicMin(&glob->crc_bad, (uint32_t)local);
+    }
+}
+
+hipError_t launch_pack(int mode, const DevRegion* regs, uint32_t n_regs, const DevRequest* reqs,
+                       const DevReqOut* out, const uint32_t* list, uint64_t slot0,
+                       uint64_t slot1, uint32_t np_shift, uint8_t* staging, int update_shadow,
+                       uint32_t* partials, const CrcTables* tabs, DevGlobal* glob, int blocks,
+                       hipStream_t s)
+{
+    if (slot1 <= slot0)
+        return hipSuccess;
+    const uint64_t n_items = (slot1 - slot0) << np_shift;
+    const uint64_t need = (n_items + 3) / 4;
+    const uint64_t nb = need < (uint64_t)blocks ? need : (uint64_t)blocks;
+    if (mode == kModePack)
+        hipLaunchKernelGGL(k_pack<kModePack>, dim3((unsigned)nb), dim3(256), 0, s, regs, n_regs,
+                           reqs, out, list, slot0, n_items, np_shift, staging, update_shadow,
+                           partials, tabs, glob);
+    else
+        hipLaunchKernelGGL(k_pack<kModeVerify>, dim3((unsigned)nb), dim3(256), 0, s, regs,
+                           n_regs, reqs, out, list, slot0, n_items, np_shift, staging, 0,
+                           partials, tabs, glob);
+    return hipGetLastError();
+}
+
+// One thread per slot: combine the slot's piece CRCs (pages above 64 KiB).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_finalize(const DevRegion* __restrict__ regs,
+                                                  uint32_t n_regs,
+                                                  const DevRequest* __restrict__ reqs,
+                                                  const DevReqOut* __restrict__ out,
+                                                  const uint32_t* __restrict__ list,
+                                                  uint64_t slot0, uint64_t n_slots,
+                                                  uint32_t np_shift,
+                                                  const uint32_t* __restrict__ partials,
+                                                  uint8_t* __restrict__ staging,
+                                                  DevGlobal* __restrict__ glob)
+{
+    if (MODE == kModeVerify && glob->fmt_bad)
+        return;
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_slots)
+        return;
+    const uint64_t k = slot0 + i;
+    const uint64_t g = list[k];
+    const DevRegion& R = regs[find_region<3>(regs, n_regs, g)];
+    if (g < R.first_page || g - R.first_page >= (R.len >> R.page_shift))
+        return;
+    const uint32_t ps = R.page_shift;
+    if (ps <= kPieceShift)
+        return;
+    const DevRequest& Q = reqs[R.req];
+    const DevReqOut& O = out[R.req];
+    const uint32_t np = 1u << (ps - kPieceShift);
+    const uint32_t K = gf2_xpow8n(1ull << kPieceShift);
+    uint32_t s = 0;
+    for (uint32_t j = 0; j < np; ++j)
+        s = gf2_mulmod(s, K) ^ partials[(i << np_shift) + j];
+    const uint64_t local = k - O.slot_base;
+    uint32_t* crc_ptr = reinterpret_cast<uint32_t*>(staging + O.img_base + Q.data_off +
+                                                    (O.n_dirty << ps)) +
+                        local;
+    const uint32_t crc = s ^ Q.init_fix;
+    if (MODE == kModePack)
+        *crc_ptr = crc;
+    else if (crc != *crc_ptr)
+        atomicMin(&glob->crc_bad, (uint32_t)local);
+}
+
+hipError_t launch_finalize(int mode, const DevRegion* regs, uint32_t n_regs,
+                           const DevRequest* reqs, const DevReqOut* out, const uint32_t* list,
+                           uint64_t slot0, uint64_t slot1, uint32_t np_shift,
+                           const uint32_t* partials, uint8_t* staging, DevGlobal* glob,
+                           hipStream_t s)
+{
+    if (slot1 <= slot0 || np_shift == 0)
+        return hipSuccess;
+    const uint64_t n = slot1 - slot0;
+    if (mode == kModePack)
+        hipLaunchKernelGGL(k_finalize<kModePack>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                           s, regs, n_regs, reqs, out, list, slot0, n, np_shift, partials, staging,
+                           glob);
+    else
+        hipLaunchKernelGGL(k_finalize<kModeVerify>, dim3((unsigned)((n + 255) / 256)), dim3(256),
+                           0, s, regs, n_regs, reqs, out, list, slot0, n, np_shift, partials,
+                           staging, glob);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ block CRC
+
+// Standard CRC-32C of n bytes at p (p 16-byte aligned) computed by one
+// 256-thread workgroup; the 4 bytes at zero_off (a multiple of 4, or ~0) are
+// read as zero.  T is the slicing table in LDS.  All threads return it.
+__device__ uint32_t block_crc(const uint8_t* __restrict__ p, uint64_t n, uint64_t zero_off,
+                              const uint32_t* __restrict__ T, uint32_t* red)
+{
+    const uint32_t tid = threadIdx.x;
+    const uint64_t per = ((n + 255) / 256 + 15) & ~15ull;
+    const uint64_t b0 = tid * per;
+    const uint64_t b1 = b0 + per < n ? b0 + per : n;
+    uint32_t s = 0;
+    uint64_t o = b0;
+    for (; o + 16 <= b1; o += 16) {
+        uint4 w = *reinterpret_cast<const uint4*>(p + o);
+        if (zero_off >= o && zero_off < o + 16) {
+            const uint32_t c = (uint32_t)(zero_off - o) >> 2;
+            if (c == 0) w.x = 0;
+            if (c == 1) w.y = 0;
+            if (c == 2) w.z = 0;
+            if (c == 3) w.w = 0;
+        }
+        w.x ^= s;
+        s = word_crc(T, w);
+    }
+    for (; o < b1; ++o) {
+        uint32_t b = p[o];
+        if (zero_off <= o && o < zero_off + 4)
+            b = 0;
+        s = (s >> 8) ^ T[(s ^ b) & 255u];
+    }
+    if (b0 < b1)
+        s = gf2_shift(s, n - b1);
+    else
+        s = 0;
+    // XOR-reduce across the workgroup
+    for (int d = 32; d >= 1; d >>= 1)
+        s ^= (uint32_t)__shfl_xor((int)s, d);
+    if ((tid & 63u) == 0)
+        red[tid >> 6] = s;
+    __syncthreads();
+    uint32_t tot = 0;
+    for (uint32_t i = 0; i < blockDim.x / 64; ++i)
+        tot ^= red[i];
+    __syncthreads();
+    return tot ^ crc_init_fix(n);
+}
+
+// ------------------------------------------------------------ k_header
+
+__global__ __launch_bounds__(256) void k_header(const DevRegion* __restrict__ regs,
+                                                const DevRequest* __restrict__ reqs,
+                                                const DevReqOut* __restrict__ out,
+                                                const uint64_t* __restrict__ bitmap,
+                                                uint8_t* __restrict__ staging,
+                                                const CrcTables* __restrict__ tabs)
+{
+    __shared__ uint32_t lds[kSliceWords];
+    __shared__ uint32_t red[4];
+    __shared__ uint32_t s_shadowed;
+    load_tables(lds, tabs, kSliceWords);
+    const uint32_t tid = threadIdx.x;
+    const DevRequest& Q = reqs[blockIdx.x];
+    const DevReqOut& O = out[blockIdx.x];
+    uint8_t* img = staging + O.img_base;
+    const uint64_t R = Q.n_regions;
+    const uint64_t prefix_end = 64 + 32 * R + 8 * Q.n_words;
+    const uint64_t D = O.n_dirty;
+    const uint64_t first_page0 = Q.first_word * 64;
+    if (tid == 0)
+        s_shadowed = 0;
+    __syncthreads();
+    for (uint64_t i = tid; i < R; i += blockDim.x) {
+        const DevRegion& G = regs[Q.first_region + i];
+        uint64_t* e = reinterpret_cast<uint64_t*>(img + 64 + 32 * i);
+        e[0] = G.id;
+        e[1] = G.len;
+        e[2] = G.first_page - first_page0;
+        e[3] = 0;
+        if (G.shadow)
+            atomicOr(&s_shadowed, 1u);
+    }
+    for (uint64_t w = tid; w < Q.n_words; w += blockDim.x)
+        reinterpret_cast<uint64_t*>(img + 64 + 32 * R)[w] = bitmap[Q.first_word + w];
+    for (uint64_t o = prefix_end + 8 * tid; o < Q.data_off; o += 8 * blockDim.x)
+        *reinterpret_cast<uint64_t*>(img + o) = 0;
+    const bool ok = O.code == 0;
+    if (ok && tid == 0 && (D & 1))
+        *reinterpret_cast<uint32_t*>(img + Q.data_off + (D << Q.page_shift) + 4 * D) = 0;
+    __syncthreads();
+    uint32_t* h32 = reinterpret_cast<uint32_t*>(img);
+    uint64_t* h64 = reinterpret_cast<uint64_t*>(img);
+    if (tid == 0) {
+        h64[0] = 0x31474D494D555243ull;  // "CRUMIMG1"
+        h32[2] = 1;
+        h32[3] = 1u << Q.page_shift;
+        h32[4] = (uint32_t)R;
+        h32[5] = s_shadowed ? 0u : 1u;
+        h64[3] = Q.n_pages;
+        h64[4] = D;
+        h64[5] = Q.seq;
+        h64[6] = Q.data_off;
+        h32[14] = 0;
+        h32[15] = 0;
+    }
+    uint32_t crcs_crc = 0;
+    if (ok)
+        crcs_crc = block_crc(img + Q.data_off + (D << Q.page_shift), 4 * D, ~0ull, lds, red);
+    if (tid == 0)
+        h32[15] = crcs_crc;
+    __threadfence_block();
+    __syncthreads();
+    const uint32_t meta = block_crc(img, prefix_end, ~0ull, lds, red);
+    if (tid == 0)
+        h32[14] = meta;
+}
+
+hipError_t launch_header(const DevRegion* regs, const DevRequest* reqs, uint32_t n_reqs,
+                         const DevReqOut* out, const uint64_t* bitmap, uint32_t,
+                         uint8_t* staging, const CrcTables* tabs, hipStream_t s)
+{
+    if (n_reqs == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_header, dim3(n_reqs), dim3(256), 0, s, regs, reqs, out, bitmap, staging,
+                       tabs);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ restore
+
+// Device-side image checks that need the bytes: meta_crc, crcs_crc, bitmap
+// population and unused bits, zero pads.  The host has already checked the
+// header fields, lengths and the region table.
+__global__ __launch_bounds__(256) void k_restore_check(const DevRequest* __restrict__ reqs,
+                                                       const DevReqOut* __restrict__ out,
+                                                       const uint8_t* __restrict__ staging,
+                                                       const CrcTables* __restrict__ tabs,
+                                                       DevGlobal* __restrict__ glob)
+{
+    __shared__ uint32_t lds[kSliceWords];
+    __shared__ uint32_t red[4];
+    __shared__ unsigned long long s_pop;
+    __shared__ uint32_t s_bad;
+    load_tables(lds, tabs, kSliceWords);
+    const uint32_t tid = threadIdx.x;
+    const DevRequest& Q = reqs[blockIdx.x];
+    const DevReqOut& O = out[blockIdx.x];
+    const uint8_t* img = staging + O.img_base;
+    const uint64_t R = Q.n_regions;
+    const uint64_t prefix_end = 64 + 32 * R + 8 * Q.n_words;
+    const uint32_t* h32 = reinterpret_cast<const uint32_t*>(img);
+    const uint64_t D = reinterpret_cast<const uint64_t*>(img)[4];
+    if (tid == 0) {
+        s_pop = 0;
+        s_bad = 0;
+    }
+    __syncthreads();
+    const uint64_t* bm = reinterpret_cast<const uint64_t*>(img + 64 + 32 * R);
+    unsigned long long pop = 0;
+    uint32_t bad = 0;
+    for (uint64_t w = tid; w < Q.n_words; w += blockDim.x) {
+        const uint64_t word = bm[w];
+        pop += __popcll(word);
+        if (w == Q.n_words - 1 && (Q.n_pages & 63)) {
+            if (word >> (Q.n_pages & 63))
+                bad = 1;
+        }
+    }
+    for (uint64_t o = prefix_end + 8 * tid; o < Q.data_off; o += 8 * blockDim.x)
+        if (*reinterpret_cast<const uint64_t*>(img + o))
+            bad = 1;
+    if (tid == 0) {
+        const uint64_t tail = Q.data_off + (D << Q.page_shift) + 4 * D;
+        for (uint64_t o = tail; o < O.image_bytes; ++o)
+            if (img[o])
+                bad = 1;
+    }
+    atomicAdd(&s_pop, pop);
+    if (bad)
+        atomicOr(&s_bad, 1u);
+    const uint32_t crcs = block_crc(img + Q.data_off + (D << Q.page_shift), 4 * D, ~0ull, lds, red);
+    const uint32_t meta = block_crc(img, prefix_end, 56, lds, red);
+    __syncthreads();
+    if (tid == 0) {
+        if (s_bad || s_pop != D || crcs != h32[15] || meta != h32[14])
+            atomicOr(&glob->fmt_bad, 1u);
+    }
+}
+
+hipError_t launch_restore_check(const DevRequest* reqs, uint32_t n_reqs, const DevReqOut* out,
+                                const uint8_t* staging, const CrcTables* tabs, DevGlobal* glob,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(k_restore_check, dim3(n_reqs), dim3(256), 0, s, reqs, out, staging, tabs,
+                       glob);
+    return hipGetLastError();
+}
+
+// Wave per (slot, 64 KiB piece): packed page -> its page (and shadow).
+__global__ __launch_bounds__(256) void k_scatter(const DevRegion* __restrict__ regs,
+                                                 uint32_t n_regs,
+                                                 const DevRequest* __restrict__ reqs,
+                                                 const DevReqOut* __restrict__ out,
+                                                 const uint32_t* __restrict__ list,
+                                                 uint64_t n_items, uint32_t np_shift,
+                                                 const uint8_t* __restrict__ staging,
+                                                 int update_shadow,
+                                                 const DevGlobal* __restrict__ glob)
+{
+    if (glob->fmt_bad || glob->crc_bad != kNoBad)
+        return;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t wave = (uint64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t n_waves = (uint64_t)gridDim.x * 4;
+    uint32_t r = 0;
+    uint64_t r_lo = 1, r_hi = 0;
+    for (uint64_t item = wave; item < n_items; item += n_waves) {
+        const uint64_t k = item >> np_shift;
+        const uint32_t piece = (uint32_t)(item & ((1ull << np_shift) - 1));
+        const uint64_t g = list[k];
+        if (g < r_lo || g >= r_hi) {
+            r = find_region<3>(regs, n_regs, g);
+            r_lo = regs[r].first_page;
+            r_hi = r_lo + (regs[r].len >> regs[r].page_shift);
+        }
+        const DevRegion& R = regs[r];
+        if (g < r_lo || g >= r_hi)
+            continue;
+        const DevRequest& Q = reqs[R.req];
+        const DevReqOut& O = out[R.req];
+        const uint32_t ps = R.page_shift;
+        const uint32_t pb_shift = ps < kPieceShift ? ps : kPieceShift;
+        if (piece >= (1u << (ps - pb_shift)))
+            continue;
+        const uint64_t page_off = (g - R.first_page) << ps;
+        const uint64_t piece_off = (uint64_t)piece << pb_shift;
+        const uint4* src = reinterpret_cast<const uint4*>(
+            staging + O.img_base + Q.data_off + ((k - O.slot_base) << ps) + piece_off);
+        uint4* dst = reinterpret_cast<uint4*>(const_cast<uint8_t*>(R.cur) + page_off + piece_off);
+        uint4* sh = (update_shadow && R.shadow)
+                        ? reinterpret_cast<uint4*>(R.shadow + page_off + piece_off)
+                        : nullptr;
+        const uint32_t n16 = 1u << (pb_shift - 4);
+        for (uint32_t i = lane; i < n16; i += 64 * 4) {
+            uint4 w[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (i + 64 * u < n16)
+                    w[u] = src[i + 64 * u];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (i + 64 * u < n16) {
+                    dst[i + 64 * u] = w[u];
+                    if (sh)
+                        sh[i + 64 * u] = w[u];
+                }
+        }
+    }
+}
+
+hipError_t launch_scatter(const DevRegion* regs, uint32_t n_regs, const DevRequest* reqs,
+                             const DevReqOut* out, const uint32_t* list, uint64_t n_slots,
+                             uint32_t np_shift, const uint8_t* staging, int update_shadow,
+                             const DevGlobal* glob, int blocks, hipStream_t s)
+{
+    if (n_slots == 0)
+        return hipSuccess;
+    const uint64_t n_items = n_slots << np_shift;
+    const uint64_t need = (n_items + 3) / 4;
+    const uint64_t nb = need < (uint64_t)blocks ? need : (uint64_t)blocks;
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)nb), dim3(256), 0, s, regs, n_regs, reqs, out,
+                       list, n_items, np_shift, staging, update_shadow, glob);
+    return hipGetLastError();
+}
+
+__global__ void k_restore_finish(DevReqOut* __restrict__ out, DevGlobal* __restrict__ glob)
+{
+    DevReqOut& O = out[0];
+    if (glob->fmt_bad) {
+        O.code = -4;  // CRUM_EFORMAT
+        O.first_bad = 0;
+    } else if (glob->crc_bad != kNoBad) {
+        O.code = -3;  // CRUM_ECRC
+        O.first_bad = glob->crc_bad;
+    } else {
+        O.code = 0;
+        O.first_bad = 0;
+    }
+}
+
+hipError_t launch_restore_finish(DevReqOut* out, uint32_t, DevGlobal* glob, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_restore_finish, dim3(1), dim3(1), 0, s, out, glob);
+    return hipGetLastError();
+}
+
+}  // namespace crum

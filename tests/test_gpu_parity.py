@@ -1,0 +1,279 @@
+"""GPU parity: the HIP snapshot/restore path, called through the C ABI, must
+produce byte-identical images (bitmap, packed pages, CRCs, header) to the CPU
+oracle, and restore must reproduce memory bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+from tests.gpu_util import gpu_snapshot, log, to_dev, upload
+
+pytestmark = pytest.mark.gpu
+
+KiB, MiB = 1 << 10, 1 << 20
+
+
+@pytest.fixture(scope="module")
+def snap():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1808_00117_amd as crum
+    crum.lib()  # the HIP library must be present; no fallback exists
+    from paper_1808_00117_amd.api import Snapshotter
+    s = Snapshotter(0)
+    yield s
+    s.close()
+
+
+def host_case(counts, P, dirty, seed, null_shadow=(), where="random"):
+    rng = np.random.default_rng(seed)
+    regs = []
+    g = 0
+    for rid, n in enumerate(counts):
+        cur = rng.integers(0, 256, n * P, dtype=np.uint8)
+        sh = cur.copy()
+        for i in range(n):
+            if g + i in dirty:
+                off = {"first": 0, "last": P - 1}.get(where, int(rng.integers(0, P)))
+                sh[i * P + off] ^= np.uint8(1 + rng.integers(0, 255))
+        g += n
+        regs.append((cur, None if rid in null_shadow else sh, 5000 + 7 * rid))
+    return regs
+
+
+def check_parity(snap, host_regs, P, seq=3, flags=0):
+    st_o, img_o, bm_o = oracle.snapshot(host_regs, P, seq=seq)
+    assert st_o.code == oracle.OK
+    dev = upload(host_regs)
+    rc, st, img, _ = gpu_snapshot(snap, dev, P, seq=seq, flags=flags)
+    assert rc == 0
+    assert st.code == 0, st
+    assert (st.n_dirty, st.total_pages, st.image_bytes) == \
+        (st_o.n_dirty, st_o.total_pages, st_o.image_bytes)
+    assert img.size == img_o.size
+    if not np.array_equal(img, img_o):
+        bad = np.flatnonzero(img != img_o)
+        raise AssertionError(f"image differs at {bad.size} bytes, first {bad[:8]}")
+    return dev, img
+
+
+CASES = [
+    # (name, counts, P, dirty set or 'all'/'none', null-shadow regions)
+    ("none_dirty", (40,), 4 * KiB, set(), ()),
+    ("all_dirty", (70,), 4 * KiB, "all", ()),
+    ("first_only", (100,), 4 * KiB, {0}, ()),
+    ("last_only", (100,), 4 * KiB, {99}, ()),
+    ("region_bounds", (3, 1, 5, 64, 2), 4 * KiB, {2, 3, 4, 8, 9, 72, 73, 74}, ()),
+    ("null_shadow_mixed", (5, 9, 3), 4 * KiB, {1, 16}, (1,)),
+    ("zero_len_regions", (0, 4, 0, 0, 7, 0), 4 * KiB, {0, 5, 10}, ()),
+    ("ragged_words", (63, 66, 1, 129), 8 * KiB, {0, 62, 63, 64, 128, 129, 258}, ()),
+    ("p64k", (17, 3), 64 * KiB, {0, 5, 16, 17, 19}, ()),
+    ("p2m", (5, 2), 2 * MiB, {1, 4, 5}, ()),
+    ("p1m_multi_piece", (6,), 1 * MiB, {0, 2, 5}, ()),
+]
+
+
+@pytest.mark.parametrize("name,counts,P,dirty,nulls", CASES, ids=[c[0] for c in CASES])
+def test_snapshot_parity_edges(snap, name, counts, P, dirty, nulls):
+    G = sum(counts)
+    if dirty == "all":
+        dirty = set(range(G))
+    log(f"[parity] {name} counts={counts} P={P} dirty={len(dirty)}")
+    for where in ("first", "last", "random"):
+        regs = host_case(counts, P, dirty, seed=G + P, null_shadow=nulls, where=where)
+        check_parity(snap, regs, P)
+
+
+def test_snapshot_parity_random_sets(snap):
+    rng = np.random.default_rng(77)
+    for trial in range(6):
+        counts = tuple(int(x) for x in rng.integers(0, 200, int(rng.integers(1, 8))))
+        G = sum(counts)
+        P = [4 * KiB, 8 * KiB, 16 * KiB, 64 * KiB][trial % 4]
+        dirty = set(int(x) for x in rng.choice(max(G, 1), size=int(rng.integers(0, G + 1)),
+                                               replace=False)) if G else set()
+        log(f"[parity] random trial={trial} counts={counts} P={P} D={len(dirty)}")
+        check_parity(snap, host_case(counts, P, dirty, seed=trial), P, seq=trial)
+
+
+def test_many_regions(snap):
+    # 4096 one-page regions (the largest table the edge list asks for)
+    rng = np.random.default_rng(5)
+    R = 4096
+    P = 4 * KiB
+    dirty = set(int(x) for x in rng.choice(R, size=900, replace=False))
+    log("[parity] 4096 regions")
+    check_parity(snap, host_case((1,) * R, P, dirty, seed=9), P)
+
+
+def test_multi_chunk_drain(snap):
+    # D*P well above the first 8 MiB drain chunk: several pack/drain chunks
+    P = 64 * KiB
+    counts = (700,)
+    dirty = set(range(0, 700, 2))
+    log("[parity] multi-chunk drain, 350 x 64 KiB dirty")
+    check_parity(snap, host_case(counts, P, dirty, seed=21), P)
+
+
+def test_plain_64mib_scenario(snap):
+    """The 64 MiB / 4 KiB / 5 % workload, filled on the device by the
+    generator and regenerated on the host for the oracle."""
+    import torch
+    import synth
+    from synth import scenarios as sc
+    from synth.device import materialize
+    s = sc.plain()
+    log("[parity] plain 64 MiB scenario")
+    dev = materialize(s)
+    torch.cuda.synchronize()
+    host = []
+    for i, r in enumerate(s.regions):
+        cur, sh = sc.materialize_host(s, i)
+        host.append((cur, sh, r.id))
+        assert np.array_equal(dev[i][0].cpu().numpy(), cur), "device fill != host fill"
+        assert np.array_equal(dev[i][1].cpu().numpy(), sh), "device mutation != host mutation"
+    st_o, img_o, bm_o = oracle.snapshot(host, s.page_size, seq=11)
+    assert st_o.n_dirty == 819
+    rc, st, img, _ = gpu_snapshot(snap, [(c, h, r.id) for (c, h), r in zip(dev, s.regions)],
+                                  s.page_size, seq=11)
+    assert rc == 0 and st.code == 0 and st.n_dirty == 819
+    assert np.array_equal(img, img_o)
+
+
+def test_restore_roundtrip_and_update_shadow(snap):
+    import torch
+    P = 4 * KiB
+    host = host_case((30, 40), P, set(range(0, 70, 3)), seed=31)
+    dev, img = check_parity(snap, host, P)
+    # restore into the shadows: they must become equal to current
+    targets = [(sh.clone(), None, rid) for _, sh, rid in dev]
+    h = torch.from_numpy(img).pin_memory()
+    staging = torch.empty(img.size, dtype=torch.uint8, device="cuda")
+    rc, st = snap.restore(targets, h, img.size, staging, flags=2)
+    assert rc == 0 and st.code == 0, st
+    for (t, _, _), (c, _, _) in zip(targets, dev):
+        assert torch.equal(t, c)
+    # snapshot with shadow update; then a re-snapshot is empty
+    rc, st, _, _ = gpu_snapshot(snap, dev, P, flags=1)
+    assert st.code == 0 and st.n_dirty == len(range(0, 70, 3))
+    for c, sh, _ in dev:
+        assert torch.equal(c, sh)
+    rc, st, img2, _ = gpu_snapshot(snap, dev, P)
+    assert st.code == 0 and st.n_dirty == 0
+
+
+def test_restore_from_device_resident_image(snap):
+    import torch
+    P = 16 * KiB
+    host = host_case((12,), P, {1, 7, 11}, seed=41)
+    dev = upload(host)
+    rc, st, _, staging = gpu_snapshot(snap, dev, P, drain=False)
+    assert st.code == 0 and st.n_dirty == 3
+    targets = [(sh.clone(), None, rid) for _, sh, rid in dev]
+    rc, st2 = snap.restore(targets, None, st.image_bytes, staging, flags=2)
+    assert rc == 0 and st2.code == 0
+    assert torch.equal(targets[0][0], dev[0][0])
+
+
+def test_restore_corrupt_page_is_rejected(snap):
+    import torch
+    P = 4 * KiB
+    host = host_case((20,), P, {2, 5, 9, 13}, seed=51)
+    dev, img = check_parity(snap, host, P)
+    bad = img.copy()
+    data_off = 4096
+    bad[data_off + 2 * P + 100] ^= 0x40   # slot 2
+    bad[data_off + 3 * P + 7] ^= 0x01     # slot 3
+    targets = [(sh.clone(), None, rid) for _, sh, rid in dev]
+    before = targets[0][0].clone()
+    staging = torch.empty(img.size, dtype=torch.uint8, device="cuda")
+    rc, st = snap.restore(targets, torch.from_numpy(bad).pin_memory(), bad.size, staging,
+                          flags=2)
+    assert rc == 0 and st.code == -3 and st.first_bad == 2, st
+    assert torch.equal(targets[0][0], before)
+    res = oracle.restore([(t[0].cpu().numpy(), None, t[2]) for t in targets], bad, oracle.VERIFY)
+    assert res.code == oracle.ECRC and res.first_bad == 2
+
+
+def test_restore_format_errors(snap):
+    import torch
+    P = 4 * KiB
+    host = host_case((10,), P, {1, 4}, seed=61)
+    dev, img = check_parity(snap, host, P)
+    staging = torch.empty(img.size, dtype=torch.uint8, device="cuda")
+    targets = [(sh.clone(), None, rid) for _, sh, rid in dev]
+    before = targets[0][0].clone()
+    # metadata bit flips: found either on the host (header fields) or on the
+    # device (meta_crc / bitmap / pads); the regions never change
+    for pos in [0, 9, 13, 17, 25, 33, 41, 49, 57, 61, 64, 72, 80, 96, 100, 200, 4095,
+                img.size - 1, img.size - 5]:
+        bad = img.copy()
+        bad[pos] ^= 0x04
+        rc, st = snap.restore(targets, torch.from_numpy(bad).pin_memory(), bad.size, staging)
+        assert st.code in (-4, -6), (pos, st)
+        assert torch.equal(targets[0][0], before), pos
+    rc, st = snap.restore(targets, torch.from_numpy(img[:-8].copy()).pin_memory(),
+                          img.size - 8, staging)
+    assert st.code == -4
+    wrong = [(targets[0][0], None, 12345)]
+    rc, st = snap.restore(wrong, torch.from_numpy(img).pin_memory(), img.size, staging)
+    assert st.code == -6
+    small = staging[: img.size - 1]
+    rc, st = snap.restore(targets, torch.from_numpy(img).pin_memory(), img.size, small)
+    assert st.code == -2
+
+
+def test_enospc_leaves_shadow_and_canary(snap):
+    import torch
+    P = 4 * KiB
+    host = host_case((32,), P, set(range(10)), seed=71)
+    dev = upload(host)
+    need = oracle.snapshot(host, P)[0].image_bytes
+    big = torch.full((need + 4096,), 0xA5, dtype=torch.uint8, device="cuda")
+    staging = big[: need - P]
+    sh_before = dev[0][1].clone()
+    h = torch.empty(need, dtype=torch.uint8, pin_memory=True)
+    rc, st = snap.snapshot(dev, P, staging, h, flags=1)
+    assert rc == 0 and st.code == -2 and st.n_dirty == 10 and st.image_bytes == need
+    assert torch.equal(dev[0][1], sh_before)
+    assert bool((big[need - P:] == 0xA5).all())
+    # the bitmap is valid in the staging prefix
+    bm = staging[64 + 32:64 + 32 + 8].cpu().numpy().view(np.uint64)[0]
+    assert int(bm) == (1 << 10) - 1
+    # host image too small also reports ENOSPC
+    rc, st = snap.snapshot(dev, P, big[:need], h[: need - 8])
+    assert st.code == -2
+
+
+def test_invalid_arguments_are_synchronous(snap):
+    import torch
+    import paper_1808_00117_amd as crum
+    P = 4 * KiB
+    cur = torch.zeros(8 * P, dtype=torch.uint8, device="cuda")
+    sh = torch.zeros(8 * P, dtype=torch.uint8, device="cuda")
+    staging = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    h = torch.empty(1 << 20, dtype=torch.uint8, pin_memory=True)
+    ok = [(cur.data_ptr(), sh.data_ptr(), 8 * P, 1)]
+    bads = [
+        (ok, 3000), (ok, 4096 * 3), ([(cur.data_ptr(), sh.data_ptr(), 8 * P - 16, 1)], P),
+        ([(cur.data_ptr() + 8, 0, P, 1)], P),
+        ([(cur.data_ptr(), cur.data_ptr() + P, 2 * P, 1)], P),
+        ([(cur.data_ptr(), 0, 2 * P, 1), (cur.data_ptr() + P, 0, P, 2)], P),
+        ([(0, 0, P, 1)], P),
+    ]
+    for regs, pg in bads:
+        rc = snap.snapshot(regs, pg, staging, h, sync=False)
+        assert rc == crum.CRUM_EINVAL, (regs, pg)
+    rc = snap.snapshot(ok, P, staging[:100], h, sync=False)
+    assert rc == crum.CRUM_EINVAL
+    rc = snap.snapshot(ok, P, staging, h, flags=0x80, sync=False)
+    assert rc == crum.CRUM_EINVAL
+
+
+def test_empty_table(snap):
+    import torch
+    staging = torch.empty(8192, dtype=torch.uint8, device="cuda")
+    h = torch.empty(8192, dtype=torch.uint8, pin_memory=True)
+    rc, st = snap.snapshot([], 4096, staging, h, seq=5)
+    assert rc == 0 and st.code == 0 and st.image_bytes == 4096
+    _, img_o, _ = oracle.snapshot([], 4096, seq=5)
+    assert np.array_equal(h[:4096].numpy(), img_o)
