@@ -1,0 +1,497 @@
+#!/usr/bin/env python3
+"""Snapshot throughput benchmark (one MI355X).
+
+A step is one incremental snapshot of the whole workload: quiesce, diff of
+every page against its HBM shadow, bitmap, prefix sum, pack with CRC-32C,
+image header, and the drain of the image to pinned host memory, ending when
+the image has landed.  Inputs are resident in HBM before the timed region.
+
+Default workload (the one the headline metric is quoted on): 64 device
+allocations with log-uniform sizes (4 KiB-1 GiB draws scaled by one factor
+to 16 GiB total), 64 KiB pages, dirty pages in clustered runs (start
+probability 0.003 per page, geometric run length with mean 32, about 9 %
+dirty), and an fp32 SAXPY loop over 4096x4096 elements co-running on a second
+stream.  Shadow update is off so every step does the same work.
+
+Device and pinned buffers, streams, events and the co-runner graph come from
+the HIP runtime directly (paper_1808_00117_amd.hip); torch is not imported, so
+the process runs on the system ROCm runtime, whose device-to-host copies use
+the SDMA engines rather than compute units.
+
+Prints one JSON line (see the fields below).  `--config plain` runs the
+64 MiB / 4 KiB / 5 % workload instead.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
+LINK_PEAK_GBS = 63.0       # PCIe 5.0 x16 per direction after 128b/130b encoding
+METRIC = "snapshot GB/s (diff+CRC+compact+drain)"
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse_args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="many", choices=["many", "plain"])
+    ap.add_argument("--no-corunner", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle baseline leg (0 disables it)")
+    ap.add_argument("--quick", action="store_true",
+                    help="skip the untimed reference phases (for profiler runs)")
+    ap.add_argument("--pmc-calibrate", action="store_true",
+                    help="run a 1 GiB plain copy kernel first (counter calibration)")
+    ap.add_argument("--trace-summary", metavar="DIR",
+                    help="summarise a rocprofv3 --kernel-trace --stats run of this script")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
+                         "this script and print the JSON that the roofline 'traffic' reads")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("crum_kernels.hip", "crum_dev.h", "gf2.h"):
+        with open(os.path.join(ROOT, "paper_1808_00117_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+CALIB_BYTES = 1 << 30
+
+
+def pmc_summary(fetch_dir: str, write_dir: str, workload: str) -> dict:
+    """Per-launch HBM traffic of k_diff from two rocprofv3 --pmc runs, each
+    counter scaled by what it reads for the 1 GiB plain copy kernel."""
+    import csv
+    import glob
+
+    def per_kernel(d, counter):
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not files:
+            raise FileNotFoundError(f"no counter_collection.csv under {d}")
+        out = {}
+        for f in files:
+            for r in csv.DictReader(open(f)):
+                if r.get("Counter_Name") != counter:
+                    continue
+                name = r["Kernel_Name"]
+                out.setdefault(name, []).append(float(r["Counter_Value"]) * 1024.0)  # KiB
+        return out
+
+    res = {"workload": workload, "kernel_source_hash": kernel_source_hash()}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        pk = per_kernel(d, counter)
+        calib = [v for k, vs in pk.items() if "synth_copy_kernel" in k for v in vs]
+        diff = [v for k, vs in pk.items() if "k_diff" in k for v in vs]
+        if not calib or not diff:
+            raise RuntimeError(f"{counter}: missing calibration or k_diff dispatches")
+        factor = statistics.median(calib) / CALIB_BYTES
+        res[counter] = {"calibration_factor": round(factor, 4),
+                        "k_diff_dispatches": len(diff),
+                        "k_diff_bytes_raw_total": sum(diff),
+                        "k_diff_bytes_per_launch": sum(diff) / len(diff) / factor}
+    res["traffic_bytes_per_launch"] = round(res["FETCH_SIZE"]["k_diff_bytes_per_launch"] +
+                                            res["WRITE_SIZE"]["k_diff_bytes_per_launch"])
+    return res
+
+
+def trace_summary(d: str, steps: int) -> str:
+    """Markdown summary of a rocprofv3 kernel-trace run of this script: the
+    per-kernel stats table, and the k_diff launches of the last `steps`
+    snapshots (the timed region), which is what the bench's avg_launch_ms
+    covers."""
+    import csv
+    import glob
+
+    def find(pat):
+        f = glob.glob(os.path.join(d, "**", pat), recursive=True)
+        return f[0] if f else None
+
+    out = []
+    ks = find("*kernel_stats.csv")
+    if ks:
+        out.append("| kernel | calls | avg us | total ms | % |")
+        out.append("|---|---:|---:|---:|---:|")
+        for r in csv.DictReader(open(ks)):
+            out.append(f"| `{r['Name'][:70]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                       f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.2f} |")
+    ms = find("*memory_copy_stats.csv")
+    if ms:
+        out.append("")
+        out.append("| copy | calls | avg us | total ms |")
+        out.append("|---|---:|---:|---:|")
+        for r in csv.DictReader(open(ms)):
+            out.append(f"| {r['Name']} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                       f"{float(r['TotalDurationNs']) / 1e6:.2f} |")
+    kt = find("*kernel_trace.csv")
+    if kt:
+        rows = [r for r in csv.DictReader(open(kt))]
+        diff = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
+                      for r in rows if "k_diff" in r["Kernel_Name"])
+        heads = sorted(int(r["Start_Timestamp"]) for r in rows if "k_header" in r["Kernel_Name"])
+        if diff and len(heads) >= steps:
+            t0 = heads[-steps - 1] if len(heads) > steps else 0
+            sel = [(a, b) for a, b in diff if a > t0]
+            avg = statistics.mean(b - a for a, b in sel) / 1e6
+            out.append("")
+            out.append(f"k_diff launches in the last {steps} snapshots (timed region): "
+                       f"{len(sel)}, average duration {avg:.4f} ms")
+    return "\n".join(out)
+
+
+def load_traffic(workload: str, launches_bytes: float):
+    """HBM traffic of the diff kernel from committed rocprofv3 counter runs,
+    if they were taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"diff_{workload}_pmc.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(scn, budget_s: float):
+    """Time the CPU oracle (single-threaded, as it stands) on a bounded
+    sample of the same workload: whole regions in table order up to 1 GiB,
+    regenerated on the host (untimed), snapshotted repeatedly until about
+    `budget_s` seconds of oracle time have accrued."""
+    import numpy as np
+    import oracle
+    from synth import scenarios as sc
+
+    regs, total, dirty = [], 0, 0
+    for i, r in enumerate(scn.regions):
+        if total + r.nbytes > (1 << 30) and regs:
+            continue
+        cur, sh = sc.materialize_host(scn, i)
+        regs.append((cur, sh, r.id))
+        total += r.nbytes
+        dirty += int(r.dirty_pages.size)
+        if total >= (1 << 30) - (64 << 20):
+            break
+    P = scn.page_size
+    G = total // P
+    cap = oracle.prefix_bytes(len(regs), G) + dirty * P + ((4 * dirty + 7) // 8) * 8
+    t_acc, n_runs = 0.0, 0
+    while t_acc < budget_s or n_runs == 0:
+        t0 = time.perf_counter()
+        st, img, _ = oracle.snapshot(regs, P, image_cap=cap)
+        t_acc += time.perf_counter() - t0
+        n_runs += 1
+        assert st.code == oracle.OK and st.n_dirty == dirty
+        del img
+    gbs = total * n_runs / t_acc / 1e9
+    return {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(regs)} whole regions in table order, {total / 2**30:.2f} GiB "
+                      f"scanned, {dirty} dirty {P // 1024} KiB pages, snapshotted "
+                      f"{n_runs}x single-threaded ({t_acc:.1f} s)"}
+
+
+def materialize_raw(scn, H):
+    """Device buffers (current, shadow) per region, filled by the generator
+    kernels: current = generator bytes, shadow = copy with the page mutations."""
+    import numpy as np
+    import synth
+    pairs = []
+    for r in scn.regions:
+        cur = H.DeviceBuffer(r.nbytes)
+        synth.fill_dev(cur.ptr, r.nbytes, r.fill_seed, r.fill_region, 0, 0)
+        sh = None
+        if r.has_shadow:
+            sh = H.DeviceBuffer(r.nbytes)
+            H.memcpy_dtod(sh.ptr, cur.ptr, r.nbytes)
+            if r.dirty_pages.size:
+                pages = np.ascontiguousarray(r.dirty_pages, np.int64)
+                d_pages = H.DeviceBuffer(pages.nbytes)
+                H.memcpy_htod(d_pages.ptr, pages.ctypes.data, pages.nbytes)
+                synth.mutate_dev(sh.ptr, r.nbytes, scn.page_size, d_pages.ptr, int(pages.size),
+                                 int(pages.max()), r.mut_kind, scn.mut_seed, r.fill_region, 0)
+                H.device_synchronize()
+                d_pages.free()
+        pairs.append((cur, sh))
+    H.device_synchronize()
+    return pairs
+
+
+def main():
+    args = parse_args()
+    if args.pmc_summary:
+        wl = "many_allocs" if args.config == "many" else "plain"
+        print(json.dumps(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], wl), indent=1))
+        return
+    if args.trace_summary:
+        print(trace_summary(args.trace_summary, args.steps))
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the snapshot path has no cross-GPU step, and "
+              "multi-GPU runs are not part of this build (each GPU would snapshot its own "
+              "regions independently).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+
+    import paper_1808_00117_amd as crum
+    import paper_1808_00117_amd.hip as H
+    import synth
+    from synth import scenarios as sc
+
+    crum.lib()
+    if H.device_count() < 1:
+        raise RuntimeError("bench.py needs a GPU")
+
+    if args.config == "many":
+        scn = sc.many_allocs()
+        workload = "many_allocs"
+        wl_name = "64 allocations log-uniform 4KiB-1GiB scaled to 16 GiB, 64 KiB pages, " \
+                  "clustered dirty runs (p_start 0.003, mean 32)"
+    else:
+        scn = sc.plain()
+        workload = "plain"
+        wl_name = "one 64 MiB allocation, 4 KiB pages, 5% of pages dirty"
+    P = scn.page_size
+    N = scn.total_bytes
+    D = scn.n_dirty
+    G = scn.total_pages
+    R = len(scn.regions)
+    log(f"[bench] workload={workload} N={N} G={G} D={D} R={R}")
+
+    if args.pmc_calibrate:
+        a, b = H.DeviceBuffer(CALIB_BYTES), H.DeviceBuffer(CALIB_BYTES)
+        synth.copy_dev(b.ptr, a.ptr, CALIB_BYTES, 0)
+        H.device_synchronize()
+        a.free()
+        b.free()
+    t0 = time.perf_counter()
+    pairs = materialize_raw(scn, H)
+    log(f"[bench] materialised in {time.perf_counter() - t0:.1f} s")
+    regs = [(c.ptr, s.ptr if s else 0, r.nbytes, r.id) for (c, s), r in zip(pairs, scn.regions)]
+    table = crum.region_table(regs)
+    image_bytes = crum.crum_image_bytes(R, G, D, P)
+    # capacity for an image with every page dirty: the snapshot then runs in
+    # its chunk-pipelined order (ENOSPC impossible)
+    cap = crum.crum_image_bytes(R, G, G, P)
+    staging = H.DeviceBuffer(cap)
+    h_image = H.PinnedBuffer(cap)
+    status = H.PinnedBuffer(64)
+    ctx = crum.crum_ctx_create(0)
+    s1, s2 = H.Stream(), H.Stream()
+
+    # co-runner: an application stream of fp32 SAXPY passes (y = a*x + y over
+    # 4096x4096 elements), one kernel per pass, captured once as a graph of
+    # PASSES kernels and replayed on its own stream
+    n_sax = 4096 * 4096
+    x = H.DeviceBuffer(4 * n_sax)
+    y = H.DeviceBuffer(4 * n_sax)
+    H.check(H.hip().hipMemset(x.ptr, 0x3F, 4 * n_sax), "hipMemset")
+    H.check(H.hip().hipMemset(y.ptr, 0x3E, 4 * n_sax), "hipMemset")
+    PASSES = 16
+
+    def capture(st):
+        for _ in range(PASSES):
+            synth.saxpy_loop_dev(y.ptr, x.ptr, 1.0001, n_sax, 1, 4096, st.handle)
+    graph = H.Graph(s2, capture)
+    H.device_synchronize()
+    sax_bytes_per_pass = 3 * 4 * n_sax
+
+    def read_status():
+        return crum.read_status(status.ptr)
+
+    def run_snapshot(eager=True):
+        crum.crum_ctx_set_param(ctx, crum.CRUM_PARAM_EAGER, 1 if eager else 0)
+        c = cap if eager else image_bytes
+        rc = crum.crum_snapshot(ctx, table, P, 0, 1, staging.ptr, c, h_image.ptr, c, s1.handle,
+                                status.ptr)
+        assert rc == 0, rc
+        s1.synchronize()
+
+    def corun(replays):
+        for _ in range(replays):
+            graph.launch(s2)
+
+    # correctness of one step before timing (status, D, and both orders agree)
+    run_snapshot()
+    st = read_status()
+    assert st.code == 0 and st.n_dirty == D and st.image_bytes == image_bytes, st
+    if not args.quick:
+        first_image = h_image.numpy(image_bytes).copy()
+        run_snapshot(eager=False)
+        assert read_status().n_dirty == D
+        assert np.array_equal(h_image.numpy(image_bytes), first_image), "orders disagree"
+        del first_image
+
+    for _ in range(args.warmup):
+        run_snapshot()
+
+    # reference phases (outside the timed region)
+    def median_ms(fn, n=5):
+        v = []
+        for _ in range(n):
+            t = time.perf_counter()
+            fn()
+            v.append(time.perf_counter() - t)
+        return 1e3 * statistics.median(v)
+    snap_alone_ms = median_ms(run_snapshot, 1 if args.quick else 5)
+    checked_ms = float("nan") if args.quick else median_ms(lambda: run_snapshot(eager=False))
+    e0, e1 = H.Event(), H.Event()
+    probe = 1 if args.quick else 20
+    e0.record(s2)
+    corun(probe)
+    e1.record(s2)
+    graph_ms = e0.elapsed_ms(e1) / probe
+    sax_alone_gbs = sax_bytes_per_pass * PASSES / (graph_ms * 1e-3) / 1e9
+    corun_on = not args.no_corunner
+    log(f"[bench] snapshot alone {snap_alone_ms:.2f} ms (diff-first order {checked_ms:.2f} ms); "
+        f"saxpy alone {sax_alone_gbs:.0f} GB/s ({graph_ms:.3f} ms per graph)")
+
+    # timed region: exactly K steps, with the co-runner application issuing
+    # SAXPY graphs continuously from its own host thread (at most two graphs
+    # queued ahead, so it stops promptly when the last step ends)
+    import threading
+    stop = threading.Event()
+    sax_graphs = [0]
+    sax_time = [0.0]
+
+    def corunner():
+        evs = []
+        while not stop.is_set():
+            a, b = H.Event(), H.Event()
+            a.record(s2)
+            graph.launch(s2)
+            b.record(s2)
+            evs.append((a, b))
+            if len(evs) > 2:
+                a0, b0 = evs.pop(0)
+                sax_time[0] += a0.elapsed_ms(b0)
+                sax_graphs[0] += 1
+        for a0, b0 in evs:
+            sax_time[0] += a0.elapsed_ms(b0)
+            sax_graphs[0] += 1
+
+    crum.crum_ctx_timing_reset(ctx)
+    crum.crum_ctx_set_timing(ctx, True)
+    lat = []
+    H.device_synchronize()
+    th = threading.Thread(target=corunner, daemon=True) if corun_on else None
+    if th:
+        th.start()
+        time.sleep(0.005)
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        t = time.perf_counter()
+        run_snapshot()
+        lat.append(time.perf_counter() - t)
+    if th:
+        stop.set()
+        th.join()
+    H.device_synchronize()
+    t_total = time.perf_counter() - t_start
+    crum.crum_ctx_set_timing(ctx, False)
+
+    timing = {}
+    for cls, name in enumerate(["diff", "pack", "drain", "scan", "header"]):
+        timing[name] = crum.crum_ctx_timing(ctx, cls)
+    st = read_status()
+    assert st.code == 0 and st.n_dirty == D, st
+
+    n_diff, diff_ms = timing["diff"]
+    n_units = N >> 13 if P >= 8192 else N >> 12  # one flag byte per diff unit
+    diff_bytes_step = 2 * N + n_units
+    diff_gbs = diff_bytes_step * args.steps / (diff_ms * 1e-3) / 1e9
+    n_dr, drain_ms = timing["drain"]
+    drain_gbs = image_bytes * args.steps / (drain_ms * 1e-3) / 1e9
+    n_pk, pack_ms = timing["pack"]
+    pack_bytes = 2 * D * P + 4 * D
+    pack_gbs = pack_bytes * args.steps / (pack_ms * 1e-3) / 1e9
+    sax_with = None
+    if sax_graphs[0]:
+        sax_with = sax_bytes_per_pass * PASSES * sax_graphs[0] / (sax_time[0] * 1e-3) / 1e9
+
+    ms_step = 1e3 * t_total / args.steps
+    value = N * args.steps / t_total / 1e9
+    lat_ms = sorted(1e3 * v for v in lat)
+    p50 = statistics.median(lat_ms)
+    p99 = lat_ms[min(len(lat_ms) - 1, int(round(0.99 * (len(lat_ms) - 1))))]
+
+    traffic = load_traffic(workload, diff_bytes_step * args.steps / max(n_diff, 1))
+    result = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic (seeded SplitMix64 bytes, PCG64 scenario)",
+        "config": {
+            "workload": wl_name,
+            "regions": R,
+            "page_size": P,
+            "scanned_bytes": N,
+            "total_pages": G,
+            "dirty_pages": D,
+            "image_bytes": image_bytes,
+            "staging_capacity": cap,
+            "order": "chunk-pipelined",
+            "co_runner": (f"fp32 SAXPY 4096x4096: graphs of {PASSES} single-pass kernels "
+                          f"issued continuously on a second stream by a second host thread "
+                          f"({sax_graphs[0]} graphs during the timed steps)") if corun_on else None,
+            "parallelism": "single GPU",
+        },
+        "latency_ms": {"p50": round(p50, 3), "p99": round(p99, 3)},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_diff",
+            "achieved": round(diff_gbs, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(diff_gbs / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_step": diff_bytes_step,
+            "avg_launch_ms": round(diff_ms / max(n_diff, 1), 4),
+            "launches": n_diff,
+        },
+        "drain": {"achieved": round(drain_gbs, 2), "peak": LINK_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(drain_gbs / LINK_PEAK_GBS, 4), "copies": n_dr},
+        "pack": {"achieved": round(pack_gbs, 1), "unit": "GB/s",
+                 "algorithmic_bytes_per_step": pack_bytes},
+        "overlap": {
+            "snapshot_ms_alone": round(snap_alone_ms, 3),
+            "snapshot_ms_with_corunner": round(p50, 3) if corun_on else None,
+            "snapshot_ms_diff_first_order": round(checked_ms, 3),
+            "saxpy_gbs_alone": round(sax_alone_gbs, 1),
+            "saxpy_gbs_with_snapshot": round(sax_with, 1) if sax_with else None,
+        },
+    }
+    if args.cpu_seconds > 0:
+        log("[bench] CPU oracle baseline ...")
+        result["cpu_baseline"] = cpu_baseline(scn, args.cpu_seconds)
+    else:
+        result["cpu_baseline"] = None
+    crum.crum_ctx_destroy(ctx)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -114,11 +114,15 @@ int crum_image_bytes(uint32_t n_regions, uint64_t total_pages, uint64_t n_dirty,
  * Enqueues on `stream` (a hipStream_t; NULL = the null stream): diff of every
  * page against its shadow -> dirty bitmap -> prefix sum -> pack of dirty pages
  * with their CRC-32C -> image header, all built in d_staging in the image
- * layout above.  The calling thread then waits for the dirty count (one small
- * device-to-host read), and enqueues the drain of the image to h_image on the
- * context's side stream, chunked so that copies overlap packing; `stream` is
- * made to wait for the drain.  With CRUM_UPDATE_SHADOW, every dirty page is
- * also copied into its shadow, but only when the status is CRUM_OK.
+ * layout above, and the drain of the image to h_image on the context's side
+ * stream; `stream` is made to wait for the drain.  The calling thread blocks
+ * only on small device-to-host reads of dirty counts.  Two orders give the
+ * same image: when both capacities hold an image with every page dirty (and
+ * CRUM_PARAM_EAGER is 1), the page space is processed in chunks and each
+ * chunk is drained while later chunks are diffed; otherwise the whole diff
+ * and the capacity check run first, then pack chunks with their drain behind
+ * them.  With CRUM_UPDATE_SHADOW, every dirty page is also copied into its
+ * shadow, but only when the status is CRUM_OK.
  *
  * d_staging: device buffer of staging_bytes, at least data_off bytes, 16-byte
  * aligned; receives the image.  h_image: pinned host buffer of h_image_bytes,
@@ -146,6 +150,35 @@ int crum_snapshot(crum_ctx* ctx, const crum_region* regions, uint32_t n_regions,
 int crum_restore(crum_ctx* ctx, const crum_region* regions, uint32_t n_regions,
                  const void* h_image, uint64_t image_bytes, uint32_t flags, void* d_staging,
                  uint64_t staging_bytes, void* stream, crum_status* h_status);
+
+/* Launch and pipeline parameters of a context (defaults in parentheses).
+ * CRUM_PARAM_DIFF_BLOCKS: persistent grid of the diff kernel, in 256-thread
+ *   workgroups (4 per compute unit).  CRUM_PARAM_PACK_BLOCKS: grid of the
+ *   pack, verify and scatter kernels (4 per compute unit).
+ * CRUM_PARAM_CHUNK_BYTES / CRUM_PARAM_CHUNK_MAX_BYTES: scanned bytes of the
+ *   first and of the largest chunk when the snapshot is pipelined by chunks
+ *   (128 MiB / 1 GiB); chunks double in size up to the maximum.
+ * CRUM_PARAM_EAGER: 1 pipelines the snapshot by chunks whenever the staging
+ *   and host capacities hold an image with every page dirty (so ENOSPC is
+ *   impossible); 0 always runs the whole diff first (1).
+ * CRUM_PARAM_DRAIN_CHUNK_BYTES: first pack/drain chunk of the non-pipelined
+ *   order (8 MiB, doubling up to 256 MiB).
+ * CRUM_PARAM_DIFF_UNIT_SHIFT: log2 of the largest diff unit, 12..14 (14):
+ *   each wave compares min(page, 2^value) bytes per step.
+ * CRUM_PARAM_DIFF_NONTEMPORAL: 1 marks the diff kernel's loads non-temporal (1).
+ * Values of 0 are rejected (CRUM_EINVAL) except for the two on/off switches. */
+enum {
+    CRUM_PARAM_DIFF_BLOCKS = 1,
+    CRUM_PARAM_PACK_BLOCKS = 2,
+    CRUM_PARAM_CHUNK_BYTES = 3,
+    CRUM_PARAM_CHUNK_MAX_BYTES = 4,
+    CRUM_PARAM_EAGER = 5,
+    CRUM_PARAM_DRAIN_CHUNK_BYTES = 6,
+    CRUM_PARAM_DIFF_UNIT_SHIFT = 7,
+    CRUM_PARAM_DIFF_NONTEMPORAL = 8
+};
+int crum_ctx_set_param(crum_ctx* ctx, int param, uint64_t value);
+int crum_ctx_get_param(crum_ctx* ctx, int param, uint64_t* value);
 
 /* Per-kernel timing, for measurement.  When enabled, the context brackets
  * each launch of its kernels and each drain copy with timing events.

@@ -152,7 +152,8 @@ def snapshot(regions, page_size: int, flags: int = 0, seq: int = 0,
         image_cap = total_cap
     if staging_cap is None:
         staging_cap = G * page_size
-    image = np.zeros(max(1, min(image_cap, total_cap)), dtype=np.uint8)
+    # every image byte is written by the C code (header, pads, pages, CRCs)
+    image = np.empty(max(1, min(image_cap, total_cap)), dtype=np.uint8)
     bitmap = np.zeros(max(1, W), dtype=np.uint64)
     st = _Status()
     arr = _regions(regions)

@@ -18,6 +18,10 @@ SO = os.path.join(HERE, "libcrum.so")
 CRUM_OK, CRUM_EINVAL, CRUM_ENOSPC, CRUM_ECRC = 0, -1, -2, -3
 CRUM_EFORMAT, CRUM_EHIP, CRUM_EMISMATCH = -4, -5, -6
 CRUM_UPDATE_SHADOW, CRUM_VERIFY = 1, 2
+CRUM_PARAM_DIFF_BLOCKS, CRUM_PARAM_PACK_BLOCKS = 1, 2
+CRUM_PARAM_CHUNK_BYTES, CRUM_PARAM_CHUNK_MAX_BYTES = 3, 4
+CRUM_PARAM_EAGER, CRUM_PARAM_DRAIN_CHUNK_BYTES = 5, 6
+CRUM_PARAM_DIFF_UNIT_SHIFT, CRUM_PARAM_DIFF_NONTEMPORAL = 7, 8
 
 CODE_NAMES = {0: "CRUM_OK", -1: "CRUM_EINVAL", -2: "CRUM_ENOSPC", -3: "CRUM_ECRC",
               -4: "CRUM_EFORMAT", -5: "CRUM_EHIP", -6: "CRUM_EMISMATCH"}
@@ -43,6 +47,8 @@ _SIGS = {
     "crum_image_bytes": (_I, [_U32, _U64, _U64, _U32, ctypes.POINTER(_U64)]),
     "crum_snapshot": (_I, [_P, _P, _U32, _U32, _U32, _U64, _P, _U64, _P, _U64, _P, _P]),
     "crum_restore": (_I, [_P, _P, _U32, _P, _U64, _U32, _P, _U64, _P, _P]),
+    "crum_ctx_set_param": (_I, [_P, _I, _U64]),
+    "crum_ctx_get_param": (_I, [_P, _I, ctypes.POINTER(_U64)]),
     "crum_ctx_set_timing": (_I, [_P, _I]),
     "crum_ctx_timing": (_I, [_P, _I, ctypes.POINTER(_U64), ctypes.POINTER(ctypes.c_double)]),
     "crum_ctx_timing_reset": (_I, [_P]),
@@ -120,6 +126,20 @@ def crum_restore(ctx: int, regions, h_image: int, image_bytes: int, flags: int,
     return lib().crum_restore(ctx, ctypes.cast(arr, _P) if n else None, n, h_image or None,
                               image_bytes, flags, d_staging, staging_bytes, stream or None,
                               h_status)
+
+
+def crum_ctx_set_param(ctx: int, param: int, value: int) -> None:
+    rc = lib().crum_ctx_set_param(ctx, param, value)
+    if rc != CRUM_OK:
+        raise ValueError(f"crum_ctx_set_param({param}, {value}): {CODE_NAMES.get(rc, rc)}")
+
+
+def crum_ctx_get_param(ctx: int, param: int) -> int:
+    v = _U64()
+    rc = lib().crum_ctx_get_param(ctx, param, ctypes.byref(v))
+    if rc != CRUM_OK:
+        raise ValueError(CODE_NAMES.get(rc, rc))
+    return v.value
 
 
 def crum_ctx_set_timing(ctx: int, enable: bool) -> None:

@@ -50,11 +50,12 @@ bool page_size_ok(uint64_t p) { return p >= 4096 && p <= (1ull << 30) && (p & (p
 // Scratch layout of one launch (offsets into ctx->d_scratch).
 struct Layout {
     size_t regs = 0, reqs = 0, out = 0, glob = 0, upload_end = 0;
-    size_t flags = 0, bitmap = 0, prefix = 0, list = 0, partials = 0, total = 0;
+    size_t flags = 0, bitmap = 0, prefix = 0, list = 0, crcs = 0, partials = 0, bounds = 0,
+           total = 0;
 };
 
 Layout make_layout(uint32_t n_regs, uint32_t n_reqs, uint64_t n_units, uint64_t n_words,
-                   uint64_t list_cap, uint64_t partial_cap)
+                   uint64_t list_cap, uint64_t partial_cap, uint64_t n_chunks)
 {
     Layout L;
     size_t off = 0;
@@ -72,7 +73,9 @@ Layout make_layout(uint32_t n_regs, uint32_t n_reqs, uint64_t n_units, uint64_t 
     L.bitmap = take(8 * std::max<uint64_t>(n_words, 1));
     L.prefix = take(4 * std::max<uint64_t>(n_words, 1));
     L.list = take(4 * std::max<uint64_t>(list_cap, 1));
+    L.crcs = take(4 * std::max<uint64_t>(list_cap, 1));
     L.partials = take(4 * std::max<uint64_t>(partial_cap, 1));
+    L.bounds = take(8 * std::max<uint64_t>(n_chunks, 1));
     L.total = off;
     return L;
 }
@@ -89,8 +92,15 @@ struct crum_ctx {
     uint8_t* h_pin = nullptr;  // uploads, then readback area
     size_t pin_cap = 0;
     hipEvent_t ev_upload = nullptr, ev_count = nullptr, ev_done = nullptr, ev_hdr = nullptr;
-    std::vector<hipEvent_t> ev_chunk;
+    std::vector<hipEvent_t> ev_chunk;  // pack of chunk i done
+    std::vector<hipEvent_t> ev_cnt;    // dirty count of chunk i read back
     LaunchShape shape{};
+    uint64_t chunk_bytes = 128ull << 20;
+    uint64_t chunk_max_bytes = 1ull << 30;
+    uint32_t unit_shift_max = kUnitShiftDefault;
+    bool diff_nt = true;
+    uint64_t drain_chunk_bytes = 8ull << 20;
+    bool eager = true;
     bool timing = false;
     std::vector<hipEvent_t> pool;
     size_t pool_used = 0;
@@ -207,29 +217,40 @@ int check_ranges(const crum_region* regs, uint32_t n)
 }
 
 // Flatten one table into DevRegion entries (single request, request 0).
-void flatten(const crum_region* regs, uint32_t n, uint32_t ps, DevRegion* out,
-             uint64_t* n_pages, uint64_t* n_tiles, uint64_t* n_units)
+void flatten(const crum_region* regs, uint32_t n, uint32_t ps, uint32_t us_max, DevRegion* out,
+             uint64_t* n_pages, uint64_t* n_units)
 {
-    uint64_t page = 0, tile = 0, unit = 0;
-    const uint32_t us = std::min<uint32_t>(ps, kTileShift);
+    uint64_t page = 0, unit = 0;
+    const uint32_t us = std::min<uint32_t>(ps, us_max);
     for (uint32_t i = 0; i < n; ++i) {
         DevRegion& d = out[i];
         d.cur = static_cast<const uint8_t*>(regs[i].base);
         d.shadow = static_cast<uint8_t*>(regs[i].shadow);
         d.len = regs[i].len;
         d.first_page = page;
-        d.first_tile = tile;
         d.first_unit = unit;
         d.id = regs[i].id;
         d.page_shift = ps;
         d.req = 0;
+        d.unit_shift = us;
+        d.pad = 0;
         page += regs[i].len >> ps;
-        tile += (regs[i].len + kTileBytes - 1) >> kTileShift;
         unit += regs[i].len >> us;
     }
     *n_pages = page;
-    *n_tiles = tile;
     *n_units = unit;
+}
+
+hipError_t ensure_events(std::vector<hipEvent_t>& v, size_t n)
+{
+    while (v.size() < n) {
+        hipEvent_t e;
+        hipError_t err = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+        if (err != hipSuccess)
+            return err;
+        v.push_back(e);
+    }
+    return hipSuccess;
 }
 
 #define CRUM_TRY(expr)                          \
@@ -279,12 +300,8 @@ int crum_ctx_create(int device, crum_ctx** out)
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
         cus > 0)
         c->cus = cus;
-    c->shape.diff_blocks = c->cus * 8;
+    c->shape.diff_blocks = c->cus * 4;
     c->shape.pack_blocks = c->cus * 4;
-    if (const char* v = std::getenv("CRUM_DIFF_BLOCKS"))
-        c->shape.diff_blocks = std::max(1, std::atoi(v));
-    if (const char* v = std::getenv("CRUM_PACK_BLOCKS"))
-        c->shape.pack_blocks = std::max(1, std::atoi(v));
     CrcTables host;
     build_crc_tables(&host);
     bool ok = hipMalloc(reinterpret_cast<void**>(&c->d_tabs), sizeof(CrcTables)) == hipSuccess &&
@@ -313,6 +330,8 @@ void crum_ctx_destroy(crum_ctx* c)
         (void)hipEventDestroy(e);
     for (hipEvent_t e : c->ev_chunk)
         (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->ev_cnt)
+        (void)hipEventDestroy(e);
     for (hipEvent_t e : {c->ev_upload, c->ev_count, c->ev_done, c->ev_hdr})
         if (e)
             (void)hipEventDestroy(e);
@@ -325,6 +344,66 @@ void crum_ctx_destroy(crum_ctx* c)
     if (c->h_pin)
         (void)hipHostFree(c->h_pin);
     delete c;
+}
+
+int crum_ctx_set_param(crum_ctx* c, int param, uint64_t v)
+{
+    if (!c)
+        return CRUM_EINVAL;
+    if (param == CRUM_PARAM_EAGER || param == CRUM_PARAM_DIFF_NONTEMPORAL) {
+        if (v > 1)
+            return CRUM_EINVAL;
+        (param == CRUM_PARAM_EAGER ? c->eager : c->diff_nt) = v != 0;
+        return CRUM_OK;
+    }
+    if (param == CRUM_PARAM_DIFF_UNIT_SHIFT) {
+        if (v < 12 || v > 14)
+            return CRUM_EINVAL;
+        c->unit_shift_max = (uint32_t)v;
+        return CRUM_OK;
+    }
+    if (v == 0)
+        return CRUM_EINVAL;
+    switch (param) {
+    case CRUM_PARAM_DIFF_BLOCKS:
+        if (v > (1u << 20))
+            return CRUM_EINVAL;
+        c->shape.diff_blocks = (int)v;
+        return CRUM_OK;
+    case CRUM_PARAM_PACK_BLOCKS:
+        if (v > (1u << 20))
+            return CRUM_EINVAL;
+        c->shape.pack_blocks = (int)v;
+        return CRUM_OK;
+    case CRUM_PARAM_CHUNK_BYTES:
+        c->chunk_bytes = v;
+        return CRUM_OK;
+    case CRUM_PARAM_CHUNK_MAX_BYTES:
+        c->chunk_max_bytes = v;
+        return CRUM_OK;
+    case CRUM_PARAM_DRAIN_CHUNK_BYTES:
+        c->drain_chunk_bytes = v;
+        return CRUM_OK;
+    default:
+        return CRUM_EINVAL;
+    }
+}
+
+int crum_ctx_get_param(crum_ctx* c, int param, uint64_t* v)
+{
+    if (!c || !v)
+        return CRUM_EINVAL;
+    switch (param) {
+    case CRUM_PARAM_DIFF_BLOCKS: *v = (uint64_t)c->shape.diff_blocks; return CRUM_OK;
+    case CRUM_PARAM_PACK_BLOCKS: *v = (uint64_t)c->shape.pack_blocks; return CRUM_OK;
+    case CRUM_PARAM_CHUNK_BYTES: *v = c->chunk_bytes; return CRUM_OK;
+    case CRUM_PARAM_CHUNK_MAX_BYTES: *v = c->chunk_max_bytes; return CRUM_OK;
+    case CRUM_PARAM_EAGER: *v = c->eager ? 1 : 0; return CRUM_OK;
+    case CRUM_PARAM_DRAIN_CHUNK_BYTES: *v = c->drain_chunk_bytes; return CRUM_OK;
+    case CRUM_PARAM_DIFF_UNIT_SHIFT: *v = c->unit_shift_max; return CRUM_OK;
+    case CRUM_PARAM_DIFF_NONTEMPORAL: *v = c->diff_nt ? 1 : 0; return CRUM_OK;
+    default: return CRUM_EINVAL;
+    }
 }
 
 int crum_ctx_set_timing(crum_ctx* c, int enable)
@@ -394,18 +473,44 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     if (staging_bytes < data_off || (h_image && h_image_bytes < data_off))
         return CRUM_EINVAL;
     const uint64_t capacity = h_image ? std::min(staging_bytes, h_image_bytes) : staging_bytes;
+    // When every page fits, ENOSPC cannot happen and the page space is
+    // processed in chunks whose drain overlaps the diff of later chunks.
+    // Otherwise the whole diff and the capacity check come before any write.
+    const uint64_t worst = data_off + (G << ps) + round_up(4 * G, 8);
+    const bool eager = c->eager && capacity >= worst && G > 0;
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     DeviceGuard g(c->device);
 
+    // ---- chunk plan (page ranges aligned to bitmap words)
+    std::vector<uint64_t> cuts{0};
+    if (eager) {
+        uint64_t chunk_bytes = c->chunk_bytes;
+        uint64_t gp = 0;
+        while (gp < G) {
+            const uint64_t pages = std::max<uint64_t>(64, (chunk_bytes >> ps) & ~63ull);
+            gp = std::min(G, gp + pages);
+            cuts.push_back(gp);
+            chunk_bytes = std::min<uint64_t>(chunk_bytes * 2,
+                                             std::max(c->chunk_max_bytes, c->chunk_bytes));
+        }
+    } else {
+        cuts.push_back(G);
+    }
+    const size_t n_chunks = cuts.size() - 1;
+
     // ---- flatten, scratch, upload
     const uint32_t np_shift = ps > kPieceShift ? ps - kPieceShift : 0;
+    const uint32_t us = std::min<uint32_t>(ps, c->unit_shift_max);
     std::vector<DevRegion> dregs(std::max<uint32_t>(1, n_regions));
-    uint64_t n_pages = 0, n_tiles = 0, n_units = 0;
-    flatten(regions, n_regions, ps, dregs.data(), &n_pages, &n_tiles, &n_units);
-    const Layout L = make_layout(n_regions, 1, n_units, W, W * 64, np_shift ? G << np_shift : 0);
+    uint64_t n_pages = 0, n_units = 0;
+    flatten(regions, n_regions, ps, c->unit_shift_max, dregs.data(), &n_pages, &n_units);
+    const Layout L =
+        make_layout(n_regions, 1, n_units, W, W * 64, np_shift ? G << np_shift : 0, n_chunks);
     CRUM_TRY(ensure_scratch(c, L.total));
     const size_t rb_off = round_up(L.upload_end, 256);
-    CRUM_TRY(ensure_pinned(c, rb_off + 128));
+    CRUM_TRY(ensure_pinned(c, rb_off + 128 + 8 * n_chunks));
+    CRUM_TRY(ensure_events(c->ev_chunk, n_chunks));
+    CRUM_TRY(ensure_events(c->ev_cnt, n_chunks));
     CRUM_TRY(hipEventSynchronize(c->ev_upload));
     uint8_t* P = c->h_pin;
     std::memset(P, 0, L.upload_end);
@@ -434,84 +539,144 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     uint64_t* d_bitmap = reinterpret_cast<uint64_t*>(S + L.bitmap);
     uint32_t* d_prefix = reinterpret_cast<uint32_t*>(S + L.prefix);
     uint32_t* d_list = reinterpret_cast<uint32_t*>(S + L.list);
+    uint32_t* d_crcs = reinterpret_cast<uint32_t*>(S + L.crcs);
     uint32_t* d_partials = reinterpret_cast<uint32_t*>(S + L.partials);
+    uint64_t* d_bounds = reinterpret_cast<uint64_t*>(S + L.bounds);
     uint8_t* staging = static_cast<uint8_t*>(d_staging);
+    uint8_t* himg = static_cast<uint8_t*>(h_image);
+    const int upd = (flags & CRUM_UPDATE_SHADOW) ? 1 : 0;
+    uint8_t* rb = P + rb_off;
 
     // the previous call on this context may still be draining from scratch
     CRUM_TRY(hipStreamWaitEvent(stream, c->ev_done, 0));
     CRUM_TRY(hipMemcpyAsync(S, P, L.upload_end, hipMemcpyHostToDevice, stream));
     CRUM_TRY(hipEventRecord(c->ev_upload, stream));
 
-    // ---- diff, bitmap, scan (device), then the count readback
-    {
-        Span sp(c, kTDiff, stream);
-        CRUM_TRY(launch_diff(d_regs, n_regions, n_tiles, d_flags, c->shape.diff_blocks, stream));
-    }
-    {
-        Span sp(c, kTScan, stream);
-        CRUM_TRY(launch_bitmap(d_regs, n_regions, W, d_flags, d_bitmap, stream));
-        CRUM_TRY(launch_scan(d_bitmap, W, d_prefix, d_reqs, 1, d_out, d_glob, capacity, 0,
-                             stream));
-    }
-    uint8_t* rb = P + rb_off;
-    CRUM_TRY(hipMemcpyAsync(rb, d_out, 128, hipMemcpyDeviceToHost, stream));
-    CRUM_TRY(hipEventRecord(c->ev_count, stream));
-    CRUM_TRY(hipEventSynchronize(c->ev_count));
-    DevReqOut o;
-    std::memcpy(&o, rb, sizeof(o));
-
-    if (o.code != CRUM_OK) {
-        // ENOSPC: header, table and bitmap only; nothing packed or drained
-        Span sp(c, kTHeader, stream);
-        CRUM_TRY(launch_header(d_regs, d_reqs, 1, d_out, d_bitmap, 0, staging, c->d_tabs, stream));
-        sp.end();
-        CRUM_TRY(hipMemcpyAsync(h_status, d_out, sizeof(crum_status), hipMemcpyDeviceToHost,
-                                stream));
-        CRUM_TRY(hipEventRecord(c->ev_done, stream));
-        return CRUM_OK;
-    }
-    const uint64_t D = o.n_dirty;
-    uint8_t* himg = static_cast<uint8_t*>(h_image);
-
-    // ---- compaction list, then pack in chunks with the drain behind it
-    if (D) {
-        Span sp(c, kTScan, stream);
-        CRUM_TRY(launch_list(d_bitmap, d_prefix, W, d_list, stream));
-    }
-    uint64_t k0 = 0;
-    uint64_t chunk_bytes = 8ull << 20;
-    size_t ci = 0;
-    while (k0 < D) {
-        const uint64_t n_slots = std::max<uint64_t>(1, chunk_bytes >> ps);
-        const uint64_t k1 = std::min(D, k0 + n_slots);
-        {
-            Span sp(c, kTPack, stream);
-            CRUM_TRY(launch_pack(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, k0, k1,
-                                 np_shift, staging, (flags & CRUM_UPDATE_SHADOW) ? 1 : 0,
-                                 d_partials, c->d_tabs, d_glob, c->shape.pack_blocks, stream));
-            CRUM_TRY(launch_finalize(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, k0, k1,
-                                     np_shift, d_partials, staging, d_glob, stream));
-        }
-        if (himg) {
-            if (ci == c->ev_chunk.size()) {
-                hipEvent_t e;
-                CRUM_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-                c->ev_chunk.push_back(e);
+    uint64_t D = 0, image_bytes = 0;
+    if (eager) {
+        // ---- enqueue every chunk: diff, bitmap, scan, count readback, list, pack
+        for (size_t ci = 0; ci < n_chunks; ++ci) {
+            const uint64_t g0 = cuts[ci], g1 = cuts[ci + 1];
+            const uint64_t w0 = g0 / 64, w1 = (g1 + 63) / 64;
+            {
+                Span sp(c, kTDiff, stream);
+                CRUM_TRY(launch_diff(d_regs, n_regions, g0 << (ps - us), g1 << (ps - us), d_flags,
+                                     c->shape.diff_blocks, c->diff_nt, stream));
+            }
+            {
+                Span sp(c, kTScan, stream);
+                CRUM_TRY(launch_bitmap(d_regs, n_regions, w0, w1, d_flags, d_bitmap, stream));
+                CRUM_TRY(launch_scan(d_bitmap, w0, w1, W, d_prefix, d_bounds + ci,
+                                     ci + 1 == n_chunks, d_reqs, 1, d_out, d_glob, capacity, 0,
+                                     stream));
+            }
+            CRUM_TRY(hipMemcpyAsync(rb + 128 + 8 * ci, d_bounds + ci, 8, hipMemcpyDeviceToHost,
+                                    stream));
+            CRUM_TRY(hipEventRecord(c->ev_cnt[ci], stream));
+            {
+                Span sp(c, kTScan, stream);
+                CRUM_TRY(launch_list(d_bitmap, d_prefix, w0, w1, d_list, stream));
+            }
+            {
+                Span sp(c, kTPack, stream);
+                SlotRange sr{0, 0, d_bounds, (uint32_t)ci, g1 - g0};
+                CRUM_TRY(launch_pack(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
+                                     np_shift, staging, upd, d_crcs, d_partials, c->d_tabs,
+                                     d_glob, c->shape.pack_blocks, stream));
+                CRUM_TRY(launch_finalize(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
+                                         np_shift, d_partials, d_crcs, staging, d_glob, stream));
             }
             CRUM_TRY(hipEventRecord(c->ev_chunk[ci], stream));
-            CRUM_TRY(hipStreamWaitEvent(c->side, c->ev_chunk[ci], 0));
-            const uint64_t off = data_off + (k0 << ps);
-            Span sp(c, kTDrain, c->side);
-            CRUM_TRY(hipMemcpyAsync(himg + off, staging + off, (k1 - k0) << ps,
-                                    hipMemcpyDeviceToHost, c->side));
         }
-        ++ci;
-        k0 = k1;
-        chunk_bytes = std::min<uint64_t>(chunk_bytes * 2, 256ull << 20);
+        // ---- drain each chunk as soon as its count is known
+        uint64_t prev = 0;
+        for (size_t ci = 0; ci < n_chunks; ++ci) {
+            CRUM_TRY(hipEventSynchronize(c->ev_cnt[ci]));
+            uint64_t cnt;
+            std::memcpy(&cnt, rb + 128 + 8 * ci, 8);
+            if (himg && cnt > prev) {
+                CRUM_TRY(hipStreamWaitEvent(c->side, c->ev_chunk[ci], 0));
+                const uint64_t off = data_off + (prev << ps);
+                Span sp(c, kTDrain, c->side);
+                CRUM_TRY(hipMemcpyAsync(himg + off, staging + off, (cnt - prev) << ps,
+                                        hipMemcpyDeviceToHost, c->side));
+            }
+            prev = cnt;
+        }
+        D = prev;
+        image_bytes = data_off + (D << ps) + round_up(4 * D, 8);
+    } else {
+        // ---- checked order: whole diff, scan with the capacity check, readback
+        {
+            Span sp(c, kTDiff, stream);
+            CRUM_TRY(launch_diff(d_regs, n_regions, 0, n_units, d_flags, c->shape.diff_blocks,
+                                 c->diff_nt, stream));
+        }
+        {
+            Span sp(c, kTScan, stream);
+            CRUM_TRY(launch_bitmap(d_regs, n_regions, 0, W, d_flags, d_bitmap, stream));
+            CRUM_TRY(launch_scan(d_bitmap, 0, W, W, d_prefix, d_bounds, 1, d_reqs, 1, d_out,
+                                 d_glob, capacity, 0, stream));
+        }
+        CRUM_TRY(hipMemcpyAsync(rb, d_out, 128, hipMemcpyDeviceToHost, stream));
+        CRUM_TRY(hipEventRecord(c->ev_count, stream));
+        CRUM_TRY(hipEventSynchronize(c->ev_count));
+        DevReqOut o;
+        std::memcpy(&o, rb, sizeof(o));
+        if (o.code != CRUM_OK) {
+            // ENOSPC: header, table and bitmap only; nothing packed or drained
+            Span sp(c, kTHeader, stream);
+            CRUM_TRY(launch_header(d_regs, d_reqs, 1, d_out, d_bitmap, d_crcs, staging,
+                                   c->d_tabs, stream));
+            sp.end();
+            CRUM_TRY(hipMemcpyAsync(h_status, d_out, sizeof(crum_status), hipMemcpyDeviceToHost,
+                                    stream));
+            CRUM_TRY(hipEventRecord(c->ev_done, stream));
+            return CRUM_OK;
+        }
+        D = o.n_dirty;
+        image_bytes = o.image_bytes;
+        if (D) {
+            Span sp(c, kTScan, stream);
+            CRUM_TRY(launch_list(d_bitmap, d_prefix, 0, W, d_list, stream));
+        }
+        // pack in slot chunks with the drain of each behind it
+        uint64_t k0 = 0;
+        uint64_t chunk_bytes = c->drain_chunk_bytes;
+        size_t ci = 0;
+        while (k0 < D) {
+            const uint64_t n_slots = std::max<uint64_t>(1, chunk_bytes >> ps);
+            const uint64_t k1 = std::min(D, k0 + n_slots);
+            {
+                Span sp(c, kTPack, stream);
+                SlotRange sr{k0, k1, nullptr, 0, k1 - k0};
+                CRUM_TRY(launch_pack(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
+                                     np_shift, staging, upd, d_crcs, d_partials, c->d_tabs,
+                                     d_glob, c->shape.pack_blocks, stream));
+                CRUM_TRY(launch_finalize(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
+                                         np_shift, d_partials, d_crcs, staging, d_glob, stream));
+            }
+            if (himg) {
+                CRUM_TRY(ensure_events(c->ev_chunk, ci + 1));
+                CRUM_TRY(hipEventRecord(c->ev_chunk[ci], stream));
+                CRUM_TRY(hipStreamWaitEvent(c->side, c->ev_chunk[ci], 0));
+                const uint64_t off = data_off + (k0 << ps);
+                Span sp(c, kTDrain, c->side);
+                CRUM_TRY(hipMemcpyAsync(himg + off, staging + off, (k1 - k0) << ps,
+                                        hipMemcpyDeviceToHost, c->side));
+            }
+            ++ci;
+            k0 = k1;
+            chunk_bytes = std::min<uint64_t>(chunk_bytes * 2,
+                                             std::max<uint64_t>(256ull << 20, chunk_bytes));
+        }
     }
+
+    // ---- header (with the CRC array), then the prefix and tail of the drain
     {
         Span sp(c, kTHeader, stream);
-        CRUM_TRY(launch_header(d_regs, d_reqs, 1, d_out, d_bitmap, 0, staging, c->d_tabs, stream));
+        CRUM_TRY(launch_header(d_regs, d_reqs, 1, d_out, d_bitmap, d_crcs, staging, c->d_tabs,
+                               stream));
     }
     if (himg) {
         CRUM_TRY(hipEventRecord(c->ev_hdr, stream));
@@ -519,8 +684,8 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
         const uint64_t tail = data_off + (D << ps);
         Span sp(c, kTDrain, c->side);
         CRUM_TRY(hipMemcpyAsync(himg, staging, data_off, hipMemcpyDeviceToHost, c->side));
-        if (o.image_bytes > tail)
-            CRUM_TRY(hipMemcpyAsync(himg + tail, staging + tail, o.image_bytes - tail,
+        if (image_bytes > tail)
+            CRUM_TRY(hipMemcpyAsync(himg + tail, staging + tail, image_bytes - tail,
                                     hipMemcpyDeviceToHost, c->side));
         sp.end();
         CRUM_TRY(hipMemcpyAsync(h_status, d_out, sizeof(crum_status), hipMemcpyDeviceToHost,
@@ -623,9 +788,9 @@ int crum_restore(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     // ---- device tables
     const uint32_t np_shift = ps > kPieceShift ? ps - kPieceShift : 0;
     std::vector<DevRegion> dregs(std::max<uint32_t>(1, n_regions));
-    uint64_t n_pages = 0, n_tiles = 0, n_units = 0;
-    flatten(regions, n_regions, ps, dregs.data(), &n_pages, &n_tiles, &n_units);
-    const Layout L = make_layout(n_regions, 1, 0, W, W * 64, np_shift ? D << np_shift : 0);
+    uint64_t n_pages = 0, n_units = 0;
+    flatten(regions, n_regions, ps, c->unit_shift_max, dregs.data(), &n_pages, &n_units);
+    const Layout L = make_layout(n_regions, 1, 0, W, W * 64, np_shift ? D << np_shift : 0, 1);
     CRUM_TRY(ensure_scratch(c, L.total));
     CRUM_TRY(ensure_pinned(c, L.upload_end));
     CRUM_TRY(hipEventSynchronize(c->ev_upload));
@@ -658,6 +823,7 @@ int crum_restore(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     uint32_t* d_prefix = reinterpret_cast<uint32_t*>(S + L.prefix);
     uint32_t* d_list = reinterpret_cast<uint32_t*>(S + L.list);
     uint32_t* d_partials = reinterpret_cast<uint32_t*>(S + L.partials);
+    uint32_t* d_crcs = reinterpret_cast<uint32_t*>(S + L.crcs);
     uint8_t* staging = static_cast<uint8_t*>(d_staging);
     const uint64_t* img_bitmap = reinterpret_cast<const uint64_t*>(staging + 64 + 32 * R);
 
@@ -669,16 +835,18 @@ int crum_restore(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     {
         Span sp(c, kTScan, stream);
         CRUM_TRY(launch_restore_check(d_reqs, 1, d_out, staging, c->d_tabs, d_glob, stream));
-        CRUM_TRY(launch_scan(img_bitmap, W, d_prefix, d_reqs, 1, d_out, d_glob, 0, 1, stream));
-        CRUM_TRY(launch_list(img_bitmap, d_prefix, W, d_list, stream));
+        CRUM_TRY(launch_scan(img_bitmap, 0, W, W, d_prefix, nullptr, 1, d_reqs, 1, d_out, d_glob,
+                             0, 1, stream));
+        CRUM_TRY(launch_list(img_bitmap, d_prefix, 0, W, d_list, stream));
     }
     if (flags & CRUM_VERIFY) {
         Span sp(c, kTVerify, stream);
-        CRUM_TRY(launch_pack(kModeVerify, d_regs, n_regions, d_reqs, d_out, d_list, 0, D,
-                             np_shift, staging, 0, d_partials, c->d_tabs, d_glob,
+        SlotRange sr{0, D, nullptr, 0, D};
+        CRUM_TRY(launch_pack(kModeVerify, d_regs, n_regions, d_reqs, d_out, d_list, sr, np_shift,
+                             staging, 0, d_crcs, d_partials, c->d_tabs, d_glob,
                              c->shape.pack_blocks, stream));
-        CRUM_TRY(launch_finalize(kModeVerify, d_regs, n_regions, d_reqs, d_out, d_list, 0, D,
-                                 np_shift, d_partials, staging, d_glob, stream));
+        CRUM_TRY(launch_finalize(kModeVerify, d_regs, n_regions, d_reqs, d_out, d_list, sr,
+                                 np_shift, d_partials, d_crcs, staging, d_glob, stream));
     }
     {
         Span sp(c, kTScatter, stream);

@@ -5,11 +5,10 @@
 
 namespace crum {
 
-// Diff tile: each wave compares kDiffUnroll * 1 KiB of a region per step
-// (64 lanes x 16 bytes per load, kDiffUnroll loads per array).
-constexpr int kDiffUnroll = 8;
-constexpr uint32_t kTileShift = 13;  // log2(kDiffUnroll * 1024)
-constexpr uint32_t kTileBytes = 1u << kTileShift;
+// Diff unit: min(page, 2^unit_shift_max) bytes, unit_shift_max in 12..14
+// (default 14).  A wave compares one unit per step with 64 lanes x 16-byte
+// loads, i.e. unit/1 KiB loads per array per lane.
+constexpr uint32_t kUnitShiftDefault = 14;
 // CRC piece: pages larger than this are split across waves and combined.
 constexpr uint32_t kPieceShift = 16;  // 64 KiB
 constexpr uint32_t kNoBad = 0xFFFFFFFFu;
@@ -23,11 +22,12 @@ struct DevRegion {
     uint8_t* shadow;     // NULL: no baseline
     uint64_t len;
     uint64_t first_page; // global page index of page 0
-    uint64_t first_tile; // global diff-tile index of tile 0
-    uint64_t first_unit; // global flag-unit index of unit 0
+    uint64_t first_unit; // global diff-unit index of unit 0
     uint64_t id;
     uint32_t page_shift; // log2 page size
     uint32_t req;        // request index
+    uint32_t unit_shift; // log2 diff unit = min(page_shift, unit_shift_max)
+    uint32_t pad;
 };
 static_assert(sizeof(DevRegion) == 64, "DevRegion layout");
 
@@ -66,7 +66,8 @@ struct DevGlobal {
     uint32_t fmt_bad;        // restore: image check failed
     uint32_t crc_bad;        // restore: lowest failing slot, kNoBad if none
     uint32_t pad0;
-    uint64_t pad[4];
+    uint64_t running;        // dirty pages counted by the scans so far
+    uint64_t pad[3];
 };
 static_assert(sizeof(DevGlobal) == 64, "DevGlobal layout");
 
@@ -86,29 +87,41 @@ struct LaunchShape {
     int pack_blocks;   // persistent grid of the pack/verify/scatter kernels
 };
 
+// Slot range of a pack launch: [lo, hi) given on the host, or, when `bounds`
+// is non-null, read on the device as [chunk ? bounds[chunk-1] : 0, bounds[chunk]).
+struct SlotRange {
+    uint64_t lo, hi;
+    const uint64_t* bounds;
+    uint32_t chunk;
+    uint64_t max_slots;  // upper bound on hi - lo (grid sizing)
+};
+
 // Kernel launchers (crum_kernels.hip).  All enqueue on `s`.
 void build_crc_tables(CrcTables* host);
-hipError_t launch_diff(const DevRegion* regs, uint32_t n_regs, uint64_t n_tiles,
-                       uint8_t* unit_flags, int blocks, hipStream_t s);
-hipError_t launch_bitmap(const DevRegion* regs, uint32_t n_regs, uint64_t n_words,
+hipError_t launch_diff(const DevRegion* regs, uint32_t n_regs, uint64_t u0, uint64_t u1,
+                       uint8_t* unit_flags, int blocks, int nontemporal, hipStream_t s);
+hipError_t launch_bitmap(const DevRegion* regs, uint32_t n_regs, uint64_t w0, uint64_t w1,
                          const uint8_t* unit_flags, uint64_t* bitmap, hipStream_t s);
-hipError_t launch_scan(const uint64_t* bitmap, uint64_t n_words, uint32_t* prefix,
-                       const DevRequest* reqs, uint32_t n_reqs, DevReqOut* out, DevGlobal* glob,
-                       uint64_t capacity, int restore_mode, hipStream_t s);
-hipError_t launch_list(const uint64_t* bitmap, const uint32_t* prefix, uint64_t n_words,
+// Scans words [w0, w1) continuing glob->running; writes the new running total
+// to *bounds_out when non-null.  With `final`, also fills the per-request
+// results over all n_words_total words and applies the capacity check.
+hipError_t launch_scan(const uint64_t* bitmap, uint64_t w0, uint64_t w1, uint64_t n_words_total,
+                       uint32_t* prefix, uint64_t* bounds_out, int final, const DevRequest* reqs,
+                       uint32_t n_reqs, DevReqOut* out, DevGlobal* glob, uint64_t capacity,
+                       int restore_mode, hipStream_t s);
+hipError_t launch_list(const uint64_t* bitmap, const uint32_t* prefix, uint64_t w0, uint64_t w1,
                        uint32_t* list, hipStream_t s);
 hipError_t launch_pack(int mode, const DevRegion* regs, uint32_t n_regs, const DevRequest* reqs,
-                       const DevReqOut* out, const uint32_t* list, uint64_t slot0,
-                       uint64_t slot1, uint32_t piece_shift, uint8_t* staging, int update_shadow,
-                       uint32_t* partials, const CrcTables* tabs, DevGlobal* glob, int blocks,
-                       hipStream_t s);
+                       const DevReqOut* out, const uint32_t* list, SlotRange range,
+                       uint32_t np_shift, uint8_t* staging, int update_shadow,
+                       uint32_t* crc_out, uint32_t* partials, const CrcTables* tabs,
+                       DevGlobal* glob, int blocks, hipStream_t s);
 hipError_t launch_finalize(int mode, const DevRegion* regs, uint32_t n_regs,
                            const DevRequest* reqs, const DevReqOut* out, const uint32_t* list,
-                           uint64_t slot0, uint64_t slot1, uint32_t piece_shift,
-                           const uint32_t* partials, uint8_t* staging, DevGlobal* glob,
-                           hipStream_t s);
+                           SlotRange range, uint32_t np_shift, const uint32_t* partials,
+                           uint32_t* crc_out, uint8_t* staging, DevGlobal* glob, hipStream_t s);
 hipError_t launch_header(const DevRegion* regs, const DevRequest* reqs, uint32_t n_reqs,
-                         const DevReqOut* out, const uint64_t* bitmap, uint32_t img_flags_mask,
+                         const DevReqOut* out, const uint64_t* bitmap, const uint32_t* crcs,
                          uint8_t* staging, const CrcTables* tabs, hipStream_t s);
 hipError_t launch_restore_check(const DevRequest* reqs, uint32_t n_reqs, const DevReqOut* out,
                                 const uint8_t* staging, const CrcTables* tabs, DevGlobal* glob,

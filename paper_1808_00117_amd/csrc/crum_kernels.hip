@@ -1,20 +1,21 @@
 // HIP kernels of the incremental snapshot (gfx950, wave64).
 //
 // Snapshot pipeline (one launch of each, except pack which runs in chunks):
-//   k_diff    per page: OR over 16-byte words of (cur ^ shadow) != 0, read with
-//             coalesced 128-bit loads; one flag byte per diff unit
-//             (min(page, tile) bytes), reduced across the wave by ballot.
+//   k_diff    per diff unit (min(page, 4-16 KiB)): OR over 16-byte words of
+//             (cur ^ shadow) != 0, read with coalesced 128-bit loads and
+//             reduced across the wave by ballot; one flag byte per unit.
 //   k_bitmap  per 64 pages: OR of each page's unit flags, then one ballot
 //             gives the u64 bitmap word.
 //   k_scan    one workgroup: exclusive prefix sum of popcount(word) -> slot of
-//             each word's first dirty page; per-request dirty counts, image
-//             offsets and the capacity check (ENOSPC before any pack write).
+//             each word's first dirty page, continuing a running total so the
+//             page space can be processed in chunks; at the end, per-request
+//             dirty counts, image offsets and the capacity check.
 //   k_list    per word: ballot compaction, lane with bit set writes its page
 //             index at prefix + popcount(bits below the lane).
 //   k_pack    per dirty page (or 64 KiB piece): copy into the image's page
 //             area, optionally into the shadow, and CRC-32C on the way.
-//   k_header  per request: header, region table, bitmap, pads, crcs_crc,
-//             meta_crc.
+//   k_header  per request: header, region table, bitmap, CRC array, pads,
+//             crcs_crc, meta_crc.
 // Restore: k_restore_check, k_scan, k_list, k_pack (verify), k_scatter.
 //
 // CRC-32C on the device.  The polynomial arithmetic is in gf2.h.  A wave
@@ -150,7 +151,7 @@ __device__ __forceinline__ uint32_t wave_piece_crc(const uint4* __restrict__ src
 
 // ------------------------------------------------------------ region lookup
 
-// Last region whose field (3 first_page, 4 first_tile) is <= key.
+// Last region whose field (3 first_page, 4 first_unit) is <= key.
 template <int FIELD>
 __device__ __forceinline__ uint32_t find_region(const DevRegion* __restrict__ regs, uint32_t n,
                                                 uint64_t key)
@@ -158,7 +159,7 @@ __device__ __forceinline__ uint32_t find_region(const DevRegion* __restrict__ re
     uint32_t lo = 0, hi = n;
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
-        const uint64_t v = FIELD == 3 ? regs[mid].first_page : regs[mid].first_tile;
+        const uint64_t v = FIELD == 3 ? regs[mid].first_page : regs[mid].first_unit;
         if (v <= key)
             lo = mid;
         else
@@ -169,93 +170,100 @@ __device__ __forceinline__ uint32_t find_region(const DevRegion* __restrict__ re
 
 // ------------------------------------------------------------ k_diff
 
-template <int UNROLL>
+// OR over the lane's LOADS 16-byte words of (a ^ b), a and b already offset
+// by the lane; loads are 1 KiB apart so each one is coalesced across the wave.
+// NT marks the loads non-temporal: the streamed bytes are not kept in the
+// caches, which stay available to co-running work.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <int LOADS, bool NT>
+__device__ __forceinline__ uint32_t xor_or(const uint4* __restrict__ a_,
+                                           const uint4* __restrict__ b_)
+{
+    const u32x4* a = reinterpret_cast<const u32x4*>(a_);
+    const u32x4* b = reinterpret_cast<const u32x4*>(b_);
+    u32x4 va[LOADS], vb[LOADS];
+#pragma unroll
+    for (int j = 0; j < LOADS; ++j) {
+        if (NT) {
+            va[j] = __builtin_nontemporal_load(a + j * 64);
+            vb[j] = __builtin_nontemporal_load(b + j * 64);
+        } else {
+            va[j] = a[j * 64];
+            vb[j] = b[j * 64];
+        }
+    }
+    u32x4 x = va[0] ^ vb[0];
+#pragma unroll
+    for (int j = 1; j < LOADS; ++j)
+        x |= va[j] ^ vb[j];
+    return x.x | x.y | x.z | x.w;
+}
+
+// One wave per diff unit of global units [u0, u1); unit_flags[u] = 1 when
+// any byte of the unit differs from the shadow (or the region has none).
+template <bool NT>
 __global__ __launch_bounds__(256) void k_diff(const DevRegion* __restrict__ regs,
-                                              uint32_t n_regs, uint64_t n_tiles,
+                                              uint32_t n_regs, uint64_t u0, uint64_t u1,
                                               uint8_t* __restrict__ unit_flags)
 {
-    static_assert(UNROLL * 1024 == (int)kTileBytes, "tile size");
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t wave = (uint64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t wave =
+        (uint64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t n_waves = (uint64_t)gridDim.x * 4;
     uint32_t r = 0;
     uint64_t r_lo = 1, r_hi = 0;
-    for (uint64_t t = wave; t < n_tiles; t += n_waves) {
-        if (t < r_lo || t >= r_hi) {
-            r = find_region<4>(regs, n_regs, t);
-            r_lo = regs[r].first_tile;
-            r_hi = r_lo + ((regs[r].len + kTileBytes - 1) >> kTileShift);
+    for (uint64_t u = u0 + wave; u < u1; u += n_waves) {
+        if (u < r_lo || u >= r_hi) {
+            r = find_region<4>(regs, n_regs, u);
+            r_lo = regs[r].first_unit;
+            r_hi = r_lo + (regs[r].len >> regs[r].unit_shift);
         }
         const DevRegion& R = regs[r];
-        const uint64_t off = (t - R.first_tile) << kTileShift;
-        const uint64_t rem = R.len - off;
-        const uint32_t us = R.page_shift < kTileShift ? R.page_shift : kTileShift;
-        const uint64_t ubase = R.first_unit + (off >> us);
-        const uint32_t nbytes = rem < kTileBytes ? (uint32_t)rem : kTileBytes;
-        const uint32_t n_units = nbytes >> us;
-        uint64_t dirty_units = 0;
-        if (R.shadow == nullptr) {
-            dirty_units = ~0ull;
-        } else {
+        const uint32_t us = R.unit_shift;
+        uint32_t x = 1;
+        if (R.shadow != nullptr) {
+            const uint64_t off = (u - R.first_unit) << us;
             const uint4* a = reinterpret_cast<const uint4*>(R.cur + off) + lane;
             const uint4* b = reinterpret_cast<const uint4*>(R.shadow + off) + lane;
-            uint32_t x[UNROLL];
-            if (nbytes == kTileBytes) {
-                uint4 va[UNROLL], vb[UNROLL];
-#pragma unroll
-                for (int j = 0; j < UNROLL; ++j) {
-                    va[j] = a[j * 64];
-                    vb[j] = b[j * 64];
-                }
-#pragma unroll
-                for (int j = 0; j < UNROLL; ++j)
-                    x[j] = (va[j].x ^ vb[j].x) | (va[j].y ^ vb[j].y) | (va[j].z ^ vb[j].z) |
-                           (va[j].w ^ vb[j].w);
-            } else {
-#pragma unroll
-                for (int j = 0; j < UNROLL; ++j) {
-                    x[j] = 0;
-                    if ((uint32_t)j * 1024u < nbytes) {
-                        const uint4 va = a[j * 64], vb = b[j * 64];
-                        x[j] = (va.x ^ vb.x) | (va.y ^ vb.y) | (va.z ^ vb.z) | (va.w ^ vb.w);
-                    }
-                }
-            }
-            const uint32_t lpu_shift = us - 10;  // log2(loads per unit)
-#pragma unroll
-            for (int j = 0; j < UNROLL; ++j) {
-                const uint64_t m = __ballot(x[j] != 0);
-                if (m)
-                    dirty_units |= 1ull << ((uint32_t)j >> lpu_shift);
-            }
+            x = us == 12 ? xor_or<4, NT>(a, b) : us == 13 ? xor_or<8, NT>(a, b)
+                                                          : xor_or<16, NT>(a, b);
         }
-        if (lane < n_units)
-            unit_flags[ubase + lane] = (uint8_t)((dirty_units >> lane) & 1u);
+        const uint64_t m = __ballot(x != 0);
+        if (lane == 0)
+            unit_flags[u] = m != 0;
     }
 }
 
-hipError_t launch_diff(const DevRegion* regs, uint32_t n_regs, uint64_t n_tiles,
-                       uint8_t* unit_flags, int blocks, hipStream_t s)
+hipError_t launch_diff(const DevRegion* regs, uint32_t n_regs, uint64_t u0, uint64_t u1,
+                       uint8_t* unit_flags, int blocks, int nontemporal, hipStream_t s)
 {
-    if (n_tiles == 0)
+    if (u1 <= u0)
         return hipSuccess;
-    const uint64_t need = (n_tiles + 3) / 4;
+    const uint64_t need = (u1 - u0 + 3) / 4;
     const uint64_t nb = need < (uint64_t)blocks ? need : (uint64_t)blocks;
-    hipLaunchKernelGGL(k_diff<kDiffUnroll>, dim3((unsigned)nb), dim3(256), 0, s, regs, n_regs,
-                       n_tiles, unit_flags);
+    if (nontemporal)
+        hipLaunchKernelGGL(k_diff<true>, dim3((unsigned)nb), dim3(256), 0, s, regs, n_regs, u0,
+                           u1, unit_flags);
+    else
+        hipLaunchKernelGGL(k_diff<false>, dim3((unsigned)nb), dim3(256), 0, s, regs, n_regs, u0,
+                           u1, unit_flags);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------ k_bitmap
 
+// One wave per bitmap word in [w0, w1): lane l owns global page 64w + l, ORs
+// its unit flags, and a ballot forms the word.
 __global__ __launch_bounds__(256) void k_bitmap(const DevRegion* __restrict__ regs,
-                                                uint32_t n_regs, uint64_t n_words,
+                                                uint32_t n_regs, uint64_t w0, uint64_t w1,
                                                 const uint8_t* __restrict__ unit_flags,
                                                 uint64_t* __restrict__ bitmap)
 {
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t w = (uint64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (w >= n_words)
+    const uint64_t w =
+        w0 + (uint64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (w >= w1)
         return;
     const uint64_t g = w * 64 + lane;
     const uint32_t r = find_region<3>(regs, n_regs, g);
@@ -264,8 +272,7 @@ __global__ __launch_bounds__(256) void k_bitmap(const DevRegion* __restrict__ re
     const uint64_t np = R.len >> R.page_shift;
     if (g >= R.first_page && g - R.first_page < np) {
         const uint64_t pi = g - R.first_page;
-        const uint32_t us = R.page_shift < kTileShift ? R.page_shift : kTileShift;
-        const uint32_t upp_shift = R.page_shift - us;
+        const uint32_t upp_shift = R.page_shift - R.unit_shift;
         const uint8_t* f = unit_flags + R.first_unit + (pi << upp_shift);
         uint32_t acc = 0;
         for (uint32_t i = 0; i < (1u << upp_shift); ++i)
@@ -277,20 +284,22 @@ __global__ __launch_bounds__(256) void k_bitmap(const DevRegion* __restrict__ re
         bitmap[w] = m;
 }
 
-hipError_t launch_bitmap(const DevRegion* regs, uint32_t n_regs, uint64_t n_words,
+hipError_t launch_bitmap(const DevRegion* regs, uint32_t n_regs, uint64_t w0, uint64_t w1,
                          const uint8_t* unit_flags, uint64_t* bitmap, hipStream_t s)
 {
-    if (n_words == 0)
+    if (w1 <= w0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_bitmap, dim3((unsigned)((n_words + 3) / 4)), dim3(256), 0, s, regs,
-                       n_regs, n_words, unit_flags, bitmap);
+    hipLaunchKernelGGL(k_bitmap, dim3((unsigned)((w1 - w0 + 3) / 4)), dim3(256), 0, s, regs,
+                       n_regs, w0, w1, unit_flags, bitmap);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------ k_scan
 
-__global__ __launch_bounds__(1024) void k_scan(const uint64_t* __restrict__ bitmap,
-                                               uint64_t n_words, uint32_t* __restrict__ prefix,
+__global__ __launch_bounds__(1024) void k_scan(const uint64_t* __restrict__ bitmap, uint64_t w0,
+                                               uint64_t w1, uint64_t n_words_total,
+                                               uint32_t* __restrict__ prefix,
+                                               uint64_t* __restrict__ bounds_out, int final,
                                                const DevRequest* __restrict__ reqs,
                                                uint32_t n_reqs, DevReqOut* __restrict__ out,
                                                DevGlobal* __restrict__ glob, uint64_t capacity,
@@ -299,14 +308,14 @@ __global__ __launch_bounds__(1024) void k_scan(const uint64_t* __restrict__ bitm
     constexpr int V = 4;  // words per thread per pass
     __shared__ uint32_t wave_tot[16];
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
-    uint32_t carry = 0;
-    for (uint64_t base = 0; base < n_words; base += 1024 * V) {
+    uint32_t carry = (uint32_t)glob->running;
+    for (uint64_t base = w0; base < w1; base += 1024 * V) {
         uint32_t c[V];
         uint32_t local = 0;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             const uint64_t w = base + (uint64_t)tid * V + v;
-            c[v] = w < n_words ? (uint32_t)__popcll(bitmap[w]) : 0u;
+            c[v] = w < w1 ? (uint32_t)__popcll(bitmap[w]) : 0u;
             local += c[v];
         }
         uint32_t incl = local;
@@ -329,7 +338,7 @@ __global__ __launch_bounds__(1024) void k_scan(const uint64_t* __restrict__ bitm
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             const uint64_t w = base + (uint64_t)tid * V + v;
-            if (w < n_words)
+            if (w < w1)
                 prefix[w] = excl;
             excl += c[v];
         }
@@ -340,13 +349,18 @@ __global__ __launch_bounds__(1024) void k_scan(const uint64_t* __restrict__ bitm
     __syncthreads();
     if (tid != 0)
         return;
+    glob->running = carry;
+    if (bounds_out)
+        *bounds_out = carry;
+    if (!final)
+        return;
     // per-request results, images laid out back to back (4 KiB aligned)
     uint64_t img = 0, used = 0;
     for (uint32_t q = 0; q < n_reqs; ++q) {
         const DevRequest& Q = reqs[q];
-        const uint64_t w0 = Q.first_word, w1 = Q.first_word + Q.n_words;
-        const uint64_t p0 = w0 < n_words ? prefix[w0] : carry;
-        const uint64_t p1 = w1 < n_words ? prefix[w1] : carry;
+        const uint64_t a = Q.first_word, b = Q.first_word + Q.n_words;
+        const uint64_t p0 = a < n_words_total ? prefix[a] : carry;
+        const uint64_t p1 = b < n_words_total ? prefix[b] : carry;
         const uint64_t D = p1 - p0;
         DevReqOut& O = out[q];
         O.n_dirty = D;
@@ -373,24 +387,28 @@ __global__ __launch_bounds__(1024) void k_scan(const uint64_t* __restrict__ bitm
     }
 }
 
-hipError_t launch_scan(const uint64_t* bitmap, uint64_t n_words, uint32_t* prefix,
-                       const DevRequest* reqs, uint32_t n_reqs, DevReqOut* out, DevGlobal* glob,
-                       uint64_t capacity, int restore_mode, hipStream_t s)
+hipError_t launch_scan(const uint64_t* bitmap, uint64_t w0, uint64_t w1, uint64_t n_words_total,
+                       uint32_t* prefix, uint64_t* bounds_out, int final, const DevRequest* reqs,
+                       uint32_t n_reqs, DevReqOut* out, DevGlobal* glob, uint64_t capacity,
+                       int restore_mode, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, bitmap, n_words, prefix, reqs, n_reqs,
-                       out, glob, capacity, restore_mode);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, bitmap, w0, w1, n_words_total, prefix,
+                       bounds_out, final, reqs, n_reqs, out, glob, capacity, restore_mode);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------ k_list
 
+// Ballot compaction: the lane of each set bit writes its page index at the
+// word's prefix plus the number of set bits below the lane.
 __global__ __launch_bounds__(256) void k_list(const uint64_t* __restrict__ bitmap,
-                                              const uint32_t* __restrict__ prefix,
-                                              uint64_t n_words, uint32_t* __restrict__ list)
+                                              const uint32_t* __restrict__ prefix, uint64_t w0,
+                                              uint64_t w1, uint32_t* __restrict__ list)
 {
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t w = (uint64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (w >= n_words)
+    const uint64_t w =
+        w0 + (uint64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (w >= w1)
         return;
     const uint64_t m = bitmap[w];
     if (m == 0)
@@ -401,26 +419,40 @@ __global__ __launch_bounds__(256) void k_list(const uint64_t* __restrict__ bitma
         list[prefix[w] + below] = (uint32_t)(w * 64 + lane);
 }
 
-hipError_t launch_list(const uint64_t* bitmap, const uint32_t* prefix, uint64_t n_words,
+hipError_t launch_list(const uint64_t* bitmap, const uint32_t* prefix, uint64_t w0, uint64_t w1,
                        uint32_t* list, hipStream_t s)
 {
-    if (n_words == 0)
+    if (w1 <= w0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_list, dim3((unsigned)((n_words + 3) / 4)), dim3(256), 0, s, bitmap,
-                       prefix, n_words, list);
+    hipLaunchKernelGGL(k_list, dim3((unsigned)((w1 - w0 + 3) / 4)), dim3(256), 0, s, bitmap,
+                       prefix, w0, w1, list);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------ k_pack / verify
 
+__device__ __forceinline__ void slot_range(const SlotRange& sr, uint64_t* lo, uint64_t* hi)
+{
+    if (sr.bounds) {
+        *lo = sr.chunk ? sr.bounds[sr.chunk - 1] : 0;
+        *hi = sr.bounds[sr.chunk];
+    } else {
+        *lo = sr.lo;
+        *hi = sr.hi;
+    }
+}
+
 // Work item = (slot, piece); pieces per slot = 2^np_shift for the launch.
+// Pack: copy the dirty page into the image's page area (and the shadow) and
+// write its CRC to crc_out[slot].  Verify: recompute the CRC of a packed page
+// of the image and compare with the image's CRC array.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs, uint32_t n_regs,
                                               const DevRequest* __restrict__ reqs,
                                               const DevReqOut* __restrict__ out,
-                                              const uint32_t* __restrict__ list, uint64_t slot0,
-                                              uint64_t n_items, uint32_t np_shift,
-                                              uint8_t* __restrict__ staging, int update_shadow,
+                                              const uint32_t* __restrict__ list, SlotRange sr,
+                                              uint32_t np_shift, uint8_t* __restrict__ staging,
+                                              int update_shadow, uint32_t* __restrict__ crc_out,
                                               uint32_t* __restrict__ partials,
                                               const CrcTables* __restrict__ tabs,
                                               DevGlobal* __restrict__ glob)
@@ -428,9 +460,15 @@ __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs
     __shared__ uint32_t lds[kTabWords];
     if (MODE == kModeVerify && glob->fmt_bad)
         return;
+    uint64_t slot0, slot1;
+    slot_range(sr, &slot0, &slot1);
+    const uint64_t n_items = (slot1 - slot0) << np_shift;
+    if (n_items == 0)
+        return;
     load_tables(lds, tabs, kTabWords);
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t wave = (uint64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t wave =
+        (uint64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t n_waves = (uint64_t)gridDim.x * 4;
     uint32_t r = 0;
     uint64_t r_lo = 1, r_hi = 0;
@@ -476,55 +514,60 @@ __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs
             partials[item] = raw;
             continue;
         }
-        uint32_t* crc_ptr =
-            reinterpret_cast<uint32_t*>(img + Q.data_off + (O.n_dirty << ps)) + local;
         const uint32_t crc = raw ^ Q.init_fix;
-        if (MODE == kModePack)
-            *crc_ptr = crc;
-        else if (crc != *crc_ptr)
-            atomicMin(&glob->crc_bad, (uint32_t)local);
+        if (MODE == kModePack) {
+            crc_out[k] = crc;
+        } else {
+            const uint32_t* img_crc =
+                reinterpret_cast<const uint32_t*>(img + Q.data_off + (O.n_dirty << ps));
+            if (crc != img_crc[local])
+                atomicMin(&glob->crc_bad, (uint32_t)local);
+        }
     }
 }
 
 hipError_t launch_pack(int mode, const DevRegion* regs, uint32_t n_regs, const DevRequest* reqs,
-                       const DevReqOut* out, const uint32_t* list, uint64_t slot0,
-                       uint64_t slot1, uint32_t np_shift, uint8_t* staging, int update_shadow,
-                       uint32_t* partials, const CrcTables* tabs, DevGlobal* glob, int blocks,
-                       hipStream_t s)
+                       const DevReqOut* out, const uint32_t* list, SlotRange range,
+                       uint32_t np_shift, uint8_t* staging, int update_shadow,
+                       uint32_t* crc_out, uint32_t* partials, const CrcTables* tabs,
+                       DevGlobal* glob, int blocks, hipStream_t s)
 {
-    if (slot1 <= slot0)
+    const uint64_t max_items = range.max_slots << np_shift;
+    if (max_items == 0)
         return hipSuccess;
-    const uint64_t n_items = (slot1 - slot0) << np_shift;
-    const uint64_t need = (n_items + 3) / 4;
+    const uint64_t need = (max_items + 3) / 4;
     const uint64_t nb = need < (uint64_t)blocks ? need : (uint64_t)blocks;
     if (mode == kModePack)
         hipLaunchKernelGGL(k_pack<kModePack>, dim3((unsigned)nb), dim3(256), 0, s, regs, n_regs,
-                           reqs, out, list, slot0, n_items, np_shift, staging, update_shadow,
+                           reqs, out, list, range, np_shift, staging, update_shadow, crc_out,
                            partials, tabs, glob);
     else
         hipLaunchKernelGGL(k_pack<kModeVerify>, dim3((unsigned)nb), dim3(256), 0, s, regs,
-                           n_regs, reqs, out, list, slot0, n_items, np_shift, staging, 0,
+                           n_regs, reqs, out, list, range, np_shift, staging, 0, crc_out,
                            partials, tabs, glob);
     return hipGetLastError();
 }
 
 // One thread per slot: combine the slot's piece CRCs (pages above 64 KiB).
+// partials are indexed by the item of the matching pack launch.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_finalize(const DevRegion* __restrict__ regs,
                                                   uint32_t n_regs,
                                                   const DevRequest* __restrict__ reqs,
                                                   const DevReqOut* __restrict__ out,
                                                   const uint32_t* __restrict__ list,
-                                                  uint64_t slot0, uint64_t n_slots,
-                                                  uint32_t np_shift,
+                                                  SlotRange sr, uint32_t np_shift,
                                                   const uint32_t* __restrict__ partials,
+                                                  uint32_t* __restrict__ crc_out,
                                                   uint8_t* __restrict__ staging,
                                                   DevGlobal* __restrict__ glob)
 {
     if (MODE == kModeVerify && glob->fmt_bad)
         return;
+    uint64_t slot0, slot1;
+    slot_range(sr, &slot0, &slot1);
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_slots)
+    if (i >= slot1 - slot0)
         return;
     const uint64_t k = slot0 + i;
     const uint64_t g = list[k];
@@ -541,34 +584,32 @@ __global__ __launch_bounds__(256) void k_finalize(const DevRegion* __restrict__ 
     uint32_t s = 0;
     for (uint32_t j = 0; j < np; ++j)
         s = gf2_mulmod(s, K) ^ partials[(i << np_shift) + j];
-    const uint64_t local = k - O.slot_base;
-    uint32_t* crc_ptr = reinterpret_cast<uint32_t*>(staging + O.img_base + Q.data_off +
-                                                    (O.n_dirty << ps)) +
-                        local;
     const uint32_t crc = s ^ Q.init_fix;
-    if (MODE == kModePack)
-        *crc_ptr = crc;
-    else if (crc != *crc_ptr)
-        atomicMin(&glob->crc_bad, (uint32_t)local);
+    if (MODE == kModePack) {
+        crc_out[k] = crc;
+    } else {
+        const uint64_t local = k - O.slot_base;
+        const uint32_t* img_crc = reinterpret_cast<const uint32_t*>(
+            staging + O.img_base + Q.data_off + (O.n_dirty << ps));
+        if (crc != img_crc[local])
+            atomicMin(&glob->crc_bad, (uint32_t)local);
+    }
 }
 
 hipError_t launch_finalize(int mode, const DevRegion* regs, uint32_t n_regs,
                            const DevRequest* reqs, const DevReqOut* out, const uint32_t* list,
-                           uint64_t slot0, uint64_t slot1, uint32_t np_shift,
-                           const uint32_t* partials, uint8_t* staging, DevGlobal* glob,
-                           hipStream_t s)
+                           SlotRange range, uint32_t np_shift, const uint32_t* partials,
+                           uint32_t* crc_out, uint8_t* staging, DevGlobal* glob, hipStream_t s)
 {
-    if (slot1 <= slot0 || np_shift == 0)
+    if (range.max_slots == 0 || np_shift == 0)
         return hipSuccess;
-    const uint64_t n = slot1 - slot0;
+    const unsigned nb = (unsigned)((range.max_slots + 255) / 256);
     if (mode == kModePack)
-        hipLaunchKernelGGL(k_finalize<kModePack>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                           s, regs, n_regs, reqs, out, list, slot0, n, np_shift, partials, staging,
-                           glob);
+        hipLaunchKernelGGL(k_finalize<kModePack>, dim3(nb), dim3(256), 0, s, regs, n_regs, reqs,
+                           out, list, range, np_shift, partials, crc_out, staging, glob);
     else
-        hipLaunchKernelGGL(k_finalize<kModeVerify>, dim3((unsigned)((n + 255) / 256)), dim3(256),
-                           0, s, regs, n_regs, reqs, out, list, slot0, n, np_shift, partials,
-                           staging, glob);
+        hipLaunchKernelGGL(k_finalize<kModeVerify>, dim3(nb), dim3(256), 0, s, regs, n_regs,
+                           reqs, out, list, range, np_shift, partials, crc_out, staging, glob);
     return hipGetLastError();
 }
 
@@ -627,6 +668,7 @@ __global__ __launch_bounds__(256) void k_header(const DevRegion* __restrict__ re
                                                 const DevRequest* __restrict__ reqs,
                                                 const DevReqOut* __restrict__ out,
                                                 const uint64_t* __restrict__ bitmap,
+                                                const uint32_t* __restrict__ crcs,
                                                 uint8_t* __restrict__ staging,
                                                 const CrcTables* __restrict__ tabs)
 {
@@ -660,8 +702,13 @@ __global__ __launch_bounds__(256) void k_header(const DevRegion* __restrict__ re
     for (uint64_t o = prefix_end + 8 * tid; o < Q.data_off; o += 8 * blockDim.x)
         *reinterpret_cast<uint64_t*>(img + o) = 0;
     const bool ok = O.code == 0;
-    if (ok && tid == 0 && (D & 1))
-        *reinterpret_cast<uint32_t*>(img + Q.data_off + (D << Q.page_shift) + 4 * D) = 0;
+    if (ok) {
+        uint32_t* dst = reinterpret_cast<uint32_t*>(img + Q.data_off + (D << Q.page_shift));
+        for (uint64_t k = tid; k < D; k += blockDim.x)
+            dst[k] = crcs[O.slot_base + k];
+        if (tid == 0 && (D & 1))
+            dst[D] = 0;
+    }
     __syncthreads();
     uint32_t* h32 = reinterpret_cast<uint32_t*>(img);
     uint64_t* h64 = reinterpret_cast<uint64_t*>(img);
@@ -691,13 +738,13 @@ __global__ __launch_bounds__(256) void k_header(const DevRegion* __restrict__ re
 }
 
 hipError_t launch_header(const DevRegion* regs, const DevRequest* reqs, uint32_t n_reqs,
-                         const DevReqOut* out, const uint64_t* bitmap, uint32_t,
+                         const DevReqOut* out, const uint64_t* bitmap, const uint32_t* crcs,
                          uint8_t* staging, const CrcTables* tabs, hipStream_t s)
 {
     if (n_reqs == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_header, dim3(n_reqs), dim3(256), 0, s, regs, reqs, out, bitmap, staging,
-                       tabs);
+    hipLaunchKernelGGL(k_header, dim3(n_reqs), dim3(256), 0, s, regs, reqs, out, bitmap, crcs,
+                       staging, tabs);
     return hipGetLastError();
 }
 

@@ -1,0 +1,177 @@
+"""Minimal HIP runtime plumbing without torch: device and pinned buffers,
+streams, events and graph capture through ctypes.
+
+It binds the HIP runtime that libcrum itself is linked against.  In a process
+that never imports torch this is the system ROCm runtime, which executes
+device-to-host hipMemcpyAsync on the SDMA copy engines; torch wheels bundle
+their own runtime, whose device-to-host copies run as blit kernels on the
+compute units.  Argument marshalling only.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+from . import _lib
+
+_hip = None
+
+hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice = 1, 2, 3
+hipStreamNonBlocking = 1
+hipStreamCaptureModeGlobal = 0
+
+
+def hip():
+    global _hip
+    if _hip is None:
+        _lib.lib()  # resolves libamdhip64 through libcrum's own dependency
+        h = ctypes.CDLL("libamdhip64.so.7")
+        V, S, I = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+        sigs = {
+            "hipMalloc": [ctypes.POINTER(V), S],
+            "hipFree": [V],
+            "hipHostMalloc": [ctypes.POINTER(V), S, ctypes.c_uint],
+            "hipHostFree": [V],
+            "hipMemcpy": [V, V, S, I],
+            "hipMemcpyAsync": [V, V, S, I, V],
+            "hipMemsetAsync": [V, I, S, V],
+            "hipMemset": [V, I, S],
+            "hipStreamCreateWithFlags": [ctypes.POINTER(V), ctypes.c_uint],
+            "hipStreamDestroy": [V],
+            "hipStreamSynchronize": [V],
+            "hipDeviceSynchronize": [],
+            "hipEventCreate": [ctypes.POINTER(V)],
+            "hipEventDestroy": [V],
+            "hipEventRecord": [V, V],
+            "hipEventSynchronize": [V],
+            "hipEventElapsedTime": [ctypes.POINTER(ctypes.c_float), V, V],
+            "hipStreamBeginCapture": [V, I],
+            "hipStreamEndCapture": [V, ctypes.POINTER(V)],
+            "hipGraphInstantiate": [ctypes.POINTER(V), V, V, V, S],
+            "hipGraphLaunch": [V, V],
+            "hipGraphExecDestroy": [V],
+            "hipGraphDestroy": [V],
+            "hipGetDeviceCount": [ctypes.POINTER(I)],
+            "hipMemGetInfo": [ctypes.POINTER(S), ctypes.POINTER(S)],
+        }
+        for name, args in sigs.items():
+            f = getattr(h, name)
+            f.restype = ctypes.c_int
+            f.argtypes = args
+        _hip = h
+    return _hip
+
+
+def check(rc: int, what: str) -> None:
+    if rc != 0:
+        raise RuntimeError(f"{what} failed with hipError {rc}")
+
+
+def device_count() -> int:
+    n = ctypes.c_int(0)
+    if hip().hipGetDeviceCount(ctypes.byref(n)) != 0:
+        return 0
+    return n.value
+
+
+class DeviceBuffer:
+    def __init__(self, nbytes: int):
+        p = ctypes.c_void_p()
+        check(hip().hipMalloc(ctypes.byref(p), max(nbytes, 16)), f"hipMalloc({nbytes})")
+        self.ptr, self.nbytes = p.value, nbytes
+
+    def free(self) -> None:
+        if self.ptr:
+            hip().hipFree(self.ptr)
+            self.ptr = 0
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class PinnedBuffer:
+    def __init__(self, nbytes: int):
+        p = ctypes.c_void_p()
+        check(hip().hipHostMalloc(ctypes.byref(p), max(nbytes, 16), 0), f"hipHostMalloc({nbytes})")
+        self.ptr, self.nbytes = p.value, nbytes
+
+    def numpy(self, n: Optional[int] = None):
+        import numpy as np
+        n = self.nbytes if n is None else n
+        return np.ctypeslib.as_array((ctypes.c_uint8 * n).from_address(self.ptr))
+
+    def free(self) -> None:
+        if self.ptr:
+            hip().hipHostFree(self.ptr)
+            self.ptr = 0
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Stream:
+    def __init__(self):
+        s = ctypes.c_void_p()
+        check(hip().hipStreamCreateWithFlags(ctypes.byref(s), hipStreamNonBlocking),
+              "hipStreamCreateWithFlags")
+        self.handle = s.value
+
+    def synchronize(self) -> None:
+        check(hip().hipStreamSynchronize(self.handle), "hipStreamSynchronize")
+
+
+class Event:
+    def __init__(self):
+        e = ctypes.c_void_p()
+        check(hip().hipEventCreate(ctypes.byref(e)), "hipEventCreate")
+        self.handle = e.value
+
+    def record(self, stream: Stream) -> None:
+        check(hip().hipEventRecord(self.handle, stream.handle), "hipEventRecord")
+
+    def elapsed_ms(self, end: "Event") -> float:
+        check(hip().hipEventSynchronize(end.handle), "hipEventSynchronize")
+        ms = ctypes.c_float()
+        check(hip().hipEventElapsedTime(ctypes.byref(ms), self.handle, end.handle),
+              "hipEventElapsedTime")
+        return ms.value
+
+
+class Graph:
+    """Capture work issued by `fn(stream)` on `stream` into an executable graph."""
+
+    def __init__(self, stream: Stream, fn):
+        h = hip()
+        check(h.hipStreamBeginCapture(stream.handle, hipStreamCaptureModeGlobal),
+              "hipStreamBeginCapture")
+        fn(stream)
+        g = ctypes.c_void_p()
+        check(h.hipStreamEndCapture(stream.handle, ctypes.byref(g)), "hipStreamEndCapture")
+        ex = ctypes.c_void_p()
+        check(h.hipGraphInstantiate(ctypes.byref(ex), g, None, None, 0), "hipGraphInstantiate")
+        self.graph, self.exec = g.value, ex.value
+
+    def launch(self, stream: Stream) -> None:
+        check(hip().hipGraphLaunch(self.exec, stream.handle), "hipGraphLaunch")
+
+
+def device_synchronize() -> None:
+    check(hip().hipDeviceSynchronize(), "hipDeviceSynchronize")
+
+
+def memcpy_dtoh(dst_host: int, src_dev: int, n: int) -> None:
+    check(hip().hipMemcpy(dst_host, src_dev, n, hipMemcpyDeviceToHost), "hipMemcpy D2H")
+
+
+def memcpy_dtod(dst: int, src: int, n: int) -> None:
+    check(hip().hipMemcpy(dst, src, n, hipMemcpyDeviceToDevice), "hipMemcpy D2D")
+
+
+def memcpy_htod(dst_dev: int, src_host: int, n: int) -> None:
+    check(hip().hipMemcpy(dst_dev, src_host, n, hipMemcpyHostToDevice), "hipMemcpy H2D")

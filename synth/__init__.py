@@ -22,4 +22,5 @@ from .lib import (  # noqa: F401
     fill_dev,
     mutate_dev,
     saxpy_loop_dev,
+    copy_dev,
 )

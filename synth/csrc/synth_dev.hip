@@ -68,6 +68,16 @@ __global__ void synth_mutate_kernel(uint8_t* __restrict__ region_bytes, uint64_t
     }
 }
 
+// Plain 16-byte copy of n16 words (a copy kernel of known size, used to
+// calibrate hardware byte counters).
+__global__ void synth_copy_kernel(uint4* __restrict__ dst, const uint4* __restrict__ src,
+                                  uint64_t n16)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+        dst[i] = src[i];
+}
+
 // y <- a*x + y, repeated `iters` times over n elements (the co-running
 // compute kernel of the many-allocations workload).
 __global__ void synth_saxpy_loop_kernel(float* __restrict__ y, const float* __restrict__ x,
@@ -111,6 +121,17 @@ int synth_mutate_dev(void* region_bytes, uint64_t page_size, const int64_t* d_pa
     hipLaunchKernelGGL(synth_mutate_kernel, dim3((unsigned)blocks), dim3(256), 0,
                        (hipStream_t)stream, (uint8_t*)region_bytes, page_size, d_pages, n_pages,
                        kind, ms, region);
+    return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+int synth_copy_dev(void* dst, const void* src, uint64_t nbytes, void* stream)
+{
+    if (((uintptr_t)dst & 15) || ((uintptr_t)src & 15) || (nbytes & 15))
+        return -1;
+    if (nbytes == 0)
+        return 0;
+    hipLaunchKernelGGL(synth_copy_kernel, dim3(4096), dim3(256), 0, (hipStream_t)stream,
+                       (uint4*)dst, (const uint4*)src, nbytes >> 4);
     return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 

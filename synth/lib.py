@@ -79,6 +79,9 @@ def dev_lib():
         lib.synth_mutate_dev.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                                          ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64,
                                          ctypes.c_uint64, ctypes.c_void_p]
+        lib.synth_copy_dev.restype = ctypes.c_int
+        lib.synth_copy_dev.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                       ctypes.c_void_p]
         lib.synth_saxpy_loop.restype = ctypes.c_int
         lib.synth_saxpy_loop.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_float,
                                          ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
@@ -135,6 +138,11 @@ def mutate_dev(ptr: int, region_bytes: int, page_size: int, d_pages_ptr: int, n_
         raise ValueError("mutated page beyond region end")
     _check(dev_lib().synth_mutate_dev(ptr, page_size, d_pages_ptr, n_pages, kind, ms, region,
                                       stream), "synth_mutate_dev")
+
+
+def copy_dev(dst: int, src: int, nbytes: int, stream: int = 0) -> None:
+    """Plain device copy kernel (16-byte aligned pointers and size)."""
+    _check(dev_lib().synth_copy_dev(dst, src, nbytes, stream), "synth_copy_dev")
 
 
 def saxpy_loop_dev(y_ptr: int, x_ptr: int, a: float, n: int, iters: int, blocks: int,

@@ -24,6 +24,19 @@ def snap():
     s.close()
 
 
+@pytest.fixture(scope="module")
+def snap_small_chunks():
+    """A context that pipelines in 64-page chunks, to cover multi-chunk runs."""
+    import paper_1808_00117_amd as crum
+    from paper_1808_00117_amd.api import Snapshotter
+    s = Snapshotter(0)
+    crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_CHUNK_BYTES, 1)
+    crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_CHUNK_MAX_BYTES, 1)
+    crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_DRAIN_CHUNK_BYTES, 1)
+    yield s
+    s.close()
+
+
 def host_case(counts, P, dirty, seed, null_shadow=(), where="random"):
     rng = np.random.default_rng(seed)
     regs = []
@@ -40,19 +53,27 @@ def host_case(counts, P, dirty, seed, null_shadow=(), where="random"):
     return regs
 
 
-def check_parity(snap, host_regs, P, seq=3, flags=0):
+def check_parity(snap, host_regs, P, seq=3, flags=0, others=()):
+    """Snapshot on the GPU and compare every image byte with the oracle: with
+    capacity for every page (chunk-pipelined order), with exactly the image's
+    capacity (diff-first order), and on any further contexts given."""
     st_o, img_o, bm_o = oracle.snapshot(host_regs, P, seq=seq)
     assert st_o.code == oracle.OK
     dev = upload(host_regs)
-    rc, st, img, _ = gpu_snapshot(snap, dev, P, seq=seq, flags=flags)
-    assert rc == 0
-    assert st.code == 0, st
-    assert (st.n_dirty, st.total_pages, st.image_bytes) == \
-        (st_o.n_dirty, st_o.total_pages, st_o.image_bytes)
-    assert img.size == img_o.size
-    if not np.array_equal(img, img_o):
-        bad = np.flatnonzero(img != img_o)
-        raise AssertionError(f"image differs at {bad.size} bytes, first {bad[:8]}")
+    runs = [(snap, None), (snap, st_o.image_bytes)] + [(o, None) for o in others]
+    img = None
+    for ctx, cap in runs:
+        rc, st, img, _ = gpu_snapshot(ctx, dev, P, seq=seq, flags=flags, staging_bytes=cap,
+                                      image_bytes=cap)
+        assert rc == 0
+        assert st.code == 0, (cap, st)
+        assert (st.n_dirty, st.total_pages, st.image_bytes) == \
+            (st_o.n_dirty, st_o.total_pages, st_o.image_bytes)
+        assert img.size == img_o.size
+        if not np.array_equal(img, img_o):
+            bad = np.flatnonzero(img != img_o)
+            raise AssertionError(f"capacity {cap}: image differs at {bad.size} bytes, "
+                                 f"first {bad[:8]}")
     return dev, img
 
 
@@ -73,17 +94,17 @@ CASES = [
 
 
 @pytest.mark.parametrize("name,counts,P,dirty,nulls", CASES, ids=[c[0] for c in CASES])
-def test_snapshot_parity_edges(snap, name, counts, P, dirty, nulls):
+def test_snapshot_parity_edges(snap, snap_small_chunks, name, counts, P, dirty, nulls):
     G = sum(counts)
     if dirty == "all":
         dirty = set(range(G))
     log(f"[parity] {name} counts={counts} P={P} dirty={len(dirty)}")
     for where in ("first", "last", "random"):
         regs = host_case(counts, P, dirty, seed=G + P, null_shadow=nulls, where=where)
-        check_parity(snap, regs, P)
+        check_parity(snap, regs, P, others=(snap_small_chunks,))
 
 
-def test_snapshot_parity_random_sets(snap):
+def test_snapshot_parity_random_sets(snap, snap_small_chunks):
     rng = np.random.default_rng(77)
     for trial in range(6):
         counts = tuple(int(x) for x in rng.integers(0, 200, int(rng.integers(1, 8))))
@@ -92,7 +113,8 @@ def test_snapshot_parity_random_sets(snap):
         dirty = set(int(x) for x in rng.choice(max(G, 1), size=int(rng.integers(0, G + 1)),
                                                replace=False)) if G else set()
         log(f"[parity] random trial={trial} counts={counts} P={P} D={len(dirty)}")
-        check_parity(snap, host_case(counts, P, dirty, seed=trial), P, seq=trial)
+        check_parity(snap, host_case(counts, P, dirty, seed=trial), P, seq=trial,
+                     others=(snap_small_chunks,))
 
 
 def test_many_regions(snap):
@@ -105,13 +127,13 @@ def test_many_regions(snap):
     check_parity(snap, host_case((1,) * R, P, dirty, seed=9), P)
 
 
-def test_multi_chunk_drain(snap):
+def test_multi_chunk_drain(snap, snap_small_chunks):
     # D*P well above the first 8 MiB drain chunk: several pack/drain chunks
     P = 64 * KiB
     counts = (700,)
     dirty = set(range(0, 700, 2))
     log("[parity] multi-chunk drain, 350 x 64 KiB dirty")
-    check_parity(snap, host_case(counts, P, dirty, seed=21), P)
+    check_parity(snap, host_case(counts, P, dirty, seed=21), P, others=(snap_small_chunks,))
 
 
 def test_plain_64mib_scenario(snap):
@@ -133,10 +155,12 @@ def test_plain_64mib_scenario(snap):
         assert np.array_equal(dev[i][1].cpu().numpy(), sh), "device mutation != host mutation"
     st_o, img_o, bm_o = oracle.snapshot(host, s.page_size, seq=11)
     assert st_o.n_dirty == 819
-    rc, st, img, _ = gpu_snapshot(snap, [(c, h, r.id) for (c, h), r in zip(dev, s.regions)],
-                                  s.page_size, seq=11)
-    assert rc == 0 and st.code == 0 and st.n_dirty == 819
-    assert np.array_equal(img, img_o)
+    regs = [(c, h, r.id) for (c, h), r in zip(dev, s.regions)]
+    for cap in (None, st_o.image_bytes):
+        rc, st, img, _ = gpu_snapshot(snap, regs, s.page_size, seq=11, staging_bytes=cap,
+                                      image_bytes=cap)
+        assert rc == 0 and st.code == 0 and st.n_dirty == 819
+        assert np.array_equal(img, img_o)
 
 
 def test_restore_roundtrip_and_update_shadow(snap):
@@ -152,8 +176,10 @@ def test_restore_roundtrip_and_update_shadow(snap):
     assert rc == 0 and st.code == 0, st
     for (t, _, _), (c, _, _) in zip(targets, dev):
         assert torch.equal(t, c)
-    # snapshot with shadow update; then a re-snapshot is empty
-    rc, st, _, _ = gpu_snapshot(snap, dev, P, flags=1)
+    # snapshot with shadow update (diff-first order); then a re-snapshot is empty
+    st_o = oracle.snapshot(host, P)[0]
+    rc, st, _, _ = gpu_snapshot(snap, dev, P, flags=1, staging_bytes=st_o.image_bytes,
+                                image_bytes=st_o.image_bytes)
     assert st.code == 0 and st.n_dirty == len(range(0, 70, 3))
     for c, sh, _ in dev:
         assert torch.equal(c, sh)
@@ -277,3 +303,52 @@ def test_empty_table(snap):
     assert rc == 0 and st.code == 0 and st.image_bytes == 4096
     _, img_o, _ = oracle.snapshot([], 4096, seq=5)
     assert np.array_equal(h[:4096].numpy(), img_o)
+
+
+def test_update_shadow_pipelined(snap_small_chunks):
+    import torch
+    P = 8 * KiB
+    host = host_case((100, 70), P, set(range(3, 170, 5)), seed=33)
+    dev, img = check_parity(snap_small_chunks, host, P)
+    rc, st, _, _ = gpu_snapshot(snap_small_chunks, dev, P, flags=1)
+    assert st.code == 0 and st.n_dirty == len(range(3, 170, 5))
+    for c, sh, _ in dev:
+        assert torch.equal(c, sh)
+    rc, st, _, _ = gpu_snapshot(snap_small_chunks, dev, P)
+    assert st.code == 0 and st.n_dirty == 0
+
+
+def test_param_api(snap):
+    import paper_1808_00117_amd as crum
+    for p in (crum.CRUM_PARAM_DIFF_BLOCKS, crum.CRUM_PARAM_PACK_BLOCKS,
+              crum.CRUM_PARAM_CHUNK_BYTES, crum.CRUM_PARAM_CHUNK_MAX_BYTES,
+              crum.CRUM_PARAM_DRAIN_CHUNK_BYTES):
+        old = crum.crum_ctx_get_param(snap.ctx, p)
+        with pytest.raises(ValueError):
+            crum.crum_ctx_set_param(snap.ctx, p, 0)
+        crum.crum_ctx_set_param(snap.ctx, p, old)
+    with pytest.raises(ValueError):
+        crum.crum_ctx_set_param(snap.ctx, crum.CRUM_PARAM_EAGER, 2)
+    with pytest.raises(ValueError):
+        crum.crum_ctx_set_param(snap.ctx, 999, 1)
+
+
+@pytest.mark.parametrize("unit_shift", [12, 13, 14])
+@pytest.mark.parametrize("nt", [0, 1])
+def test_diff_variants(unit_shift, nt):
+    """Every diff unit size and load kind gives the oracle's image."""
+    import paper_1808_00117_amd as crum
+    from paper_1808_00117_amd.api import Snapshotter
+    s = Snapshotter(0)
+    try:
+        crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_DIFF_UNIT_SHIFT, unit_shift)
+        crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_DIFF_NONTEMPORAL, nt)
+        crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_DIFF_BLOCKS, 7)
+        for P, counts in [(4 * KiB, (37, 70)), (8 * KiB, (9, 60)), (32 * KiB, (13, 5)),
+                          (64 * KiB, (6,))]:
+            G = sum(counts)
+            dirty = set(range(0, G, 3)) | {G - 1}
+            for where in ("first", "last"):
+                check_parity(s, host_case(counts, P, dirty, seed=P + G, where=where), P)
+    finally:
+        s.close()
