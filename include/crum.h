@@ -151,6 +151,63 @@ int crum_restore(crum_ctx* ctx, const crum_region* regions, uint32_t n_regions,
                  const void* h_image, uint64_t image_bytes, uint32_t flags, void* d_staging,
                  uint64_t staging_bytes, void* stream, crum_status* h_status);
 
+/* ---------------------------------------------------------------- batched
+ * Many snapshot requests in one plan (the batched pattern).  Each request is a
+ * region table with its own page size, flags (CRUM_UPDATE_SHADOW) and seq,
+ * and produces exactly the image that crum_snapshot would produce for it.
+ * Requests are grouped in order (groups of whole requests, scanned bytes per
+ * group starting at CRUM_PARAM_CHUNK_BYTES and doubling up to
+ * CRUM_PARAM_CHUNK_MAX_BYTES); each group's device work -- one persistent diff
+ * over all units of its requests, bitmap, scan, compaction, pack with CRCs and
+ * headers -- is captured once as a HIP graph at plan creation.  Request images
+ * are laid out back to back in d_staging (each at a 4 KiB-aligned offset) and
+ * copied to the same offsets of h_images, one contiguous copy per group on the
+ * context's side stream as soon as the group is done. */
+typedef struct {
+    const crum_region* regions; /* caller-owned, read at plan creation */
+    uint32_t n_regions;
+    uint32_t page_size;
+    uint32_t flags;             /* CRUM_UPDATE_SHADOW or 0 */
+    uint32_t reserved;          /* 0 */
+    uint64_t seq;
+} crum_request;
+
+/* Per-request result of a plan launch; image_offset is the byte offset of
+ * the request's image in d_staging and h_images. */
+typedef struct {
+    crum_status status;
+    uint64_t image_offset;
+} crum_request_status;
+
+/* Validate the requests (as crum_snapshot does, and all current and shadow
+ * ranges of all requests pairwise disjoint), flatten them, upload the tables
+ * and capture the group graphs, using the context's current parameters.  The
+ * plan keeps the region pointers, d_staging and h_images (pinned host memory
+ * or NULL).  If the images of a group do not fit the capacity
+ * (min(staging_bytes, h_images_bytes)), that group and every later group
+ * report CRUM_ENOSPC and write no page, CRC or shadow.
+ * Returns CRUM_OK, CRUM_EINVAL or CRUM_EHIP. */
+int crum_plan_create(crum_ctx* ctx, const crum_request* reqs, uint32_t n_reqs, void* d_staging,
+                     uint64_t staging_bytes, void* h_images, uint64_t h_images_bytes,
+                     crum_plan** out);
+
+/* Snapshot every request of the plan: launch the group graphs on `stream`,
+ * and drain each group behind it (the calling thread waits for each group's
+ * end to size its copy).  h_status: pinned array of n_reqs entries, valid
+ * once `stream` passes the launch.  Calls on one plan must not overlap. */
+int crum_plan_launch(crum_plan* plan, void* stream, crum_request_status* h_status);
+
+/* Group layout: n_groups, and first_request[0..n_groups] (group g holds
+ * requests [first_request[g], first_request[g+1])), up to cap entries. */
+int crum_plan_groups(crum_plan* plan, uint32_t* n_groups, uint32_t* first_request, uint32_t cap);
+
+/* For the last launch: milliseconds from its start to the end of each
+ * group's drain (waits for them), up to cap entries. */
+int crum_plan_group_times(crum_plan* plan, double* ms, uint32_t cap);
+
+/* Destroy a plan (waits for its outstanding work). NULL is ignored. */
+void crum_plan_destroy(crum_plan* plan);
+
 /* Launch and pipeline parameters of a context (defaults in parentheses).
  * CRUM_PARAM_DIFF_BLOCKS: persistent grid of the diff kernel, in 256-thread
  *   workgroups (4 per compute unit).  CRUM_PARAM_PACK_BLOCKS: grid of the

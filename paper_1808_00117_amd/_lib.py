@@ -38,6 +38,16 @@ class crum_status(ctypes.Structure):
                 ("image_bytes", ctypes.c_uint64)]
 
 
+class crum_request(ctypes.Structure):
+    _fields_ = [("regions", ctypes.c_void_p), ("n_regions", ctypes.c_uint32),
+                ("page_size", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("seq", ctypes.c_uint64)]
+
+
+class crum_request_status(ctypes.Structure):
+    _fields_ = [("status", crum_status), ("image_offset", ctypes.c_uint64)]
+
+
 _P = ctypes.c_void_p
 _U32, _U64, _I = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
 _SIGS = {
@@ -47,6 +57,11 @@ _SIGS = {
     "crum_image_bytes": (_I, [_U32, _U64, _U64, _U32, ctypes.POINTER(_U64)]),
     "crum_snapshot": (_I, [_P, _P, _U32, _U32, _U32, _U64, _P, _U64, _P, _U64, _P, _P]),
     "crum_restore": (_I, [_P, _P, _U32, _P, _U64, _U32, _P, _U64, _P, _P]),
+    "crum_plan_create": (_I, [_P, _P, _U32, _P, _U64, _P, _U64, ctypes.POINTER(_P)]),
+    "crum_plan_launch": (_I, [_P, _P, _P]),
+    "crum_plan_groups": (_I, [_P, ctypes.POINTER(_U32), _P, _U32]),
+    "crum_plan_group_times": (_I, [_P, _P, _U32]),
+    "crum_plan_destroy": (None, [_P]),
     "crum_ctx_set_param": (_I, [_P, _I, _U64]),
     "crum_ctx_get_param": (_I, [_P, _I, ctypes.POINTER(_U64)]),
     "crum_ctx_set_timing": (_I, [_P, _I]),
@@ -126,6 +141,66 @@ def crum_restore(ctx: int, regions, h_image: int, image_bytes: int, flags: int,
     return lib().crum_restore(ctx, ctypes.cast(arr, _P) if n else None, n, h_image or None,
                               image_bytes, flags, d_staging, staging_bytes, stream or None,
                               h_status)
+
+
+class Plan:
+    """Owns a crum_plan and the ctypes arrays it was created from.
+
+    requests: sequence of (regions, page_size, flags, seq) where regions is a
+    sequence of (base, shadow, len, id)."""
+
+    def __init__(self, ctx: int, requests, d_staging: int, staging_bytes: int, h_images: int,
+                 h_images_bytes: int):
+        self._tables = [region_table(regs) for regs, _, _, _ in requests]
+        self.n = len(requests)
+        arr = (crum_request * max(1, self.n))()
+        for i, ((regs, ps, flags, seq), tab) in enumerate(zip(requests, self._tables)):
+            arr[i] = crum_request(ctypes.cast(tab, _P) if len(regs) else None, len(regs), ps,
+                                  flags, 0, seq)
+        self._reqs = arr
+        h = _P()
+        rc = lib().crum_plan_create(ctx, ctypes.cast(arr, _P) if self.n else None, self.n,
+                                    d_staging, staging_bytes, h_images or None, h_images_bytes,
+                                    ctypes.byref(h))
+        if rc != CRUM_OK:
+            raise RuntimeError(f"crum_plan_create: {CODE_NAMES.get(rc, rc)}")
+        self.handle = h.value
+
+    def launch(self, stream: int, h_status: int) -> int:
+        return lib().crum_plan_launch(self.handle, stream or None, h_status)
+
+    def groups(self):
+        n = _U32()
+        lib().crum_plan_groups(self.handle, ctypes.byref(n), None, 0)
+        arr = (_U32 * (n.value + 1))()
+        lib().crum_plan_groups(self.handle, ctypes.byref(n), ctypes.cast(arr, _P), n.value + 1)
+        return list(arr)
+
+    def group_times(self):
+        n = len(self.groups()) - 1
+        arr = (ctypes.c_double * max(1, n))()
+        rc = lib().crum_plan_group_times(self.handle, ctypes.cast(arr, _P), n)
+        if rc != CRUM_OK:
+            raise RuntimeError(CODE_NAMES.get(rc, rc))
+        return list(arr)[:n]
+
+    def destroy(self) -> None:
+        if self.handle:
+            lib().crum_plan_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def read_request_statuses(addr: int, n: int):
+    arr = (crum_request_status * max(1, n)).from_address(addr)
+    return [(arr[i].status.code, arr[i].status.first_bad, arr[i].status.n_dirty,
+             arr[i].status.total_pages, arr[i].status.image_bytes, arr[i].image_offset)
+            for i in range(n)]
 
 
 def crum_ctx_set_param(ctx: int, param: int, value: int) -> None:

@@ -1,0 +1,110 @@
+"""Autotuner for launch and pipeline shapes.
+
+Searches the context parameters that shape the device work (diff unit size,
+non-temporal loads, diff and pack grid sizes, chunk or group sizes) by timing
+a caller-supplied workload, and keeps the winners in a JSON cache keyed by the
+device name, the HIP runtime version and the workload class, so later runs
+start from tuned shapes without searching again.
+"""
+from __future__ import annotations
+
+import ctypes
+import itertools
+import json
+import os
+import time
+from typing import Callable, Dict, Iterable, List, Optional
+
+from . import _lib as C
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_CACHE = os.path.join(HERE, "tuning_cache.json")
+
+PARAMS = {
+    "diff_unit_shift": C.CRUM_PARAM_DIFF_UNIT_SHIFT,
+    "diff_nontemporal": C.CRUM_PARAM_DIFF_NONTEMPORAL,
+    "diff_blocks": C.CRUM_PARAM_DIFF_BLOCKS,
+    "pack_blocks": C.CRUM_PARAM_PACK_BLOCKS,
+    "chunk_bytes": C.CRUM_PARAM_CHUNK_BYTES,
+    "chunk_max_bytes": C.CRUM_PARAM_CHUNK_MAX_BYTES,
+}
+
+
+def device_key() -> str:
+    """'<device name>|hip<runtime version>' of device 0."""
+    from . import hip as H
+    h = H.hip()
+    ver = ctypes.c_int(0)
+    h.hipRuntimeGetVersion.restype = ctypes.c_int
+    h.hipRuntimeGetVersion.argtypes = [ctypes.POINTER(ctypes.c_int)]
+    h.hipRuntimeGetVersion(ctypes.byref(ver))
+    name = ctypes.create_string_buffer(256)
+    h.hipDeviceGetName.restype = ctypes.c_int
+    h.hipDeviceGetName.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.c_int]
+    h.hipDeviceGetName(name, 256, 0)
+    return f"{name.value.decode(errors='replace').strip()}|hip{ver.value}"
+
+
+def apply(ctx: int, params: Dict[str, int]) -> None:
+    for k, v in params.items():
+        C.crum_ctx_set_param(ctx, PARAMS[k], int(v))
+
+
+def current(ctx: int) -> Dict[str, int]:
+    return {k: C.crum_ctx_get_param(ctx, p) for k, p in PARAMS.items()}
+
+
+def load(workload: str, path: str = DEFAULT_CACHE) -> Optional[Dict[str, int]]:
+    try:
+        with open(path) as f:
+            cache = json.load(f)
+    except (OSError, ValueError):
+        return None
+    entry = cache.get(device_key(), {}).get(workload)
+    return dict(entry["params"]) if entry else None
+
+
+def save(workload: str, params: Dict[str, int], table: List, path: str = DEFAULT_CACHE) -> None:
+    try:
+        with open(path) as f:
+            cache = json.load(f)
+    except (OSError, ValueError):
+        cache = {}
+    cache.setdefault(device_key(), {})[workload] = {"params": params, "trials": table}
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def search(ctx: int, run: Callable[[], float], space: Dict[str, Iterable[int]],
+           repeats: int = 2, log: Optional[Callable[[str], None]] = None):
+    """Coordinate search: starting from the context's current parameters,
+    sweep one parameter at a time over its candidate values (others fixed at
+    their best so far), keeping the value with the lowest median time of
+    `repeats` runs of `run()` (which returns seconds and must rebuild any
+    state that depends on the parameters).  Returns (best params, trials)."""
+    best = current(ctx)
+    trials = []
+
+    def measure(params):
+        apply(ctx, params)
+        ts = sorted(run() for _ in range(repeats))
+        t = ts[len(ts) // 2]
+        trials.append({"params": dict(params), "seconds": t})
+        if log:
+            log(f"[autotune] {params} -> {t * 1e3:.2f} ms")
+        return t
+
+    best_t = measure(best)
+    for name, values in space.items():
+        for v in values:
+            if best.get(name) == v:
+                continue
+            cand = dict(best)
+            cand[name] = v
+            t = measure(cand)
+            if t < best_t:
+                best, best_t = cand, t
+    apply(ctx, best)
+    return best, trials

@@ -3,6 +3,7 @@
 // snapshot and restore pipelines, and the chunked drain.
 #include "crum.h"
 #include "crum_dev.h"
+#include "crum_internal.h"
 #include "gf2.h"
 
 #include <algorithm>
@@ -15,37 +16,6 @@ using namespace crum;
 
 namespace {
 
-constexpr int kTimingClasses = 7;
-enum { kTDiff = 0, kTPack = 1, kTDrain = 2, kTScan = 3, kTHeader = 4, kTVerify = 5, kTScatter = 6 };
-
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess)
-            prev = -1;
-        if (prev != dev)
-            (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard()
-    {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev)
-            (void)hipSetDevice(prev);
-    }
-};
-
-uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
-
-int log2_exact(uint64_t p)
-{
-    int s = 0;
-    while ((1ull << s) < p)
-        ++s;
-    return s;
-}
-
-bool page_size_ok(uint64_t p) { return p >= 4096 && p <= (1ull << 30) && (p & (p - 1)) == 0; }
 
 // Scratch layout of one launch (offsets into ctx->d_scratch).
 struct Layout {
@@ -81,31 +51,6 @@ Layout make_layout(uint32_t n_regs, uint32_t n_reqs, uint64_t n_units, uint64_t 
 }
 
 }  // namespace
-
-struct crum_ctx {
-    int device = 0;
-    int cus = 256;
-    hipStream_t side = nullptr;
-    CrcTables* d_tabs = nullptr;
-    uint8_t* d_scratch = nullptr;
-    size_t scratch_cap = 0;
-    uint8_t* h_pin = nullptr;  // uploads, then readback area
-    size_t pin_cap = 0;
-    hipEvent_t ev_upload = nullptr, ev_count = nullptr, ev_done = nullptr, ev_hdr = nullptr;
-    std::vector<hipEvent_t> ev_chunk;  // pack of chunk i done
-    std::vector<hipEvent_t> ev_cnt;    // dirty count of chunk i read back
-    LaunchShape shape{};
-    uint64_t chunk_bytes = 128ull << 20;
-    uint64_t chunk_max_bytes = 1ull << 30;
-    uint32_t unit_shift_max = kUnitShiftDefault;
-    bool diff_nt = true;
-    uint64_t drain_chunk_bytes = 8ull << 20;
-    bool eager = true;
-    bool timing = false;
-    std::vector<hipEvent_t> pool;
-    size_t pool_used = 0;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> spans[kTimingClasses];
-};
 
 namespace {
 
@@ -182,43 +127,9 @@ hipError_t ensure_pinned(crum_ctx* c, size_t bytes)
     return e;
 }
 
-// Pointer rules shared by snapshot and restore: non-empty regions have a
-// base, every pointer is 16-byte aligned, and no current or shadow range
-// overlaps another.
-int check_ranges(const crum_region* regs, uint32_t n)
-{
-    std::vector<std::pair<uintptr_t, uintptr_t>> iv;
-    iv.reserve(2 * (size_t)n);
-    for (uint32_t i = 0; i < n; ++i) {
-        const crum_region& r = regs[i];
-        if ((reinterpret_cast<uintptr_t>(r.base) & 15u) ||
-            (reinterpret_cast<uintptr_t>(r.shadow) & 15u))
-            return CRUM_EINVAL;
-        if (r.len == 0)
-            continue;
-        if (!r.base)
-            return CRUM_EINVAL;
-        const uintptr_t b = reinterpret_cast<uintptr_t>(r.base);
-        if (b + r.len < b)
-            return CRUM_EINVAL;
-        iv.emplace_back(b, b + r.len);
-        if (r.shadow) {
-            const uintptr_t s = reinterpret_cast<uintptr_t>(r.shadow);
-            if (s + r.len < s)
-                return CRUM_EINVAL;
-            iv.emplace_back(s, s + r.len);
-        }
-    }
-    std::sort(iv.begin(), iv.end());
-    for (size_t i = 1; i < iv.size(); ++i)
-        if (iv[i].first < iv[i - 1].second)
-            return CRUM_EINVAL;
-    return CRUM_OK;
-}
-
 // Flatten one table into DevRegion entries (single request, request 0).
-void flatten(const crum_region* regs, uint32_t n, uint32_t ps, uint32_t us_max, DevRegion* out,
-             uint64_t* n_pages, uint64_t* n_units)
+void flatten(const crum_region* regs, uint32_t n, uint32_t ps, uint32_t us_max,
+             uint32_t region_flags, DevRegion* out, uint64_t* n_pages, uint64_t* n_units)
 {
     uint64_t page = 0, unit = 0;
     const uint32_t us = std::min<uint32_t>(ps, us_max);
@@ -233,7 +144,7 @@ void flatten(const crum_region* regs, uint32_t n, uint32_t ps, uint32_t us_max, 
         d.page_shift = ps;
         d.req = 0;
         d.unit_shift = us;
-        d.pad = 0;
+        d.flags = region_flags;
         page += regs[i].len >> ps;
         unit += regs[i].len >> us;
     }
@@ -503,7 +414,8 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     const uint32_t us = std::min<uint32_t>(ps, c->unit_shift_max);
     std::vector<DevRegion> dregs(std::max<uint32_t>(1, n_regions));
     uint64_t n_pages = 0, n_units = 0;
-    flatten(regions, n_regions, ps, c->unit_shift_max, dregs.data(), &n_pages, &n_units);
+    flatten(regions, n_regions, ps, c->unit_shift_max, (flags & CRUM_UPDATE_SHADOW) ? 1u : 0u,
+            dregs.data(), &n_pages, &n_units);
     const Layout L =
         make_layout(n_regions, 1, n_units, W, W * 64, np_shift ? G << np_shift : 0, n_chunks);
     CRUM_TRY(ensure_scratch(c, L.total));
@@ -544,7 +456,6 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     uint64_t* d_bounds = reinterpret_cast<uint64_t*>(S + L.bounds);
     uint8_t* staging = static_cast<uint8_t*>(d_staging);
     uint8_t* himg = static_cast<uint8_t*>(h_image);
-    const int upd = (flags & CRUM_UPDATE_SHADOW) ? 1 : 0;
     uint8_t* rb = P + rb_off;
 
     // the previous call on this context may still be draining from scratch
@@ -567,8 +478,8 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
                 Span sp(c, kTScan, stream);
                 CRUM_TRY(launch_bitmap(d_regs, n_regions, w0, w1, d_flags, d_bitmap, stream));
                 CRUM_TRY(launch_scan(d_bitmap, w0, w1, W, d_prefix, d_bounds + ci,
-                                     ci + 1 == n_chunks, d_reqs, 1, d_out, d_glob, capacity, 0,
-                                     stream));
+                                     ci + 1 == n_chunks, d_reqs, 0, 1, d_out, d_glob, capacity,
+                                     0, stream));
             }
             CRUM_TRY(hipMemcpyAsync(rb + 128 + 8 * ci, d_bounds + ci, 8, hipMemcpyDeviceToHost,
                                     stream));
@@ -581,8 +492,8 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
                 Span sp(c, kTPack, stream);
                 SlotRange sr{0, 0, d_bounds, (uint32_t)ci, g1 - g0};
                 CRUM_TRY(launch_pack(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
-                                     np_shift, staging, upd, d_crcs, d_partials, c->d_tabs,
-                                     d_glob, c->shape.pack_blocks, stream));
+                                     np_shift, staging, d_crcs, d_partials, c->d_tabs, d_glob,
+                                     c->shape.pack_blocks, stream));
                 CRUM_TRY(launch_finalize(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                          np_shift, d_partials, d_crcs, staging, d_glob, stream));
             }
@@ -615,7 +526,7 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
         {
             Span sp(c, kTScan, stream);
             CRUM_TRY(launch_bitmap(d_regs, n_regions, 0, W, d_flags, d_bitmap, stream));
-            CRUM_TRY(launch_scan(d_bitmap, 0, W, W, d_prefix, d_bounds, 1, d_reqs, 1, d_out,
+            CRUM_TRY(launch_scan(d_bitmap, 0, W, W, d_prefix, d_bounds, 1, d_reqs, 0, 1, d_out,
                                  d_glob, capacity, 0, stream));
         }
         CRUM_TRY(hipMemcpyAsync(rb, d_out, 128, hipMemcpyDeviceToHost, stream));
@@ -626,8 +537,8 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
         if (o.code != CRUM_OK) {
             // ENOSPC: header, table and bitmap only; nothing packed or drained
             Span sp(c, kTHeader, stream);
-            CRUM_TRY(launch_header(d_regs, d_reqs, 1, d_out, d_bitmap, d_crcs, staging,
-                                   c->d_tabs, stream));
+            CRUM_TRY(launch_header(d_regs, d_reqs, 0, 1, d_out, d_bitmap, d_crcs, staging,
+                                   capacity, c->d_tabs, stream));
             sp.end();
             CRUM_TRY(hipMemcpyAsync(h_status, d_out, sizeof(crum_status), hipMemcpyDeviceToHost,
                                     stream));
@@ -651,8 +562,8 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
                 Span sp(c, kTPack, stream);
                 SlotRange sr{k0, k1, nullptr, 0, k1 - k0};
                 CRUM_TRY(launch_pack(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
-                                     np_shift, staging, upd, d_crcs, d_partials, c->d_tabs,
-                                     d_glob, c->shape.pack_blocks, stream));
+                                     np_shift, staging, d_crcs, d_partials, c->d_tabs, d_glob,
+                                     c->shape.pack_blocks, stream));
                 CRUM_TRY(launch_finalize(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                          np_shift, d_partials, d_crcs, staging, d_glob, stream));
             }
@@ -675,8 +586,8 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     // ---- header (with the CRC array), then the prefix and tail of the drain
     {
         Span sp(c, kTHeader, stream);
-        CRUM_TRY(launch_header(d_regs, d_reqs, 1, d_out, d_bitmap, d_crcs, staging, c->d_tabs,
-                               stream));
+        CRUM_TRY(launch_header(d_regs, d_reqs, 0, 1, d_out, d_bitmap, d_crcs, staging, capacity,
+                               c->d_tabs, stream));
     }
     if (himg) {
         CRUM_TRY(hipEventRecord(c->ev_hdr, stream));
@@ -789,7 +700,7 @@ int crum_restore(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     const uint32_t np_shift = ps > kPieceShift ? ps - kPieceShift : 0;
     std::vector<DevRegion> dregs(std::max<uint32_t>(1, n_regions));
     uint64_t n_pages = 0, n_units = 0;
-    flatten(regions, n_regions, ps, c->unit_shift_max, dregs.data(), &n_pages, &n_units);
+    flatten(regions, n_regions, ps, c->unit_shift_max, 0, dregs.data(), &n_pages, &n_units);
     const Layout L = make_layout(n_regions, 1, 0, W, W * 64, np_shift ? D << np_shift : 0, 1);
     CRUM_TRY(ensure_scratch(c, L.total));
     CRUM_TRY(ensure_pinned(c, L.upload_end));
@@ -835,15 +746,15 @@ int crum_restore(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     {
         Span sp(c, kTScan, stream);
         CRUM_TRY(launch_restore_check(d_reqs, 1, d_out, staging, c->d_tabs, d_glob, stream));
-        CRUM_TRY(launch_scan(img_bitmap, 0, W, W, d_prefix, nullptr, 1, d_reqs, 1, d_out, d_glob,
-                             0, 1, stream));
+        CRUM_TRY(launch_scan(img_bitmap, 0, W, W, d_prefix, nullptr, 1, d_reqs, 0, 1, d_out,
+                             d_glob, 0, 1, stream));
         CRUM_TRY(launch_list(img_bitmap, d_prefix, 0, W, d_list, stream));
     }
     if (flags & CRUM_VERIFY) {
         Span sp(c, kTVerify, stream);
         SlotRange sr{0, D, nullptr, 0, D};
         CRUM_TRY(launch_pack(kModeVerify, d_regs, n_regions, d_reqs, d_out, d_list, sr, np_shift,
-                             staging, 0, d_crcs, d_partials, c->d_tabs, d_glob,
+                             staging, d_crcs, d_partials, c->d_tabs, d_glob,
                              c->shape.pack_blocks, stream));
         CRUM_TRY(launch_finalize(kModeVerify, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                  np_shift, d_partials, d_crcs, staging, d_glob, stream));

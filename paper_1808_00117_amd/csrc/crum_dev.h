@@ -27,7 +27,7 @@ struct DevRegion {
     uint32_t page_shift; // log2 page size
     uint32_t req;        // request index
     uint32_t unit_shift; // log2 diff unit = min(page_shift, unit_shift_max)
-    uint32_t pad;
+    uint32_t flags;      // bit 0: copy dirty pages into the shadow
 };
 static_assert(sizeof(DevRegion) == 64, "DevRegion layout");
 
@@ -67,7 +67,8 @@ struct DevGlobal {
     uint32_t crc_bad;        // restore: lowest failing slot, kNoBad if none
     uint32_t pad0;
     uint64_t running;        // dirty pages counted by the scans so far
-    uint64_t pad[3];
+    uint64_t img_next;       // 4 KiB-aligned staging offset for the next image
+    uint64_t pad[2];
 };
 static_assert(sizeof(DevGlobal) == 64, "DevGlobal layout");
 
@@ -103,26 +104,37 @@ hipError_t launch_diff(const DevRegion* regs, uint32_t n_regs, uint64_t u0, uint
 hipError_t launch_bitmap(const DevRegion* regs, uint32_t n_regs, uint64_t w0, uint64_t w1,
                          const uint8_t* unit_flags, uint64_t* bitmap, hipStream_t s);
 // Scans words [w0, w1) continuing glob->running; writes the new running total
-// to *bounds_out when non-null.  With `final`, also fills the per-request
-// results over all n_words_total words and applies the capacity check.
+// to *bounds_out when non-null.  With `final`, also fills the results of
+// requests [q0, q1) (whose words must all have been scanned), lays their
+// images out from glob->img_next and applies the capacity check: a group that
+// does not fit, and every later group, gets CRUM_ENOSPC.
 hipError_t launch_scan(const uint64_t* bitmap, uint64_t w0, uint64_t w1, uint64_t n_words_total,
                        uint32_t* prefix, uint64_t* bounds_out, int final, const DevRequest* reqs,
-                       uint32_t n_reqs, DevReqOut* out, DevGlobal* glob, uint64_t capacity,
-                       int restore_mode, hipStream_t s);
+                       uint32_t q0, uint32_t q1, DevReqOut* out, DevGlobal* glob,
+                       uint64_t capacity, int restore_mode, hipStream_t s);
 hipError_t launch_list(const uint64_t* bitmap, const uint32_t* prefix, uint64_t w0, uint64_t w1,
                        uint32_t* list, hipStream_t s);
+// Pack: shadows are updated for regions whose flags bit 0 is set.
 hipError_t launch_pack(int mode, const DevRegion* regs, uint32_t n_regs, const DevRequest* reqs,
                        const DevReqOut* out, const uint32_t* list, SlotRange range,
-                       uint32_t np_shift, uint8_t* staging, int update_shadow,
-                       uint32_t* crc_out, uint32_t* partials, const CrcTables* tabs,
-                       DevGlobal* glob, int blocks, hipStream_t s);
+                       uint32_t np_shift, uint8_t* staging, uint32_t* crc_out,
+                       uint32_t* partials, const CrcTables* tabs, DevGlobal* glob, int blocks,
+                       hipStream_t s);
 hipError_t launch_finalize(int mode, const DevRegion* regs, uint32_t n_regs,
                            const DevRequest* reqs, const DevReqOut* out, const uint32_t* list,
                            SlotRange range, uint32_t np_shift, const uint32_t* partials,
                            uint32_t* crc_out, uint8_t* staging, DevGlobal* glob, hipStream_t s);
-hipError_t launch_header(const DevRegion* regs, const DevRequest* reqs, uint32_t n_reqs,
+// One workgroup per request of [q0, q1).  Requests with ENOSPC get only their
+// prefix (header, table, bitmap), and only when it fits within `capacity`.
+hipError_t launch_header(const DevRegion* regs, const DevRequest* reqs, uint32_t q0, uint32_t q1,
                          const DevReqOut* out, const uint64_t* bitmap, const uint32_t* crcs,
-                         uint8_t* staging, const CrcTables* tabs, hipStream_t s);
+                         uint8_t* staging, uint64_t capacity, const CrcTables* tabs,
+                         hipStream_t s);
+// Resets the launch-wide counters (graph-safe: a kernel, not a memset).
+hipError_t launch_plan_init(DevGlobal* glob, hipStream_t s);
+// Compact per-request results: {code, first_bad, n_dirty, total_pages,
+// image_bytes, image_offset} (40 bytes each) for requests [0, n).
+hipError_t launch_plan_status(const DevReqOut* out, uint32_t n, uint8_t* dst, hipStream_t s);
 hipError_t launch_restore_check(const DevRequest* reqs, uint32_t n_reqs, const DevReqOut* out,
                                 const uint8_t* staging, const CrcTables* tabs, DevGlobal* glob,
                                 hipStream_t s);

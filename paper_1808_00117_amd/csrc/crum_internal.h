@@ -1,0 +1,133 @@
+// Internal host-side definitions shared by the C-ABI sources of libcrum.
+#pragma once
+#include "crum.h"
+#include "crum_dev.h"
+
+#include <algorithm>
+#include <utility>
+#include <vector>
+
+namespace crum {
+
+constexpr int kTimingClasses = 7;
+enum { kTDiff = 0, kTPack = 1, kTDrain = 2, kTScan = 3, kTHeader = 4, kTVerify = 5, kTScatter = 6 };
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess)
+            prev = -1;
+        if (prev != dev)
+            (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev)
+            (void)hipSetDevice(prev);
+    }
+};
+
+inline uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+inline int log2_exact(uint64_t p)
+{
+    int s = 0;
+    while ((1ull << s) < p)
+        ++s;
+    return s;
+}
+
+inline bool page_size_ok(uint64_t p) { return p >= 4096 && p <= (1ull << 30) && (p & (p - 1)) == 0; }
+
+
+// Pointer rules shared by snapshot and restore: non-empty regions have a
+// base, every pointer is 16-byte aligned, and no current or shadow range
+// overlaps another.
+inline int check_ranges(const crum_region* regs, uint32_t n)
+{
+    std::vector<std::pair<uintptr_t, uintptr_t>> iv;
+    iv.reserve(2 * (size_t)n);
+    for (uint32_t i = 0; i < n; ++i) {
+        const crum_region& r = regs[i];
+        if ((reinterpret_cast<uintptr_t>(r.base) & 15u) ||
+            (reinterpret_cast<uintptr_t>(r.shadow) & 15u))
+            return CRUM_EINVAL;
+        if (r.len == 0)
+            continue;
+        if (!r.base)
+            return CRUM_EINVAL;
+        const uintptr_t b = reinterpret_cast<uintptr_t>(r.base);
+        if (b + r.len < b)
+            return CRUM_EINVAL;
+        iv.emplace_back(b, b + r.len);
+        if (r.shadow) {
+            const uintptr_t s = reinterpret_cast<uintptr_t>(r.shadow);
+            if (s + r.len < s)
+                return CRUM_EINVAL;
+            iv.emplace_back(s, s + r.len);
+        }
+    }
+    std::sort(iv.begin(), iv.end());
+    for (size_t i = 1; i < iv.size(); ++i)
+        if (iv[i].first < iv[i - 1].second)
+            return CRUM_EINVAL;
+    return CRUM_OK;
+}
+
+
+}  // namespace crum
+
+struct crum_ctx {
+    using CrcTables = crum::CrcTables;
+    using LaunchShape = crum::LaunchShape;
+    int device = 0;
+    int cus = 256;
+    hipStream_t side = nullptr;
+    CrcTables* d_tabs = nullptr;
+    uint8_t* d_scratch = nullptr;
+    size_t scratch_cap = 0;
+    uint8_t* h_pin = nullptr;  // uploads, then readback area
+    size_t pin_cap = 0;
+    hipEvent_t ev_upload = nullptr, ev_count = nullptr, ev_done = nullptr, ev_hdr = nullptr;
+    std::vector<hipEvent_t> ev_chunk;  // pack of chunk i done
+    std::vector<hipEvent_t> ev_cnt;    // dirty count of chunk i read back
+    LaunchShape shape{};
+    uint64_t chunk_bytes = 128ull << 20;
+    uint64_t chunk_max_bytes = 1ull << 30;
+    uint32_t unit_shift_max = crum::kUnitShiftDefault;
+    bool diff_nt = true;
+    uint64_t drain_chunk_bytes = 8ull << 20;
+    bool eager = true;
+    bool timing = false;
+    std::vector<hipEvent_t> pool;
+    size_t pool_used = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> spans[crum::kTimingClasses];
+};
+
+
+namespace crum {
+
+// Accessors used by the batched-plan code.
+using DeviceGuardC = DeviceGuard;
+inline bool ctx_page_size_ok(uint64_t p) { return page_size_ok(p); }
+inline int ctx_log2(uint64_t p) { return log2_exact(p); }
+inline int ctx_check_ranges(const crum_region* r, uint32_t n) { return check_ranges(r, n); }
+inline uint32_t ctx_unit_shift_max(const crum_ctx* c) { return c->unit_shift_max; }
+inline uint64_t ctx_chunk_bytes(const crum_ctx* c) { return c->chunk_bytes; }
+inline uint64_t ctx_chunk_max_bytes(const crum_ctx* c) { return c->chunk_max_bytes; }
+inline int ctx_device(const crum_ctx* c) { return c->device; }
+inline LaunchShape ctx_shape(const crum_ctx* c) { return c->shape; }
+inline const CrcTables* ctx_tables(const crum_ctx* c) { return c->d_tabs; }
+inline int ctx_diff_nt(const crum_ctx* c) { return c->diff_nt ? 1 : 0; }
+inline hipStream_t ctx_side_stream(const crum_ctx* c) { return c->side; }
+
+}  // namespace crum
+
+#define CRUM_TRY_C(expr)                        \
+    do {                                        \
+        hipError_t e_ = (expr);                 \
+        if (e_ != hipSuccess)                   \
+            return CRUM_EHIP;                   \
+    } while (0)

@@ -300,8 +300,8 @@ __global__ __launch_bounds__(1024) void k_scan(const uint64_t* __restrict__ bitm
                                                uint64_t w1, uint64_t n_words_total,
                                                uint32_t* __restrict__ prefix,
                                                uint64_t* __restrict__ bounds_out, int final,
-                                               const DevRequest* __restrict__ reqs,
-                                               uint32_t n_reqs, DevReqOut* __restrict__ out,
+                                               const DevRequest* __restrict__ reqs, uint32_t q0,
+                                               uint32_t q1, DevReqOut* __restrict__ out,
                                                DevGlobal* __restrict__ glob, uint64_t capacity,
                                                int restore_mode)
 {
@@ -354,13 +354,16 @@ __global__ __launch_bounds__(1024) void k_scan(const uint64_t* __restrict__ bitm
         *bounds_out = carry;
     if (!final)
         return;
-    // per-request results, images laid out back to back (4 KiB aligned)
-    uint64_t img = 0, used = 0;
-    for (uint32_t q = 0; q < n_reqs; ++q) {
+    // results of requests [q0, q1); their images follow glob->img_next (4 KiB aligned)
+    uint64_t img = glob->img_next, used = glob->staging_used;
+    const bool full = glob->code != 0;
+    for (uint32_t q = q0; q < q1; ++q) {
         const DevRequest& Q = reqs[q];
+        // every word of these requests lies in [.., w1): a prefix at or past
+        // w1 is the running total, not a (not yet scanned) later word
         const uint64_t a = Q.first_word, b = Q.first_word + Q.n_words;
-        const uint64_t p0 = a < n_words_total ? prefix[a] : carry;
-        const uint64_t p1 = b < n_words_total ? prefix[b] : carry;
+        const uint64_t p0 = a < w1 ? prefix[a] : carry;
+        const uint64_t p1 = b < w1 ? prefix[b] : carry;
         const uint64_t D = p1 - p0;
         DevReqOut& O = out[q];
         O.n_dirty = D;
@@ -378,22 +381,25 @@ __global__ __launch_bounds__(1024) void k_scan(const uint64_t* __restrict__ bitm
     }
     glob->total_dirty = carry;
     if (!restore_mode) {
-        glob->staging_used = used;
-        const int32_t code = used > capacity ? -2 /* CRUM_ENOSPC */ : 0;
-        glob->code = code;
-        if (code)
-            for (uint32_t q = 0; q < n_reqs; ++q)
-                out[q].code = code;
+        if (full || used > capacity) {
+            // the group does not fit: no request of it (or of a later group) is packed
+            glob->code = -2;  // CRUM_ENOSPC
+            for (uint32_t q = q0; q < q1; ++q)
+                out[q].code = -2;
+        } else {
+            glob->staging_used = used;
+            glob->img_next = img;
+        }
     }
 }
 
 hipError_t launch_scan(const uint64_t* bitmap, uint64_t w0, uint64_t w1, uint64_t n_words_total,
                        uint32_t* prefix, uint64_t* bounds_out, int final, const DevRequest* reqs,
-                       uint32_t n_reqs, DevReqOut* out, DevGlobal* glob, uint64_t capacity,
-                       int restore_mode, hipStream_t s)
+                       uint32_t q0, uint32_t q1, DevReqOut* out, DevGlobal* glob,
+                       uint64_t capacity, int restore_mode, hipStream_t s)
 {
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, bitmap, w0, w1, n_words_total, prefix,
-                       bounds_out, final, reqs, n_reqs, out, glob, capacity, restore_mode);
+                       bounds_out, final, reqs, q0, q1, out, glob, capacity, restore_mode);
     return hipGetLastError();
 }
 
@@ -452,7 +458,7 @@ __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs
                                               const DevReqOut* __restrict__ out,
                                               const uint32_t* __restrict__ list, SlotRange sr,
                                               uint32_t np_shift, uint8_t* __restrict__ staging,
-                                              int update_shadow, uint32_t* __restrict__ crc_out,
+                                              uint32_t* __restrict__ crc_out,
                                               uint32_t* __restrict__ partials,
                                               const CrcTables* __restrict__ tabs,
                                               DevGlobal* __restrict__ glob)
@@ -486,6 +492,8 @@ __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs
             continue;  // only reachable for a corrupt restore bitmap (gated above)
         const DevRequest& Q = reqs[R.req];
         const DevReqOut& O = out[R.req];
+        if (MODE == kModePack && O.code != 0)
+            continue;  // the request's image did not fit: nothing is written
         const uint32_t ps = R.page_shift;
         const uint32_t pb_shift = ps < kPieceShift ? ps : kPieceShift;
         if (piece >= (1u << (ps - pb_shift)))
@@ -499,7 +507,7 @@ __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs
         uint32_t raw;
         if (MODE == kModePack) {
             const uint4* src = reinterpret_cast<const uint4*>(R.cur + page_off + piece_off);
-            uint4* sh = (update_shadow && R.shadow)
+            uint4* sh = ((R.flags & 1u) && R.shadow)
                             ? reinterpret_cast<uint4*>(R.shadow + page_off + piece_off)
                             : nullptr;
             raw = wave_piece_crc<true>(src, reinterpret_cast<uint4*>(slot_ptr), sh, steps, lane,
@@ -528,9 +536,9 @@ __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs
 
 hipError_t launch_pack(int mode, const DevRegion* regs, uint32_t n_regs, const DevRequest* reqs,
                        const DevReqOut* out, const uint32_t* list, SlotRange range,
-                       uint32_t np_shift, uint8_t* staging, int update_shadow,
-                       uint32_t* crc_out, uint32_t* partials, const CrcTables* tabs,
-                       DevGlobal* glob, int blocks, hipStream_t s)
+                       uint32_t np_shift, uint8_t* staging, uint32_t* crc_out,
+                       uint32_t* partials, const CrcTables* tabs, DevGlobal* glob, int blocks,
+                       hipStream_t s)
 {
     const uint64_t max_items = range.max_slots << np_shift;
     if (max_items == 0)
@@ -539,12 +547,12 @@ hipError_t launch_pack(int mode, const DevRegion* regs, uint32_t n_regs, const D
     const uint64_t nb = need < (uint64_t)blocks ? need : (uint64_t)blocks;
     if (mode == kModePack)
         hipLaunchKernelGGL(k_pack<kModePack>, dim3((unsigned)nb), dim3(256), 0, s, regs, n_regs,
-                           reqs, out, list, range, np_shift, staging, update_shadow, crc_out,
-                           partials, tabs, glob);
+                           reqs, out, list, range, np_shift, staging, crc_out, partials, tabs,
+                           glob);
     else
         hipLaunchKernelGGL(k_pack<kModeVerify>, dim3((unsigned)nb), dim3(256), 0, s, regs,
-                           n_regs, reqs, out, list, range, np_shift, staging, 0, crc_out,
-                           partials, tabs, glob);
+                           n_regs, reqs, out, list, range, np_shift, staging, crc_out, partials,
+                           tabs, glob);
     return hipGetLastError();
 }
 
@@ -579,6 +587,8 @@ __global__ __launch_bounds__(256) void k_finalize(const DevRegion* __restrict__ 
         return;
     const DevRequest& Q = reqs[R.req];
     const DevReqOut& O = out[R.req];
+    if (MODE == kModePack && O.code != 0)
+        return;
     const uint32_t np = 1u << (ps - kPieceShift);
     const uint32_t K = gf2_xpow8n(1ull << kPieceShift);
     uint32_t s = 0;
@@ -669,16 +679,19 @@ __global__ __launch_bounds__(256) void k_header(const DevRegion* __restrict__ re
                                                 const DevReqOut* __restrict__ out,
                                                 const uint64_t* __restrict__ bitmap,
                                                 const uint32_t* __restrict__ crcs,
-                                                uint8_t* __restrict__ staging,
+                                                uint8_t* __restrict__ staging, uint32_t q0,
+                                                uint64_t capacity,
                                                 const CrcTables* __restrict__ tabs)
 {
     __shared__ uint32_t lds[kSliceWords];
     __shared__ uint32_t red[4];
     __shared__ uint32_t s_shadowed;
+    const DevRequest& Q = reqs[q0 + blockIdx.x];
+    const DevReqOut& O = out[q0 + blockIdx.x];
+    if (O.code != 0 && O.img_base + Q.data_off > capacity)
+        return;  // no room even for the prefix
     load_tables(lds, tabs, kSliceWords);
     const uint32_t tid = threadIdx.x;
-    const DevRequest& Q = reqs[blockIdx.x];
-    const DevReqOut& O = out[blockIdx.x];
     uint8_t* img = staging + O.img_base;
     const uint64_t R = Q.n_regions;
     const uint64_t prefix_end = 64 + 32 * R + 8 * Q.n_words;
@@ -737,14 +750,56 @@ __global__ __launch_bounds__(256) void k_header(const DevRegion* __restrict__ re
         h32[14] = meta;
 }
 
-hipError_t launch_header(const DevRegion* regs, const DevRequest* reqs, uint32_t n_reqs,
+hipError_t launch_header(const DevRegion* regs, const DevRequest* reqs, uint32_t q0, uint32_t q1,
                          const DevReqOut* out, const uint64_t* bitmap, const uint32_t* crcs,
-                         uint8_t* staging, const CrcTables* tabs, hipStream_t s)
+                         uint8_t* staging, uint64_t capacity, const CrcTables* tabs,
+                         hipStream_t s)
 {
-    if (n_reqs == 0)
+    if (q1 <= q0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_header, dim3(n_reqs), dim3(256), 0, s, regs, reqs, out, bitmap, crcs,
-                       staging, tabs);
+    hipLaunchKernelGGL(k_header, dim3(q1 - q0), dim3(256), 0, s, regs, reqs, out, bitmap, crcs,
+                       staging, q0, capacity, tabs);
+    return hipGetLastError();
+}
+
+__global__ void k_plan_init(DevGlobal* __restrict__ glob)
+{
+    glob->total_dirty = 0;
+    glob->staging_used = 0;
+    glob->code = 0;
+    glob->fmt_bad = 0;
+    glob->crc_bad = kNoBad;
+    glob->running = 0;
+    glob->img_next = 0;
+}
+
+hipError_t launch_plan_init(DevGlobal* glob, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_plan_init, dim3(1), dim3(1), 0, s, glob);
+    return hipGetLastError();
+}
+
+__global__ void k_plan_status(const DevReqOut* __restrict__ out, uint32_t n,
+                              uint8_t* __restrict__ dst)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n)
+        return;
+    const DevReqOut& O = out[q];
+    uint8_t* d = dst + 40ull * q;
+    *reinterpret_cast<int32_t*>(d) = O.code;
+    *reinterpret_cast<uint32_t*>(d + 4) = O.first_bad;
+    *reinterpret_cast<uint64_t*>(d + 8) = O.n_dirty;
+    *reinterpret_cast<uint64_t*>(d + 16) = O.total_pages;
+    *reinterpret_cast<uint64_t*>(d + 24) = O.image_bytes;
+    *reinterpret_cast<uint64_t*>(d + 32) = O.img_base;
+}
+
+hipError_t launch_plan_status(const DevReqOut* out, uint32_t n, uint8_t* dst, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_plan_status, dim3((n + 255) / 256), dim3(256), 0, s, out, n, dst);
     return hipGetLastError();
 }
 
