@@ -48,7 +48,17 @@ def parse_args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="many", choices=["many", "plain"])
+    ap.add_argument("--config", default="many", choices=["many", "plain", "batched", "served"])
+    ap.add_argument("--duration", type=float, default=60.0, help="served: trace seconds")
+    ap.add_argument("--slots", type=int, default=6, help="served: concurrent request slots")
+    ap.add_argument("--rate", type=float, default=200.0, help="served: arrivals per second")
+    ap.add_argument("--policy", type=int, default=0,
+                    help="served: 0 adaptive, 1 two-stage, 2 pipelined snapshot admission")
+    ap.add_argument("--tune", action="store_true",
+                    help="batched: run the autotuner and store the result in the tuning cache")
+    ap.add_argument("--requests", type=int, default=256, help="batched: number of requests")
+    ap.add_argument("--tune-cache", default=None,
+                    help="tuning cache path (default: the package's tuning_cache.json)")
     ap.add_argument("--no-corunner", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline leg (0 disables it)")
@@ -232,6 +242,268 @@ def materialize_raw(scn, H):
     return pairs
 
 
+def percentile(v, q):
+    v = sorted(v)
+    return v[min(len(v) - 1, int(round(q * (len(v) - 1))))]
+
+
+def bench_batched(args):
+    """Batched workload: 256 requests (1-32 allocations each, request totals
+    log-uniform 1 MiB-2 GiB, 4 KiB or 64 KiB pages, dirty fraction U(1%, 50%)
+    in runs of mean 16) snapshotted by one plan launch (captured graphs, one
+    per group of requests), against 256 one-at-a-time plain snapshots of the
+    same requests into the same host offsets; images compared byte for byte."""
+    import numpy as np
+
+    import paper_1808_00117_amd as crum
+    import paper_1808_00117_amd.hip as H
+    from paper_1808_00117_amd import autotune
+    from synth import scenarios as sc
+
+    crum.lib()
+    reqs = sc.batched(seed=1004, n_requests=args.requests)
+    N = sum(r.total_bytes for r in reqs)
+    Dsum = sum(r.n_dirty for r in reqs)
+    log(f"[batched] {len(reqs)} requests, {N / 1e9:.1f} GB scanned, "
+        f"{sum(r.n_dirty * r.page_size for r in reqs) / 1e9:.1f} GB dirty")
+    t0 = time.perf_counter()
+    pairs = [materialize_raw(r, H) for r in reqs]
+    log(f"[batched] materialised in {time.perf_counter() - t0:.1f} s")
+    tables = []
+    for r, pr in zip(reqs, pairs):
+        tables.append([(c.ptr, s.ptr if s else 0, g.nbytes, g.id) for (c, s), g in
+                       zip(pr, r.regions)])
+    sizes = [crum.crum_image_bytes(len(r.regions), r.total_pages, r.n_dirty, r.page_size)
+             for r in reqs]
+    total = sum((b + 4095) // 4096 * 4096 for b in sizes)
+    cap = total + (64 << 20)
+    staging = H.DeviceBuffer(cap)
+    h_images = H.PinnedBuffer(cap)
+    status = H.PinnedBuffer(40 * len(reqs))
+    ctx = crum.crum_ctx_create(0)
+    stream = H.Stream()
+    plan_reqs = [(t, r.page_size, 0, 5) for t, r in zip(tables, reqs)]
+
+    def make_plan():
+        return crum.Plan(ctx, plan_reqs, staging.ptr, cap, h_images.ptr, cap)
+
+    def launch(plan):
+        t = time.perf_counter()
+        rc = plan.launch(stream.handle, status.ptr)
+        assert rc == 0, rc
+        stream.synchronize()
+        return time.perf_counter() - t
+
+    cache = args.tune_cache or autotune.DEFAULT_CACHE
+    tuned = autotune.load("batched", cache)
+    if args.tune:
+        def trial():
+            plan = make_plan()
+            launch(plan)  # warm
+            t = launch(plan)
+            plan.destroy()
+            return t
+        space = {"chunk_bytes": [64 << 20, 256 << 20, 1 << 30],
+                 "chunk_max_bytes": [1 << 30, 4 << 30, 16 << 30],
+                 "pack_blocks": [512, 1024, 2048],
+                 "diff_blocks": [512, 1024, 2048]}
+        best, trials = autotune.search(ctx, trial, space, repeats=2, log=log)
+        autotune.save("batched", best, trials, cache)
+        tuned = best
+    if tuned:
+        autotune.apply(ctx, tuned)
+    params = autotune.current(ctx)
+    plan = make_plan()
+    groups = plan.groups()
+    n_groups = len(groups) - 1
+    group_of = np.zeros(len(reqs), np.int64)
+    for g in range(n_groups):
+        group_of[groups[g]:groups[g + 1]] = g
+    for _ in range(args.warmup):
+        launch(plan)
+    sts = crum.read_request_statuses(status.ptr, len(reqs))
+    for q, (code, _, D, G, ib, off) in enumerate(sts):
+        assert code == 0 and D == reqs[q].n_dirty and ib == sizes[q], (q, sts[q])
+    offsets = [st[5] for st in sts]
+    # timed plan launches
+    mk, lat_b = [], []
+    for _ in range(args.steps):
+        mk.append(launch(plan))
+        gt = plan.group_times()
+        lat_b.extend(gt[g] for g in group_of)
+    batched_image = h_images.numpy(cap)[: offsets[-1] + sizes[-1]].copy()
+    plan.destroy()
+
+    # one-at-a-time plain path, same host offsets
+    worst = max(crum.crum_image_bytes(len(r.regions), r.total_pages, r.total_pages,
+                                      r.page_size) for r in reqs)
+    pstage = H.DeviceBuffer(worst)
+    pstatus = H.PinnedBuffer(64)
+    crum.crum_ctx_set_param(ctx, crum.CRUM_PARAM_CHUNK_BYTES, 128 << 20)
+    crum.crum_ctx_set_param(ctx, crum.CRUM_PARAM_CHUNK_MAX_BYTES, 1 << 30)
+
+    def plain_all():
+        lat = []
+        t0 = time.perf_counter()
+        for q, r in enumerate(reqs):
+            tab = crum.region_table(tables[q])
+            rc = crum.crum_snapshot(ctx, tab, r.page_size, 0, 5, pstage.ptr, worst,
+                                    h_images.ptr + offsets[q], cap - offsets[q], stream.handle,
+                                    pstatus.ptr)
+            assert rc == 0
+            stream.synchronize()
+            st = crum.read_status(pstatus.ptr)
+            assert st.code == 0 and st.image_bytes == sizes[q]
+            lat.append(time.perf_counter() - t0)
+        return time.perf_counter() - t0, lat
+
+    plain_all()  # warm
+    h_images.numpy(cap)[:] = 0
+    t_plain, lat_p = plain_all()
+    same = all(np.array_equal(h_images.numpy(cap)[o:o + b], batched_image[o:o + b])
+               for o, b in zip(offsets, sizes))
+    assert same, "batched and plain images differ"
+    mk_ms = 1e3 * statistics.median(mk)
+    result = {
+        "metric": "snapshot GB/s (diff+CRC+compact+drain), batched vs plain",
+        "value": round(N / (statistics.median(mk)) / 1e9, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(mk_ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic (seeded SplitMix64 bytes, PCG64 scenario)",
+        "config": {"workload": f"{len(reqs)} snapshot requests, 1-32 allocations each, "
+                               "request totals log-uniform 1 MiB-2 GiB, 4/64 KiB pages, dirty "
+                               "U(1%,50%) in runs of mean 16",
+                   "scanned_bytes": N, "dirty_pages": Dsum, "image_bytes": sum(sizes),
+                   "groups": n_groups, "params": params, "tuned": bool(tuned)},
+        "batched": {"makespan_ms": round(mk_ms, 2),
+                    "latency_ms": {"p50": round(percentile(lat_b, 0.5), 2),
+                                   "p99": round(percentile(lat_b, 0.99), 2)},
+                    "drain_gbs": round(sum(sizes) / statistics.median(mk) / 1e9, 2)},
+        "plain": {"makespan_ms": round(1e3 * t_plain, 2),
+                  "gbs": round(N / t_plain / 1e9, 2),
+                  "latency_ms": {"p50": round(1e3 * percentile(lat_p, 0.5), 2),
+                                 "p99": round(1e3 * percentile(lat_p, 0.99), 2)}},
+        "bit_exact_vs_plain": same,
+    }
+    crum.crum_ctx_destroy(ctx)
+    print(json.dumps(result), flush=True)
+
+
+def bench_served(args):
+    """Served workload: 32 clients with persistent device state (log-uniform
+    64 MiB-8 GiB, 64 KiB pages, resident shadows), open-loop Poisson arrivals
+    at 200 req/s, snapshot:restore 4:1, a 64 GiB pinned budget.  The same trace
+    runs through the serving loop with several slots and with one slot (the
+    plain one-request-at-a-time path)."""
+    import threading
+
+    import paper_1808_00117_amd as crum
+    import paper_1808_00117_amd.hip as H
+    import synth
+    from synth import scenarios as sc
+
+    crum.lib()
+    P = 64 * 1024
+    sizes = sc.served_clients()
+    trace = sc.served_trace(duration=args.duration, rate=args.rate)
+    warm = min(5.0, args.duration / 6)
+    # offered device-to-host load: expected dirty bytes of the snapshots per second
+    offered = sum(sizes[c] * f for t, c, k, f in trace if k == 1) / args.duration
+    log(f"[served] {len(sizes)} clients, {sum(sizes) / 2**30:.1f} GiB, {len(trace)} requests "
+        f"over {args.duration:.0f} s, offered D2H {offered / 1e9:.1f} GB/s")
+    cur = [H.DeviceBuffer(n) for n in sizes]
+    sh = [H.DeviceBuffer(n) for n in sizes]
+    clients = [([(c.ptr, s.ptr, n, 500 + i)], P) for i, (c, s, n) in enumerate(zip(cur, sh, sizes))]
+    fracs = [f for _, _, _, f in trace]
+    BASE = 1 << 40
+
+    def reset_state():
+        for i, (c, s, n) in enumerate(zip(cur, sh, sizes)):
+            synth.fill_dev(c.ptr, n, 1005, i, 0, 0)
+            H.memcpy_dtod(s.ptr, c.ptr, n)
+        H.device_synchronize()
+
+    last_sel = {}
+
+    def prepare(user, client, kind, tag, stream):
+        n = sizes[client]
+        if kind == 1:
+            f = 0.0 if tag >= BASE else fracs[tag]
+            last_sel[client] = (tag, f)
+            if f > 0:
+                synth.mutate_frac_dev(cur[client].ptr, n, P, tag, f, tag, client, stream)
+        else:
+            sel, f = last_sel[client]
+            if f > 0:
+                synth.clobber_frac_dev(cur[client].ptr, n, P, sel, f, 777, client, stream)
+
+    def run(n_slots):
+        reset_state()
+        last_sel.clear()
+        srv = crum.Server(clients, n_slots, 64 << 30, prepare=prepare)
+        srv.set_policy(args.policy)
+        for i in range(len(sizes)):  # untimed base image per client
+            srv.submit(i, 1, BASE + i)
+        srv.poll(wait_all=True)
+        t0 = srv.time()
+
+        def driver():
+            for i, (t, c, kind, _) in enumerate(trace):
+                dt = t0 + t - srv.time()
+                if dt > 0:
+                    time.sleep(dt)
+                srv.submit(c, kind, i)
+        th = threading.Thread(target=driver)
+        th.start()
+        th.join()
+        done = srv.poll(wait_all=True, max_n=1 << 16)
+        t_end = srv.time()
+        srv.destroy()
+        recs = [d for d in done if d["tag"] < BASE]
+        assert all(d["code"] == 0 for d in recs), [d for d in recs if d["code"] != 0][:3]
+        win = [d for d in recs if d["arrival_s"] - t0 >= warm]
+        lat = [1e3 * (d["done_s"] - d["arrival_s"]) for d in win]
+        snaps = [d for d in win if d["kind"] == 1]
+        span = max(d["done_s"] for d in win) - (t0 + warm)
+        scanned = sum(sizes[d["client"]] for d in snaps)
+        drained = sum(d["image_bytes"] for d in snaps)
+        return {"slots": n_slots, "requests": len(win),
+                "latency_ms": {"p50": round(percentile(lat, 0.5), 2),
+                               "p99": round(percentile(lat, 0.99), 2)},
+                "snapshot_gbs": round(scanned / span / 1e9, 2),
+                "drain_gbs": round(drained / span / 1e9, 2),
+                "restore_h2d_gbs": round(sum(d["image_bytes"] for d in win if d["kind"] == 2)
+                                         / span / 1e9, 2),
+                "tail_s": round(t_end - t0 - args.duration, 2)}
+
+    served = run(args.slots)
+    log(f"[served] {served}")
+    plain = run(1)
+    log(f"[served] plain {plain}")
+    result = {
+        "metric": "snapshot GB/s and p99 latency, served vs plain",
+        "value": served["snapshot_gbs"], "unit": "GB/s", "n_gpus": 1, "steps": len(trace),
+        "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic (seeded SplitMix64 bytes, PCG64 trace)",
+        "config": {"workload": f"{len(sizes)} clients log-uniform 64 MiB-8 GiB "
+                               f"({sum(sizes) / 2**30:.1f} GiB), 64 KiB pages, Poisson "
+                               f"{args.rate:g} req/s, "
+                               f"snapshot:restore 4:1, dirty U(2%,30%), 64 GiB pinned budget",
+                   "duration_s": args.duration, "excluded_s": warm, "policy": args.policy,
+                   "offered_d2h_gbs": round(offered / 1e9, 2)},
+        "served": served, "plain": plain,
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     args = parse_args()
     if args.pmc_summary:
@@ -246,6 +518,10 @@ def main():
               "multi-GPU runs are not part of this build (each GPU would snapshot its own "
               "regions independently).", file=sys.stderr)
         sys.exit(2)
+    if args.config == "batched":
+        return bench_batched(args)
+    if args.config == "served":
+        return bench_served(args)
     import numpy as np
 
     import paper_1808_00117_amd as crum

@@ -50,6 +50,7 @@ extern "C" {
 
 typedef struct crum_ctx crum_ctx;
 typedef struct crum_plan crum_plan;
+typedef struct crum_server crum_server;
 
 /* One snapshotted allocation.  base: device or managed address of the
  * current bytes; shadow: device address of the baseline copy, or NULL (all
@@ -207,6 +208,82 @@ int crum_plan_group_times(crum_plan* plan, double* ms, uint32_t cap);
 
 /* Destroy a plan (waits for its outstanding work). NULL is ignored. */
 void crum_plan_destroy(crum_plan* plan);
+
+/* ---------------------------------------------------------------- serving
+ * A request loop for many clients, each owning persistent device state
+ * (regions with resident shadows).  Requests run first-in first-out per
+ * client, so a client's results do not depend on the other clients; up to
+ * n_slots requests of different clients run at once, each slot with its own
+ * context, streams and device staging buffer (sized for the largest client's
+ * worst-case image), so their device work overlaps.  Snapshots use
+ * CRUM_UPDATE_SHADOW and land in a pinned arena of pinned_budget bytes: on the
+ * pipelined path (see crum_server_set_policy) the client's worst-case image is
+ * reserved when it fits at once, the snapshot drains into it while it runs,
+ * and the reservation is trimmed to the image; otherwise the image is built on the device first, the
+ * client's previous image is released (the shadow now holds the new
+ * snapshot), exactly the new image's bytes are reserved -- waiting while the
+ * arena is full, CRUM_ENOSPC after 30 s -- and the image is drained into them.
+ * A restore re-applies the client's latest image with CRUM_VERIFY |
+ * CRUM_UPDATE_SHADOW. */
+enum { CRUM_REQ_SNAPSHOT = 1, CRUM_REQ_RESTORE = 2 };
+
+typedef struct {
+    const crum_region* regions; /* every region needs a shadow; copied at creation */
+    uint32_t n_regions;
+    uint32_t page_size;
+} crum_client;
+
+typedef struct {
+    uint64_t id;          /* as returned by crum_server_submit */
+    uint64_t tag;         /* caller value given at submit */
+    uint32_t client;
+    uint32_t kind;        /* CRUM_REQ_SNAPSHOT or CRUM_REQ_RESTORE */
+    int32_t code;         /* CRUM_OK or an error */
+    uint32_t meta_crc;    /* bytes 56..59 of the image (with crcs_crc, a digest of it) */
+    uint32_t crcs_crc;
+    uint32_t reserved;
+    uint64_t n_dirty;
+    uint64_t image_bytes;
+    double arrival_s;     /* seconds since server creation: submit, start, completion */
+    double start_s;
+    double done_s;
+} crum_server_completion;
+
+/* Called on a worker thread before a request runs, with the stream the
+ * request will use; a harness enqueues its own work (for example changes to
+ * the client's memory) on that stream. */
+typedef void (*crum_server_prepare_fn)(void* user, uint32_t client, uint32_t kind, uint64_t tag,
+                                       void* stream);
+
+/* Returns CRUM_OK, CRUM_EINVAL (bad client table, overlapping ranges, a
+ * region without shadow, n_slots outside 1..64) or CRUM_EHIP. */
+int crum_server_create(int device, const crum_client* clients, uint32_t n_clients,
+                       uint32_t n_slots, uint64_t pinned_budget, crum_server** out);
+int crum_server_set_prepare(crum_server* server, crum_server_prepare_fn fn, void* user);
+/* Which snapshot path to use: CRUM_SERVE_TWO_STAGE always builds the image on
+ * the device before reserving; CRUM_SERVE_PIPELINED reserves the worst case
+ * whenever it fits; CRUM_SERVE_ADAPTIVE (default) pipelines only when no other
+ * request is waiting (latency), and builds first under a backlog (throughput:
+ * one long copy per request keeps the link busier than many short ones). */
+enum { CRUM_SERVE_ADAPTIVE = 0, CRUM_SERVE_TWO_STAGE = 1, CRUM_SERVE_PIPELINED = 2 };
+int crum_server_set_policy(crum_server* server, int policy);
+/* Enqueue a request (non-blocking); *id receives its id. */
+int crum_server_submit(crum_server* server, uint32_t client, uint32_t kind, uint64_t tag,
+                       uint64_t* id);
+/* Move up to max completions into out (*n of them); with wait_all, first wait
+ * until no request is queued or running. */
+int crum_server_poll(crum_server* server, crum_server_completion* out, uint32_t max, uint32_t* n,
+                     int wait_all);
+/* Seconds since the server was created (the clock of the completion times). */
+double crum_server_time(crum_server* server);
+/* Pinned bytes currently reserved by images. */
+int crum_server_pinned_used(crum_server* server, uint64_t* bytes);
+/* The client's latest image (pinned host memory owned by the server); valid
+ * while no request of that client is queued or running. */
+int crum_server_latest_image(crum_server* server, uint32_t client, const void** ptr,
+                             uint64_t* bytes);
+/* Finish queued requests, stop the workers and free everything. */
+void crum_server_destroy(crum_server* server);
 
 /* Launch and pipeline parameters of a context (defaults in parentheses).
  * CRUM_PARAM_DIFF_BLOCKS: persistent grid of the diff kernel, in 256-thread

@@ -44,6 +44,26 @@ class crum_request(ctypes.Structure):
                 ("reserved", ctypes.c_uint32), ("seq", ctypes.c_uint64)]
 
 
+class crum_client(ctypes.Structure):
+    _fields_ = [("regions", ctypes.c_void_p), ("n_regions", ctypes.c_uint32),
+                ("page_size", ctypes.c_uint32)]
+
+
+class crum_server_completion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("client", ctypes.c_uint32),
+                ("kind", ctypes.c_uint32), ("code", ctypes.c_int32),
+                ("meta_crc", ctypes.c_uint32), ("crcs_crc", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("n_dirty", ctypes.c_uint64),
+                ("image_bytes", ctypes.c_uint64), ("arrival_s", ctypes.c_double),
+                ("start_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+
+
+PREPARE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                              ctypes.c_uint64, ctypes.c_void_p)
+CRUM_REQ_SNAPSHOT, CRUM_REQ_RESTORE = 1, 2
+CRUM_SERVE_ADAPTIVE, CRUM_SERVE_TWO_STAGE, CRUM_SERVE_PIPELINED = 0, 1, 2
+
+
 class crum_request_status(ctypes.Structure):
     _fields_ = [("status", crum_status), ("image_offset", ctypes.c_uint64)]
 
@@ -62,6 +82,15 @@ _SIGS = {
     "crum_plan_groups": (_I, [_P, ctypes.POINTER(_U32), _P, _U32]),
     "crum_plan_group_times": (_I, [_P, _P, _U32]),
     "crum_plan_destroy": (None, [_P]),
+    "crum_server_create": (_I, [_I, _P, _U32, _U32, _U64, ctypes.POINTER(_P)]),
+    "crum_server_set_prepare": (_I, [_P, _P, _P]),
+    "crum_server_set_policy": (_I, [_P, _I]),
+    "crum_server_submit": (_I, [_P, _U32, _U32, _U64, ctypes.POINTER(_U64)]),
+    "crum_server_poll": (_I, [_P, _P, _U32, ctypes.POINTER(_U32), _I]),
+    "crum_server_time": (ctypes.c_double, [_P]),
+    "crum_server_pinned_used": (_I, [_P, ctypes.POINTER(_U64)]),
+    "crum_server_latest_image": (_I, [_P, _U32, ctypes.POINTER(_P), ctypes.POINTER(_U64)]),
+    "crum_server_destroy": (None, [_P]),
     "crum_ctx_set_param": (_I, [_P, _I, _U64]),
     "crum_ctx_get_param": (_I, [_P, _I, ctypes.POINTER(_U64)]),
     "crum_ctx_set_timing": (_I, [_P, _I]),
@@ -187,6 +216,82 @@ class Plan:
     def destroy(self) -> None:
         if self.handle:
             lib().crum_plan_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class Server:
+    """Owns a crum_server.  clients: sequence of (regions, page_size) where
+    regions is a sequence of (base, shadow, len, id)."""
+
+    def __init__(self, clients, n_slots: int, pinned_budget: int, device: int = 0,
+                 prepare=None):
+        self._tables = [region_table(regs) for regs, _ in clients]
+        arr = (crum_client * max(1, len(clients)))()
+        for i, ((regs, ps), tab) in enumerate(zip(clients, self._tables)):
+            arr[i] = crum_client(ctypes.cast(tab, _P) if len(regs) else None, len(regs), ps)
+        self._clients = arr
+        h = _P()
+        rc = lib().crum_server_create(device, ctypes.cast(arr, _P), len(clients), n_slots,
+                                      pinned_budget, ctypes.byref(h))
+        if rc != CRUM_OK:
+            raise RuntimeError(f"crum_server_create: {CODE_NAMES.get(rc, rc)}")
+        self.handle = h.value
+        self._prepare = None
+        if prepare is not None:
+            self._prepare = PREPARE_FN(prepare)
+            lib().crum_server_set_prepare(self.handle, ctypes.cast(self._prepare, _P), None)
+
+    def set_policy(self, policy: int) -> None:
+        rc = lib().crum_server_set_policy(self.handle, policy)
+        if rc != CRUM_OK:
+            raise ValueError(CODE_NAMES.get(rc, rc))
+
+    def submit(self, client: int, kind: int, tag: int = 0) -> int:
+        i = _U64()
+        rc = lib().crum_server_submit(self.handle, client, kind, tag, ctypes.byref(i))
+        if rc != CRUM_OK:
+            raise RuntimeError(f"crum_server_submit: {CODE_NAMES.get(rc, rc)}")
+        return i.value
+
+    def poll(self, wait_all: bool = False, max_n: int = 4096):
+        arr = (crum_server_completion * max_n)()
+        n = _U32()
+        rc = lib().crum_server_poll(self.handle, ctypes.cast(arr, _P), max_n, ctypes.byref(n),
+                                    1 if wait_all else 0)
+        if rc != CRUM_OK:
+            raise RuntimeError(f"crum_server_poll: {CODE_NAMES.get(rc, rc)}")
+        out = []
+        for i in range(n.value):
+            c = arr[i]
+            out.append({f: getattr(c, f) for f, _ in crum_server_completion._fields_})
+        if wait_all and n.value == max_n:
+            out.extend(self.poll(True, max_n))
+        return out
+
+    def time(self) -> float:
+        return lib().crum_server_time(self.handle)
+
+    def pinned_used(self) -> int:
+        v = _U64()
+        lib().crum_server_pinned_used(self.handle, ctypes.byref(v))
+        return v.value
+
+    def latest_image(self, client: int):
+        p, n = _P(), _U64()
+        rc = lib().crum_server_latest_image(self.handle, client, ctypes.byref(p), ctypes.byref(n))
+        if rc != CRUM_OK:
+            return None
+        return p.value, n.value
+
+    def destroy(self) -> None:
+        if self.handle:
+            lib().crum_server_destroy(self.handle)
             self.handle = 0
 
     def __del__(self):

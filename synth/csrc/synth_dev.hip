@@ -68,6 +68,50 @@ __global__ void synth_mutate_kernel(uint8_t* __restrict__ region_bytes, uint64_t
     }
 }
 
+// Page selection by hash: page p of a region is chosen for (sel_seed) when
+// mix(sel_seed * G + p * R) < threshold, i.e. with probability threshold/2^64,
+// independently per page.  One workgroup per page.
+__device__ __forceinline__ bool page_chosen(uint64_t sel_seed, uint64_t p, uint64_t threshold)
+{
+    return sm64_mix(sel_seed * 0x9E3779B97F4A7C15ULL + p * 0xD1B54A32D192ED03ULL) < threshold;
+}
+
+// Chosen pages get the word mutation (kind 0) of synth_mutate_kernel.
+__global__ void synth_mutate_frac_kernel(uint8_t* __restrict__ region_bytes, uint64_t page_size,
+                                         uint64_t n_pages, uint64_t sel_seed, uint64_t threshold,
+                                         uint64_t ms, uint64_t region)
+{
+    const uint64_t page = blockIdx.x;
+    if (page >= n_pages || !page_chosen(sel_seed, page, threshold) || threadIdx.x >= 16)
+        return;
+    const uint64_t t = threadIdx.x;
+    uint8_t* pb = region_bytes + page * page_size;
+    const uint64_t h0 = mut_hash(ms, region, page, 0);
+    const uint64_t W = page_size / 4;
+    const uint64_t k = 1 + (h0 & 15);
+    if (t >= k)
+        return;
+    const uint64_t start = (h0 >> 8) % W;
+    const uint64_t step = ((h0 >> 40) | 1) % W;
+    const uint64_t pos = (start + t * step) % W;
+    const uint32_t m = (uint32_t)(1 + mut_hash(ms, region, page, t + 1) % 0xFFFFFFFFULL);
+    uint32_t* w = (uint32_t*)(pb + 4 * pos);
+    *w ^= m;
+}
+
+// Chosen pages are overwritten with generator bytes of another stream.
+__global__ void synth_clobber_frac_kernel(uint64_t* __restrict__ region_words, uint64_t page_size,
+                                          uint64_t n_pages, uint64_t sel_seed,
+                                          uint64_t threshold, uint64_t base)
+{
+    const uint64_t page = blockIdx.x;
+    if (page >= n_pages || !page_chosen(sel_seed, page, threshold))
+        return;
+    const uint64_t wpp = page_size / 8;
+    for (uint64_t i = threadIdx.x; i < wpp; i += blockDim.x)
+        region_words[page * wpp + i] = sm64_mix(base + page * wpp + i);
+}
+
 // Plain 16-byte copy of n16 words (a copy kernel of known size, used to
 // calibrate hardware byte counters).
 __global__ void synth_copy_kernel(uint4* __restrict__ dst, const uint4* __restrict__ src,
@@ -121,6 +165,38 @@ int synth_mutate_dev(void* region_bytes, uint64_t page_size, const int64_t* d_pa
     hipLaunchKernelGGL(synth_mutate_kernel, dim3((unsigned)blocks), dim3(256), 0,
                        (hipStream_t)stream, (uint8_t*)region_bytes, page_size, d_pages, n_pages,
                        kind, ms, region);
+    return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+int synth_mutate_frac_dev(void* region_bytes, uint64_t nbytes, uint64_t page_size,
+                          uint64_t sel_seed, uint64_t threshold, uint64_t ms, uint64_t region,
+                          void* stream)
+{
+    if (page_size < 4096 || (page_size & (page_size - 1)) || nbytes % page_size)
+        return -1;
+    const uint64_t n = nbytes / page_size;
+    if (n == 0)
+        return 0;
+    hipLaunchKernelGGL(synth_mutate_frac_kernel, dim3((unsigned)n), dim3(64), 0,
+                       (hipStream_t)stream, (uint8_t*)region_bytes, page_size, n, sel_seed,
+                       threshold, ms, region);
+    return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+int synth_clobber_frac_dev(void* region_bytes, uint64_t nbytes, uint64_t page_size,
+                           uint64_t sel_seed, uint64_t threshold, uint64_t seed, uint64_t region,
+                           void* stream)
+{
+    if (((uintptr_t)region_bytes & 7) || page_size < 4096 || (page_size & (page_size - 1)) ||
+        nbytes % page_size)
+        return -1;
+    const uint64_t n = nbytes / page_size;
+    if (n == 0)
+        return 0;
+    const uint64_t base = seed * 0x9E3779B97F4A7C15ULL + region * 0xD1B54A32D192ED03ULL;
+    hipLaunchKernelGGL(synth_clobber_frac_kernel, dim3((unsigned)n), dim3(256), 0,
+                       (hipStream_t)stream, (uint64_t*)region_bytes, page_size, n, sel_seed,
+                       threshold, base);
     return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 

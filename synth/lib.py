@@ -79,6 +79,11 @@ def dev_lib():
         lib.synth_mutate_dev.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                                          ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64,
                                          ctypes.c_uint64, ctypes.c_void_p]
+        for nm in ("synth_mutate_frac_dev", "synth_clobber_frac_dev"):
+            f = getattr(lib, nm)
+            f.restype = ctypes.c_int
+            f.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                          ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p]
         lib.synth_copy_dev.restype = ctypes.c_int
         lib.synth_copy_dev.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                        ctypes.c_void_p]
@@ -138,6 +143,25 @@ def mutate_dev(ptr: int, region_bytes: int, page_size: int, d_pages_ptr: int, n_
         raise ValueError("mutated page beyond region end")
     _check(dev_lib().synth_mutate_dev(ptr, page_size, d_pages_ptr, n_pages, kind, ms, region,
                                       stream), "synth_mutate_dev")
+
+
+def frac_threshold(f: float) -> int:
+    return min((1 << 64) - 1, int(f * (1 << 64)))
+
+
+def mutate_frac_dev(ptr: int, nbytes: int, page_size: int, sel_seed: int, frac: float, ms: int,
+                    region: int, stream: int = 0) -> None:
+    """Word mutation of the pages selected by hash with probability `frac`."""
+    _check(dev_lib().synth_mutate_frac_dev(ptr, nbytes, page_size, sel_seed, frac_threshold(frac),
+                                           ms, region, stream), "synth_mutate_frac_dev")
+
+
+def clobber_frac_dev(ptr: int, nbytes: int, page_size: int, sel_seed: int, frac: float,
+                     seed: int, region: int, stream: int = 0) -> None:
+    """Overwrite the same hash-selected pages with bytes of another stream."""
+    _check(dev_lib().synth_clobber_frac_dev(ptr, nbytes, page_size, sel_seed,
+                                            frac_threshold(frac), seed, region, stream),
+           "synth_clobber_frac_dev")
 
 
 def copy_dev(dst: int, src: int, nbytes: int, stream: int = 0) -> None:

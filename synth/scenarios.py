@@ -221,3 +221,38 @@ def host_page(scn: Scenario, index: int, page: int, shadow: bool):
 def _mutate_one(page_buf: np.ndarray, P: int, page: int, kind: int, ms: int, region: int):
     from .lib import host_lib
     host_lib().synth_mutate_page_host(page_buf.ctypes.data, P, kind, ms, region, page)
+
+
+def served_clients(seed: int = 1005, n_clients: int = 32, min_bytes: int = 64 * MiB,
+                   max_bytes: int = 8 * GiB, page_size: int = 64 * KiB,
+                   cap_total: int = 120 * GiB) -> List[int]:
+    """Client state sizes: log-uniform in [min_bytes, max_bytes], rounded up to
+    whole pages; the draw is repeated if the total exceeds cap_total."""
+    rng = _rng(seed)
+    lo, hi = math.log2(min_bytes), math.log2(max_bytes)
+    while True:
+        raw = np.exp2(lo + (hi - lo) * rng.random(n_clients))
+        sizes = [int(math.ceil(x / page_size)) * page_size for x in raw]
+        if sum(sizes) <= cap_total:
+            return sizes
+
+
+def served_trace(seed: int = 1005, n_clients: int = 32, rate: float = 200.0,
+                 duration: float = 60.0, snapshot_share: float = 0.8,
+                 frac_lo: float = 0.02, frac_hi: float = 0.30):
+    """Open-loop Poisson arrivals at `rate` requests/s over `duration` s; each
+    request picks a client uniformly and is a snapshot with probability
+    `snapshot_share` (4:1), else a restore; snapshots carry the fraction of the
+    client's pages changed before them, U(frac_lo, frac_hi).
+    Returns a list of (arrival_s, client, kind, frac) with kind 1 snapshot,
+    2 restore."""
+    rng = _rng(seed + 17)
+    t, out = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            return out
+        c = int(rng.integers(0, n_clients))
+        snap = rng.random() < snapshot_share
+        f = float(frac_lo + (frac_hi - frac_lo) * rng.random()) if snap else 0.0
+        out.append((t, c, 1 if snap else 2, f))
