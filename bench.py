@@ -48,7 +48,8 @@ def parse_args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="many", choices=["many", "plain", "batched", "served"])
+    ap.add_argument("--config", default="many",
+                    choices=["many", "plain", "batched", "served", "managed"])
     ap.add_argument("--duration", type=float, default=60.0, help="served: trace seconds")
     ap.add_argument("--slots", type=int, default=6, help="served: concurrent request slots")
     ap.add_argument("--rate", type=float, default=200.0, help="served: arrivals per second")
@@ -60,6 +61,9 @@ def parse_args():
     ap.add_argument("--tune-cache", default=None,
                     help="tuning cache path (default: the package's tuning_cache.json)")
     ap.add_argument("--no-corunner", action="store_true")
+    ap.add_argument("--cold", action="store_true",
+                    help="plain workload: rotate over 8 independent (current, shadow) pairs "
+                         "(1 GiB working set, larger than the 256 MB last-level cache)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline leg (0 disables it)")
     ap.add_argument("--quick", action="store_true",
@@ -296,15 +300,26 @@ def bench_batched(args):
 
     cache = args.tune_cache or autotune.DEFAULT_CACHE
     tuned = autotune.load("batched", cache)
+
+    def mean_request_latency(plan):
+        """Mean over requests of the time from launch start to the end of the
+        drain of the request's group, in seconds."""
+        gr = plan.groups()
+        gt = plan.group_times()
+        return sum((gr[g + 1] - gr[g]) * gt[g] for g in range(len(gt))) / len(reqs) / 1e3
+
     if args.tune:
+        # objective: mean request completion time (latency), which also
+        # tracks the makespan since the batch is drain-bound
         def trial():
             plan = make_plan()
             launch(plan)  # warm
-            t = launch(plan)
+            launch(plan)
+            t = mean_request_latency(plan)
             plan.destroy()
             return t
-        space = {"chunk_bytes": [64 << 20, 256 << 20, 1 << 30],
-                 "chunk_max_bytes": [1 << 30, 4 << 30, 16 << 30],
+        space = {"chunk_bytes": [4 << 20, 16 << 20, 64 << 20, 256 << 20],
+                 "chunk_max_bytes": [64 << 20, 256 << 20, 1 << 30, 4 << 30],
                  "pack_blocks": [512, 1024, 2048],
                  "diff_blocks": [512, 1024, 2048]}
         best, trials = autotune.search(ctx, trial, space, repeats=2, log=log)
@@ -504,6 +519,165 @@ def bench_served(args):
     print(json.dumps(result), flush=True)
 
 
+def fill_managed_host(buf, scn, region_index, pages, threads=16):
+    """Write the generator bytes of the listed pages from host threads."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import synth
+    r = scn.regions[region_index]
+    P = scn.page_size
+
+    def one(p):
+        synth.fill_host(P, r.fill_seed, r.fill_region, int(p) * P, out=buf.numpy(int(p) * P, P))
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(one, pages))
+
+
+def fill_managed_device(buf, scn, region_index, pages):
+    """Prefetch the listed pages to the device (runs coalesced), then write
+    their generator bytes with a device kernel."""
+    import paper_1808_00117_amd.hip as H
+    import synth
+    r = scn.regions[region_index]
+    P = scn.page_size
+    pages = sorted(int(p) for p in pages)
+    i, prefetch_rc = 0, set()
+    while i < len(pages):
+        j = i
+        while j + 1 < len(pages) and pages[j + 1] == pages[j] + 1:
+            j += 1
+        prefetch_rc.add(buf.prefetch(pages[i] * P, (j - i + 1) * P, 0, 0))
+        synth.fill_dev(buf.ptr + pages[i] * P, (j - i + 1) * P, r.fill_seed, r.fill_region,
+                       pages[i] * P, 0)
+        i = j + 1
+    H.device_synchronize()
+    return sorted(prefetch_rc)
+
+
+def bench_managed(args):
+    """Managed-memory workload: one 32 GiB hipMallocManaged region, 2 MiB
+    pages; 70 % of pages written last by host threads, 30 % prefetched to the
+    device and written by a kernel; the HBM shadow differs on 20 % of pages
+    by a 256-byte span.  The image must not depend on residency: it is
+    checked on sampled pages against bytes regenerated on the host, its
+    bitmap against the chosen set, and its checksums by the oracle's parser."""
+    import numpy as np
+
+    import oracle
+    import paper_1808_00117_amd as crum
+    import paper_1808_00117_amd.hip as H
+    import synth
+    from synth import scenarios as sc
+
+    crum.lib()
+    scn = sc.managed()
+    r = scn.regions[0]
+    P, G, N, D = scn.page_size, scn.total_pages, scn.total_bytes, scn.n_dirty
+    dev_pages = scn.meta["device_pages"]
+    host_pages = np.setdiff1d(np.arange(G), dev_pages)
+    t0 = time.perf_counter()
+    cur = H.ManagedBuffer(N)
+    attrs = H.pointer_attributes(cur.ptr)
+    log(f"[managed] pointer attributes {attrs}")
+    if not cur.device_mapped():
+        raise SystemExit("managed allocation is not mapped for the device; not launching")
+    fill_managed_host(cur, scn, 0, host_pages)
+    t_host = time.perf_counter() - t0
+    prefetch_rc = fill_managed_device(cur, scn, 0, dev_pages)
+    sh = H.DeviceBuffer(N)
+    synth.fill_dev(sh.ptr, N, r.fill_seed, r.fill_region, 0, 0)
+    pages_d = H.DeviceBuffer(8 * r.dirty_pages.size)
+    pd = np.ascontiguousarray(r.dirty_pages, np.int64)
+    H.memcpy_htod(pages_d.ptr, pd.ctypes.data, pd.nbytes)
+    synth.mutate_dev(sh.ptr, N, P, pages_d.ptr, pd.size, int(pd.max()), r.mut_kind, scn.mut_seed,
+                     r.fill_region, 0)
+    H.device_synchronize()
+    log(f"[managed] filled in {time.perf_counter() - t0:.1f} s (host part {t_host:.1f} s); "
+        f"prefetch status {prefetch_rc}")
+
+    def residency(pages):
+        locs = {}
+        for p in pages[:: max(1, len(pages) // 32)]:
+            rc, loc = cur.last_prefetch_location(int(p) * P, P)
+            locs[f"rc{rc}:loc{loc}"] = locs.get(f"rc{rc}:loc{loc}", 0) + 1
+        return locs
+    res_before = {"device_pages": residency(dev_pages), "host_pages": residency(host_pages)}
+    image_bytes = crum.crum_image_bytes(1, G, D, P)
+    cap = crum.crum_image_bytes(1, G, G, P)
+    staging = H.DeviceBuffer(cap)
+    himg = H.PinnedBuffer(cap)
+    status = H.PinnedBuffer(64)
+    ctx = crum.crum_ctx_create(0)
+    s1 = H.Stream()
+    table = crum.region_table([(cur.ptr, sh.ptr, N, r.id)])
+
+    def snap():
+        rc = crum.crum_snapshot(ctx, table, P, 0, 3, staging.ptr, cap, himg.ptr, cap, s1.handle,
+                                status.ptr)
+        assert rc == 0
+        s1.synchronize()
+        st = crum.read_status(status.ptr)
+        assert st.code == 0 and st.n_dirty == D and st.image_bytes == image_bytes, st
+
+    snap()
+    for _ in range(args.warmup):
+        snap()
+    crum.crum_ctx_timing_reset(ctx)
+    crum.crum_ctx_set_timing(ctx, True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        snap()
+    t_total = time.perf_counter() - t0
+    crum.crum_ctx_set_timing(ctx, False)
+    n_diff, diff_ms = crum.crum_ctx_timing(ctx, 0)
+    n_dr, drain_ms = crum.crum_ctx_timing(ctx, 2)
+    # parity on the image: checksums and layout by the oracle's parser, the
+    # bitmap against the chosen set, sampled pages and CRCs against bytes
+    # regenerated on the host
+    img = himg.numpy(image_bytes)
+    rc, hdr = oracle.parse(img)
+    assert rc == oracle.OK and hdr["n_dirty"] == D
+    W = (G + 63) // 64
+    bm = np.frombuffer(img[96:96 + 8 * W].tobytes(), np.uint64)
+    got = np.flatnonzero(np.unpackbits(bm.view(np.uint8), bitorder="little"))
+    assert np.array_equal(got, r.dirty_pages), "bitmap differs from the chosen set"
+    data_off = hdr["data_off"]
+    rng = np.random.default_rng(5)
+    for k in rng.choice(D, size=24, replace=False):
+        g = int(r.dirty_pages[k])
+        page = img[data_off + k * P: data_off + (k + 1) * P]
+        exp = synth.fill_host(P, r.fill_seed, r.fill_region, g * P)
+        assert np.array_equal(page, exp), f"page {g}"
+        crc = int(np.frombuffer(img[data_off + D * P + 4 * k: data_off + D * P + 4 * k + 4]
+                                .tobytes(), np.uint32)[0])
+        assert crc == oracle.crc32c(exp)
+    res_after = {"device_pages": residency(dev_pages), "host_pages": residency(host_pages)}
+    value = N * args.steps / t_total / 1e9
+    result = {
+        "metric": "snapshot GB/s (diff+CRC+compact+drain), managed memory",
+        "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * t_total / args.steps, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic (seeded SplitMix64 bytes, PCG64 scenario)",
+        "config": {"workload": "one 32 GiB hipMallocManaged region, 2 MiB pages, 70% of pages "
+                               "written last by host threads, 30% prefetched to the device and "
+                               "written by a kernel, shadow differs on 20% of pages (256-byte "
+                               "spans)", "scanned_bytes": N, "dirty_pages": D,
+                   "image_bytes": image_bytes},
+        "diff": {"achieved_gbs": round(2 * N * args.steps / (diff_ms * 1e-3) / 1e9, 1),
+                 "launches": n_diff},
+        "drain": {"achieved_gbs": round(image_bytes * args.steps / (drain_ms * 1e-3) / 1e9, 2)},
+        "residency": {"pointer_attributes": {k: v for k, v in attrs.items()
+                                             if k in ("type", "isManaged", "allocationFlags")},
+                      "before": res_before, "after": res_after,
+                      "prefetch_status": prefetch_rc},
+        "parity": "bitmap exact; 24 sampled pages and CRCs equal to host-regenerated bytes; "
+                  "image checksums verified by the oracle parser",
+    }
+    crum.crum_ctx_destroy(ctx)
+    print(json.dumps(result), flush=True)
+
+
 def main():
     args = parse_args()
     if args.pmc_summary:
@@ -522,6 +696,8 @@ def main():
         return bench_batched(args)
     if args.config == "served":
         return bench_served(args)
+    if args.config == "managed":
+        return bench_managed(args)
     import numpy as np
 
     import paper_1808_00117_amd as crum
@@ -542,6 +718,10 @@ def main():
         scn = sc.plain()
         workload = "plain"
         wl_name = "one 64 MiB allocation, 4 KiB pages, 5% of pages dirty"
+        if args.cold:
+            workload = "plain_cold"
+            wl_name += "; 8 independent copies rotated per step (1 GiB working set)"
+    copies = 8 if (args.config == "plain" and args.cold) else 1
     P = scn.page_size
     N = scn.total_bytes
     D = scn.n_dirty
@@ -556,10 +736,12 @@ def main():
         a.free()
         b.free()
     t0 = time.perf_counter()
-    pairs = materialize_raw(scn, H)
+    pair_sets = [materialize_raw(scn, H) for _ in range(copies)]
     log(f"[bench] materialised in {time.perf_counter() - t0:.1f} s")
-    regs = [(c.ptr, s.ptr if s else 0, r.nbytes, r.id) for (c, s), r in zip(pairs, scn.regions)]
-    table = crum.region_table(regs)
+    tables = [crum.region_table([(c.ptr, s.ptr if s else 0, r.nbytes, r.id)
+                                 for (c, s), r in zip(pairs, scn.regions)])
+              for pairs in pair_sets]
+    step_no = [0]
     image_bytes = crum.crum_image_bytes(R, G, D, P)
     # capacity for an image with every page dirty: the snapshot then runs in
     # its chunk-pipelined order (ENOSPC impossible)
@@ -593,6 +775,8 @@ def main():
     def run_snapshot(eager=True):
         crum.crum_ctx_set_param(ctx, crum.CRUM_PARAM_EAGER, 1 if eager else 0)
         c = cap if eager else image_bytes
+        table = tables[step_no[0] % copies]
+        step_no[0] += 1
         rc = crum.crum_snapshot(ctx, table, P, 0, 1, staging.ptr, c, h_image.ptr, c, s1.handle,
                                 status.ptr)
         assert rc == 0, rc
@@ -633,7 +817,7 @@ def main():
     e1.record(s2)
     graph_ms = e0.elapsed_ms(e1) / probe
     sax_alone_gbs = sax_bytes_per_pass * PASSES / (graph_ms * 1e-3) / 1e9
-    corun_on = not args.no_corunner
+    corun_on = args.config == "many" and not args.no_corunner
     log(f"[bench] snapshot alone {snap_alone_ms:.2f} ms (diff-first order {checked_ms:.2f} ms); "
         f"saxpy alone {sax_alone_gbs:.0f} GB/s ({graph_ms:.3f} ms per graph)")
 
@@ -688,7 +872,9 @@ def main():
     assert st.code == 0 and st.n_dirty == D, st
 
     n_diff, diff_ms = timing["diff"]
-    n_units = N >> 13 if P >= 8192 else N >> 12  # one flag byte per diff unit
+    # one flag byte per diff unit of min(P, 2^DIFF_UNIT_SHIFT) bytes
+    unit_shift = min(P.bit_length() - 1, crum.crum_ctx_get_param(ctx, crum.CRUM_PARAM_DIFF_UNIT_SHIFT))
+    n_units = N >> unit_shift
     diff_bytes_step = 2 * N + n_units
     diff_gbs = diff_bytes_step * args.steps / (diff_ms * 1e-3) / 1e9
     n_dr, drain_ms = timing["drain"]
@@ -705,6 +891,39 @@ def main():
     lat_ms = sorted(1e3 * v for v in lat)
     p50 = statistics.median(lat_ms)
     p99 = lat_ms[min(len(lat_ms) - 1, int(round(0.99 * (len(lat_ms) - 1))))]
+    p90 = lat_ms[min(len(lat_ms) - 1, int(round(0.90 * (len(lat_ms) - 1))))]
+
+    # restore (inverse path, outside the timed snapshot steps): the image just
+    # taken, uploaded from pinned host memory, every page CRC verified before
+    # any write, then scattered into the regions (their bytes already equal
+    # the image's pages, so the workload is unchanged for the next step)
+    crum.crum_ctx_timing_reset(ctx)
+    crum.crum_ctx_set_timing(ctx, True)
+    rest_lat = []
+    for i in range(2 if args.quick else 6):
+        t = time.perf_counter()
+        rc = crum.crum_restore(ctx, tables[0], h_image.ptr, image_bytes, crum.CRUM_VERIFY,
+                               staging.ptr, cap, s1.handle, status.ptr)
+        assert rc == 0, rc
+        s1.synchronize()
+        if i:
+            rest_lat.append(time.perf_counter() - t)
+        rst = read_status()
+        assert rst.code == 0 and rst.n_dirty == D, rst
+    crum.crum_ctx_set_timing(ctx, False)
+    n_v, verify_ms = crum.crum_ctx_timing(ctx, 5)
+    n_sc, scatter_ms = crum.crum_ctx_timing(ctx, 6)
+    rest_ms = 1e3 * statistics.median(rest_lat)
+    restore = {
+        "ms": round(rest_ms, 3),
+        "image_gbs": round(image_bytes / (rest_ms * 1e-3) / 1e9, 2),
+        "link_frac": round(image_bytes / (rest_ms * 1e-3) / 1e9 / LINK_PEAK_GBS, 4),
+        "verify_gbs": round((D * P + 4 * D) * n_v / max(verify_ms * 1e-3, 1e-12) / 1e9, 1)
+        if n_v else None,
+        "scatter_gbs": round(2 * D * P * n_sc / max(scatter_ms * 1e-3, 1e-12) / 1e9, 1)
+        if n_sc else None,
+        "what": "H2D of the image from pinned memory, CRC verify of every page, scatter",
+    }
 
     traffic = load_traffic(workload, diff_bytes_step * args.steps / max(n_diff, 1))
     result = {
@@ -735,7 +954,8 @@ def main():
                           f"({sax_graphs[0]} graphs during the timed steps)") if corun_on else None,
             "parallelism": "single GPU",
         },
-        "latency_ms": {"p50": round(p50, 3), "p99": round(p99, 3)},
+        "latency_ms": {"p50": round(p50, 3), "p90": round(p90, 3), "p99": round(p99, 3)},
+        "restore": restore,
         "roofline": {
             "bound": "hbm",
             "kernel": "k_diff",
@@ -756,7 +976,7 @@ def main():
             "snapshot_ms_alone": round(snap_alone_ms, 3),
             "snapshot_ms_with_corunner": round(p50, 3) if corun_on else None,
             "snapshot_ms_diff_first_order": round(checked_ms, 3),
-            "saxpy_gbs_alone": round(sax_alone_gbs, 1),
+            "saxpy_gbs_alone": round(sax_alone_gbs, 1) if corun_on else None,
             "saxpy_gbs_with_snapshot": round(sax_with, 1) if sax_with else None,
         },
     }

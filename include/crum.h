@@ -286,6 +286,7 @@ int crum_server_latest_image(crum_server* server, uint32_t client, const void** 
 void crum_server_destroy(crum_server* server);
 
 /* Launch and pipeline parameters of a context (defaults in parentheses).
+ * They change speed only: every image is the same whatever their values.
  * CRUM_PARAM_DIFF_BLOCKS: persistent grid of the diff kernel, in 256-thread
  *   workgroups (4 per compute unit).  CRUM_PARAM_PACK_BLOCKS: grid of the
  *   pack, verify and scatter kernels (4 per compute unit).
@@ -300,6 +301,11 @@ void crum_server_destroy(crum_server* server);
  * CRUM_PARAM_DIFF_UNIT_SHIFT: log2 of the largest diff unit, 12..14 (14):
  *   each wave compares min(page, 2^value) bytes per step.
  * CRUM_PARAM_DIFF_NONTEMPORAL: 1 marks the diff kernel's loads non-temporal (1).
+ * CRUM_PARAM_PIECE_SHIFT: log2 of the largest piece of a page one wave packs,
+ *   verifies or scatters, 12..16 (16); larger pages are split into pieces
+ *   whose CRCs are combined afterwards.
+ * CRUM_PARAM_PACK_DEPTH: 16-byte loads each lane keeps in flight in the pack
+ *   and verify kernels, 4, 8 or 16 (4).
  * Values of 0 are rejected (CRUM_EINVAL) except for the two on/off switches. */
 enum {
     CRUM_PARAM_DIFF_BLOCKS = 1,
@@ -309,7 +315,9 @@ enum {
     CRUM_PARAM_EAGER = 5,
     CRUM_PARAM_DRAIN_CHUNK_BYTES = 6,
     CRUM_PARAM_DIFF_UNIT_SHIFT = 7,
-    CRUM_PARAM_DIFF_NONTEMPORAL = 8
+    CRUM_PARAM_DIFF_NONTEMPORAL = 8,
+    CRUM_PARAM_PIECE_SHIFT = 9,
+    CRUM_PARAM_PACK_DEPTH = 10
 };
 int crum_ctx_set_param(crum_ctx* ctx, int param, uint64_t value);
 int crum_ctx_get_param(crum_ctx* ctx, int param, uint64_t* value);

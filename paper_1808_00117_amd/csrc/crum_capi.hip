@@ -273,6 +273,18 @@ int crum_ctx_set_param(crum_ctx* c, int param, uint64_t v)
         c->unit_shift_max = (uint32_t)v;
         return CRUM_OK;
     }
+    if (param == CRUM_PARAM_PIECE_SHIFT) {
+        if (v < kPieceShiftMin || v > kPieceShift)
+            return CRUM_EINVAL;
+        c->piece_shift = (uint32_t)v;
+        return CRUM_OK;
+    }
+    if (param == CRUM_PARAM_PACK_DEPTH) {
+        if (v != 4 && v != 8 && v != 16)
+            return CRUM_EINVAL;
+        c->pack_depth = (int)v;
+        return CRUM_OK;
+    }
     if (v == 0)
         return CRUM_EINVAL;
     switch (param) {
@@ -313,6 +325,8 @@ int crum_ctx_get_param(crum_ctx* c, int param, uint64_t* v)
     case CRUM_PARAM_DRAIN_CHUNK_BYTES: *v = c->drain_chunk_bytes; return CRUM_OK;
     case CRUM_PARAM_DIFF_UNIT_SHIFT: *v = c->unit_shift_max; return CRUM_OK;
     case CRUM_PARAM_DIFF_NONTEMPORAL: *v = c->diff_nt ? 1 : 0; return CRUM_OK;
+    case CRUM_PARAM_PIECE_SHIFT: *v = c->piece_shift; return CRUM_OK;
+    case CRUM_PARAM_PACK_DEPTH: *v = (uint64_t)c->pack_depth; return CRUM_OK;
     default: return CRUM_EINVAL;
     }
 }
@@ -410,7 +424,8 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     const size_t n_chunks = cuts.size() - 1;
 
     // ---- flatten, scratch, upload
-    const uint32_t np_shift = ps > kPieceShift ? ps - kPieceShift : 0;
+    const uint32_t pc_shift = c->piece_shift;
+    const uint32_t np_shift = ps > pc_shift ? ps - pc_shift : 0;
     const uint32_t us = std::min<uint32_t>(ps, c->unit_shift_max);
     std::vector<DevRegion> dregs(std::max<uint32_t>(1, n_regions));
     uint64_t n_pages = 0, n_units = 0;
@@ -492,10 +507,12 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
                 Span sp(c, kTPack, stream);
                 SlotRange sr{0, 0, d_bounds, (uint32_t)ci, g1 - g0};
                 CRUM_TRY(launch_pack(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
-                                     np_shift, staging, d_crcs, d_partials, c->d_tabs, d_glob,
-                                     c->shape.pack_blocks, stream));
+                                     np_shift, pc_shift, staging, d_crcs, d_partials,
+                                     c->d_tabs, d_glob, c->shape.pack_blocks, c->pack_depth,
+                                     stream));
                 CRUM_TRY(launch_finalize(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
-                                         np_shift, d_partials, d_crcs, staging, d_glob, stream));
+                                         np_shift, pc_shift, d_partials, d_crcs, staging, d_glob,
+                                         stream));
             }
             CRUM_TRY(hipEventRecord(c->ev_chunk[ci], stream));
         }
@@ -562,10 +579,12 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
                 Span sp(c, kTPack, stream);
                 SlotRange sr{k0, k1, nullptr, 0, k1 - k0};
                 CRUM_TRY(launch_pack(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
-                                     np_shift, staging, d_crcs, d_partials, c->d_tabs, d_glob,
-                                     c->shape.pack_blocks, stream));
+                                     np_shift, pc_shift, staging, d_crcs, d_partials,
+                                     c->d_tabs, d_glob, c->shape.pack_blocks, c->pack_depth,
+                                     stream));
                 CRUM_TRY(launch_finalize(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
-                                         np_shift, d_partials, d_crcs, staging, d_glob, stream));
+                                         np_shift, pc_shift, d_partials, d_crcs, staging, d_glob,
+                                         stream));
             }
             if (himg) {
                 CRUM_TRY(ensure_events(c->ev_chunk, ci + 1));
@@ -697,7 +716,8 @@ int crum_restore(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
         return restore_fail(h_status, CRUM_ENOSPC, D, G, image_bytes);
 
     // ---- device tables
-    const uint32_t np_shift = ps > kPieceShift ? ps - kPieceShift : 0;
+    const uint32_t pc_shift = c->piece_shift;
+    const uint32_t np_shift = ps > pc_shift ? ps - pc_shift : 0;
     std::vector<DevRegion> dregs(std::max<uint32_t>(1, n_regions));
     uint64_t n_pages = 0, n_units = 0;
     flatten(regions, n_regions, ps, c->unit_shift_max, 0, dregs.data(), &n_pages, &n_units);
@@ -754,14 +774,16 @@ int crum_restore(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
         Span sp(c, kTVerify, stream);
         SlotRange sr{0, D, nullptr, 0, D};
         CRUM_TRY(launch_pack(kModeVerify, d_regs, n_regions, d_reqs, d_out, d_list, sr, np_shift,
-                             staging, d_crcs, d_partials, c->d_tabs, d_glob,
-                             c->shape.pack_blocks, stream));
+                             pc_shift, staging, d_crcs, d_partials, c->d_tabs, d_glob,
+                             c->shape.pack_blocks, c->pack_depth, stream));
         CRUM_TRY(launch_finalize(kModeVerify, d_regs, n_regions, d_reqs, d_out, d_list, sr,
-                                 np_shift, d_partials, d_crcs, staging, d_glob, stream));
+                                 np_shift, pc_shift, d_partials, d_crcs, staging, d_glob,
+                                 stream));
     }
     {
         Span sp(c, kTScatter, stream);
-        CRUM_TRY(launch_scatter(d_regs, n_regions, d_reqs, d_out, d_list, D, np_shift, staging,
+        CRUM_TRY(launch_scatter(d_regs, n_regions, d_reqs, d_out, d_list, D, np_shift, pc_shift,
+                                staging,
                                 (flags & CRUM_UPDATE_SHADOW) ? 1 : 0, d_glob,
                                 c->shape.pack_blocks, stream));
     }

@@ -10,7 +10,8 @@ namespace crum {
 // loads, i.e. unit/1 KiB loads per array per lane.
 constexpr uint32_t kUnitShiftDefault = 14;
 // CRC piece: pages larger than this are split across waves and combined.
-constexpr uint32_t kPieceShift = 16;  // 64 KiB
+constexpr uint32_t kPieceShift = 16;  // largest (and default) pack piece: 64 KiB
+constexpr uint32_t kPieceShiftMin = 12;
 constexpr uint32_t kNoBad = 0xFFFFFFFFu;
 
 // One region of the flattened page space (host-built, uploaded per call).
@@ -114,16 +115,22 @@ hipError_t launch_scan(const uint64_t* bitmap, uint64_t w0, uint64_t w1, uint64_
                        uint64_t capacity, int restore_mode, hipStream_t s);
 hipError_t launch_list(const uint64_t* bitmap, const uint32_t* prefix, uint64_t w0, uint64_t w1,
                        uint32_t* list, hipStream_t s);
-// Pack: shadows are updated for regions whose flags bit 0 is set.
+// Pack, verify and scatter work on (slot, piece) items: a page of 2^ps bytes
+// is cut into pieces of 2^min(ps, piece_shift) bytes, np_shift is log2 of the
+// largest piece count per slot in the launch, and finalize combines the piece
+// CRCs of pages larger than one piece.  depth: 16-byte loads in flight per
+// lane (4, 8 or 16).  Pack updates the shadows of regions whose flags bit 0
+// is set.
 hipError_t launch_pack(int mode, const DevRegion* regs, uint32_t n_regs, const DevRequest* reqs,
                        const DevReqOut* out, const uint32_t* list, SlotRange range,
-                       uint32_t np_shift, uint8_t* staging, uint32_t* crc_out,
-                       uint32_t* partials, const CrcTables* tabs, DevGlobal* glob, int blocks,
-                       hipStream_t s);
+                       uint32_t np_shift, uint32_t piece_shift, uint8_t* staging,
+                       uint32_t* crc_out, uint32_t* partials, const CrcTables* tabs,
+                       DevGlobal* glob, int blocks, int depth, hipStream_t s);
 hipError_t launch_finalize(int mode, const DevRegion* regs, uint32_t n_regs,
                            const DevRequest* reqs, const DevReqOut* out, const uint32_t* list,
-                           SlotRange range, uint32_t np_shift, const uint32_t* partials,
-                           uint32_t* crc_out, uint8_t* staging, DevGlobal* glob, hipStream_t s);
+                           SlotRange range, uint32_t np_shift, uint32_t piece_shift,
+                           const uint32_t* partials, uint32_t* crc_out, uint8_t* staging,
+                           DevGlobal* glob, hipStream_t s);
 // One workgroup per request of [q0, q1).  Requests with ENOSPC get only their
 // prefix (header, table, bitmap), and only when it fits within `capacity`.
 hipError_t launch_header(const DevRegion* regs, const DevRequest* reqs, uint32_t q0, uint32_t q1,
@@ -140,7 +147,8 @@ hipError_t launch_restore_check(const DevRequest* reqs, uint32_t n_reqs, const D
                                 hipStream_t s);
 hipError_t launch_scatter(const DevRegion* regs, uint32_t n_regs, const DevRequest* reqs,
                           const DevReqOut* out, const uint32_t* list, uint64_t n_slots,
-                          uint32_t np_shift, const uint8_t* staging, int update_shadow,
+                          uint32_t np_shift, uint32_t piece_shift, const uint8_t* staging,
+                          int update_shadow,
                           const DevGlobal* glob, int blocks, hipStream_t s);
 hipError_t launch_restore_finish(DevReqOut* out, uint32_t n_reqs, DevGlobal* glob,
                                  hipStream_t s);

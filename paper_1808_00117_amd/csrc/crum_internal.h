@@ -99,6 +99,8 @@ struct crum_ctx {
     uint32_t unit_shift_max = crum::kUnitShiftDefault;
     bool diff_nt = true;
     uint64_t drain_chunk_bytes = 8ull << 20;
+    uint32_t piece_shift = crum::kPieceShift;
+    int pack_depth = 4;
     bool eager = true;
     bool timing = false;
     std::vector<hipEvent_t> pool;
@@ -122,6 +124,8 @@ inline LaunchShape ctx_shape(const crum_ctx* c) { return c->shape; }
 inline const CrcTables* ctx_tables(const crum_ctx* c) { return c->d_tabs; }
 inline int ctx_diff_nt(const crum_ctx* c) { return c->diff_nt ? 1 : 0; }
 inline hipStream_t ctx_side_stream(const crum_ctx* c) { return c->side; }
+inline uint32_t ctx_piece_shift(const crum_ctx* c) { return c->piece_shift; }
+inline int ctx_pack_depth(const crum_ctx* c) { return c->pack_depth; }
 
 }  // namespace crum
 

@@ -108,7 +108,39 @@ __device__ __forceinline__ uint32_t lane_combine(const uint32_t* __restrict__ ld
 
 // Raw (zero-initialised) CRC of `steps` KiB at src, copied to dst (and sh)
 // when STORE.  All lanes return the same value.
-template <bool STORE>
+template <bool STORE, int U>
+__device__ __forceinline__ uint32_t piece_steps(const uint4* __restrict__ src,
+                                                uint4* __restrict__ dst, uint4* __restrict__ sh,
+                                                uint32_t* t_io, uint32_t steps, uint32_t lane,
+                                                const uint32_t* __restrict__ lds, uint32_t s)
+{
+    const uint32_t* Z1024 = lds + kSliceWords + 5 * 1024;
+    uint32_t t = *t_io;
+    for (; t + U <= steps; t += U) {
+        uint4 w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            w[u] = src[(t + u) * 64 + lane];
+        if (STORE) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                dst[(t + u) * 64 + lane] = w[u];
+            if (sh) {
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    sh[(t + u) * 64 + lane] = w[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            s = shiftz(Z1024, s) ^ word_crc(lds, w[u]);
+    }
+    *t_io = t;
+    return s;
+}
+
+// DEPTH: 16-byte loads each lane issues before it folds them into its CRC.
+template <bool STORE, int DEPTH>
 __device__ __forceinline__ uint32_t wave_piece_crc(const uint4* __restrict__ src,
                                                    uint4* __restrict__ dst,
                                                    uint4* __restrict__ sh, uint32_t steps,
@@ -118,25 +150,9 @@ __device__ __forceinline__ uint32_t wave_piece_crc(const uint4* __restrict__ src
     const uint32_t* Z1024 = lds + kSliceWords + 5 * 1024;
     uint32_t s = 0;
     uint32_t t = 0;
-    for (; t + 4 <= steps; t += 4) {
-        uint4 w[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            w[u] = src[(t + u) * 64 + lane];
-        if (STORE) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                dst[(t + u) * 64 + lane] = w[u];
-            if (sh) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    sh[(t + u) * 64 + lane] = w[u];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            s = shiftz(Z1024, s) ^ word_crc(lds, w[u]);
-    }
+    s = piece_steps<STORE, DEPTH>(src, dst, sh, &t, steps, lane, lds, s);
+    if (DEPTH > 4)
+        s = piece_steps<STORE, 4>(src, dst, sh, &t, steps, lane, lds, s);
     for (; t < steps; ++t) {
         const uint4 w = src[t * 64 + lane];
         if (STORE) {
@@ -452,12 +468,13 @@ __device__ __forceinline__ void slot_range(const SlotRange& sr, uint64_t* lo, ui
 // Pack: copy the dirty page into the image's page area (and the shadow) and
 // write its CRC to crc_out[slot].  Verify: recompute the CRC of a packed page
 // of the image and compare with the image's CRC array.
-template <int MODE>
+template <int MODE, int DEPTH>
 __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs, uint32_t n_regs,
                                               const DevRequest* __restrict__ reqs,
                                               const DevReqOut* __restrict__ out,
                                               const uint32_t* __restrict__ list, SlotRange sr,
-                                              uint32_t np_shift, uint8_t* __restrict__ staging,
+                                              uint32_t np_shift, uint32_t piece_shift,
+                                              uint8_t* __restrict__ staging,
                                               uint32_t* __restrict__ crc_out,
                                               uint32_t* __restrict__ partials,
                                               const CrcTables* __restrict__ tabs,
@@ -495,7 +512,7 @@ __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs
         if (MODE == kModePack && O.code != 0)
             continue;  // the request's image did not fit: nothing is written
         const uint32_t ps = R.page_shift;
-        const uint32_t pb_shift = ps < kPieceShift ? ps : kPieceShift;
+        const uint32_t pb_shift = ps < piece_shift ? ps : piece_shift;
         if (piece >= (1u << (ps - pb_shift)))
             continue;
         const uint64_t local = k - O.slot_base;
@@ -510,11 +527,11 @@ __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs
             uint4* sh = ((R.flags & 1u) && R.shadow)
                             ? reinterpret_cast<uint4*>(R.shadow + page_off + piece_off)
                             : nullptr;
-            raw = wave_piece_crc<true>(src, reinterpret_cast<uint4*>(slot_ptr), sh, steps, lane,
-                                       lds);
+            raw = wave_piece_crc<true, DEPTH>(src, reinterpret_cast<uint4*>(slot_ptr), sh, steps,
+                                              lane, lds);
         } else {
-            raw = wave_piece_crc<false>(reinterpret_cast<const uint4*>(slot_ptr), nullptr,
-                                        nullptr, steps, lane, lds);
+            raw = wave_piece_crc<false, DEPTH>(reinterpret_cast<const uint4*>(slot_ptr), nullptr,
+                                               nullptr, steps, lane, lds);
         }
         if (lane != 0)
             continue;
@@ -534,25 +551,49 @@ __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs
     }
 }
 
+template <int MODE>
+static void launch_pack_mode(dim3 grid, int depth, hipStream_t s, const DevRegion* regs,
+                             uint32_t n_regs, const DevRequest* reqs, const DevReqOut* out,
+                             const uint32_t* list, SlotRange range, uint32_t np_shift,
+                             uint32_t piece_shift, uint8_t* staging, uint32_t* crc_out,
+                             uint32_t* partials, const CrcTables* tabs, DevGlobal* glob)
+{
+    if (depth == 16)
+        hipLaunchKernelGGL((k_pack<MODE, 16>), grid, dim3(256), 0, s, regs, n_regs, reqs, out,
+                           list, range, np_shift, piece_shift, staging, crc_out, partials, tabs,
+                           glob);
+    else if (depth == 8)
+        hipLaunchKernelGGL((k_pack<MODE, 8>), grid, dim3(256), 0, s, regs, n_regs, reqs, out,
+                           list, range, np_shift, piece_shift, staging, crc_out, partials, tabs,
+                           glob);
+    else
+        hipLaunchKernelGGL((k_pack<MODE, 4>), grid, dim3(256), 0, s, regs, n_regs, reqs, out,
+                           list, range, np_shift, piece_shift, staging, crc_out, partials, tabs,
+                           glob);
+}
+
 hipError_t launch_pack(int mode, const DevRegion* regs, uint32_t n_regs, const DevRequest* reqs,
                        const DevReqOut* out, const uint32_t* list, SlotRange range,
-                       uint32_t np_shift, uint8_t* staging, uint32_t* crc_out,
-                       uint32_t* partials, const CrcTables* tabs, DevGlobal* glob, int blocks,
-                       hipStream_t s)
+                       uint32_t np_shift, uint32_t piece_shift, uint8_t* staging,
+                       uint32_t* crc_out, uint32_t* partials, const CrcTables* tabs,
+                       DevGlobal* glob, int blocks, int depth, hipStream_t s)
 {
     const uint64_t max_items = range.max_slots << np_shift;
     if (max_items == 0)
         return hipSuccess;
+    if (piece_shift < kPieceShiftMin || piece_shift > kPieceShift)
+        return hipErrorInvalidValue;
     const uint64_t need = (max_items + 3) / 4;
     const uint64_t nb = need < (uint64_t)blocks ? need : (uint64_t)blocks;
+    const dim3 grid((unsigned)nb);
     if (mode == kModePack)
-        hipLaunchKernelGGL(k_pack<kModePack>, dim3((unsigned)nb), dim3(256), 0, s, regs, n_regs,
-                           reqs, out, list, range, np_shift, staging, crc_out, partials, tabs,
-                           glob);
+        launch_pack_mode<kModePack>(grid, depth, s, regs, n_regs, reqs, out, list, range,
+                                    np_shift, piece_shift, staging, crc_out, partials, tabs,
+                                    glob);
     else
-        hipLaunchKernelGGL(k_pack<kModeVerify>, dim3((unsigned)nb), dim3(256), 0, s, regs,
-                           n_regs, reqs, out, list, range, np_shift, staging, crc_out, partials,
-                           tabs, glob);
+        launch_pack_mode<kModeVerify>(grid, depth, s, regs, n_regs, reqs, out, list, range,
+                                      np_shift, piece_shift, staging, crc_out, partials, tabs,
+                                      glob);
     return hipGetLastError();
 }
 
@@ -565,6 +606,7 @@ __global__ __launch_bounds__(256) void k_finalize(const DevRegion* __restrict__ 
                                                   const DevReqOut* __restrict__ out,
                                                   const uint32_t* __restrict__ list,
                                                   SlotRange sr, uint32_t np_shift,
+                                                  uint32_t piece_shift,
                                                   const uint32_t* __restrict__ partials,
                                                   uint32_t* __restrict__ crc_out,
                                                   uint8_t* __restrict__ staging,
@@ -583,14 +625,14 @@ __global__ __launch_bounds__(256) void k_finalize(const DevRegion* __restrict__ 
     if (g < R.first_page || g - R.first_page >= (R.len >> R.page_shift))
         return;
     const uint32_t ps = R.page_shift;
-    if (ps <= kPieceShift)
+    if (ps <= piece_shift)
         return;
     const DevRequest& Q = reqs[R.req];
     const DevReqOut& O = out[R.req];
     if (MODE == kModePack && O.code != 0)
         return;
-    const uint32_t np = 1u << (ps - kPieceShift);
-    const uint32_t K = gf2_xpow8n(1ull << kPieceShift);
+    const uint32_t np = 1u << (ps - piece_shift);
+    const uint32_t K = gf2_xpow8n(1ull << piece_shift);
     uint32_t s = 0;
     for (uint32_t j = 0; j < np; ++j)
         s = gf2_mulmod(s, K) ^ partials[(i << np_shift) + j];
@@ -608,18 +650,21 @@ __global__ __launch_bounds__(256) void k_finalize(const DevRegion* __restrict__ 
 
 hipError_t launch_finalize(int mode, const DevRegion* regs, uint32_t n_regs,
                            const DevRequest* reqs, const DevReqOut* out, const uint32_t* list,
-                           SlotRange range, uint32_t np_shift, const uint32_t* partials,
-                           uint32_t* crc_out, uint8_t* staging, DevGlobal* glob, hipStream_t s)
+                           SlotRange range, uint32_t np_shift, uint32_t piece_shift,
+                           const uint32_t* partials, uint32_t* crc_out, uint8_t* staging,
+                           DevGlobal* glob, hipStream_t s)
 {
     if (range.max_slots == 0 || np_shift == 0)
         return hipSuccess;
     const unsigned nb = (unsigned)((range.max_slots + 255) / 256);
     if (mode == kModePack)
         hipLaunchKernelGGL(k_finalize<kModePack>, dim3(nb), dim3(256), 0, s, regs, n_regs, reqs,
-                           out, list, range, np_shift, partials, crc_out, staging, glob);
+                           out, list, range, np_shift, piece_shift, partials, crc_out, staging,
+                           glob);
     else
         hipLaunchKernelGGL(k_finalize<kModeVerify>, dim3(nb), dim3(256), 0, s, regs, n_regs,
-                           reqs, out, list, range, np_shift, partials, crc_out, staging, glob);
+                           reqs, out, list, range, np_shift, piece_shift, partials, crc_out,
+                           staging, glob);
     return hipGetLastError();
 }
 
@@ -873,13 +918,14 @@ hipError_t launch_restore_check(const DevRequest* reqs, uint32_t n_reqs, const D
     return hipGetLastError();
 }
 
-// Wave per (slot, 64 KiB piece): packed page -> its page (and shadow).
+// Wave per (slot, piece): packed page -> its page (and shadow).
 __global__ __launch_bounds__(256) void k_scatter(const DevRegion* __restrict__ regs,
                                                  uint32_t n_regs,
                                                  const DevRequest* __restrict__ reqs,
                                                  const DevReqOut* __restrict__ out,
                                                  const uint32_t* __restrict__ list,
                                                  uint64_t n_items, uint32_t np_shift,
+                                                 uint32_t piece_shift,
                                                  const uint8_t* __restrict__ staging,
                                                  int update_shadow,
                                                  const DevGlobal* __restrict__ glob)
@@ -906,7 +952,7 @@ __global__ __launch_bounds__(256) void k_scatter(const DevRegion* __restrict__ r
         const DevRequest& Q = reqs[R.req];
         const DevReqOut& O = out[R.req];
         const uint32_t ps = R.page_shift;
-        const uint32_t pb_shift = ps < kPieceShift ? ps : kPieceShift;
+        const uint32_t pb_shift = ps < piece_shift ? ps : piece_shift;
         if (piece >= (1u << (ps - pb_shift)))
             continue;
         const uint64_t page_off = (g - R.first_page) << ps;
@@ -937,16 +983,18 @@ __global__ __launch_bounds__(256) void k_scatter(const DevRegion* __restrict__ r
 
 hipError_t launch_scatter(const DevRegion* regs, uint32_t n_regs, const DevRequest* reqs,
                              const DevReqOut* out, const uint32_t* list, uint64_t n_slots,
-                             uint32_t np_shift, const uint8_t* staging, int update_shadow,
-                             const DevGlobal* glob, int blocks, hipStream_t s)
+                             uint32_t np_shift, uint32_t piece_shift, const uint8_t* staging,
+                             int update_shadow, const DevGlobal* glob, int blocks, hipStream_t s)
 {
     if (n_slots == 0)
         return hipSuccess;
+    if (piece_shift < kPieceShiftMin || piece_shift > kPieceShift)
+        return hipErrorInvalidValue;
     const uint64_t n_items = n_slots << np_shift;
     const uint64_t need = (n_items + 3) / 4;
     const uint64_t nb = need < (uint64_t)blocks ? need : (uint64_t)blocks;
     hipLaunchKernelGGL(k_scatter, dim3((unsigned)nb), dim3(256), 0, s, regs, n_regs, reqs, out,
-                       list, n_items, np_shift, staging, update_shadow, glob);
+                       list, n_items, np_shift, piece_shift, staging, update_shadow, glob);
     return hipGetLastError();
 }
 

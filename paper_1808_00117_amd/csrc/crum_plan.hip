@@ -101,6 +101,7 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
     std::vector<DevRequest> dreq(std::max<uint32_t>(1, n_reqs));
     std::vector<uint64_t> req_unit0(n_reqs + 1, 0), req_bytes(n_reqs, 0);
     uint64_t page = 0, unit = 0, ri = 0, max_np_shift = 0;
+    const uint32_t pc_shift = ctx_piece_shift(c);
     for (uint32_t q = 0; q < n_reqs; ++q) {
         const crum_request& r = reqs[q];
         const uint32_t ps = (uint32_t)ctx_log2(r.page_size);
@@ -136,8 +137,8 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
         Q.n_words = (g + 63) / 64;
         Q.data_off = (64 + 32ull * r.n_regions + 8 * Q.n_words + 4095) / 4096 * 4096;
         page += Q.n_words * 64;
-        if (ps > kPieceShift)
-            max_np_shift = std::max<uint64_t>(max_np_shift, ps - kPieceShift);
+        if (ps > pc_shift)
+            max_np_shift = std::max<uint64_t>(max_np_shift, ps - pc_shift);
     }
     req_unit0[n_reqs] = unit;
     const uint64_t G = page, W = page / 64;
@@ -255,10 +256,11 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
         SlotRange sr{0, 0, d_bounds, (uint32_t)gi, (w1 - w0) * 64};
         if (e == hipSuccess)
             e = launch_pack(kModePack, d_regs, p->n_regs, d_reqs, d_out, d_list, sr, np_shift,
-                            p->staging, d_crcs, d_part, tabs, d_glob, shape.pack_blocks, s);
+                            pc_shift, p->staging, d_crcs, d_part, tabs, d_glob,
+                            shape.pack_blocks, ctx_pack_depth(c), s);
         if (e == hipSuccess)
             e = launch_finalize(kModePack, d_regs, p->n_regs, d_reqs, d_out, d_list, sr, np_shift,
-                                d_part, d_crcs, p->staging, d_glob, s);
+                                pc_shift, d_part, d_crcs, p->staging, d_glob, s);
         if (e == hipSuccess)
             e = launch_header(d_regs, d_reqs, q0, q1, d_out, d_bitmap, d_crcs, p->staging,
                               capacity, tabs, s);

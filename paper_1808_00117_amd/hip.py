@@ -53,6 +53,11 @@ def hip():
             "hipGraphDestroy": [V],
             "hipGetDeviceCount": [ctypes.POINTER(I)],
             "hipMemGetInfo": [ctypes.POINTER(S), ctypes.POINTER(S)],
+            "hipMallocManaged": [ctypes.POINTER(V), S, ctypes.c_uint],
+            "hipMemPrefetchAsync": [V, S, I, V],
+            "hipMemAdvise": [V, S, I, I],
+            "hipMemRangeGetAttribute": [V, S, I, V, S],
+            "hipPointerGetAttributes": [V, V],
         }
         for name, args in sigs.items():
             f = getattr(h, name)
@@ -79,6 +84,69 @@ class DeviceBuffer:
         p = ctypes.c_void_p()
         check(hip().hipMalloc(ctypes.byref(p), max(nbytes, 16)), f"hipMalloc({nbytes})")
         self.ptr, self.nbytes = p.value, nbytes
+
+    def free(self) -> None:
+        if self.ptr:
+            hip().hipFree(self.ptr)
+            self.ptr = 0
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+hipMemAttachGlobal = 1
+hipMemAdviseSetPreferredLocation = 3
+hipMemRangeAttributeLastPrefetchLocation = 4
+hipCpuDeviceId = -1
+
+
+class PointerAttributes(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int), ("device", ctypes.c_int),
+                ("devicePointer", ctypes.c_void_p), ("hostPointer", ctypes.c_void_p),
+                ("isManaged", ctypes.c_int), ("allocationFlags", ctypes.c_uint)]
+
+
+def pointer_attributes(ptr: int) -> dict:
+    a = PointerAttributes()
+    check(hip().hipPointerGetAttributes(ctypes.byref(a), ptr), "hipPointerGetAttributes")
+    return {"type": a.type, "device": a.device, "devicePointer": a.devicePointer or 0,
+            "hostPointer": a.hostPointer or 0, "isManaged": a.isManaged,
+            "allocationFlags": a.allocationFlags}
+
+
+class ManagedBuffer:
+    """hipMallocManaged memory (host and device may both touch it)."""
+
+    def __init__(self, nbytes: int):
+        p = ctypes.c_void_p()
+        check(hip().hipMallocManaged(ctypes.byref(p), max(nbytes, 16), hipMemAttachGlobal),
+              f"hipMallocManaged({nbytes})")
+        self.ptr, self.nbytes = p.value, nbytes
+
+    def device_mapped(self) -> bool:
+        """True when the runtime reports the allocation mapped into the
+        device's address space at the same address (the condition for a
+        kernel to read it through this pointer)."""
+        a = pointer_attributes(self.ptr)
+        return a["devicePointer"] == self.ptr
+
+    def prefetch(self, offset: int, nbytes: int, device: int, stream: int = 0) -> int:
+        """hipMemPrefetchAsync of a sub-range; returns the HIP status."""
+        return hip().hipMemPrefetchAsync(self.ptr + offset, nbytes, device, stream)
+
+    def last_prefetch_location(self, offset: int, nbytes: int):
+        v = ctypes.c_int(-99)
+        rc = hip().hipMemRangeGetAttribute(ctypes.byref(v), 4,
+                                           hipMemRangeAttributeLastPrefetchLocation,
+                                           self.ptr + offset, nbytes)
+        return rc, v.value
+
+    def numpy(self, offset: int, n: int):
+        import numpy as np
+        return np.ctypeslib.as_array((ctypes.c_uint8 * n).from_address(self.ptr + offset))
 
     def free(self) -> None:
         if self.ptr:
