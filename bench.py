@@ -61,6 +61,8 @@ def parse_args():
     ap.add_argument("--tune-cache", default=None,
                     help="tuning cache path (default: the package's tuning_cache.json)")
     ap.add_argument("--no-corunner", action="store_true")
+    ap.add_argument("--diff-prio", type=int, default=None,
+                    help="issue priority of the diff kernel's waves (0..3)")
     ap.add_argument("--cold", action="store_true",
                     help="plain workload: rotate over 8 independent (current, shadow) pairs "
                          "(1 GiB working set, larger than the 256 MB last-level cache)")
@@ -750,6 +752,8 @@ def main():
     h_image = H.PinnedBuffer(cap)
     status = H.PinnedBuffer(64)
     ctx = crum.crum_ctx_create(0)
+    if args.diff_prio is not None:
+        crum.crum_ctx_set_param(ctx, crum.CRUM_PARAM_DIFF_PRIORITY, args.diff_prio)
     s1, s2 = H.Stream(), H.Stream()
 
     # co-runner: an application stream of fp32 SAXPY passes (y = a*x + y over
@@ -808,7 +812,17 @@ def main():
             fn()
             v.append(time.perf_counter() - t)
         return 1e3 * statistics.median(v)
-    snap_alone_ms = median_ms(run_snapshot, 1 if args.quick else 5)
+    # one flag byte per diff unit of min(P, 2^DIFF_UNIT_SHIFT) bytes
+    unit_shift = min(P.bit_length() - 1,
+                     crum.crum_ctx_get_param(ctx, crum.CRUM_PARAM_DIFF_UNIT_SHIFT))
+    diff_bytes_step = 2 * N + (N >> unit_shift)
+    crum.crum_ctx_timing_reset(ctx)
+    crum.crum_ctx_set_timing(ctx, True)
+    n_alone = 1 if args.quick else 5
+    snap_alone_ms = median_ms(run_snapshot, n_alone)
+    crum.crum_ctx_set_timing(ctx, False)
+    n_da, da_ms = crum.crum_ctx_timing(ctx, 0)
+    diff_alone_gbs = diff_bytes_step * n_alone / (da_ms * 1e-3) / 1e9
     checked_ms = float("nan") if args.quick else median_ms(lambda: run_snapshot(eager=False))
     e0, e1 = H.Event(), H.Event()
     probe = 1 if args.quick else 20
@@ -872,10 +886,6 @@ def main():
     assert st.code == 0 and st.n_dirty == D, st
 
     n_diff, diff_ms = timing["diff"]
-    # one flag byte per diff unit of min(P, 2^DIFF_UNIT_SHIFT) bytes
-    unit_shift = min(P.bit_length() - 1, crum.crum_ctx_get_param(ctx, crum.CRUM_PARAM_DIFF_UNIT_SHIFT))
-    n_units = N >> unit_shift
-    diff_bytes_step = 2 * N + n_units
     diff_gbs = diff_bytes_step * args.steps / (diff_ms * 1e-3) / 1e9
     n_dr, drain_ms = timing["drain"]
     drain_gbs = image_bytes * args.steps / (drain_ms * 1e-3) / 1e9
@@ -967,7 +977,12 @@ def main():
             "algorithmic_bytes_per_step": diff_bytes_step,
             "avg_launch_ms": round(diff_ms / max(n_diff, 1), 4),
             "launches": n_diff,
+            "measured_with": "co-runner active" if corun_on else "alone",
         },
+        "roofline_alone": {"kernel": "k_diff", "achieved": round(diff_alone_gbs, 1),
+                           "frac": round(diff_alone_gbs / HBM_PEAK_GBS, 4),
+                           "avg_launch_ms": round(da_ms / max(n_da, 1), 4),
+                           "what": "same snapshot steps without the co-runner"},
         "drain": {"achieved": round(drain_gbs, 2), "peak": LINK_PEAK_GBS, "unit": "GB/s",
                   "frac": round(drain_gbs / LINK_PEAK_GBS, 4), "copies": n_dr},
         "pack": {"achieved": round(pack_gbs, 1), "unit": "GB/s",

@@ -306,7 +306,10 @@ void crum_server_destroy(crum_server* server);
  *   whose CRCs are combined afterwards.
  * CRUM_PARAM_PACK_DEPTH: 16-byte loads each lane keeps in flight in the pack
  *   and verify kernels, 4, 8 or 16 (4).
- * Values of 0 are rejected (CRUM_EINVAL) except for the two on/off switches. */
+ * CRUM_PARAM_DIFF_PRIORITY: issue priority of the diff kernel's waves on
+ *   their compute units relative to co-running kernels, 0..3 (0).
+ * Values of 0 are rejected (CRUM_EINVAL) except for the two on/off switches
+ * and the priority. */
 enum {
     CRUM_PARAM_DIFF_BLOCKS = 1,
     CRUM_PARAM_PACK_BLOCKS = 2,
@@ -317,7 +320,8 @@ enum {
     CRUM_PARAM_DIFF_UNIT_SHIFT = 7,
     CRUM_PARAM_DIFF_NONTEMPORAL = 8,
     CRUM_PARAM_PIECE_SHIFT = 9,
-    CRUM_PARAM_PACK_DEPTH = 10
+    CRUM_PARAM_PACK_DEPTH = 10,
+    CRUM_PARAM_DIFF_PRIORITY = 11
 };
 int crum_ctx_set_param(crum_ctx* ctx, int param, uint64_t value);
 int crum_ctx_get_param(crum_ctx* ctx, int param, uint64_t* value);

@@ -279,6 +279,12 @@ int crum_ctx_set_param(crum_ctx* c, int param, uint64_t v)
         c->piece_shift = (uint32_t)v;
         return CRUM_OK;
     }
+    if (param == CRUM_PARAM_DIFF_PRIORITY) {
+        if (v > 3)
+            return CRUM_EINVAL;
+        c->diff_prio = (int)v;
+        return CRUM_OK;
+    }
     if (param == CRUM_PARAM_PACK_DEPTH) {
         if (v != 4 && v != 8 && v != 16)
             return CRUM_EINVAL;
@@ -327,6 +333,7 @@ int crum_ctx_get_param(crum_ctx* c, int param, uint64_t* v)
     case CRUM_PARAM_DIFF_NONTEMPORAL: *v = c->diff_nt ? 1 : 0; return CRUM_OK;
     case CRUM_PARAM_PIECE_SHIFT: *v = c->piece_shift; return CRUM_OK;
     case CRUM_PARAM_PACK_DEPTH: *v = (uint64_t)c->pack_depth; return CRUM_OK;
+    case CRUM_PARAM_DIFF_PRIORITY: *v = (uint64_t)c->diff_prio; return CRUM_OK;
     default: return CRUM_EINVAL;
     }
 }
@@ -487,7 +494,7 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
             {
                 Span sp(c, kTDiff, stream);
                 CRUM_TRY(launch_diff(d_regs, n_regions, g0 << (ps - us), g1 << (ps - us), d_flags,
-                                     c->shape.diff_blocks, c->diff_nt, stream));
+                                     c->shape.diff_blocks, c->diff_nt, c->diff_prio, stream));
             }
             {
                 Span sp(c, kTScan, stream);
@@ -507,9 +514,9 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
                 Span sp(c, kTPack, stream);
                 SlotRange sr{0, 0, d_bounds, (uint32_t)ci, g1 - g0};
                 CRUM_TRY(launch_pack(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
-                                     np_shift, pc_shift, staging, d_crcs, d_partials,
-                                     c->d_tabs, d_glob, c->shape.pack_blocks, c->pack_depth,
-                                     stream));
+                                     np_shift, pc_shift, d_flags, staging, d_crcs,
+                                     d_partials, c->d_tabs, d_glob, c->shape.pack_blocks,
+                                     c->pack_depth, stream));
                 CRUM_TRY(launch_finalize(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                          np_shift, pc_shift, d_partials, d_crcs, staging, d_glob,
                                          stream));
@@ -538,7 +545,7 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
         {
             Span sp(c, kTDiff, stream);
             CRUM_TRY(launch_diff(d_regs, n_regions, 0, n_units, d_flags, c->shape.diff_blocks,
-                                 c->diff_nt, stream));
+                                 c->diff_nt, c->diff_prio, stream));
         }
         {
             Span sp(c, kTScan, stream);
@@ -579,9 +586,9 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
                 Span sp(c, kTPack, stream);
                 SlotRange sr{k0, k1, nullptr, 0, k1 - k0};
                 CRUM_TRY(launch_pack(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
-                                     np_shift, pc_shift, staging, d_crcs, d_partials,
-                                     c->d_tabs, d_glob, c->shape.pack_blocks, c->pack_depth,
-                                     stream));
+                                     np_shift, pc_shift, d_flags, staging, d_crcs,
+                                     d_partials, c->d_tabs, d_glob, c->shape.pack_blocks,
+                                     c->pack_depth, stream));
                 CRUM_TRY(launch_finalize(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                          np_shift, pc_shift, d_partials, d_crcs, staging, d_glob,
                                          stream));
@@ -774,8 +781,8 @@ int crum_restore(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
         Span sp(c, kTVerify, stream);
         SlotRange sr{0, D, nullptr, 0, D};
         CRUM_TRY(launch_pack(kModeVerify, d_regs, n_regions, d_reqs, d_out, d_list, sr, np_shift,
-                             pc_shift, staging, d_crcs, d_partials, c->d_tabs, d_glob,
-                             c->shape.pack_blocks, c->pack_depth, stream));
+                             pc_shift, nullptr, staging, d_crcs, d_partials, c->d_tabs,
+                             d_glob, c->shape.pack_blocks, c->pack_depth, stream));
         CRUM_TRY(launch_finalize(kModeVerify, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                  np_shift, pc_shift, d_partials, d_crcs, staging, d_glob,
                                  stream));

@@ -101,7 +101,8 @@ struct SlotRange {
 // Kernel launchers (crum_kernels.hip).  All enqueue on `s`.
 void build_crc_tables(CrcTables* host);
 hipError_t launch_diff(const DevRegion* regs, uint32_t n_regs, uint64_t u0, uint64_t u1,
-                       uint8_t* unit_flags, int blocks, int nontemporal, hipStream_t s);
+                       uint8_t* unit_flags, int blocks, int nontemporal, int prio,
+                       hipStream_t s);
 hipError_t launch_bitmap(const DevRegion* regs, uint32_t n_regs, uint64_t w0, uint64_t w1,
                          const uint8_t* unit_flags, uint64_t* bitmap, hipStream_t s);
 // Scans words [w0, w1) continuing glob->running; writes the new running total
@@ -120,12 +121,14 @@ hipError_t launch_list(const uint64_t* bitmap, const uint32_t* prefix, uint64_t 
 // largest piece count per slot in the launch, and finalize combines the piece
 // CRCs of pages larger than one piece.  depth: 16-byte loads in flight per
 // lane (4, 8 or 16).  Pack updates the shadows of regions whose flags bit 0
-// is set.
+// is set.  unit_flags (pack only, may be null): the diff's per-unit flags of
+// the same page space; units flagged clean are then read from the shadow.
 hipError_t launch_pack(int mode, const DevRegion* regs, uint32_t n_regs, const DevRequest* reqs,
                        const DevReqOut* out, const uint32_t* list, SlotRange range,
-                       uint32_t np_shift, uint32_t piece_shift, uint8_t* staging,
-                       uint32_t* crc_out, uint32_t* partials, const CrcTables* tabs,
-                       DevGlobal* glob, int blocks, int depth, hipStream_t s);
+                       uint32_t np_shift, uint32_t piece_shift, const uint8_t* unit_flags,
+                       uint8_t* staging, uint32_t* crc_out, uint32_t* partials,
+                       const CrcTables* tabs, DevGlobal* glob, int blocks, int depth,
+                       hipStream_t s);
 hipError_t launch_finalize(int mode, const DevRegion* regs, uint32_t n_regs,
                            const DevRequest* reqs, const DevReqOut* out, const uint32_t* list,
                            SlotRange range, uint32_t np_shift, uint32_t piece_shift,

@@ -101,6 +101,7 @@ struct crum_ctx {
     uint64_t drain_chunk_bytes = 8ull << 20;
     uint32_t piece_shift = crum::kPieceShift;
     int pack_depth = 4;
+    int diff_prio = 0;
     bool eager = true;
     bool timing = false;
     std::vector<hipEvent_t> pool;
@@ -126,6 +127,7 @@ inline int ctx_diff_nt(const crum_ctx* c) { return c->diff_nt ? 1 : 0; }
 inline hipStream_t ctx_side_stream(const crum_ctx* c) { return c->side; }
 inline uint32_t ctx_piece_shift(const crum_ctx* c) { return c->piece_shift; }
 inline int ctx_pack_depth(const crum_ctx* c) { return c->pack_depth; }
+inline int ctx_diff_prio(const crum_ctx* c) { return c->diff_prio; }
 
 }  // namespace crum
 

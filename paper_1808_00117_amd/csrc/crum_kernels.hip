@@ -106,12 +106,27 @@ __device__ __forceinline__ uint32_t lane_combine(const uint32_t* __restrict__ ld
     return s;
 }
 
-// Raw (zero-initialised) CRC of `steps` KiB at src, copied to dst (and sh)
-// when STORE.  All lanes return the same value.
+// Source of a piece, 1 KiB step by step.  Bit j of `dirty` tells whether
+// diff unit j of the piece (units of 2^(ush+10) bytes) differed from the
+// shadow; a clean unit's bytes equal the shadow's, so they may be read from
+// `alt` (the shadow) instead of `cur`.  That keeps re-reads off the host link
+// when the current bytes live in host memory.  alt == nullptr: always cur.
+struct PieceSrc {
+    const uint4* cur;
+    const uint4* alt;
+    uint32_t dirty;
+    uint32_t ush;
+    __device__ __forceinline__ bool is_dirty(uint32_t t) const { return (dirty >> (t >> ush)) & 1u; }
+    __device__ __forceinline__ const uint4* at(uint32_t t) const
+    {
+        return (alt && !is_dirty(t)) ? alt : cur;
+    }
+};
+
 template <bool STORE, int U>
-__device__ __forceinline__ uint32_t piece_steps(const uint4* __restrict__ src,
-                                                uint4* __restrict__ dst, uint4* __restrict__ sh,
-                                                uint32_t* t_io, uint32_t steps, uint32_t lane,
+__device__ __forceinline__ uint32_t piece_steps(const PieceSrc& src, uint4* __restrict__ dst,
+                                                uint4* __restrict__ sh, uint32_t* t_io,
+                                                uint32_t steps, uint32_t lane,
                                                 const uint32_t* __restrict__ lds, uint32_t s)
 {
     const uint32_t* Z1024 = lds + kSliceWords + 5 * 1024;
@@ -120,15 +135,17 @@ __device__ __forceinline__ uint32_t piece_steps(const uint4* __restrict__ src,
         uint4 w[U];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            w[u] = src[(t + u) * 64 + lane];
+            w[u] = src.at(t + u)[(t + u) * 64 + lane];
         if (STORE) {
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 dst[(t + u) * 64 + lane] = w[u];
             if (sh) {
+                // clean units already hold these bytes in the shadow
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    sh[(t + u) * 64 + lane] = w[u];
+                    if (src.is_dirty(t + u))
+                        sh[(t + u) * 64 + lane] = w[u];
             }
         }
 #pragma unroll
@@ -139,29 +156,21 @@ __device__ __forceinline__ uint32_t piece_steps(const uint4* __restrict__ src,
     return s;
 }
 
-// DEPTH: 16-byte loads each lane issues before it folds them into its CRC.
+// Raw (zero-initialised) CRC of `steps` KiB, copied to dst (and to the shadow
+// sh, dirty units only) when STORE.  DEPTH: 16-byte loads each lane issues
+// before it folds them into its CRC.  All lanes return the same value.
 template <bool STORE, int DEPTH>
-__device__ __forceinline__ uint32_t wave_piece_crc(const uint4* __restrict__ src,
-                                                   uint4* __restrict__ dst,
+__device__ __forceinline__ uint32_t wave_piece_crc(const PieceSrc& src, uint4* __restrict__ dst,
                                                    uint4* __restrict__ sh, uint32_t steps,
                                                    uint32_t lane,
                                                    const uint32_t* __restrict__ lds)
 {
-    const uint32_t* Z1024 = lds + kSliceWords + 5 * 1024;
     uint32_t s = 0;
     uint32_t t = 0;
     s = piece_steps<STORE, DEPTH>(src, dst, sh, &t, steps, lane, lds, s);
     if (DEPTH > 4)
         s = piece_steps<STORE, 4>(src, dst, sh, &t, steps, lane, lds, s);
-    for (; t < steps; ++t) {
-        const uint4 w = src[t * 64 + lane];
-        if (STORE) {
-            dst[t * 64 + lane] = w;
-            if (sh)
-                sh[t * 64 + lane] = w;
-        }
-        s = shiftz(Z1024, s) ^ word_crc(lds, w);
-    }
+    s = piece_steps<STORE, 1>(src, dst, sh, &t, steps, lane, lds, s);
     return lane_combine(lds, s, lane);
 }
 
@@ -218,11 +227,19 @@ __device__ __forceinline__ uint32_t xor_or(const uint4* __restrict__ a_,
 
 // One wave per diff unit of global units [u0, u1); unit_flags[u] = 1 when
 // any byte of the unit differs from the shadow (or the region has none).
+// prio 1..3 raises the waves' issue priority on their compute unit above
+// that of co-running kernels' waves (0 leaves it at the default).
 template <bool NT>
 __global__ __launch_bounds__(256) void k_diff(const DevRegion* __restrict__ regs,
                                               uint32_t n_regs, uint64_t u0, uint64_t u1,
-                                              uint8_t* __restrict__ unit_flags)
+                                              uint8_t* __restrict__ unit_flags, uint32_t prio)
 {
+    if (prio == 1)
+        __builtin_amdgcn_s_setprio(1);
+    else if (prio == 2)
+        __builtin_amdgcn_s_setprio(2);
+    else if (prio >= 3)
+        __builtin_amdgcn_s_setprio(3);
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t wave =
         (uint64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -252,7 +269,8 @@ __global__ __launch_bounds__(256) void k_diff(const DevRegion* __restrict__ regs
 }
 
 hipError_t launch_diff(const DevRegion* regs, uint32_t n_regs, uint64_t u0, uint64_t u1,
-                       uint8_t* unit_flags, int blocks, int nontemporal, hipStream_t s)
+                       uint8_t* unit_flags, int blocks, int nontemporal, int prio,
+                       hipStream_t s)
 {
     if (u1 <= u0)
         return hipSuccess;
@@ -260,10 +278,10 @@ hipError_t launch_diff(const DevRegion* regs, uint32_t n_regs, uint64_t u0, uint
     const uint64_t nb = need < (uint64_t)blocks ? need : (uint64_t)blocks;
     if (nontemporal)
         hipLaunchKernelGGL(k_diff<true>, dim3((unsigned)nb), dim3(256), 0, s, regs, n_regs, u0,
-                           u1, unit_flags);
+                           u1, unit_flags, (uint32_t)prio);
     else
         hipLaunchKernelGGL(k_diff<false>, dim3((unsigned)nb), dim3(256), 0, s, regs, n_regs, u0,
-                           u1, unit_flags);
+                           u1, unit_flags, (uint32_t)prio);
     return hipGetLastError();
 }
 
@@ -474,6 +492,7 @@ __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs
                                               const DevReqOut* __restrict__ out,
                                               const uint32_t* __restrict__ list, SlotRange sr,
                                               uint32_t np_shift, uint32_t piece_shift,
+                                              const uint8_t* __restrict__ unit_flags,
                                               uint8_t* __restrict__ staging,
                                               uint32_t* __restrict__ crc_out,
                                               uint32_t* __restrict__ partials,
@@ -523,15 +542,28 @@ __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs
         const uint32_t steps = 1u << (pb_shift - 10);
         uint32_t raw;
         if (MODE == kModePack) {
-            const uint4* src = reinterpret_cast<const uint4*>(R.cur + page_off + piece_off);
+            PieceSrc src{reinterpret_cast<const uint4*>(R.cur + page_off + piece_off), nullptr,
+                         ~0u, 0};
+            if (unit_flags && R.shadow) {
+                // the piece's diff units: clean ones are read from the shadow
+                const uint32_t us = R.unit_shift;
+                const uint64_t u0 = R.first_unit + ((page_off + piece_off) >> us);
+                const uint32_t n_u = pb_shift > us ? 1u << (pb_shift - us) : 1u;
+                uint32_t m = 0;
+                for (uint32_t j = 0; j < n_u; ++j)
+                    m |= (unit_flags[u0 + j] ? 1u : 0u) << j;
+                src.alt = reinterpret_cast<const uint4*>(R.shadow + page_off + piece_off);
+                src.dirty = m;
+                src.ush = us - 10;
+            }
             uint4* sh = ((R.flags & 1u) && R.shadow)
                             ? reinterpret_cast<uint4*>(R.shadow + page_off + piece_off)
                             : nullptr;
             raw = wave_piece_crc<true, DEPTH>(src, reinterpret_cast<uint4*>(slot_ptr), sh, steps,
                                               lane, lds);
         } else {
-            raw = wave_piece_crc<false, DEPTH>(reinterpret_cast<const uint4*>(slot_ptr), nullptr,
-                                               nullptr, steps, lane, lds);
+            const PieceSrc src{reinterpret_cast<const uint4*>(slot_ptr), nullptr, ~0u, 0};
+            raw = wave_piece_crc<false, DEPTH>(src, nullptr, nullptr, steps, lane, lds);
         }
         if (lane != 0)
             continue;
@@ -555,28 +587,30 @@ template <int MODE>
 static void launch_pack_mode(dim3 grid, int depth, hipStream_t s, const DevRegion* regs,
                              uint32_t n_regs, const DevRequest* reqs, const DevReqOut* out,
                              const uint32_t* list, SlotRange range, uint32_t np_shift,
-                             uint32_t piece_shift, uint8_t* staging, uint32_t* crc_out,
-                             uint32_t* partials, const CrcTables* tabs, DevGlobal* glob)
+                             uint32_t piece_shift, const uint8_t* unit_flags, uint8_t* staging,
+                             uint32_t* crc_out, uint32_t* partials, const CrcTables* tabs,
+                             DevGlobal* glob)
 {
     if (depth == 16)
         hipLaunchKernelGGL((k_pack<MODE, 16>), grid, dim3(256), 0, s, regs, n_regs, reqs, out,
-                           list, range, np_shift, piece_shift, staging, crc_out, partials, tabs,
-                           glob);
+                           list, range, np_shift, piece_shift, unit_flags, staging, crc_out,
+                           partials, tabs, glob);
     else if (depth == 8)
         hipLaunchKernelGGL((k_pack<MODE, 8>), grid, dim3(256), 0, s, regs, n_regs, reqs, out,
-                           list, range, np_shift, piece_shift, staging, crc_out, partials, tabs,
-                           glob);
+                           list, range, np_shift, piece_shift, unit_flags, staging, crc_out,
+                           partials, tabs, glob);
     else
         hipLaunchKernelGGL((k_pack<MODE, 4>), grid, dim3(256), 0, s, regs, n_regs, reqs, out,
-                           list, range, np_shift, piece_shift, staging, crc_out, partials, tabs,
-                           glob);
+                           list, range, np_shift, piece_shift, unit_flags, staging, crc_out,
+                           partials, tabs, glob);
 }
 
 hipError_t launch_pack(int mode, const DevRegion* regs, uint32_t n_regs, const DevRequest* reqs,
                        const DevReqOut* out, const uint32_t* list, SlotRange range,
-                       uint32_t np_shift, uint32_t piece_shift, uint8_t* staging,
-                       uint32_t* crc_out, uint32_t* partials, const CrcTables* tabs,
-                       DevGlobal* glob, int blocks, int depth, hipStream_t s)
+                       uint32_t np_shift, uint32_t piece_shift, const uint8_t* unit_flags,
+                       uint8_t* staging, uint32_t* crc_out, uint32_t* partials,
+                       const CrcTables* tabs, DevGlobal* glob, int blocks, int depth,
+                       hipStream_t s)
 {
     const uint64_t max_items = range.max_slots << np_shift;
     if (max_items == 0)
@@ -588,12 +622,12 @@ hipError_t launch_pack(int mode, const DevRegion* regs, uint32_t n_regs, const D
     const dim3 grid((unsigned)nb);
     if (mode == kModePack)
         launch_pack_mode<kModePack>(grid, depth, s, regs, n_regs, reqs, out, list, range,
-                                    np_shift, piece_shift, staging, crc_out, partials, tabs,
-                                    glob);
+                                    np_shift, piece_shift, unit_flags, staging, crc_out,
+                                    partials, tabs, glob);
     else
         launch_pack_mode<kModeVerify>(grid, depth, s, regs, n_regs, reqs, out, list, range,
-                                      np_shift, piece_shift, staging, crc_out, partials, tabs,
-                                      glob);
+                                      np_shift, piece_shift, nullptr, staging, crc_out, partials,
+                                      tabs, glob);
     return hipGetLastError();
 }
 

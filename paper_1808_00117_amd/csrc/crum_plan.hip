@@ -242,7 +242,7 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
             e = launch_plan_init(d_glob, s);
         if (e == hipSuccess)
             e = launch_diff(d_regs, p->n_regs, u0, u1, d_flags, shape.diff_blocks,
-                            ctx_diff_nt(c), s);
+                            ctx_diff_nt(c), ctx_diff_prio(c), s);
         if (e == hipSuccess)
             e = launch_bitmap(d_regs, p->n_regs, w0, w1, d_flags, d_bitmap, s);
         if (e == hipSuccess)
@@ -256,7 +256,7 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
         SlotRange sr{0, 0, d_bounds, (uint32_t)gi, (w1 - w0) * 64};
         if (e == hipSuccess)
             e = launch_pack(kModePack, d_regs, p->n_regs, d_reqs, d_out, d_list, sr, np_shift,
-                            pc_shift, p->staging, d_crcs, d_part, tabs, d_glob,
+                            pc_shift, d_flags, p->staging, d_crcs, d_part, tabs, d_glob,
                             shape.pack_blocks, ctx_pack_depth(c), s);
         if (e == hipSuccess)
             e = launch_finalize(kModePack, d_regs, p->n_regs, d_reqs, d_out, d_list, sr, np_shift,

@@ -403,3 +403,20 @@ def test_pack_variants(piece_shift, depth):
             crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_PACK_DEPTH, 6)
     finally:
         s.close()
+
+
+def test_diff_priority():
+    """The diff kernel's wave priority changes nothing in the image."""
+    import paper_1808_00117_amd as crum
+    from paper_1808_00117_amd.api import Snapshotter
+    s = Snapshotter(0)
+    try:
+        for prio in (3, 1):
+            crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_DIFF_PRIORITY, prio)
+            assert crum.crum_ctx_get_param(s.ctx, crum.CRUM_PARAM_DIFF_PRIORITY) == prio
+            P = 16 * KiB
+            check_parity(s, host_case((40, 25), P, set(range(1, 65, 4)), seed=prio), P)
+        with pytest.raises(ValueError):
+            crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_DIFF_PRIORITY, 4)
+    finally:
+        s.close()
