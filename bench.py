@@ -400,6 +400,7 @@ def bench_batched(args):
                    "scanned_bytes": N, "dirty_pages": Dsum, "image_bytes": sum(sizes),
                    "groups": n_groups, "params": params, "tuned": bool(tuned)},
         "batched": {"makespan_ms": round(mk_ms, 2),
+                    "makespans_ms": [round(1e3 * v, 1) for v in mk],
                     "latency_ms": {"p50": round(percentile(lat_b, 0.5), 2),
                                    "p99": round(percentile(lat_b, 0.99), 2)},
                     "drain_gbs": round(sum(sizes) / statistics.median(mk) / 1e9, 2)},
@@ -746,7 +747,8 @@ def main():
     step_no = [0]
     image_bytes = crum.crum_image_bytes(R, G, D, P)
     # capacity for an image with every page dirty: the snapshot then runs in
-    # its chunk-pipelined order (ENOSPC impossible)
+    # its chunk-pipelined order when the pages span several chunks (ENOSPC
+    # impossible)
     cap = crum.crum_image_bytes(R, G, G, P)
     staging = H.DeviceBuffer(cap)
     h_image = H.PinnedBuffer(cap)
@@ -817,21 +819,23 @@ def main():
                      crum.crum_ctx_get_param(ctx, crum.CRUM_PARAM_DIFF_UNIT_SHIFT))
     diff_bytes_step = 2 * N + (N >> unit_shift)
     crum.crum_ctx_timing_reset(ctx)
-    crum.crum_ctx_set_timing(ctx, True)
+    crum.crum_ctx_set_timing(ctx, crum.TIMING_DIFF)
     n_alone = 1 if args.quick else 5
     snap_alone_ms = median_ms(run_snapshot, n_alone)
     crum.crum_ctx_set_timing(ctx, False)
     n_da, da_ms = crum.crum_ctx_timing(ctx, 0)
     diff_alone_gbs = diff_bytes_step * n_alone / (da_ms * 1e-3) / 1e9
     checked_ms = float("nan") if args.quick else median_ms(lambda: run_snapshot(eager=False))
-    e0, e1 = H.Event(), H.Event()
-    probe = 1 if args.quick else 20
-    e0.record(s2)
-    corun(probe)
-    e1.record(s2)
-    graph_ms = e0.elapsed_ms(e1) / probe
-    sax_alone_gbs = sax_bytes_per_pass * PASSES / (graph_ms * 1e-3) / 1e9
     corun_on = args.config == "many" and not args.no_corunner
+    graph_ms, sax_alone_gbs = float("nan"), float("nan")
+    if corun_on:
+        e0, e1 = H.Event(), H.Event()
+        probe = 1 if args.quick else 20
+        e0.record(s2)
+        corun(probe)
+        e1.record(s2)
+        graph_ms = e0.elapsed_ms(e1) / probe
+        sax_alone_gbs = sax_bytes_per_pass * PASSES / (graph_ms * 1e-3) / 1e9
     log(f"[bench] snapshot alone {snap_alone_ms:.2f} ms (diff-first order {checked_ms:.2f} ms); "
         f"saxpy alone {sax_alone_gbs:.0f} GB/s ({graph_ms:.3f} ms per graph)")
 
@@ -859,8 +863,13 @@ def main():
             sax_time[0] += a0.elapsed_ms(b0)
             sax_graphs[0] += 1
 
+    # Timing events cost host time per record: for short snapshots only the
+    # diff launches are timed inside the timed region, and pack / drain /
+    # header are timed in a separate pass afterwards.
+    breakdown_in_timed = snap_alone_ms > 5.0
+    mask_rest = crum.TIMING_PACK | crum.TIMING_DRAIN | crum.TIMING_SCAN | crum.TIMING_HEADER
     crum.crum_ctx_timing_reset(ctx)
-    crum.crum_ctx_set_timing(ctx, True)
+    crum.crum_ctx_set_timing(ctx, crum.TIMING_DIFF | (mask_rest if breakdown_in_timed else 0))
     lat = []
     H.device_synchronize()
     th = threading.Thread(target=corunner, daemon=True) if corun_on else None
@@ -884,14 +893,26 @@ def main():
         timing[name] = crum.crum_ctx_timing(ctx, cls)
     st = read_status()
     assert st.code == 0 and st.n_dirty == D, st
+    n_breakdown = args.steps
+    if not breakdown_in_timed:
+        crum.crum_ctx_timing_reset(ctx)
+        crum.crum_ctx_set_timing(ctx, mask_rest)
+        n_breakdown = min(args.steps, 10)
+        for _ in range(n_breakdown):
+            run_snapshot()
+        crum.crum_ctx_set_timing(ctx, False)
+        for cls, name in enumerate(["diff", "pack", "drain", "scan", "header"]):
+            if cls:
+                timing[name] = crum.crum_ctx_timing(ctx, cls)
 
     n_diff, diff_ms = timing["diff"]
     diff_gbs = diff_bytes_step * args.steps / (diff_ms * 1e-3) / 1e9
     n_dr, drain_ms = timing["drain"]
-    drain_gbs = image_bytes * args.steps / (drain_ms * 1e-3) / 1e9
+    drain_gbs = image_bytes * n_breakdown / (drain_ms * 1e-3) / 1e9
     n_pk, pack_ms = timing["pack"]
     pack_bytes = 2 * D * P + 4 * D
-    pack_gbs = pack_bytes * args.steps / (pack_ms * 1e-3) / 1e9
+    pack_gbs = pack_bytes * n_breakdown / (pack_ms * 1e-3) / 1e9
+    n_hd, header_ms = timing["header"]
     sax_with = None
     if sax_graphs[0]:
         sax_with = sax_bytes_per_pass * PASSES * sax_graphs[0] / (sax_time[0] * 1e-3) / 1e9
@@ -908,7 +929,7 @@ def main():
     # any write, then scattered into the regions (their bytes already equal
     # the image's pages, so the workload is unchanged for the next step)
     crum.crum_ctx_timing_reset(ctx)
-    crum.crum_ctx_set_timing(ctx, True)
+    crum.crum_ctx_set_timing(ctx, crum.TIMING_VERIFY | crum.TIMING_SCATTER)
     rest_lat = []
     for i in range(2 if args.quick else 6):
         t = time.perf_counter()
@@ -958,7 +979,8 @@ def main():
             "dirty_pages": D,
             "image_bytes": image_bytes,
             "staging_capacity": cap,
-            "order": "chunk-pipelined",
+            "order": ("chunk-pipelined" if N > crum.crum_ctx_get_param(
+                ctx, crum.CRUM_PARAM_CHUNK_BYTES) else "diff-first (the pages make one chunk)"),
             "co_runner": (f"fp32 SAXPY 4096x4096: graphs of {PASSES} single-pass kernels "
                           f"issued continuously on a second stream by a second host thread "
                           f"({sax_graphs[0]} graphs during the timed steps)") if corun_on else None,
@@ -987,6 +1009,9 @@ def main():
                   "frac": round(drain_gbs / LINK_PEAK_GBS, 4), "copies": n_dr},
         "pack": {"achieved": round(pack_gbs, 1), "unit": "GB/s",
                  "algorithmic_bytes_per_step": pack_bytes},
+        "header": {"avg_launch_ms": round(header_ms / max(n_hd, 1), 4)},
+        "breakdown_timed": "in the timed steps" if breakdown_in_timed else
+                           f"separate pass of {n_breakdown} snapshots after the timed steps",
         "overlap": {
             "snapshot_ms_alone": round(snap_alone_ms, 3),
             "snapshot_ms_with_corunner": round(p50, 3) if corun_on else None,

@@ -118,9 +118,10 @@ int crum_image_bytes(uint32_t n_regions, uint64_t total_pages, uint64_t n_dirty,
  * layout above, and the drain of the image to h_image on the context's side
  * stream; `stream` is made to wait for the drain.  The calling thread blocks
  * only on small device-to-host reads of dirty counts.  Two orders give the
- * same image: when both capacities hold an image with every page dirty (and
- * CRUM_PARAM_EAGER is 1), the page space is processed in chunks and each
- * chunk is drained while later chunks are diffed; otherwise the whole diff
+ * same image: when both capacities hold an image with every page dirty, the
+ * pages span more than one chunk and CRUM_PARAM_EAGER is 1, the page space is
+ * processed in chunks and each chunk is drained while later chunks are
+ * diffed; otherwise the whole diff
  * and the capacity check run first, then pack chunks with their drain behind
  * them.  With CRUM_UPDATE_SHADOW, every dirty page is also copied into its
  * shadow, but only when the status is CRUM_OK.
@@ -295,7 +296,8 @@ void crum_server_destroy(crum_server* server);
  *   (128 MiB / 1 GiB); chunks double in size up to the maximum.
  * CRUM_PARAM_EAGER: 1 pipelines the snapshot by chunks whenever the staging
  *   and host capacities hold an image with every page dirty (so ENOSPC is
- *   impossible); 0 always runs the whole diff first (1).
+ *   impossible) and the pages span more than one chunk; 0 always runs the
+ *   whole diff first (1).
  * CRUM_PARAM_DRAIN_CHUNK_BYTES: first pack/drain chunk of the non-pipelined
  *   order (8 MiB, doubling up to 256 MiB).
  * CRUM_PARAM_DIFF_UNIT_SHIFT: log2 of the largest diff unit, 12..14 (14):
@@ -326,13 +328,15 @@ enum {
 int crum_ctx_set_param(crum_ctx* ctx, int param, uint64_t value);
 int crum_ctx_get_param(crum_ctx* ctx, int param, uint64_t* value);
 
-/* Per-kernel timing, for measurement.  When enabled, the context brackets
- * each launch of its kernels and each drain copy with timing events.
- * crum_ctx_timing returns, for kernel class `which` (0 diff, 1 pack,
- * 2 drain copies, 3 scan/bitmap/list, 4 header, 5 verify, 6 scatter), the
- * number of launches and the summed duration in milliseconds since the last
- * reset; it waits for the recorded events. */
-int crum_ctx_set_timing(crum_ctx* ctx, int enable);
+/* Per-kernel timing, for measurement.  The context brackets each launch of
+ * the selected kernel classes (0 diff, 1 pack, 2 drain copies,
+ * 3 scan/bitmap/list, 4 header, 5 verify, 6 scatter) with timing events:
+ * `classes` is a bit mask (bit c selects class c), 0 turns timing off and a
+ * negative value selects every class.  Each event record costs host time, so
+ * short snapshots are timed with few classes.  crum_ctx_timing returns, for
+ * class `which`, the number of launches and the summed duration in
+ * milliseconds since the last reset; it waits for the recorded events. */
+int crum_ctx_set_timing(crum_ctx* ctx, int classes);
 int crum_ctx_timing(crum_ctx* ctx, int which, uint64_t* launches, double* total_ms);
 int crum_ctx_timing_reset(crum_ctx* ctx);
 

@@ -323,8 +323,19 @@ def crum_ctx_get_param(ctx: int, param: int) -> int:
     return v.value
 
 
-def crum_ctx_set_timing(ctx: int, enable: bool) -> None:
-    lib().crum_ctx_set_timing(ctx, 1 if enable else 0)
+TIMING_DIFF, TIMING_PACK, TIMING_DRAIN, TIMING_SCAN, TIMING_HEADER = 1, 2, 4, 8, 16
+TIMING_VERIFY, TIMING_SCATTER = 32, 64
+
+
+def crum_ctx_set_timing(ctx: int, classes) -> None:
+    """classes: True (every class), False (off) or a bit mask of TIMING_*."""
+    if classes is True:
+        classes = -1
+    elif classes is False:
+        classes = 0
+    rc = lib().crum_ctx_set_timing(ctx, int(classes))
+    if rc != CRUM_OK:
+        raise ValueError(CODE_NAMES.get(rc, rc))
 
 
 def crum_ctx_timing(ctx: int, which: int):

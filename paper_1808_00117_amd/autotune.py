@@ -30,19 +30,28 @@ PARAMS = {
 }
 
 
+# hipDeviceAttribute_t values (hip_runtime_api.h, ROCm 7)
+_ATTR_CC_MAJOR, _ATTR_CC_MINOR, _ATTR_CUS = 23, 61, 63
+
+
 def device_key() -> str:
-    """'<device name>|hip<runtime version>' of device 0."""
+    """'cc<major>.<minor>-<CUs>cu|hip<runtime version>' of device 0 (the
+    marketing name can be empty, so the key uses the compute capability that
+    HIP reports, 9.5 for gfx950, and the compute unit count)."""
     from . import hip as H
     h = H.hip()
     ver = ctypes.c_int(0)
     h.hipRuntimeGetVersion.restype = ctypes.c_int
     h.hipRuntimeGetVersion.argtypes = [ctypes.POINTER(ctypes.c_int)]
     h.hipRuntimeGetVersion(ctypes.byref(ver))
-    name = ctypes.create_string_buffer(256)
-    h.hipDeviceGetName.restype = ctypes.c_int
-    h.hipDeviceGetName.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.c_int]
-    h.hipDeviceGetName(name, 256, 0)
-    return f"{name.value.decode(errors='replace').strip()}|hip{ver.value}"
+    h.hipDeviceGetAttribute.restype = ctypes.c_int
+    h.hipDeviceGetAttribute.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int]
+
+    def attr(a):
+        v = ctypes.c_int(-1)
+        h.hipDeviceGetAttribute(ctypes.byref(v), a, 0)
+        return v.value
+    return f"cc{attr(_ATTR_CC_MAJOR)}.{attr(_ATTR_CC_MINOR)}-{attr(_ATTR_CUS)}cu|hip{ver.value}"
 
 
 def apply(ctx: int, params: Dict[str, int]) -> None:

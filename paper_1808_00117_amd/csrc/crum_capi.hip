@@ -73,7 +73,7 @@ struct Span {
     hipEvent_t a = nullptr;
     Span(crum_ctx* c_, int cls_, hipStream_t s_) : c(c_), cls(cls_), s(s_)
     {
-        if (c->timing && (a = timing_event(c)))
+        if (((c->timing_mask >> cls) & 1u) && (a = timing_event(c)))
             (void)hipEventRecord(a, s);
     }
     void end()
@@ -338,11 +338,11 @@ int crum_ctx_get_param(crum_ctx* c, int param, uint64_t* v)
     }
 }
 
-int crum_ctx_set_timing(crum_ctx* c, int enable)
+int crum_ctx_set_timing(crum_ctx* c, int classes)
 {
     if (!c)
         return CRUM_EINVAL;
-    c->timing = enable != 0;
+    c->timing_mask = classes < 0 ? (1u << kTimingClasses) - 1 : (uint32_t)classes;
     return CRUM_OK;
 }
 
@@ -407,9 +407,10 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     const uint64_t capacity = h_image ? std::min(staging_bytes, h_image_bytes) : staging_bytes;
     // When every page fits, ENOSPC cannot happen and the page space is
     // processed in chunks whose drain overlaps the diff of later chunks.
-    // Otherwise the whole diff and the capacity check come before any write.
+    // Otherwise, or when the pages make a single chunk (nothing to overlap),
+    // the whole diff and the capacity check come before any write.
     const uint64_t worst = data_off + (G << ps) + round_up(4 * G, 8);
-    const bool eager = c->eager && capacity >= worst && G > 0;
+    bool eager = c->eager && capacity >= worst && G > 0;
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     DeviceGuard g(c->device);
 
@@ -425,6 +426,8 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
             chunk_bytes = std::min<uint64_t>(chunk_bytes * 2,
                                              std::max(c->chunk_max_bytes, c->chunk_bytes));
         }
+        if (cuts.size() == 2)
+            eager = false;
     } else {
         cuts.push_back(G);
     }

@@ -77,9 +77,12 @@ static_assert(sizeof(DevGlobal) == 64, "DevGlobal layout");
 //   t[k][b]    = b * x^(8(k+1))        (slicing-by-16 for one 16-byte word)
 //   z[j][i][b] = (b << 8i) * x^(8 L_j)  (shift of a 32-bit state by L_j bytes)
 // with L_j = 32, 64, 128, 256, 512, 1024 for j = 0..5.
+// t[k][b] = b * x^(8(k+1)) (slicing by 16); z[j][i][b] = (b << 8i) * x^(8 L_j)
+// for L = 32, 64, 128, 256, 512, 1024, 4096 bytes; xp[i] = x^(8 * 2^i).
 struct CrcTables {
     uint32_t t[16][256];
-    uint32_t z[6][4][256];
+    uint32_t z[7][4][256];
+    uint32_t xp[64];
 };
 
 enum PackMode { kModePack = 0, kModeVerify = 1 };

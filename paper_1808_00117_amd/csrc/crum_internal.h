@@ -103,7 +103,7 @@ struct crum_ctx {
     int pack_depth = 4;
     int diff_prio = 0;
     bool eager = true;
-    bool timing = false;
+    uint32_t timing_mask = 0;  // bit c: time launches of class c
     std::vector<hipEvent_t> pool;
     size_t pool_used = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> spans[crum::kTimingClasses];

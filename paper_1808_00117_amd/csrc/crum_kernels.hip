@@ -42,17 +42,20 @@ void build_crc_tables(CrcTables* h)
         for (int b = 0; b < 256; ++b)
             h->t[k][b] = gf2_mulmod((uint32_t)b, xk);
     }
-    const uint64_t L[6] = {32, 64, 128, 256, 512, 1024};
-    for (int j = 0; j < 6; ++j) {
+    const uint64_t L[7] = {32, 64, 128, 256, 512, 1024, 4096};
+    for (int j = 0; j < 7; ++j) {
         const uint32_t xl = gf2_xpow8n(L[j]);
         for (int i = 0; i < 4; ++i)
             for (int b = 0; b < 256; ++b)
                 h->z[j][i][b] = gf2_mulmod((uint32_t)b << (8 * i), xl);
     }
+    for (int i = 0; i < 64; ++i)
+        h->xp[i] = gf2_xpow8n(1ull << i);
 }
 
-constexpr int kTabWords = 16 * 256 + 6 * 4 * 256;  // 40 KiB
-constexpr int kSliceWords = 16 * 256;              // 16 KiB
+constexpr int kSliceWords = 16 * 256;                 // 16 KiB
+constexpr int kTabWords = kSliceWords + 6 * 4 * 256;  // shifts up to 1 KiB: 40 KiB (pack)
+constexpr int kAllTabWords = kTabWords + 4 * 256;     // and by 4 KiB: 44 KiB (header)
 
 // raw CRC of one 16-byte word (bytes b0..b15, b0 = low byte of w.x)
 __device__ __forceinline__ uint32_t word_crc(const uint32_t* __restrict__ T, uint4 w)
@@ -707,51 +710,85 @@ hipError_t launch_finalize(int mode, const DevRegion* regs, uint32_t n_regs,
 // Standard CRC-32C of n bytes at p (p 16-byte aligned) computed by one
 // 256-thread workgroup; the 4 bytes at zero_off (a multiple of 4, or ~0) are
 // read as zero.  T is the slicing table in LDS.  All threads return it.
-__device__ uint32_t block_crc(const uint8_t* __restrict__ p, uint64_t n, uint64_t zero_off,
-                              const uint32_t* __restrict__ T, uint32_t* red)
+// x^(8n) mod P from the table xp[i] = x^(8 * 2^i): the product of the
+// entries for the set bits of n, reduced across the wave.  Every lane returns
+// it; all lanes of the wave must call.
+__device__ __forceinline__ uint32_t xpow8n_wave(uint64_t n, const uint32_t* __restrict__ xp,
+                                               uint32_t lane)
+{
+    uint32_t v = ((n >> lane) & 1u) ? xp[lane] : 0x80000000u;  // x^0 when the bit is clear
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1)
+        v = gf2_mulmod(v, (uint32_t)__shfl_xor((int)v, d));
+    return v;
+}
+
+// Standard CRC-32C of n bytes at p (p and n multiples of 4) by one
+// 256-thread workgroup; the 4 bytes at zero_off (a multiple of 4, or ~0) are
+// read as zero.  The message is taken as left-padded with zero bytes to a
+// multiple of 4096 (which leaves a zero-initialised CRC unchanged); thread t
+// reads 16-byte words t, t+256, ... and keeps a Horner accumulator with a
+// "shift by 4096 bytes" step, the wave butterfly combines lanes and each wave
+// is shifted by the 1 KiB stripes that follow it.  lds: slicing tables and
+// all seven shift levels.  All threads return the value.
+__device__ uint32_t wg_crc(const uint8_t* __restrict__ p, uint64_t n, uint64_t zero_off,
+                           const uint32_t* __restrict__ lds, const uint32_t* __restrict__ xp,
+                           uint32_t* red)
 {
     const uint32_t tid = threadIdx.x;
-    const uint64_t per = ((n + 255) / 256 + 15) & ~15ull;
-    const uint64_t b0 = tid * per;
-    const uint64_t b1 = b0 + per < n ? b0 + per : n;
+    const uint32_t lane = tid & 63u;
+    const uint32_t wave = tid >> 6;
+    const uint32_t* Z1024 = lds + kSliceWords + 5 * 1024;
+    const uint32_t* Z4096 = lds + kSliceWords + 6 * 1024;
+    const uint64_t steps = (n + 4095) / 4096;
+    const int64_t pad = (int64_t)(steps * 4096 - n);
     uint32_t s = 0;
-    uint64_t o = b0;
-    for (; o + 16 <= b1; o += 16) {
-        uint4 w = *reinterpret_cast<const uint4*>(p + o);
-        if (zero_off >= o && zero_off < o + 16) {
-            const uint32_t c = (uint32_t)(zero_off - o) >> 2;
-            if (c == 0) w.x = 0;
-            if (c == 1) w.y = 0;
-            if (c == 2) w.z = 0;
-            if (c == 3) w.w = 0;
+    for (uint64_t j = 0; j < steps; ++j) {
+        const int64_t v = (int64_t)((j * 256 + tid) * 16) - pad;
+        uint32_t w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t r = v + 4 * i;
+            w[i] = (r >= 0 && (uint64_t)r != zero_off)
+                       ? *reinterpret_cast<const uint32_t*>(p + r)
+                       : 0u;
         }
-        w.x ^= s;
-        s = word_crc(T, w);
+        s = shiftz(Z4096, s) ^ word_crc(lds, make_uint4(w[0], w[1], w[2], w[3]));
     }
-    for (; o < b1; ++o) {
-        uint32_t b = p[o];
-        if (zero_off <= o && o < zero_off + 4)
-            b = 0;
-        s = (s >> 8) ^ T[(s ^ b) & 255u];
-    }
-    if (b0 < b1)
-        s = gf2_shift(s, n - b1);
-    else
-        s = 0;
-    // XOR-reduce across the workgroup
-    for (int d = 32; d >= 1; d >>= 1)
-        s ^= (uint32_t)__shfl_xor((int)s, d);
-    if ((tid & 63u) == 0)
-        red[tid >> 6] = s;
+    s = lane_combine(lds, s, lane);
+    for (uint32_t k = wave; k < 3; ++k)
+        s = shiftz(Z1024, s);
+    if (lane == 0)
+        red[wave] = s;
+    const uint32_t fix = gf2_mulmod(0xFFFFFFFFu, xpow8n_wave(n, xp, lane)) ^ 0xFFFFFFFFu;
     __syncthreads();
-    uint32_t tot = 0;
-    for (uint32_t i = 0; i < blockDim.x / 64; ++i)
-        tot ^= red[i];
+    const uint32_t raw = red[0] ^ red[1] ^ red[2] ^ red[3];
     __syncthreads();
-    return tot ^ crc_init_fix(n);
+    return raw ^ fix;
 }
 
 // ------------------------------------------------------------ k_header
+
+// dst[i] = src[i] for i < n by one workgroup, 8 loads in flight per thread.
+template <typename T>
+__device__ __forceinline__ void copy_words(T* __restrict__ dst, const T* __restrict__ src,
+                                           uint64_t n)
+{
+    constexpr uint32_t U = 8;
+    const uint64_t stride = (uint64_t)blockDim.x * U;
+    uint64_t i = threadIdx.x;
+    for (; i + (U - 1) * blockDim.x < n; i += stride) {
+        T v[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u)
+            v[u] = src[i + u * blockDim.x];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u)
+            dst[i + u * blockDim.x] = v[u];
+    }
+    for (; i < n; i += blockDim.x)
+        dst[i] = src[i];
+}
 
 __global__ __launch_bounds__(256) void k_header(const DevRegion* __restrict__ regs,
                                                 const DevRequest* __restrict__ reqs,
@@ -762,14 +799,14 @@ __global__ __launch_bounds__(256) void k_header(const DevRegion* __restrict__ re
                                                 uint64_t capacity,
                                                 const CrcTables* __restrict__ tabs)
 {
-    __shared__ uint32_t lds[kSliceWords];
+    __shared__ uint32_t lds[kAllTabWords];
     __shared__ uint32_t red[4];
     __shared__ uint32_t s_shadowed;
     const DevRequest& Q = reqs[q0 + blockIdx.x];
     const DevReqOut& O = out[q0 + blockIdx.x];
     if (O.code != 0 && O.img_base + Q.data_off > capacity)
         return;  // no room even for the prefix
-    load_tables(lds, tabs, kSliceWords);
+    load_tables(lds, tabs, kAllTabWords);
     const uint32_t tid = threadIdx.x;
     uint8_t* img = staging + O.img_base;
     const uint64_t R = Q.n_regions;
@@ -789,15 +826,14 @@ __global__ __launch_bounds__(256) void k_header(const DevRegion* __restrict__ re
         if (G.shadow)
             atomicOr(&s_shadowed, 1u);
     }
-    for (uint64_t w = tid; w < Q.n_words; w += blockDim.x)
-        reinterpret_cast<uint64_t*>(img + 64 + 32 * R)[w] = bitmap[Q.first_word + w];
+    copy_words(reinterpret_cast<uint64_t*>(img + 64 + 32 * R), bitmap + Q.first_word,
+               Q.n_words);
     for (uint64_t o = prefix_end + 8 * tid; o < Q.data_off; o += 8 * blockDim.x)
         *reinterpret_cast<uint64_t*>(img + o) = 0;
     const bool ok = O.code == 0;
     if (ok) {
         uint32_t* dst = reinterpret_cast<uint32_t*>(img + Q.data_off + (D << Q.page_shift));
-        for (uint64_t k = tid; k < D; k += blockDim.x)
-            dst[k] = crcs[O.slot_base + k];
+        copy_words(dst, crcs + O.slot_base, D);
         if (tid == 0 && (D & 1))
             dst[D] = 0;
     }
@@ -819,12 +855,13 @@ __global__ __launch_bounds__(256) void k_header(const DevRegion* __restrict__ re
     }
     uint32_t crcs_crc = 0;
     if (ok)
-        crcs_crc = block_crc(img + Q.data_off + (D << Q.page_shift), 4 * D, ~0ull, lds, red);
+        crcs_crc = wg_crc(img + Q.data_off + (D << Q.page_shift), 4 * D, ~0ull, lds, tabs->xp,
+                          red);
     if (tid == 0)
         h32[15] = crcs_crc;
     __threadfence_block();
     __syncthreads();
-    const uint32_t meta = block_crc(img, prefix_end, ~0ull, lds, red);
+    const uint32_t meta = wg_crc(img, prefix_end, ~0ull, lds, tabs->xp, red);
     if (tid == 0)
         h32[14] = meta;
 }
@@ -893,11 +930,11 @@ __global__ __launch_bounds__(256) void k_restore_check(const DevRequest* __restr
                                                        const CrcTables* __restrict__ tabs,
                                                        DevGlobal* __restrict__ glob)
 {
-    __shared__ uint32_t lds[kSliceWords];
+    __shared__ uint32_t lds[kAllTabWords];
     __shared__ uint32_t red[4];
     __shared__ unsigned long long s_pop;
     __shared__ uint32_t s_bad;
-    load_tables(lds, tabs, kSliceWords);
+    load_tables(lds, tabs, kAllTabWords);
     const uint32_t tid = threadIdx.x;
     const DevRequest& Q = reqs[blockIdx.x];
     const DevReqOut& O = out[blockIdx.x];
@@ -934,8 +971,9 @@ __global__ __launch_bounds__(256) void k_restore_check(const DevRequest* __restr
     atomicAdd(&s_pop, pop);
     if (bad)
         atomicOr(&s_bad, 1u);
-    const uint32_t crcs = block_crc(img + Q.data_off + (D << Q.page_shift), 4 * D, ~0ull, lds, red);
-    const uint32_t meta = block_crc(img, prefix_end, 56, lds, red);
+    const uint32_t crcs =
+        wg_crc(img + Q.data_off + (D << Q.page_shift), 4 * D, ~0ull, lds, tabs->xp, red);
+    const uint32_t meta = wg_crc(img, prefix_end, 56, lds, tabs->xp, red);
     __syncthreads();
     if (tid == 0) {
         if (s_bad || s_pop != D || crcs != h32[15] || meta != h32[14])
