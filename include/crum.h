@@ -289,11 +289,11 @@ void crum_server_destroy(crum_server* server);
 /* Launch and pipeline parameters of a context (defaults in parentheses).
  * They change speed only: every image is the same whatever their values.
  * CRUM_PARAM_DIFF_BLOCKS: persistent grid of the diff kernel, in 256-thread
- *   workgroups (4 per compute unit).  CRUM_PARAM_PACK_BLOCKS: grid of the
+ *   workgroups (8 per compute unit).  CRUM_PARAM_PACK_BLOCKS: grid of the
  *   pack, verify and scatter kernels (4 per compute unit).
  * CRUM_PARAM_CHUNK_BYTES / CRUM_PARAM_CHUNK_MAX_BYTES: scanned bytes of the
  *   first and of the largest chunk when the snapshot is pipelined by chunks
- *   (128 MiB / 1 GiB); chunks double in size up to the maximum.
+ *   (128 MiB / 4 GiB); chunks double in size up to the maximum.
  * CRUM_PARAM_EAGER: 1 pipelines the snapshot by chunks whenever the staging
  *   and host capacities hold an image with every page dirty (so ENOSPC is
  *   impossible) and the pages span more than one chunk; 0 always runs the

@@ -27,6 +27,10 @@ PARAMS = {
     "pack_blocks": C.CRUM_PARAM_PACK_BLOCKS,
     "chunk_bytes": C.CRUM_PARAM_CHUNK_BYTES,
     "chunk_max_bytes": C.CRUM_PARAM_CHUNK_MAX_BYTES,
+    "drain_chunk_bytes": C.CRUM_PARAM_DRAIN_CHUNK_BYTES,
+    "piece_shift": C.CRUM_PARAM_PIECE_SHIFT,
+    "pack_depth": C.CRUM_PARAM_PACK_DEPTH,
+    "diff_priority": C.CRUM_PARAM_DIFF_PRIORITY,
 }
 
 

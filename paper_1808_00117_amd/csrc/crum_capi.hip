@@ -211,7 +211,7 @@ int crum_ctx_create(int device, crum_ctx** out)
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
         cus > 0)
         c->cus = cus;
-    c->shape.diff_blocks = c->cus * 4;
+    c->shape.diff_blocks = c->cus * 8;
     c->shape.pack_blocks = c->cus * 4;
     CrcTables host;
     build_crc_tables(&host);

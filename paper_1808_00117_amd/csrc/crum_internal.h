@@ -95,7 +95,7 @@ struct crum_ctx {
     std::vector<hipEvent_t> ev_cnt;    // dirty count of chunk i read back
     LaunchShape shape{};
     uint64_t chunk_bytes = 128ull << 20;
-    uint64_t chunk_max_bytes = 1ull << 30;
+    uint64_t chunk_max_bytes = 4ull << 30;
     uint32_t unit_shift_max = crum::kUnitShiftDefault;
     bool diff_nt = true;
     uint64_t drain_chunk_bytes = 8ull << 20;

@@ -58,13 +58,15 @@ def run_plan(ctx, host_reqs, flags=None, launches=1, staging_bytes=None, small_g
     himg = torch.empty(max(sb, 16), dtype=torch.uint8, pin_memory=True)
     status = torch.zeros(40 * max(1, len(host_reqs)), dtype=torch.uint8, pin_memory=True)
     if small_groups:
+        saved = [crum.crum_ctx_get_param(ctx.ctx, p) for p in
+                 (crum.CRUM_PARAM_CHUNK_BYTES, crum.CRUM_PARAM_CHUNK_MAX_BYTES)]
         crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_CHUNK_BYTES, 1)
         crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_CHUNK_MAX_BYTES, 1)
     reqs = [(regions_of(d), P, f, seq) for d, (_, P, seq), f in zip(dev, host_reqs, flags)]
     plan = crum.Plan(ctx.ctx, reqs, staging.data_ptr(), sb, himg.data_ptr(), sb)
     if small_groups:
-        crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_CHUNK_BYTES, 128 << 20)
-        crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_CHUNK_MAX_BYTES, 1 << 30)
+        crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_CHUNK_BYTES, saved[0])
+        crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_CHUNK_MAX_BYTES, saved[1])
     results = []
     for _ in range(launches):
         s = torch.cuda.current_stream()
