@@ -1,0 +1,216 @@
+"""GPU parity at the benchmark workloads' full sizes, in the launch
+configuration bench.py times (default context shapes, the chunk-pipelined
+order where the capacity allows it).  The oracle cannot take 16-71 GB whole,
+so these tests check what it can compute one page at a time and properties
+that hold at any size:
+
+* the bitmap equals the scenario's chosen dirty set (each chosen page differs
+  from its shadow by construction, every other page is equal);
+* sampled packed pages equal the generator bytes regenerated on the host, and
+  their CRCs equal the oracle's CRC-32C of those bytes;
+* the oracle's parser accepts the image (magic, layout, popcount, both
+  checksums, length);
+* the diff-first order gives the same image byte for byte;
+* a restore repairs pages overwritten on the device.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from tests.gpu_util import log
+
+pytestmark = pytest.mark.gpu
+
+KiB, MiB, GiB = 1 << 10, 1 << 20, 1 << 30
+
+
+def page_index(scn):
+    """(region index, local page) of every global page, as two arrays."""
+    P = scn.page_size
+    counts = np.array([r.nbytes // P for r in scn.regions], np.int64)
+    starts = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    return counts, starts
+
+
+def check_image(img, scn, n_samples, rng, seq):
+    """Layout, bitmap and sampled pages of one image against the scenario."""
+    from synth import scenarios as sc
+    P = scn.page_size
+    rc, hdr = oracle.parse(img)
+    assert rc == oracle.OK, rc
+    assert hdr["n_dirty"] == scn.n_dirty and hdr["total_pages"] == scn.total_pages
+    assert hdr["page_size"] == P and hdr["seq"] == seq
+    R = len(scn.regions)
+    W = (scn.total_pages + 63) // 64
+    bm = np.frombuffer(img[64 + 32 * R: 64 + 32 * R + 8 * W].tobytes(), np.uint64)
+    got = np.flatnonzero(np.unpackbits(bm.view(np.uint8), bitorder="little"))
+    want = scn.dirty_global()
+    assert np.array_equal(got, want), "bitmap differs from the chosen dirty set"
+    counts, starts = page_index(scn)
+    D, off = scn.n_dirty, hdr["data_off"]
+    crcs = np.frombuffer(img[off + D * P: off + D * P + 4 * D].tobytes(), np.uint32)
+    for k in rng.choice(D, size=min(n_samples, D), replace=False):
+        g = int(want[k])
+        ri = int(np.searchsorted(starts, g, side="right") - 1)
+        page = sc.host_page(scn, ri, g - int(starts[ri]), shadow=False)
+        assert np.array_equal(img[off + k * P: off + (k + 1) * P], page), f"slot {k}"
+        assert int(crcs[k]) == oracle.crc32c(page), f"crc of slot {k}"
+
+
+def test_many_allocs_16gib():
+    """The 16 GiB many-allocations workload (64 regions, 64 KiB pages)."""
+    import bench
+    import paper_1808_00117_amd as crum
+    import paper_1808_00117_amd.hip as H
+    import synth
+    from synth import scenarios as sc
+
+    scn = sc.many_allocs()
+    P, G, D, R = scn.page_size, scn.total_pages, scn.n_dirty, len(scn.regions)
+    log(f"[fullsize] many_allocs N={scn.total_bytes} D={D}")
+    pairs = bench.materialize_raw(scn, H)
+    table = crum.region_table([(c.ptr, s.ptr, r.nbytes, r.id)
+                               for (c, s), r in zip(pairs, scn.regions)])
+    ib = crum.crum_image_bytes(R, G, D, P)
+    cap = crum.crum_image_bytes(R, G, G, P)
+    staging = H.DeviceBuffer(cap)
+    himg = H.PinnedBuffer(cap)
+    status = H.PinnedBuffer(64)
+    ctx = crum.crum_ctx_create(0)
+    s = H.Stream()
+    try:
+        images = []
+        for c in (cap, ib):  # pipelined (bench's order), then diff-first
+            assert crum.crum_snapshot(ctx, table, P, 0, 11, staging.ptr, c, himg.ptr, c,
+                                      s.handle, status.ptr) == 0
+            s.synchronize()
+            st = crum.read_status(status.ptr)
+            assert st.code == 0 and st.n_dirty == D and st.image_bytes == ib, st
+            images.append(himg.numpy(ib).copy())
+        assert np.array_equal(images[0], images[1]), "the two orders disagree"
+        rng = np.random.default_rng(16)
+        check_image(images[0], scn, 64, rng, seq=11)
+        # overwrite 8 dirty pages on the device, restore, check them and a clean page
+        counts, starts = page_index(scn)
+        want = scn.dirty_global()
+        picks = [int(g) for g in rng.choice(want, size=8, replace=False)]
+        for g in picks:
+            ri = int(np.searchsorted(starts, g, side="right") - 1)
+            synth.fill_dev(pairs[ri][0].ptr + (g - int(starts[ri])) * P, P, 999, 5, 0, 0)
+        H.device_synchronize()
+        assert crum.crum_restore(ctx, table, himg.ptr, ib, crum.CRUM_VERIFY, staging.ptr, cap,
+                                 s.handle, status.ptr) == 0
+        s.synchronize()
+        assert crum.read_status(status.ptr).code == 0
+        buf = np.empty(P, np.uint8)
+        for g in picks + [int(np.setdiff1d(np.arange(64), want)[0])]:
+            ri = int(np.searchsorted(starts, g, side="right") - 1)
+            H.memcpy_dtoh(buf.ctypes.data, pairs[ri][0].ptr + (g - int(starts[ri])) * P, P)
+            assert np.array_equal(buf, sc.host_page(scn, ri, g - int(starts[ri]), False)), g
+    finally:
+        crum.crum_ctx_destroy(ctx)
+        for c, sh in pairs:
+            c.free()
+            sh.free()
+        staging.free()
+        himg.free()
+
+
+def test_managed_32gib():
+    """The 32 GiB managed workload, 70 % of pages written by host threads and
+    30 % prefetched and written by a kernel."""
+    import bench
+    import paper_1808_00117_amd as crum
+    import paper_1808_00117_amd.hip as H
+    import synth
+    from synth import scenarios as sc
+
+    scn = sc.managed()
+    r = scn.regions[0]
+    P, G, D, N = scn.page_size, scn.total_pages, scn.n_dirty, scn.total_bytes
+    log(f"[fullsize] managed N={N} D={D}")
+    cur = H.ManagedBuffer(N)
+    assert cur.device_mapped()
+    dev_pages = scn.meta["device_pages"]
+    bench.fill_managed_host(cur, scn, 0, np.setdiff1d(np.arange(G), dev_pages))
+    bench.fill_managed_device(cur, scn, 0, dev_pages)
+    sh = H.DeviceBuffer(N)
+    synth.fill_dev(sh.ptr, N, r.fill_seed, r.fill_region, 0, 0)
+    pd = np.ascontiguousarray(r.dirty_pages, np.int64)
+    d_pages = H.DeviceBuffer(pd.nbytes)
+    H.memcpy_htod(d_pages.ptr, pd.ctypes.data, pd.nbytes)
+    synth.mutate_dev(sh.ptr, N, P, d_pages.ptr, pd.size, int(pd.max()), r.mut_kind,
+                     scn.mut_seed, r.fill_region, 0)
+    H.device_synchronize()
+    ib = crum.crum_image_bytes(1, G, D, P)
+    cap = crum.crum_image_bytes(1, G, G, P)
+    staging = H.DeviceBuffer(cap)
+    himg = H.PinnedBuffer(cap)
+    status = H.PinnedBuffer(64)
+    ctx = crum.crum_ctx_create(0)
+    s = H.Stream()
+    try:
+        table = crum.region_table([(cur.ptr, sh.ptr, N, r.id)])
+        assert crum.crum_snapshot(ctx, table, P, 0, 3, staging.ptr, cap, himg.ptr, cap,
+                                  s.handle, status.ptr) == 0
+        s.synchronize()
+        st = crum.read_status(status.ptr)
+        assert st.code == 0 and st.n_dirty == D and st.image_bytes == ib, st
+        check_image(himg.numpy(ib), scn, 24, np.random.default_rng(32), seq=3)
+    finally:
+        crum.crum_ctx_destroy(ctx)
+        cur.free()
+        sh.free()
+        staging.free()
+        himg.free()
+
+
+def test_batched_256_requests():
+    """The 256-request batch (71 GB scanned) in one plan launch with the
+    package's tuned shapes: every request's status, and sampled requests'
+    images against their scenarios."""
+    import bench
+    import paper_1808_00117_amd as crum
+    import paper_1808_00117_amd.hip as H
+    from paper_1808_00117_amd import autotune
+    from synth import scenarios as sc
+
+    reqs = sc.batched(seed=1004, n_requests=256)
+    log(f"[fullsize] batched {len(reqs)} requests")
+    pairs = [bench.materialize_raw(r, H) for r in reqs]
+    tables = [[(c.ptr, s.ptr if s else 0, g.nbytes, g.id) for (c, s), g in zip(pr, r.regions)]
+              for r, pr in zip(reqs, pairs)]
+    sizes = [crum.crum_image_bytes(len(r.regions), r.total_pages, r.n_dirty, r.page_size)
+             for r in reqs]
+    cap = sum((b + 4095) // 4096 * 4096 for b in sizes) + (64 << 20)
+    staging = H.DeviceBuffer(cap)
+    himg = H.PinnedBuffer(cap)
+    status = H.PinnedBuffer(40 * len(reqs))
+    ctx = crum.crum_ctx_create(0)
+    s = H.Stream()
+    try:
+        tuned = autotune.load("batched")
+        if tuned:
+            autotune.apply(ctx, tuned)
+        plan = crum.Plan(ctx, [(t, r.page_size, 0, 9) for t, r in zip(tables, reqs)],
+                         staging.ptr, cap, himg.ptr, cap)
+        assert plan.launch(s.handle, status.ptr) == 0
+        s.synchronize()
+        sts = crum.read_request_statuses(status.ptr, len(reqs))
+        for q, (code, _, D, G, b, off) in enumerate(sts):
+            assert code == 0 and D == reqs[q].n_dirty and G == reqs[q].total_pages, q
+            assert b == sizes[q] and off % 4096 == 0, q
+        rng = np.random.default_rng(256)
+        for q in rng.choice(len(reqs), size=24, replace=False):
+            off, b = sts[q][5], sts[q][4]
+            check_image(himg.numpy(off + b)[off:], reqs[q], 4, rng, seq=9)
+        plan.destroy()
+    finally:
+        crum.crum_ctx_destroy(ctx)
+        for pr in pairs:
+            for c, sh in pr:
+                c.free()
+                if sh:
+                    sh.free()
+        staging.free()
+        himg.free()
