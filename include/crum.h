@@ -310,6 +310,11 @@ void crum_server_destroy(crum_server* server);
  *   and verify kernels, 4, 8 or 16 (4).
  * CRUM_PARAM_DIFF_PRIORITY: issue priority of the diff kernel's waves on
  *   their compute units relative to co-running kernels, 0..3 (0).
+ * CRUM_PARAM_CRC_VARIANT: how the pack and verify kernels' CRC step splits
+ *   its table lookups between 256-entry byte tables (bank conflicts) and
+ *   16-entry nibble tables (conflict-free, more ALU work): 0 = byte tables
+ *   only, 1..5 = mixes, 6 = byte tables for pack and mix 3 for verify, the
+ *   fastest of each on MI355X (6).
  * Values of 0 are rejected (CRUM_EINVAL) except for the two on/off switches
  * and the priority. */
 enum {
@@ -323,7 +328,8 @@ enum {
     CRUM_PARAM_DIFF_NONTEMPORAL = 8,
     CRUM_PARAM_PIECE_SHIFT = 9,
     CRUM_PARAM_PACK_DEPTH = 10,
-    CRUM_PARAM_DIFF_PRIORITY = 11
+    CRUM_PARAM_DIFF_PRIORITY = 11,
+    CRUM_PARAM_CRC_VARIANT = 12
 };
 int crum_ctx_set_param(crum_ctx* ctx, int param, uint64_t value);
 int crum_ctx_get_param(crum_ctx* ctx, int param, uint64_t* value);

@@ -31,6 +31,7 @@ PARAMS = {
     "piece_shift": C.CRUM_PARAM_PIECE_SHIFT,
     "pack_depth": C.CRUM_PARAM_PACK_DEPTH,
     "diff_priority": C.CRUM_PARAM_DIFF_PRIORITY,
+    "crc_variant": C.CRUM_PARAM_CRC_VARIANT,
 }
 
 

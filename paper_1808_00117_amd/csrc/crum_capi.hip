@@ -279,6 +279,12 @@ int crum_ctx_set_param(crum_ctx* c, int param, uint64_t v)
         c->piece_shift = (uint32_t)v;
         return CRUM_OK;
     }
+    if (param == CRUM_PARAM_CRC_VARIANT) {
+        if (v > (uint64_t)kCrcVariantAuto)
+            return CRUM_EINVAL;
+        c->crc_variant = (int)v;
+        return CRUM_OK;
+    }
     if (param == CRUM_PARAM_DIFF_PRIORITY) {
         if (v > 3)
             return CRUM_EINVAL;
@@ -334,6 +340,7 @@ int crum_ctx_get_param(crum_ctx* c, int param, uint64_t* v)
     case CRUM_PARAM_PIECE_SHIFT: *v = c->piece_shift; return CRUM_OK;
     case CRUM_PARAM_PACK_DEPTH: *v = (uint64_t)c->pack_depth; return CRUM_OK;
     case CRUM_PARAM_DIFF_PRIORITY: *v = (uint64_t)c->diff_prio; return CRUM_OK;
+    case CRUM_PARAM_CRC_VARIANT: *v = (uint64_t)c->crc_variant; return CRUM_OK;
     default: return CRUM_EINVAL;
     }
 }
@@ -519,7 +526,7 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
                 CRUM_TRY(launch_pack(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                      np_shift, pc_shift, d_flags, staging, d_crcs,
                                      d_partials, c->d_tabs, d_glob, c->shape.pack_blocks,
-                                     c->pack_depth, stream));
+                                     c->pack_depth, c->crc_variant, stream));
                 CRUM_TRY(launch_finalize(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                          np_shift, pc_shift, d_partials, d_crcs, staging, d_glob,
                                          stream));
@@ -591,7 +598,7 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
                 CRUM_TRY(launch_pack(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                      np_shift, pc_shift, d_flags, staging, d_crcs,
                                      d_partials, c->d_tabs, d_glob, c->shape.pack_blocks,
-                                     c->pack_depth, stream));
+                                     c->pack_depth, c->crc_variant, stream));
                 CRUM_TRY(launch_finalize(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                          np_shift, pc_shift, d_partials, d_crcs, staging, d_glob,
                                          stream));
@@ -785,7 +792,8 @@ int crum_restore(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
         SlotRange sr{0, D, nullptr, 0, D};
         CRUM_TRY(launch_pack(kModeVerify, d_regs, n_regions, d_reqs, d_out, d_list, sr, np_shift,
                              pc_shift, nullptr, staging, d_crcs, d_partials, c->d_tabs,
-                             d_glob, c->shape.pack_blocks, c->pack_depth, stream));
+                             d_glob, c->shape.pack_blocks, c->pack_depth, c->crc_variant,
+                             stream));
         CRUM_TRY(launch_finalize(kModeVerify, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                  np_shift, pc_shift, d_partials, d_crcs, staging, d_glob,
                                  stream));

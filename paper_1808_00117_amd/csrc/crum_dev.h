@@ -12,6 +12,9 @@ constexpr uint32_t kUnitShiftDefault = 14;
 // CRC piece: pages larger than this are split across waves and combined.
 constexpr uint32_t kPieceShift = 16;  // largest (and default) pack piece: 64 KiB
 constexpr uint32_t kPieceShiftMin = 12;
+// CRC step variants 0..5 (see launch_pack); kCrcVariantAuto picks the one
+// measured fastest per kernel: byte tables for pack, variant 3 for verify.
+constexpr int kCrcVariantAuto = 6;
 constexpr uint32_t kNoBad = 0xFFFFFFFFu;
 
 // One region of the flattened page space (host-built, uploaded per call).
@@ -79,10 +82,15 @@ static_assert(sizeof(DevGlobal) == 64, "DevGlobal layout");
 // with L_j = 32, 64, 128, 256, 512, 1024 for j = 0..5.
 // t[k][b] = b * x^(8(k+1)) (slicing by 16); z[j][i][b] = (b << 8i) * x^(8 L_j)
 // for L = 32, 64, 128, 256, 512, 1024, 4096 bytes; xp[i] = x^(8 * 2^i).
+// nib[k] splits a byte table by nibbles (a table is linear in its index):
+// nib[k][0][n] = T[n] and nib[k][1][n] = T[n << 4] for T = t[k] (k < 16) or
+// T = z[5][k - 16] (the shift by 1 KiB), so T[b] = nib[k][0][b & 15] ^
+// nib[k][1][b >> 4] with two 16-entry lookups that never conflict in LDS banks.
 struct CrcTables {
     uint32_t t[16][256];
     uint32_t z[7][4][256];
     uint32_t xp[64];
+    uint32_t nib[20][2][16];
 };
 
 enum PackMode { kModePack = 0, kModeVerify = 1 };
@@ -123,7 +131,8 @@ hipError_t launch_list(const uint64_t* bitmap, const uint32_t* prefix, uint64_t 
 // is cut into pieces of 2^min(ps, piece_shift) bytes, np_shift is log2 of the
 // largest piece count per slot in the launch, and finalize combines the piece
 // CRCs of pages larger than one piece.  depth: 16-byte loads in flight per
-// lane (4, 8 or 16).  Pack updates the shadows of regions whose flags bit 0
+// lane (4, 8 or 16).  variant (0..5): how the CRC step splits its table
+// lookups between byte and nibble tables.  Pack updates the shadows of regions whose flags bit 0
 // is set.  unit_flags (pack only, may be null): the diff's per-unit flags of
 // the same page space; units flagged clean are then read from the shadow.
 hipError_t launch_pack(int mode, const DevRegion* regs, uint32_t n_regs, const DevRequest* reqs,
@@ -131,7 +140,7 @@ hipError_t launch_pack(int mode, const DevRegion* regs, uint32_t n_regs, const D
                        uint32_t np_shift, uint32_t piece_shift, const uint8_t* unit_flags,
                        uint8_t* staging, uint32_t* crc_out, uint32_t* partials,
                        const CrcTables* tabs, DevGlobal* glob, int blocks, int depth,
-                       hipStream_t s);
+                       int variant, hipStream_t s);
 hipError_t launch_finalize(int mode, const DevRegion* regs, uint32_t n_regs,
                            const DevRequest* reqs, const DevReqOut* out, const uint32_t* list,
                            SlotRange range, uint32_t np_shift, uint32_t piece_shift,

@@ -102,6 +102,7 @@ struct crum_ctx {
     uint32_t piece_shift = crum::kPieceShift;
     int pack_depth = 4;
     int diff_prio = 0;
+    int crc_variant = crum::kCrcVariantAuto;
     bool eager = true;
     uint32_t timing_mask = 0;  // bit c: time launches of class c
     std::vector<hipEvent_t> pool;
@@ -128,6 +129,7 @@ inline hipStream_t ctx_side_stream(const crum_ctx* c) { return c->side; }
 inline uint32_t ctx_piece_shift(const crum_ctx* c) { return c->piece_shift; }
 inline int ctx_pack_depth(const crum_ctx* c) { return c->pack_depth; }
 inline int ctx_diff_prio(const crum_ctx* c) { return c->diff_prio; }
+inline int ctx_crc_variant(const crum_ctx* c) { return c->crc_variant; }
 
 }  // namespace crum
 

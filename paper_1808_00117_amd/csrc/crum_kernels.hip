@@ -51,11 +51,49 @@ void build_crc_tables(CrcTables* h)
     }
     for (int i = 0; i < 64; ++i)
         h->xp[i] = gf2_xpow8n(1ull << i);
+    for (int k = 0; k < 20; ++k) {
+        const uint32_t* T = k < 16 ? h->t[k] : h->z[5][k - 16];
+        for (int n = 0; n < 16; ++n) {
+            h->nib[k][0][n] = T[n];
+            h->nib[k][1][n] = T[n << 4];
+        }
+    }
 }
 
 constexpr int kSliceWords = 16 * 256;                 // 16 KiB
 constexpr int kTabWords = kSliceWords + 6 * 4 * 256;  // shifts up to 1 KiB: 40 KiB (pack)
 constexpr int kAllTabWords = kTabWords + 4 * 256;     // and by 4 KiB: 44 KiB (header)
+
+// LDS layout of the pack and verify kernels (words): slicing tables, nibble
+// tables, shift-by-1-KiB tables; 22.5 KiB.  The butterfly's shift tables
+// (used once per piece) are read from global memory.
+constexpr int kNibOff = kSliceWords;
+constexpr int kZ5Off = kNibOff + 20 * 2 * 16;
+constexpr int kPackLdsWords = kZ5Off + 4 * 256;
+
+__device__ __forceinline__ void load_pack_tables(uint32_t* lds, const CrcTables* tabs)
+{
+    for (int i = threadIdx.x; i < kSliceWords; i += blockDim.x)
+        lds[i] = (&tabs->t[0][0])[i];
+    for (int i = threadIdx.x; i < 20 * 2 * 16; i += blockDim.x)
+        lds[kNibOff + i] = (&tabs->nib[0][0][0])[i];
+    for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x)
+        lds[kZ5Off + i] = (&tabs->z[5][0][0])[i];
+    __syncthreads();
+}
+
+// Variants of the per-word CRC step that trade LDS bank conflicts (a byte
+// lookup into a 256-entry table) against VALU work (two conflict-free nibble
+// lookups): the first NB of the 16 data bytes use byte tables, the rest
+// nibble tables; SB selects byte tables for the 4-byte shift by 1 KiB.
+template <int V> struct CrcVariant;
+template <> struct CrcVariant<0> { static constexpr int NB = 16, SB = 1; };
+template <> struct CrcVariant<1> { static constexpr int NB = 8, SB = 0; };
+template <> struct CrcVariant<2> { static constexpr int NB = 6, SB = 0; };
+template <> struct CrcVariant<3> { static constexpr int NB = 4, SB = 0; };
+template <> struct CrcVariant<4> { static constexpr int NB = 0, SB = 0; };
+template <> struct CrcVariant<5> { static constexpr int NB = 6, SB = 1; };
+constexpr int kCrcVariants = 6;
 
 // raw CRC of one 16-byte word (bytes b0..b15, b0 = low byte of w.x)
 __device__ __forceinline__ uint32_t word_crc(const uint32_t* __restrict__ T, uint4 w)
@@ -92,9 +130,102 @@ __device__ __forceinline__ void load_tables(uint32_t* lds, const CrcTables* tabs
     __syncthreads();
 }
 
+// LDS word at byte offset `off` (a multiple of 4)
+__device__ __forceinline__ uint32_t lds_at(const uint32_t* __restrict__ L, uint32_t off)
+{
+    return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(L) + off);
+}
+
+// byte jj of q in the low byte, zeros above (one v_perm_b32)
+__device__ __forceinline__ uint32_t byte_of(uint32_t q, int jj)
+{
+    return __builtin_amdgcn_perm(0u, q, 0x0c0c0c00u | (uint32_t)jj);
+}
+
+// a ^ b ^ c in one instruction
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+// XOR of the table entries of the 4 bytes of q, byte jj at table position
+// k0 - jj (k0 = 15 - 4*word for data words).  Nibble lookups take their
+// addresses from two masked copies of q that hold 4*nibble in every byte, so
+// each lookup costs one byte extract; byte lookups shift the extracted byte.
+// `nb` (constant after unrolling) is how many of the 4 bytes use byte tables.
+__device__ __forceinline__ uint32_t word4_crc(const uint32_t* __restrict__ L, uint32_t q,
+                                              int nb, int byte_base0, int byte_step,
+                                              int nib_k0, uint32_t r)
+{
+    const uint32_t lo4 = (q << 2) & 0x3C3C3C3Cu;
+    const uint32_t hi4 = (q >> 2) & 0x3C3C3C3Cu;
+    uint32_t pend = 0;  // a byte-table value waiting for a partner in xor3
+    bool have = false;
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+        if (jj < nb) {
+            const uint32_t a = byte_of(q, jj) << 2;
+            const uint32_t v = lds_at(L, 4u * (uint32_t)(byte_base0 + jj * byte_step) + a);
+            if (have) {
+                r = xor3(r, pend, v);
+                have = false;
+            } else {
+                pend = v;
+                have = true;
+            }
+        } else {
+            const uint32_t base = 4u * (uint32_t)(kNibOff + (nib_k0 - jj) * 32);
+            r = xor3(r, lds_at(L, base + byte_of(lo4, jj)), lds_at(L, base + 64u + byte_of(hi4, jj)));
+        }
+    }
+    return have ? r ^ pend : r;
+}
+
+// raw CRC of one 16-byte word with the pack layout (as word_crc): byte j of
+// the word uses table position 15 - j; the first NB bytes use byte tables
+template <int V>
+__device__ __forceinline__ uint32_t word_crc_v(const uint32_t* __restrict__ L, uint4 w)
+{
+    constexpr int NB = CrcVariant<V>::NB;
+    const uint32_t v[4] = {w.x, w.y, w.z, w.w};
+    uint32_t r = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int nb = NB - 4 * q < 0 ? 0 : (NB - 4 * q > 4 ? 4 : NB - 4 * q);
+        r = word4_crc(L, v[q], nb, (15 - 4 * q) * 256, -256, 15 - 4 * q, r);
+    }
+    return r;
+}
+
+// state carried through 1024 zero bytes with the pack layout: byte i of the
+// state uses z[5][i], i.e. nibble position 16 + i
+template <int V>
+__device__ __forceinline__ uint32_t shift1k_v(const uint32_t* __restrict__ L, uint32_t s)
+{
+    constexpr int SB = CrcVariant<V>::SB;
+    if (SB) {
+        return lds_at(L, 4u * kZ5Off + ((s << 2) & 0x3FCu)) ^
+               lds_at(L, 4u * (kZ5Off + 256) + ((s >> 6) & 0x3FCu)) ^
+               lds_at(L, 4u * (kZ5Off + 512) + ((s >> 14) & 0x3FCu)) ^
+               lds_at(L, 4u * (kZ5Off + 768) + ((s >> 22) & 0x3FCu));
+    }
+    // nibble positions 16..19 ascend with the byte index
+    const uint32_t lo4 = (s << 2) & 0x3C3C3C3Cu;
+    const uint32_t hi4 = (s >> 2) & 0x3C3C3C3Cu;
+    uint32_t r = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t base = 4u * (uint32_t)(kNibOff + (16 + i) * 32);
+        r = xor3(r, lds_at(L, base + byte_of(lo4, i)), lds_at(L, base + 64u + byte_of(hi4, i)));
+    }
+    return r;
+}
+
 // Butterfly over the 64 lanes: afterwards every lane holds sum_l C_l*x^(128(63-l)).
-__device__ __forceinline__ uint32_t lane_combine(const uint32_t* __restrict__ lds, uint32_t s,
-                                                 uint32_t lane)
+// T: the slicing tables; Z: z[0] of the shift tables (LDS or global memory).
+__device__ __forceinline__ uint32_t lane_combine_z(const uint32_t* __restrict__ T,
+                                                   const uint32_t* __restrict__ Z, uint32_t s,
+                                                   uint32_t lane)
 {
 #pragma unroll
     for (int lvl = 0; lvl < 6; ++lvl) {
@@ -102,11 +233,17 @@ __device__ __forceinline__ uint32_t lane_combine(const uint32_t* __restrict__ ld
         const bool upper = (lane >> lvl) & 1u;
         const uint32_t left = upper ? other : s;
         const uint32_t right = upper ? s : other;
-        const uint32_t sh = lvl == 0 ? shift16(lds, left)
-                                     : shiftz(lds + kSliceWords + (lvl - 1) * 1024, left);
+        const uint32_t sh = lvl == 0 ? shift16(T, left) : shiftz(Z + (lvl - 1) * 1024, left);
         s = sh ^ right;
     }
     return s;
+}
+
+// The butterfly with all tables in LDS in the header layout.
+__device__ __forceinline__ uint32_t lane_combine(const uint32_t* __restrict__ lds, uint32_t s,
+                                                 uint32_t lane)
+{
+    return lane_combine_z(lds, lds + kSliceWords, s, lane);
 }
 
 // Source of a piece, 1 KiB step by step.  Bit j of `dirty` tells whether
@@ -126,13 +263,13 @@ struct PieceSrc {
     }
 };
 
-template <bool STORE, int U>
+// lds: the pack layout (kPackLdsWords); V: the CRC step variant.
+template <bool STORE, int U, int V>
 __device__ __forceinline__ uint32_t piece_steps(const PieceSrc& src, uint4* __restrict__ dst,
                                                 uint4* __restrict__ sh, uint32_t* t_io,
                                                 uint32_t steps, uint32_t lane,
                                                 const uint32_t* __restrict__ lds, uint32_t s)
 {
-    const uint32_t* Z1024 = lds + kSliceWords + 5 * 1024;
     uint32_t t = *t_io;
     for (; t + U <= steps; t += U) {
         uint4 w[U];
@@ -153,7 +290,7 @@ __device__ __forceinline__ uint32_t piece_steps(const PieceSrc& src, uint4* __re
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            s = shiftz(Z1024, s) ^ word_crc(lds, w[u]);
+            s = shift1k_v<V>(lds, s) ^ word_crc_v<V>(lds, w[u]);
     }
     *t_io = t;
     return s;
@@ -162,19 +299,21 @@ __device__ __forceinline__ uint32_t piece_steps(const PieceSrc& src, uint4* __re
 // Raw (zero-initialised) CRC of `steps` KiB, copied to dst (and to the shadow
 // sh, dirty units only) when STORE.  DEPTH: 16-byte loads each lane issues
 // before it folds them into its CRC.  All lanes return the same value.
-template <bool STORE, int DEPTH>
+// gz: z[0] of the shift tables in global memory (the butterfly's shifts).
+template <bool STORE, int DEPTH, int V>
 __device__ __forceinline__ uint32_t wave_piece_crc(const PieceSrc& src, uint4* __restrict__ dst,
                                                    uint4* __restrict__ sh, uint32_t steps,
                                                    uint32_t lane,
-                                                   const uint32_t* __restrict__ lds)
+                                                   const uint32_t* __restrict__ lds,
+                                                   const uint32_t* __restrict__ gz)
 {
     uint32_t s = 0;
     uint32_t t = 0;
-    s = piece_steps<STORE, DEPTH>(src, dst, sh, &t, steps, lane, lds, s);
+    s = piece_steps<STORE, DEPTH, V>(src, dst, sh, &t, steps, lane, lds, s);
     if (DEPTH > 4)
-        s = piece_steps<STORE, 4>(src, dst, sh, &t, steps, lane, lds, s);
-    s = piece_steps<STORE, 1>(src, dst, sh, &t, steps, lane, lds, s);
-    return lane_combine(lds, s, lane);
+        s = piece_steps<STORE, 4, V>(src, dst, sh, &t, steps, lane, lds, s);
+    s = piece_steps<STORE, 1, V>(src, dst, sh, &t, steps, lane, lds, s);
+    return lane_combine_z(lds, gz, s, lane);
 }
 
 // ------------------------------------------------------------ region lookup
@@ -489,7 +628,7 @@ __device__ __forceinline__ void slot_range(const SlotRange& sr, uint64_t* lo, ui
 // Pack: copy the dirty page into the image's page area (and the shadow) and
 // write its CRC to crc_out[slot].  Verify: recompute the CRC of a packed page
 // of the image and compare with the image's CRC array.
-template <int MODE, int DEPTH>
+template <int MODE, int DEPTH, int V>
 __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs, uint32_t n_regs,
                                               const DevRequest* __restrict__ reqs,
                                               const DevReqOut* __restrict__ out,
@@ -502,7 +641,7 @@ __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs
                                               const CrcTables* __restrict__ tabs,
                                               DevGlobal* __restrict__ glob)
 {
-    __shared__ uint32_t lds[kTabWords];
+    __shared__ uint32_t lds[kPackLdsWords];
     if (MODE == kModeVerify && glob->fmt_bad)
         return;
     uint64_t slot0, slot1;
@@ -510,7 +649,8 @@ __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs
     const uint64_t n_items = (slot1 - slot0) << np_shift;
     if (n_items == 0)
         return;
-    load_tables(lds, tabs, kTabWords);
+    load_pack_tables(lds, tabs);
+    const uint32_t* gz = &tabs->z[0][0][0];
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t wave =
         (uint64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -562,11 +702,11 @@ __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs
             uint4* sh = ((R.flags & 1u) && R.shadow)
                             ? reinterpret_cast<uint4*>(R.shadow + page_off + piece_off)
                             : nullptr;
-            raw = wave_piece_crc<true, DEPTH>(src, reinterpret_cast<uint4*>(slot_ptr), sh, steps,
-                                              lane, lds);
+            raw = wave_piece_crc<true, DEPTH, V>(src, reinterpret_cast<uint4*>(slot_ptr), sh,
+                                                 steps, lane, lds, gz);
         } else {
             const PieceSrc src{reinterpret_cast<const uint4*>(slot_ptr), nullptr, ~0u, 0};
-            raw = wave_piece_crc<false, DEPTH>(src, nullptr, nullptr, steps, lane, lds);
+            raw = wave_piece_crc<false, DEPTH, V>(src, nullptr, nullptr, steps, lane, lds, gz);
         }
         if (lane != 0)
             continue;
@@ -586,26 +726,61 @@ __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs
     }
 }
 
+template <int MODE, int DEPTH, int V>
+static void launch_pack_one(dim3 grid, hipStream_t s, const DevRegion* regs, uint32_t n_regs,
+                            const DevRequest* reqs, const DevReqOut* out, const uint32_t* list,
+                            SlotRange range, uint32_t np_shift, uint32_t piece_shift,
+                            const uint8_t* unit_flags, uint8_t* staging, uint32_t* crc_out,
+                            uint32_t* partials, const CrcTables* tabs, DevGlobal* glob)
+{
+    hipLaunchKernelGGL((k_pack<MODE, DEPTH, V>), grid, dim3(256), 0, s, regs, n_regs, reqs, out,
+                       list, range, np_shift, piece_shift, unit_flags, staging, crc_out,
+                       partials, tabs, glob);
+}
+
+template <int MODE, int DEPTH>
+static void launch_pack_depth(int variant, dim3 grid, hipStream_t s, const DevRegion* regs,
+                              uint32_t n_regs, const DevRequest* reqs, const DevReqOut* out,
+                              const uint32_t* list, SlotRange range, uint32_t np_shift,
+                              uint32_t piece_shift, const uint8_t* unit_flags, uint8_t* staging,
+                              uint32_t* crc_out, uint32_t* partials, const CrcTables* tabs,
+                              DevGlobal* glob)
+{
+#define CRUM_PACK_V(v)                                                                        \
+    launch_pack_one<MODE, DEPTH, v>(grid, s, regs, n_regs, reqs, out, list, range, np_shift, \
+                                    piece_shift, unit_flags, staging, crc_out, partials, tabs, \
+                                    glob)
+    switch (variant) {
+    case 0: CRUM_PACK_V(0); break;
+    case 1: CRUM_PACK_V(1); break;
+    case 2: CRUM_PACK_V(2); break;
+    case 3: CRUM_PACK_V(3); break;
+    case 4: CRUM_PACK_V(4); break;
+    default: CRUM_PACK_V(5); break;
+    }
+#undef CRUM_PACK_V
+}
+
 template <int MODE>
-static void launch_pack_mode(dim3 grid, int depth, hipStream_t s, const DevRegion* regs,
-                             uint32_t n_regs, const DevRequest* reqs, const DevReqOut* out,
-                             const uint32_t* list, SlotRange range, uint32_t np_shift,
-                             uint32_t piece_shift, const uint8_t* unit_flags, uint8_t* staging,
-                             uint32_t* crc_out, uint32_t* partials, const CrcTables* tabs,
-                             DevGlobal* glob)
+static void launch_pack_mode(dim3 grid, int depth, int variant, hipStream_t s,
+                             const DevRegion* regs, uint32_t n_regs, const DevRequest* reqs,
+                             const DevReqOut* out, const uint32_t* list, SlotRange range,
+                             uint32_t np_shift, uint32_t piece_shift, const uint8_t* unit_flags,
+                             uint8_t* staging, uint32_t* crc_out, uint32_t* partials,
+                             const CrcTables* tabs, DevGlobal* glob)
 {
     if (depth == 16)
-        hipLaunchKernelGGL((k_pack<MODE, 16>), grid, dim3(256), 0, s, regs, n_regs, reqs, out,
-                           list, range, np_shift, piece_shift, unit_flags, staging, crc_out,
-                           partials, tabs, glob);
+        launch_pack_depth<MODE, 16>(variant, grid, s, regs, n_regs, reqs, out, list, range,
+                                    np_shift, piece_shift, unit_flags, staging, crc_out,
+                                    partials, tabs, glob);
     else if (depth == 8)
-        hipLaunchKernelGGL((k_pack<MODE, 8>), grid, dim3(256), 0, s, regs, n_regs, reqs, out,
-                           list, range, np_shift, piece_shift, unit_flags, staging, crc_out,
-                           partials, tabs, glob);
+        launch_pack_depth<MODE, 8>(variant, grid, s, regs, n_regs, reqs, out, list, range,
+                                   np_shift, piece_shift, unit_flags, staging, crc_out, partials,
+                                   tabs, glob);
     else
-        hipLaunchKernelGGL((k_pack<MODE, 4>), grid, dim3(256), 0, s, regs, n_regs, reqs, out,
-                           list, range, np_shift, piece_shift, unit_flags, staging, crc_out,
-                           partials, tabs, glob);
+        launch_pack_depth<MODE, 4>(variant, grid, s, regs, n_regs, reqs, out, list, range,
+                                   np_shift, piece_shift, unit_flags, staging, crc_out, partials,
+                                   tabs, glob);
 }
 
 hipError_t launch_pack(int mode, const DevRegion* regs, uint32_t n_regs, const DevRequest* reqs,
@@ -613,7 +788,7 @@ hipError_t launch_pack(int mode, const DevRegion* regs, uint32_t n_regs, const D
                        uint32_t np_shift, uint32_t piece_shift, const uint8_t* unit_flags,
                        uint8_t* staging, uint32_t* crc_out, uint32_t* partials,
                        const CrcTables* tabs, DevGlobal* glob, int blocks, int depth,
-                       hipStream_t s)
+                       int variant, hipStream_t s)
 {
     const uint64_t max_items = range.max_slots << np_shift;
     if (max_items == 0)
@@ -623,14 +798,16 @@ hipError_t launch_pack(int mode, const DevRegion* regs, uint32_t n_regs, const D
     const uint64_t need = (max_items + 3) / 4;
     const uint64_t nb = need < (uint64_t)blocks ? need : (uint64_t)blocks;
     const dim3 grid((unsigned)nb);
+    if (variant == kCrcVariantAuto)
+        variant = mode == kModePack ? 0 : 3;
     if (mode == kModePack)
-        launch_pack_mode<kModePack>(grid, depth, s, regs, n_regs, reqs, out, list, range,
-                                    np_shift, piece_shift, unit_flags, staging, crc_out,
+        launch_pack_mode<kModePack>(grid, depth, variant, s, regs, n_regs, reqs, out, list,
+                                    range, np_shift, piece_shift, unit_flags, staging, crc_out,
                                     partials, tabs, glob);
     else
-        launch_pack_mode<kModeVerify>(grid, depth, s, regs, n_regs, reqs, out, list, range,
-                                      np_shift, piece_shift, nullptr, staging, crc_out, partials,
-                                      tabs, glob);
+        launch_pack_mode<kModeVerify>(grid, depth, variant, s, regs, n_regs, reqs, out, list,
+                                      range, np_shift, piece_shift, nullptr, staging, crc_out,
+                                      partials, tabs, glob);
     return hipGetLastError();
 }
 

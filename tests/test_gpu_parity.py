@@ -354,19 +354,24 @@ def test_diff_variants(unit_shift, nt):
         s.close()
 
 
-@pytest.mark.parametrize("piece_shift,depth", [(12, 16), (13, 4), (14, 8), (16, 16)])
-def test_pack_variants(piece_shift, depth):
-    """Every pack piece size and load depth gives the oracle's image, and the
-    restore (verify + scatter over the same pieces) reproduces memory; a page
-    corrupted in the image is still rejected with its slot."""
+@pytest.mark.parametrize("piece_shift,depth,crc_variant",
+                         [(12, 16, 1), (13, 4, 2), (14, 8, 3), (16, 16, 4), (16, 4, 5),
+                          (16, 8, 0), (16, 4, 6)])
+def test_pack_variants(piece_shift, depth, crc_variant):
+    """Every pack piece size, load depth and CRC step variant gives the
+    oracle's image, and the restore (verify + scatter over the same pieces)
+    reproduces memory; a page corrupted in the image is still rejected with
+    its slot."""
     import torch
     import paper_1808_00117_amd as crum
     from paper_1808_00117_amd.api import Snapshotter
-    log(f"[pack] piece_shift={piece_shift} depth={depth}")
+    log(f"[pack] piece_shift={piece_shift} depth={depth} crc_variant={crc_variant}")
     s = Snapshotter(0)
     try:
         crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_PIECE_SHIFT, piece_shift)
         crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_PACK_DEPTH, depth)
+        crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_CRC_VARIANT, crc_variant)
+        assert crum.crum_ctx_get_param(s.ctx, crum.CRUM_PARAM_CRC_VARIANT) == crc_variant
         crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_PACK_BLOCKS, 5)
         assert crum.crum_ctx_get_param(s.ctx, crum.CRUM_PARAM_PIECE_SHIFT) == piece_shift
         assert crum.crum_ctx_get_param(s.ctx, crum.CRUM_PARAM_PACK_DEPTH) == depth
@@ -401,6 +406,8 @@ def test_pack_variants(piece_shift, depth):
                 crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_PIECE_SHIFT, bad_v)
         with pytest.raises(ValueError):
             crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_PACK_DEPTH, 6)
+        with pytest.raises(ValueError):
+            crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_CRC_VARIANT, 7)
     finally:
         s.close()
 
