@@ -88,11 +88,16 @@ struct Span {
     ~Span() { end(); }
 };
 
+// Grows the context's device scratch.  A call that enqueued all its work
+// recorded ev_done after its last use of the scratch (kernels, read-backs and
+// the status copy), so waiting for that is enough and other contexts on the
+// device keep running; after a call that stopped part-way (a HIP error while
+// enqueueing), the whole device is waited for.
 hipError_t ensure_scratch(crum_ctx* c, size_t bytes)
 {
     if (bytes <= c->scratch_cap)
         return hipSuccess;
-    hipError_t e = hipDeviceSynchronize();
+    hipError_t e = c->partial_call ? hipDeviceSynchronize() : hipEventSynchronize(c->ev_done);
     if (e != hipSuccess)
         return e;
     if (c->d_scratch)
@@ -110,7 +115,7 @@ hipError_t ensure_pinned(crum_ctx* c, size_t bytes)
 {
     if (bytes <= c->pin_cap)
         return hipSuccess;
-    hipError_t e = hipEventSynchronize(c->ev_upload);
+    hipError_t e = c->partial_call ? hipDeviceSynchronize() : hipEventSynchronize(c->ev_upload);
     if (e != hipSuccess)
         return e;
     e = hipEventSynchronize(c->ev_done);
@@ -491,6 +496,7 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     uint8_t* rb = P + rb_off;
 
     // the previous call on this context may still be draining from scratch
+    c->partial_call = true;  // cleared once ev_done is recorded
     CRUM_TRY(hipStreamWaitEvent(stream, c->ev_done, 0));
     CRUM_TRY(hipMemcpyAsync(S, P, L.upload_end, hipMemcpyHostToDevice, stream));
     CRUM_TRY(hipEventRecord(c->ev_upload, stream));
@@ -577,6 +583,7 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
             CRUM_TRY(hipMemcpyAsync(h_status, d_out, sizeof(crum_status), hipMemcpyDeviceToHost,
                                     stream));
             CRUM_TRY(hipEventRecord(c->ev_done, stream));
+            c->partial_call = false;
             return CRUM_OK;
         }
         D = o.n_dirty;
@@ -638,11 +645,13 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
         CRUM_TRY(hipMemcpyAsync(h_status, d_out, sizeof(crum_status), hipMemcpyDeviceToHost,
                                 c->side));
         CRUM_TRY(hipEventRecord(c->ev_done, c->side));
+        c->partial_call = false;
         CRUM_TRY(hipStreamWaitEvent(stream, c->ev_done, 0));
     } else {
         CRUM_TRY(hipMemcpyAsync(h_status, d_out, sizeof(crum_status), hipMemcpyDeviceToHost,
                                 stream));
         CRUM_TRY(hipEventRecord(c->ev_done, stream));
+        c->partial_call = false;
     }
     return CRUM_OK;
 }
@@ -775,6 +784,7 @@ int crum_restore(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     uint8_t* staging = static_cast<uint8_t*>(d_staging);
     const uint64_t* img_bitmap = reinterpret_cast<const uint64_t*>(staging + 64 + 32 * R);
 
+    c->partial_call = true;
     CRUM_TRY(hipStreamWaitEvent(stream, c->ev_done, 0));
     CRUM_TRY(hipMemcpyAsync(S, P, L.upload_end, hipMemcpyHostToDevice, stream));
     CRUM_TRY(hipEventRecord(c->ev_upload, stream));
@@ -808,6 +818,7 @@ int crum_restore(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     CRUM_TRY(launch_restore_finish(d_out, 1, d_glob, stream));
     CRUM_TRY(hipMemcpyAsync(h_status, d_out, sizeof(crum_status), hipMemcpyDeviceToHost, stream));
     CRUM_TRY(hipEventRecord(c->ev_done, stream));
+    c->partial_call = false;
     return CRUM_OK;
 }
 

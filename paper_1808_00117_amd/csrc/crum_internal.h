@@ -105,6 +105,7 @@ struct crum_ctx {
     int crc_variant = crum::kCrcVariantAuto;
     bool eager = true;
     uint32_t timing_mask = 0;  // bit c: time launches of class c
+    bool partial_call = false;  // a call stopped part-way through its enqueue
     std::vector<hipEvent_t> pool;
     size_t pool_used = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> spans[crum::kTimingClasses];

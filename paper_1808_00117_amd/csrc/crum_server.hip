@@ -177,6 +177,14 @@ void worker(crum_server* s, int slot)
         hipMalloc(reinterpret_cast<void**>(&staging), std::max<uint64_t>(s->max_worst, 4096)) !=
             hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&st), sizeof(crum_status), 0) != hipSuccess) {
+        // release what was created; the server reports CRUM_EHIP from now on
+        if (st)
+            (void)hipHostFree(st);
+        if (staging)
+            (void)hipFree(staging);
+        if (stream)
+            (void)hipStreamDestroy(stream);
+        crum_ctx_destroy(ctx);
         s->fatal = 1;
         std::lock_guard<std::mutex> lk(s->mu);
         s->cv_done.notify_all();
