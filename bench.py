@@ -49,7 +49,12 @@ def parse_args():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="many",
-                    choices=["many", "plain", "batched", "served", "managed"])
+                    choices=["many", "plain", "batched", "served", "managed", "persist"])
+    ap.add_argument("--persist-dir", default=None,
+                    help="persist: directory for the checkpoint files ($TMPDIR/crum_persist)")
+    ap.add_argument("--app-ms", type=float, default=500.0,
+                    help="persist: application compute time between checkpoints")
+    ap.add_argument("--writer-threads", type=int, default=4)
     ap.add_argument("--duration", type=float, default=60.0, help="served: trace seconds")
     ap.add_argument("--slots", type=int, default=6, help="served: concurrent request slots")
     ap.add_argument("--rate", type=float, default=200.0, help="served: arrivals per second")
@@ -587,6 +592,164 @@ def bench_served(args):
     print(json.dumps(result), flush=True)
 
 
+def mount_of(path: str) -> dict:
+    """File system type and device of the mount holding `path` (/proc/mounts)."""
+    path = os.path.realpath(path)
+    best = None
+    try:
+        for line in open("/proc/mounts"):
+            dev, mnt, fstype = line.split()[:3]
+            if (path == mnt or path.startswith(mnt.rstrip("/") + "/")) and \
+                    (best is None or len(mnt) > len(best[1])):
+                best = (dev, mnt, fstype)
+    except OSError:
+        pass
+    return {"device": best[0], "mount": best[1], "fstype": best[2]} if best else {}
+
+
+def bench_persist(args):
+    """Phase two: checkpoints of the 16 GiB many-allocations workload written
+    to files.  Naive: each checkpoint snapshots, then writes its image and
+    waits (the application is paused for both).  Overlapped: the image goes
+    to a writer thread pool and the application resumes; two pinned image
+    buffers alternate, so a checkpoint waits only if the write from two
+    checkpoints back has not finished.  Between checkpoints the application
+    computes (SAXPY graphs) for --app-ms."""
+    import numpy as np
+
+    import oracle
+    import paper_1808_00117_amd as crum
+    import paper_1808_00117_amd.hip as H
+    import synth
+    from synth import scenarios as sc
+
+    crum.lib()
+    scn = sc.many_allocs()
+    P, N, D, G, R = scn.page_size, scn.total_bytes, scn.n_dirty, scn.total_pages, len(scn.regions)
+    pairs = materialize_raw(scn, H)
+    table = crum.region_table([(c.ptr, s.ptr if s else 0, r.nbytes, r.id)
+                               for (c, s), r in zip(pairs, scn.regions)])
+    ib = crum.crum_image_bytes(R, G, D, P)
+    cap = crum.crum_image_bytes(R, G, G, P)
+    staging = H.DeviceBuffer(cap)
+    bufs = [H.PinnedBuffer(cap), H.PinnedBuffer(cap)]
+    status = H.PinnedBuffer(64)
+    settle = settle_copy_engines(H, staging.ptr, bufs[0].ptr)
+    ctx = crum.crum_ctx_create(0)
+    s1, s2 = H.Stream(), H.Stream()
+    d = args.persist_dir or os.path.join(os.environ.get("TMPDIR", "/tmp"), "crum_persist")
+    os.makedirs(d, exist_ok=True)
+    fs = mount_of(d)
+    writer = crum.Writer(n_threads=args.writer_threads, chunk_bytes=64 << 20)
+    n_sax = 4096 * 4096
+    x, y = H.DeviceBuffer(4 * n_sax), H.DeviceBuffer(4 * n_sax)
+    H.check(H.hip().hipMemset(x.ptr, 0x3F, 4 * n_sax), "hipMemset")
+    H.check(H.hip().hipMemset(y.ptr, 0x3E, 4 * n_sax), "hipMemset")
+    graph = H.Graph(s2, lambda st: [synth.saxpy_loop_dev(y.ptr, x.ptr, 1.0001, n_sax, 1, 4096,
+                                                          st.handle) for _ in range(16)])
+
+    def app():
+        t_end = time.perf_counter() + args.app_ms * 1e-3
+        while time.perf_counter() < t_end:
+            graph.launch(s2)
+            s2.synchronize()
+
+    def snap(buf, seq):
+        rc = crum.crum_snapshot(ctx, table, P, 0, seq, staging.ptr, cap, buf.ptr, cap,
+                                s1.handle, status.ptr)
+        assert rc == 0, rc
+        s1.synchronize()
+        st = crum.read_status(status.ptr)
+        assert st.code == 0 and st.n_dirty == D and st.image_bytes == ib, st
+
+    snap(bufs[0], 1)
+    K = args.steps
+    writes = []
+    log(f"[persist] {K} checkpoints of {ib / 1e9:.2f} GB images to {d} ({fs})")
+    # naive: snapshot + synchronous write
+    naive = []
+    snap_only = []
+
+    def drain_gbs():
+        n, ms_ = crum.crum_ctx_timing(ctx, 2)
+        crum.crum_ctx_timing_reset(ctx)
+        return round(ib * K / (ms_ * 1e-3) / 1e9, 2) if ms_ else None
+    crum.crum_ctx_timing_reset(ctx)
+    crum.crum_ctx_set_timing(ctx, crum.TIMING_DRAIN)
+    for i in range(K):
+        app()
+        t = time.perf_counter()
+        snap(bufs[0], 100 + i)
+        snap_only.append(time.perf_counter() - t)
+        st = writer.poll(writer.submit(os.path.join(d, f"naive{i % 2}.crum"), bufs[0].ptr, ib))
+        assert st["code"] == 0, st
+        writes.append(st)
+        naive.append(time.perf_counter() - t)
+    drain_naive = drain_gbs()
+    # overlapped: snapshot, hand the image to the writer, resume
+    over, waits, submits, pending = [], [], [], [None, None]
+    t_all = time.perf_counter()
+    for i in range(K):
+        app()
+        t = time.perf_counter()
+        b = i % 2
+        if pending[b] is not None:
+            st = writer.poll(pending[b])
+            assert st["code"] == 0, st
+            writes.append(st)
+        waits.append(time.perf_counter() - t)
+        snap(bufs[b], 200 + i)
+        t_sub = time.perf_counter()
+        pending[b] = writer.submit(os.path.join(d, f"over{b}.crum"), bufs[b].ptr, ib)
+        submits.append(time.perf_counter() - t_sub)
+        over.append(time.perf_counter() - t)
+    last = (K - 1) % 2
+    for b in (1 - last, last):
+        if pending[b] is not None:
+            st = writer.poll(pending[b])
+            assert st["code"] == 0, st
+            writes.append(st)
+    t_all = time.perf_counter() - t_all
+    drain_over = drain_gbs()
+    crum.crum_ctx_set_timing(ctx, False)
+    # the last file equals its image and parses
+    back = np.fromfile(os.path.join(d, f"over{last}.crum"), np.uint8)
+    same = bool(np.array_equal(back, bufs[last].numpy(ib)))
+    rc, hdr = oracle.parse(back)
+    assert same and rc == oracle.OK and hdr["seq"] == 200 + K - 1
+    del back
+    for f in os.listdir(d):
+        if f.endswith(".crum"):
+            os.remove(os.path.join(d, f))
+    writer.destroy()
+    wr = [w["bytes"] / w["seconds"] / 1e9 for w in writes]
+    ms = lambda v: round(1e3 * v, 2)  # noqa: E731
+    result = {
+        "metric": "checkpoint pause (snapshot + persist to a file), overlapped vs naive",
+        "value": ms(statistics.median(over)), "unit": "ms", "n_gpus": 1, "steps": K,
+        "warmup": 1, "ms_per_step": ms(statistics.median(over)), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic (seeded SplitMix64 bytes, PCG64 scenario)",
+        "config": {"workload": "64 allocations scaled to 16 GiB, 64 KiB pages, clustered "
+                               "dirty runs; each checkpoint's image written to a file",
+                   "image_bytes": ib, "app_ms_between": args.app_ms,
+                   "writer_threads": args.writer_threads, "dir": d, "filesystem": fs,
+                   "settle": settle},
+        "overlapped": {"pause_ms": {"p50": ms(statistics.median(over)), "max": ms(max(over))},
+                       "buffer_wait_ms_max": ms(max(waits)),
+                       "submit_ms_max": ms(max(submits)), "total_s": round(t_all, 2),
+                       "drain_gbs": drain_over},
+        "naive": {"pause_ms": {"p50": ms(statistics.median(naive)), "max": ms(max(naive))},
+                  "snapshot_part_ms_p50": ms(statistics.median(snap_only)),
+                  "drain_gbs": drain_naive},
+        "persist_gbs": {"p50": round(statistics.median(wr), 2), "min": round(min(wr), 2),
+                        "direct": bool(writes[-1]["direct"])},
+        "file_equals_image": same,
+    }
+    crum.crum_ctx_destroy(ctx)
+    print(json.dumps(result), flush=True)
+
+
 def fill_managed_host(buf, scn, region_index, pages, threads=16):
     """Write the generator bytes of the listed pages from host threads."""
     from concurrent.futures import ThreadPoolExecutor
@@ -767,6 +930,8 @@ def main():
         return bench_served(args)
     if args.config == "managed":
         return bench_managed(args)
+    if args.config == "persist":
+        return bench_persist(args)
     import numpy as np
 
     import paper_1808_00117_amd as crum

@@ -346,6 +346,55 @@ int crum_ctx_set_timing(crum_ctx* ctx, int classes);
 int crum_ctx_timing(crum_ctx* ctx, int which, uint64_t* launches, double* total_ms);
 int crum_ctx_timing_reset(crum_ctx* ctx);
 
+/* ---------------------------------------------------------------------------
+ * Persisting images: phase two of the paper's checkpoint (section 3.3), where
+ * a forked child writes the image to storage while the application resumes.
+ * Here the image is already in pinned host memory when the snapshot ends, so
+ * a pool of writer threads persists it to a file while the caller goes on
+ * (for example with its next snapshot into another buffer).  The file is cut
+ * into chunks of chunk_bytes written in parallel with pwrite at their
+ * offsets; with CRUM_WRITE_DIRECT, chunks whose length, offset and buffer
+ * are 4 KiB aligned go through an O_DIRECT descriptor when the file system
+ * supports one and the kernel accepts the buffer for direct I/O (HIP pinned
+ * memory is refused on some systems), the rest through the page cache.  With CRUM_WRITE_SYNC the
+ * file's data is flushed (fdatasync) before the write counts as done.
+ * Host code only: no HIP call is made.
+ * -------------------------------------------------------------------------*/
+typedef struct crum_writer crum_writer;
+
+typedef struct {
+    int32_t code;      /* CRUM_OK or CRUM_EIO */
+    int32_t err;       /* errno of the first failing call, else 0 */
+    uint64_t bytes;    /* bytes written (0 on error) */
+    uint32_t direct;   /* 1 when some chunk was written with O_DIRECT */
+    uint32_t reserved;
+    double seconds;    /* from submit until the last byte is written (and synced) */
+} crum_write_status;
+
+enum {
+    CRUM_EIO = -7,     /* a file could not be opened or written */
+    CRUM_EAGAIN = -8   /* crum_writer_poll without wait: not done yet */
+};
+enum { CRUM_WRITE_DIRECT = 1u, CRUM_WRITE_SYNC = 2u };
+
+/* n_threads 1..256; chunk_bytes a positive multiple of 4096.  Returns
+ * CRUM_OK or CRUM_EINVAL. */
+int crum_writer_create(uint32_t n_threads, uint64_t chunk_bytes, uint32_t flags,
+                       crum_writer** out);
+/* Creates or overwrites `path` (its length becomes `bytes` when the write
+ * completes) and queues the write of image[0, bytes).  The
+ * caller keeps the buffer valid and unchanged until crum_writer_poll reports
+ * the ticket done.  Returns CRUM_OK (queued), CRUM_EINVAL, or CRUM_EIO when
+ * the file cannot be opened (nothing queued). */
+int crum_writer_submit(crum_writer* writer, const char* path, const void* image,
+                       uint64_t bytes, uint64_t* ticket);
+/* With wait != 0 blocks until the ticket's write is done; fills *out and
+ * forgets the ticket.  Without wait returns CRUM_EAGAIN while it runs.
+ * CRUM_EINVAL for an unknown (or already collected) ticket. */
+int crum_writer_poll(crum_writer* writer, uint64_t ticket, int wait, crum_write_status* out);
+/* Waits for every submitted write, then stops the threads. */
+void crum_writer_destroy(crum_writer* writer);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,6 +17,7 @@ SO = os.path.join(HERE, "libcrum.so")
 
 CRUM_OK, CRUM_EINVAL, CRUM_ENOSPC, CRUM_ECRC = 0, -1, -2, -3
 CRUM_EFORMAT, CRUM_EHIP, CRUM_EMISMATCH = -4, -5, -6
+CRUM_EIO, CRUM_EAGAIN = -7, -8
 CRUM_UPDATE_SHADOW, CRUM_VERIFY = 1, 2
 CRUM_PARAM_DIFF_BLOCKS, CRUM_PARAM_PACK_BLOCKS = 1, 2
 CRUM_PARAM_CHUNK_BYTES, CRUM_PARAM_CHUNK_MAX_BYTES = 3, 4
@@ -26,7 +27,8 @@ CRUM_PARAM_PIECE_SHIFT, CRUM_PARAM_PACK_DEPTH, CRUM_PARAM_DIFF_PRIORITY = 9, 10,
 CRUM_PARAM_CRC_VARIANT = 12
 
 CODE_NAMES = {0: "CRUM_OK", -1: "CRUM_EINVAL", -2: "CRUM_ENOSPC", -3: "CRUM_ECRC",
-              -4: "CRUM_EFORMAT", -5: "CRUM_EHIP", -6: "CRUM_EMISMATCH"}
+              -4: "CRUM_EFORMAT", -5: "CRUM_EHIP", -6: "CRUM_EMISMATCH", -7: "CRUM_EIO",
+              -8: "CRUM_EAGAIN"}
 
 
 class crum_region(ctypes.Structure):
@@ -66,6 +68,15 @@ CRUM_REQ_SNAPSHOT, CRUM_REQ_RESTORE = 1, 2
 CRUM_SERVE_ADAPTIVE, CRUM_SERVE_TWO_STAGE, CRUM_SERVE_PIPELINED = 0, 1, 2
 
 
+class crum_write_status(ctypes.Structure):
+    _fields_ = [("code", ctypes.c_int32), ("err", ctypes.c_int32), ("bytes", ctypes.c_uint64),
+                ("direct", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("seconds", ctypes.c_double)]
+
+
+CRUM_WRITE_DIRECT, CRUM_WRITE_SYNC = 1, 2
+
+
 class crum_request_status(ctypes.Structure):
     _fields_ = [("status", crum_status), ("image_offset", ctypes.c_uint64)]
 
@@ -98,6 +109,10 @@ _SIGS = {
     "crum_ctx_set_timing": (_I, [_P, _I]),
     "crum_ctx_timing": (_I, [_P, _I, ctypes.POINTER(_U64), ctypes.POINTER(ctypes.c_double)]),
     "crum_ctx_timing_reset": (_I, [_P]),
+    "crum_writer_create": (_I, [_U32, _U64, _U32, ctypes.POINTER(_P)]),
+    "crum_writer_submit": (_I, [_P, ctypes.c_char_p, _P, _U64, ctypes.POINTER(_U64)]),
+    "crum_writer_poll": (_I, [_P, _U64, _I, _P]),
+    "crum_writer_destroy": (None, [_P]),
 }
 
 _lib = None
@@ -358,3 +373,44 @@ def read_status(addr: int) -> crum_status:
     st = crum_status()
     ctypes.memmove(ctypes.byref(st), addr, ctypes.sizeof(st))
     return st
+
+
+class Writer:
+    """Owns a crum_writer: persists host images to files on a thread pool."""
+
+    def __init__(self, n_threads: int = 4, chunk_bytes: int = 64 << 20,
+                 flags: int = CRUM_WRITE_DIRECT | CRUM_WRITE_SYNC):
+        h = _P()
+        rc = lib().crum_writer_create(n_threads, chunk_bytes, flags, ctypes.byref(h))
+        if rc != CRUM_OK:
+            raise ValueError(f"crum_writer_create: {CODE_NAMES.get(rc, rc)}")
+        self.handle = h.value
+
+    def submit(self, path: str, image_ptr: int, nbytes: int) -> int:
+        t = _U64()
+        rc = lib().crum_writer_submit(self.handle, os.fsencode(path), image_ptr or None, nbytes,
+                                      ctypes.byref(t))
+        if rc != CRUM_OK:
+            raise OSError(f"crum_writer_submit({path}): {CODE_NAMES.get(rc, rc)}")
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = True):
+        """dict of the write's status, or None while it runs (wait=False)."""
+        st = crum_write_status()
+        rc = lib().crum_writer_poll(self.handle, ticket, 1 if wait else 0, ctypes.byref(st))
+        if rc == CRUM_EAGAIN:
+            return None
+        if rc != CRUM_OK:
+            raise ValueError(f"crum_writer_poll: {CODE_NAMES.get(rc, rc)}")
+        return {f: getattr(st, f) for f, _ in crum_write_status._fields_}
+
+    def destroy(self) -> None:
+        if self.handle:
+            lib().crum_writer_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

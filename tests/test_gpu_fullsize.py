@@ -214,3 +214,51 @@ def test_batched_256_requests():
                     sh.free()
         staging.free()
         himg.free()
+
+
+def test_persist_16gib_image(tmp_path):
+    """The 16 GiB workload's image, persisted by the writer while the next
+    snapshot runs into a second buffer: both files equal their images."""
+    import bench
+    import paper_1808_00117_amd as crum
+    import paper_1808_00117_amd.hip as H
+    from synth import scenarios as sc
+
+    scn = sc.many_allocs()
+    P, G, D, R = scn.page_size, scn.total_pages, scn.n_dirty, len(scn.regions)
+    log("[fullsize] persist")
+    pairs = bench.materialize_raw(scn, H)
+    table = crum.region_table([(c.ptr, s.ptr, r.nbytes, r.id)
+                               for (c, s), r in zip(pairs, scn.regions)])
+    ib = crum.crum_image_bytes(R, G, D, P)
+    cap = crum.crum_image_bytes(R, G, G, P)
+    staging = H.DeviceBuffer(cap)
+    bufs = [H.PinnedBuffer(cap), H.PinnedBuffer(cap)]
+    status = H.PinnedBuffer(64)
+    ctx = crum.crum_ctx_create(0)
+    s = H.Stream()
+    w = crum.Writer(n_threads=4, chunk_bytes=64 << 20)
+    try:
+        tickets = []
+        for i in range(2):
+            assert crum.crum_snapshot(ctx, table, P, 0, 20 + i, staging.ptr, cap, bufs[i].ptr,
+                                      cap, s.handle, status.ptr) == 0
+            s.synchronize()
+            assert crum.read_status(status.ptr).code == 0
+            tickets.append(w.submit(str(tmp_path / f"ckpt{i}.crum"), bufs[i].ptr, ib))
+        for i, t in enumerate(tickets):
+            st = w.poll(t)
+            assert st["code"] == 0 and st["bytes"] == ib, st
+            back = np.fromfile(tmp_path / f"ckpt{i}.crum", np.uint8)
+            assert np.array_equal(back, bufs[i].numpy(ib))
+            rc, hdr = oracle.parse(back)
+            assert rc == oracle.OK and hdr["seq"] == 20 + i and hdr["n_dirty"] == D
+    finally:
+        w.destroy()
+        crum.crum_ctx_destroy(ctx)
+        for c, sh in pairs:
+            c.free()
+            sh.free()
+        staging.free()
+        for b in bufs:
+            b.free()
