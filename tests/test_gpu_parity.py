@@ -427,3 +427,40 @@ def test_diff_priority():
             crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_DIFF_PRIORITY, 4)
     finally:
         s.close()
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_random_tables(snap, snap_small_chunks, seed):
+    """Seeded random region tables: page size 4 KiB-1 MiB, 0-6 regions of
+    0-60 pages (empty regions included), dirty pages anywhere in a page,
+    some regions without shadow, with or without shadow update, in both
+    orders and on a context that pipelines in 64-page chunks.  Image, status
+    and the shadows afterwards must equal the oracle's."""
+    import torch
+    rng = np.random.default_rng(1000 + seed)
+    P = int(rng.choice([4 * KiB, 8 * KiB, 16 * KiB, 64 * KiB, 128 * KiB, 1 * MiB],
+                       p=[0.3, 0.15, 0.15, 0.2, 0.1, 0.1]))
+    n_reg = int(rng.integers(0, 7))
+    max_pages = 60 if P <= 64 * KiB else 12
+    counts = [int(rng.integers(0, max_pages + 1)) for _ in range(n_reg)]
+    G = sum(counts)
+    frac = float(rng.choice([0.0, 0.05, 0.3, 1.0]))
+    dirty = set(int(g) for g in np.flatnonzero(rng.random(G) < frac))
+    nulls = tuple(i for i in range(n_reg) if rng.random() < 0.15)
+    host = host_case(counts, P, dirty, seed=seed, null_shadow=nulls)
+    flags = int(rng.integers(0, 2))
+    log(f"[random] seed={seed} P={P} counts={counts} dirty={len(dirty)} nulls={nulls} "
+        f"flags={flags}")
+    others = (snap_small_chunks,) if flags == 0 else ()
+    st_o, img_o, _ = oracle.snapshot(host, P, seq=seed)
+    if flags == 0:
+        check_parity(snap, host, P, seq=seed, others=others)
+        return
+    # with shadow update: the image, then every shadow equals its current region
+    dev = upload(host)
+    rc, st, img, _ = gpu_snapshot(snap, dev, P, seq=seed, flags=1)
+    assert rc == 0 and st.code == 0 and np.array_equal(img, img_o)
+    for (c, s, _), (hc, hs, _) in zip(dev, host):
+        assert torch.equal(c.cpu(), torch.from_numpy(hc))
+        if s is not None:
+            assert torch.equal(s, c)
