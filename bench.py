@@ -88,10 +88,15 @@ def parse_args():
 
 
 def kernel_source_hash() -> str:
+    """Hash of the device code's sources without comments and blank lines, so
+    that counters taken on a kernel stay valid across comment edits only."""
+    import re
     h = hashlib.sha256()
     for f in ("crum_kernels.hip", "crum_dev.h", "gf2.h"):
-        with open(os.path.join(ROOT, "paper_1808_00117_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1808_00117_amd", "csrc", f)) as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        lines = (re.sub(r"//.*", "", ln).rstrip() for ln in text.splitlines())
+        h.update("\n".join(ln for ln in lines if ln).encode())
     return h.hexdigest()[:16]
 
 

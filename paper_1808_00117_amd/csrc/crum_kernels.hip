@@ -1,6 +1,7 @@
 // HIP kernels of the incremental snapshot (gfx950, wave64).
 //
-// Snapshot pipeline (one launch of each, except pack which runs in chunks):
+// Snapshot pipeline (one launch of each per chunk of the page space, or per
+// group of requests of a plan):
 //   k_diff    per diff unit (min(page, 4-16 KiB)): OR over 16-byte words of
 //             (cur ^ shadow) != 0, read with coalesced 128-bit loads and
 //             reduced across the wave by ballot; one flag byte per unit.
@@ -12,8 +13,9 @@
 //             dirty counts, image offsets and the capacity check.
 //   k_list    per word: ballot compaction, lane with bit set writes its page
 //             index at prefix + popcount(bits below the lane).
-//   k_pack    per dirty page (or 64 KiB piece): copy into the image's page
-//             area, optionally into the shadow, and CRC-32C on the way.
+//   k_pack    per dirty page (or piece of up to 64 KiB): copy into the
+//             image's page area, optionally into the shadow, and CRC-32C on
+//             the way; k_finalize combines the piece CRCs of larger pages.
 //   k_header  per request: header, region table, bitmap, CRC array, pads,
 //             crcs_crc, meta_crc.
 // Restore: k_restore_check, k_scan, k_list, k_pack (verify), k_scatter.
@@ -27,7 +29,9 @@
 //   sum_l C_l * x^(8*16*(63-l)),
 // formed by a 6-level butterfly over lanes (level k shifts the lower half by
 // 16*2^k bytes).  Pieces of one page combine the same way with a shift by the
-// piece length; the standard CRC adds crc_init_fix(page bytes).
+// piece length; the standard CRC adds crc_init_fix(page bytes).  Each table
+// lookup may also be done as two lookups into 16-entry nibble tables, which
+// never conflict in LDS banks (CrcVariant).
 #include "crum_dev.h"
 #include "gf2.h"
 
@@ -60,9 +64,10 @@ void build_crc_tables(CrcTables* h)
     }
 }
 
-constexpr int kSliceWords = 16 * 256;                 // 16 KiB
-constexpr int kTabWords = kSliceWords + 6 * 4 * 256;  // shifts up to 1 KiB: 40 KiB (pack)
-constexpr int kAllTabWords = kTabWords + 4 * 256;     // and by 4 KiB: 44 KiB (header)
+// LDS layout of the header and restore-check kernels (words): the slicing
+// tables, then all seven shift levels z[0..6] (44 KiB), as in CrcTables.
+constexpr int kSliceWords = 16 * 256;                      // 16 KiB
+constexpr int kAllTabWords = kSliceWords + 7 * 4 * 256;    // 44 KiB
 
 // LDS layout of the pack and verify kernels (words): slicing tables, nibble
 // tables, shift-by-1-KiB tables; 22.5 KiB.  The butterfly's shift tables
