@@ -381,15 +381,31 @@ def bench_batched(args):
         gt = plan.group_times()
         return sum((gr[g + 1] - gr[g]) * gt[g] for g in range(len(gt))) / len(reqs) / 1e3
 
+    def digests():
+        """Per request: status code and the image's two checksums (meta_crc
+        covers header, table and bitmap; crcs_crc covers every page CRC)."""
+        img = h_images.numpy(cap)
+        out = []
+        for code, _, _, _, b, off in crum.read_request_statuses(status.ptr, len(reqs)):
+            out.append((code, b, img[off + 56:off + 64].tobytes() if code == 0 else b""))
+        return out
+
     if args.tune:
         # objective: mean request completion time (latency), which also
-        # tracks the makespan since the batch is drain-bound
+        # tracks the makespan since the batch is drain-bound; every candidate
+        # must give the same images as the first
+        ref = []
+
         def trial():
             plan = make_plan()
             launch(plan)  # warm
             launch(plan)
             t = mean_request_latency(plan)
             plan.destroy()
+            dg = digests()
+            if not ref:
+                ref.append(dg)
+            assert dg == ref[0], "a tuning candidate changed the images"
             return t
         space = {"chunk_bytes": [4 << 20, 16 << 20, 64 << 20, 256 << 20],
                  "chunk_max_bytes": [64 << 20, 256 << 20, 1 << 30, 4 << 30],

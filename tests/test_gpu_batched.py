@@ -209,3 +209,46 @@ def test_batched_scenario_matches_sequential(ctx):
     assert np.array_equal(himg[off:off + ib].numpy(),
                           oracle.snapshot(hr, reqs[q].page_size, seq=3)[1])
     plan.destroy()
+
+
+def test_autotune_keeps_images(tmp_path):
+    """The shape tuner on a small batch: every candidate shape gives the
+    same images as the oracle, the best shapes are applied and cached."""
+    import time
+    import torch
+    import paper_1808_00117_amd as crum
+    from paper_1808_00117_amd import autotune
+    from paper_1808_00117_amd.api import regions_of
+    host = make_requests(11, 12, max_regions=3)
+    expected = [oracle.snapshot(r, P, seq=s)[1] for r, P, s in host]
+    dev = [upload(regs) for regs, _, _ in host]
+    ctx = crum.crum_ctx_create(0)
+    try:
+        cap = sum((e.size + 4095) // 4096 * 4096 for e in expected) + (1 << 20)
+        staging = torch.empty(cap, dtype=torch.uint8, device="cuda")
+        himg = torch.empty(cap, dtype=torch.uint8, pin_memory=True)
+        status = torch.zeros(40 * len(host), dtype=torch.uint8, pin_memory=True)
+        reqs = [(regions_of(d), P, 0, s) for d, (_, P, s) in zip(dev, host)]
+
+        def run():
+            plan = crum.Plan(ctx, reqs, staging.data_ptr(), cap, himg.data_ptr(), cap)
+            t = time.perf_counter()
+            assert plan.launch(torch.cuda.current_stream().cuda_stream, status.data_ptr()) == 0
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t
+            for q, (code, _, _, _, b, off) in enumerate(
+                    crum.read_request_statuses(status.data_ptr(), len(host))):
+                assert code == 0 and np.array_equal(himg[off:off + b].numpy(), expected[q]), q
+            plan.destroy()
+            return t
+        space = {"pack_blocks": [8, 256], "chunk_bytes": [4096, 1 << 20],
+                 "crc_variant": [0, 3], "diff_blocks": [16, 1024]}
+        best, trials = autotune.search(ctx, run, space, repeats=1)
+        assert len(trials) == 1 + sum(len(v) for v in space.values()) - sum(
+            1 for k, v in space.items() if trials[0]["params"][k] in v)
+        assert autotune.current(ctx) == best
+        path = str(tmp_path / "cache.json")
+        autotune.save("test", best, trials, path)
+        assert autotune.load("test", path) == best
+    finally:
+        crum.crum_ctx_destroy(ctx)

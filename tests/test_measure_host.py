@@ -1,0 +1,96 @@
+"""Host-side measurement and tuning logic (no GPU): the counter calibration
+arithmetic, the trace summary's choice of the timed launches, the kernel
+source hash, and the tuner's coordinate search and cache."""
+import json
+
+import pytest
+
+import bench
+
+
+def write_csv(path, header, rows):
+    with open(path, "w") as f:
+        f.write(",".join(header) + "\n")
+        for r in rows:
+            f.write(",".join(str(x) for x in r) + "\n")
+
+
+def test_pmc_summary_scales_by_the_copy_kernel(tmp_path):
+    """Counters are KiB per dispatch; each is divided by what it reads for
+    the 1 GiB copy kernel per byte of it."""
+    hdr = ["Kernel_Name", "Counter_Name", "Counter_Value"]
+    fetch, write = tmp_path / "f", tmp_path / "w"
+    fetch.mkdir()
+    write.mkdir()
+    gib_kib = bench.CALIB_BYTES / 1024
+    write_csv(fetch / "run_counter_collection.csv", hdr,
+              [("synth_copy_kernel(x)", "FETCH_SIZE", 0.5 * gib_kib),
+               ("crum::k_diff<true>(y)", "FETCH_SIZE", 100.0),
+               ("crum::k_diff<true>(y)", "FETCH_SIZE", 300.0),
+               ("other", "FETCH_SIZE", 7.0)])
+    write_csv(write / "run_counter_collection.csv", hdr,
+              [("synth_copy_kernel(x)", "WRITE_SIZE", 1.0 * gib_kib),
+               ("crum::k_diff<true>(y)", "WRITE_SIZE", 2.0),
+               ("crum::k_diff<true>(y)", "WRITE_SIZE", 2.0)])
+    res = bench.pmc_summary(str(fetch), str(write), "many_allocs")
+    assert res["FETCH_SIZE"]["calibration_factor"] == 0.5
+    assert res["FETCH_SIZE"]["k_diff_dispatches"] == 2
+    # (100 + 300) KiB / 2 launches / 0.5
+    assert res["FETCH_SIZE"]["k_diff_bytes_per_launch"] == pytest.approx(400 * 1024)
+    assert res["WRITE_SIZE"]["k_diff_bytes_per_launch"] == pytest.approx(2 * 1024)
+    assert res["traffic_bytes_per_launch"] == round(400 * 1024 + 2 * 1024)
+    assert res["kernel_source_hash"] == bench.kernel_source_hash()
+
+
+def test_trace_summary_takes_the_last_steps(tmp_path):
+    """k_diff launches after the header that closes the last untimed
+    snapshot are the timed ones."""
+    hdr = ["Kernel_Name", "Start_Timestamp", "End_Timestamp"]
+    rows = []
+    t = 0
+    for snap in range(5):  # 2 untimed + 3 timed snapshots, 2 diffs each
+        dur = 1000 if snap < 2 else 3000
+        for _ in range(2):
+            rows.append(("crum::k_diff<true>", t, t + dur))
+            t += 10000
+        rows.append(("crum::k_header", t, t + 10))
+        t += 10000
+    write_csv(tmp_path / "run_kernel_trace.csv", hdr, rows)
+    out = bench.trace_summary(str(tmp_path), 3)
+    assert "6, average duration 0.0030 ms" in out
+
+
+def test_kernel_hash_ignores_comments(tmp_path, monkeypatch):
+    src = tmp_path / "paper_1808_00117_amd" / "csrc"
+    src.mkdir(parents=True)
+    for f in ("crum_kernels.hip", "crum_dev.h", "gf2.h"):
+        (src / f).write_text("int a; // one\n/* two\n lines */\nint b;\n\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h1 = bench.kernel_source_hash()
+    (src / "gf2.h").write_text("int a; // changed comment\n\nint b;\n")
+    assert bench.kernel_source_hash() == h1
+    (src / "gf2.h").write_text("int a;\nint c;\n")
+    assert bench.kernel_source_hash() != h1
+
+
+def test_autotune_search_and_cache(tmp_path, monkeypatch):
+    """Coordinate search finds the minimum of a separable objective and the
+    cache round-trips per device key and workload."""
+    from paper_1808_00117_amd import autotune
+    state = {"a": 1, "b": 1}
+    monkeypatch.setattr(autotune, "current", lambda ctx: dict(state))
+    monkeypatch.setattr(autotune, "apply", lambda ctx, p: state.update(p))
+    monkeypatch.setattr(autotune, "device_key", lambda: "test-device|hip0")
+    best, trials = autotune.search(
+        None, lambda: (state["a"] - 3) ** 2 + (state["b"] - 5) ** 2 + 1.0,
+        {"a": [1, 2, 3, 4], "b": [2, 5, 8]}, repeats=3)
+    assert best == {"a": 3, "b": 5} and state == best
+    assert trials[0]["params"] == {"a": 1, "b": 1}
+    assert min(t["seconds"] for t in trials) == 1.0
+    path = str(tmp_path / "cache.json")
+    autotune.save("batched", best, trials, path)
+    autotune.save("other", {"a": 9}, [], path)
+    assert autotune.load("batched", path) == best
+    assert autotune.load("missing", path) is None
+    assert autotune.load("batched", str(tmp_path / "none.json")) is None
+    assert set(json.load(open(path))["test-device|hip0"]) == {"batched", "other"}
