@@ -417,26 +417,45 @@ def bench_batched(args):
     if tuned:
         autotune.apply(ctx, tuned)
     params = autotune.current(ctx)
+
+    def timed(plan):
+        """Warm-up and timed launches of a plan: makespans, per-request
+        latencies (launch start to the end of the request's group drain) and
+        the last statuses."""
+        order, gr = plan.order(), plan.groups()
+        group_of = np.zeros(len(reqs), np.int64)
+        for g in range(len(gr) - 1):
+            for pos in range(gr[g], gr[g + 1]):
+                group_of[order[pos]] = g
+        for _ in range(args.warmup):
+            launch(plan)
+        sts = crum.read_request_statuses(status.ptr, len(reqs))
+        for q, (code, _, D, G, ib, off) in enumerate(sts):
+            assert code == 0 and D == reqs[q].n_dirty and ib == sizes[q], (q, sts[q])
+        mk, lat = [], []
+        for _ in range(args.steps):
+            mk.append(launch(plan))
+            gt = plan.group_times()
+            lat.extend(gt[g] for g in group_of)
+        return mk, lat, sts, len(gr) - 1
+
     plan = make_plan()
-    groups = plan.groups()
-    n_groups = len(groups) - 1
-    group_of = np.zeros(len(reqs), np.int64)
-    for g in range(n_groups):
-        group_of[groups[g]:groups[g + 1]] = g
-    for _ in range(args.warmup):
-        launch(plan)
-    sts = crum.read_request_statuses(status.ptr, len(reqs))
-    for q, (code, _, D, G, ib, off) in enumerate(sts):
-        assert code == 0 and D == reqs[q].n_dirty and ib == sizes[q], (q, sts[q])
+    mk, lat_b, sts, n_groups = timed(plan)
     offsets = [st[5] for st in sts]
-    # timed plan launches
-    mk, lat_b = [], []
-    for _ in range(args.steps):
-        mk.append(launch(plan))
-        gt = plan.group_times()
-        lat_b.extend(gt[g] for g in group_of)
-    batched_image = h_images.numpy(cap)[: offsets[-1] + sizes[-1]].copy()
+    batched_image = h_images.numpy(cap)[: max(o + b for o, b in zip(offsets, sizes))].copy()
     plan.destroy()
+
+    # the same plan with the smallest requests first: same images, each at
+    # its own offset
+    crum.crum_ctx_set_param(ctx, crum.CRUM_PARAM_PLAN_ORDER, 1)
+    plan = make_plan()
+    mk_s, lat_s, sts_s, n_groups_s = timed(plan)
+    img_s = h_images.numpy(cap)
+    same_s = all(np.array_equal(img_s[st[5]:st[5] + b], batched_image[o:o + b])
+                 for st, o, b in zip(sts_s, offsets, sizes))
+    assert same_s, "smallest-first images differ from the given-order ones"
+    plan.destroy()
+    crum.crum_ctx_set_param(ctx, crum.CRUM_PARAM_PLAN_ORDER, params.get("plan_order", 0))
 
     # one-at-a-time plain path, same host offsets
     worst = max(crum.crum_image_bytes(len(r.regions), r.total_pages, r.total_pages,
@@ -491,6 +510,11 @@ def bench_batched(args):
                     "latency_ms": {"p50": round(percentile(lat_b, 0.5), 2),
                                    "p99": round(percentile(lat_b, 0.99), 2)},
                     "drain_gbs": round(sum(sizes) / statistics.median(mk) / 1e9, 2)},
+        "batched_smallest_first": {
+            "makespan_ms": round(1e3 * statistics.median(mk_s), 2),
+            "latency_ms": {"p50": round(percentile(lat_s, 0.5), 2),
+                           "p99": round(percentile(lat_s, 0.99), 2)},
+            "groups": n_groups_s, "same_images": same_s},
         "plain": {"makespan_ms": round(1e3 * t_plain, 2),
                   "gbs": round(N / t_plain / 1e9, 2),
                   "latency_ms": {"p50": round(1e3 * percentile(lat_p, 0.5), 2),

@@ -157,12 +157,15 @@ int crum_restore(crum_ctx* ctx, const crum_region* regions, uint32_t n_regions,
  * Many snapshot requests in one plan (the batched pattern).  Each request is a
  * region table with its own page size, flags (CRUM_UPDATE_SHADOW) and seq,
  * and produces exactly the image that crum_snapshot would produce for it.
- * Requests are grouped in order (groups of whole requests, scanned bytes per
- * group starting at CRUM_PARAM_CHUNK_BYTES and doubling up to
- * CRUM_PARAM_CHUNK_MAX_BYTES); each group's device work -- one persistent diff
+ * Requests are processed in the caller's order, or smallest scanned bytes
+ * first when CRUM_PARAM_PLAN_ORDER is 1 (a request then waits only for
+ * smaller ones), and grouped in that order (groups of whole requests,
+ * scanned bytes per group starting at CRUM_PARAM_CHUNK_BYTES and doubling up
+ * to CRUM_PARAM_CHUNK_MAX_BYTES); each group's device work -- one persistent diff
  * over all units of its requests, bitmap, scan, compaction, pack with CRCs and
  * headers -- is captured once as a HIP graph at plan creation.  Request images
- * are laid out back to back in d_staging (each at a 4 KiB-aligned offset) and
+ * are laid out back to back in processing order in d_staging (each at a 4
+ * KiB-aligned offset) and
  * copied to the same offsets of h_images, one contiguous copy per group on the
  * context's side stream as soon as the group is done. */
 typedef struct {
@@ -186,8 +189,8 @@ typedef struct {
  * and capture the group graphs, using the context's current parameters.  The
  * plan keeps the region pointers, d_staging and h_images (pinned host memory
  * or NULL).  If the images of a group do not fit the capacity
- * (min(staging_bytes, h_images_bytes)), that group and every later group
- * report CRUM_ENOSPC and write no page, CRC or shadow.
+ * (min(staging_bytes, h_images_bytes)), that group and every later group (in
+ * processing order) report CRUM_ENOSPC and write no page, CRC or shadow.
  * Returns CRUM_OK, CRUM_EINVAL or CRUM_EHIP. */
 int crum_plan_create(crum_ctx* ctx, const crum_request* reqs, uint32_t n_reqs, void* d_staging,
                      uint64_t staging_bytes, void* h_images, uint64_t h_images_bytes,
@@ -196,12 +199,18 @@ int crum_plan_create(crum_ctx* ctx, const crum_request* reqs, uint32_t n_reqs, v
 /* Snapshot every request of the plan: launch the group graphs on `stream`,
  * and drain each group behind it (the calling thread waits for each group's
  * end to size its copy).  h_status: pinned array of n_reqs entries, valid
- * once `stream` passes the launch.  Calls on one plan must not overlap. */
+ * once `stream` passes the launch, indexed in the caller's order of the
+ * requests.  Calls on one plan must not overlap. */
 int crum_plan_launch(crum_plan* plan, void* stream, crum_request_status* h_status);
 
-/* Group layout: n_groups, and first_request[0..n_groups] (group g holds
- * requests [first_request[g], first_request[g+1])), up to cap entries. */
+/* Group layout: n_groups, and first_request[0..n_groups] (group g holds the
+ * requests at processing positions [first_request[g], first_request[g+1])),
+ * up to cap entries. */
 int crum_plan_groups(crum_plan* plan, uint32_t* n_groups, uint32_t* first_request, uint32_t cap);
+
+/* Processing order: order[k] is the caller's index of the request at
+ * position k, for k < min(n_reqs, cap). */
+int crum_plan_order(crum_plan* plan, uint32_t* order, uint32_t cap);
 
 /* For the last launch: milliseconds from its start to the end of each
  * group's drain (waits for them), up to cap entries. */
@@ -310,6 +319,8 @@ void crum_server_destroy(crum_server* server);
  *   and verify kernels, 4, 8 or 16 (4).
  * CRUM_PARAM_DIFF_PRIORITY: issue priority of the diff kernel's waves on
  *   their compute units relative to co-running kernels, 0..3 (0).
+ * CRUM_PARAM_PLAN_ORDER: processing order of a plan's requests, 0 = the
+ *   caller's, 1 = smallest scanned bytes first (0).
  * CRUM_PARAM_CRC_VARIANT: how the pack and verify kernels' CRC step splits
  *   its table lookups between 256-entry byte tables (bank conflicts) and
  *   16-entry nibble tables (conflict-free, more ALU work): 0 = byte tables
@@ -329,7 +340,8 @@ enum {
     CRUM_PARAM_PIECE_SHIFT = 9,
     CRUM_PARAM_PACK_DEPTH = 10,
     CRUM_PARAM_DIFF_PRIORITY = 11,
-    CRUM_PARAM_CRC_VARIANT = 12
+    CRUM_PARAM_CRC_VARIANT = 12,
+    CRUM_PARAM_PLAN_ORDER = 13
 };
 int crum_ctx_set_param(crum_ctx* ctx, int param, uint64_t value);
 int crum_ctx_get_param(crum_ctx* ctx, int param, uint64_t* value);

@@ -24,7 +24,7 @@ CRUM_PARAM_CHUNK_BYTES, CRUM_PARAM_CHUNK_MAX_BYTES = 3, 4
 CRUM_PARAM_EAGER, CRUM_PARAM_DRAIN_CHUNK_BYTES = 5, 6
 CRUM_PARAM_DIFF_UNIT_SHIFT, CRUM_PARAM_DIFF_NONTEMPORAL = 7, 8
 CRUM_PARAM_PIECE_SHIFT, CRUM_PARAM_PACK_DEPTH, CRUM_PARAM_DIFF_PRIORITY = 9, 10, 11
-CRUM_PARAM_CRC_VARIANT = 12
+CRUM_PARAM_CRC_VARIANT, CRUM_PARAM_PLAN_ORDER = 12, 13
 
 CODE_NAMES = {0: "CRUM_OK", -1: "CRUM_EINVAL", -2: "CRUM_ENOSPC", -3: "CRUM_ECRC",
               -4: "CRUM_EFORMAT", -5: "CRUM_EHIP", -6: "CRUM_EMISMATCH", -7: "CRUM_EIO",
@@ -94,6 +94,7 @@ _SIGS = {
     "crum_plan_launch": (_I, [_P, _P, _P]),
     "crum_plan_groups": (_I, [_P, ctypes.POINTER(_U32), _P, _U32]),
     "crum_plan_group_times": (_I, [_P, _P, _U32]),
+    "crum_plan_order": (_I, [_P, _P, _U32]),
     "crum_plan_destroy": (None, [_P]),
     "crum_server_create": (_I, [_I, _P, _U32, _U32, _U64, ctypes.POINTER(_P)]),
     "crum_server_set_prepare": (_I, [_P, _P, _P]),
@@ -214,6 +215,12 @@ class Plan:
 
     def launch(self, stream: int, h_status: int) -> int:
         return lib().crum_plan_launch(self.handle, stream or None, h_status)
+
+    def order(self):
+        """Caller's index of the request at each processing position."""
+        arr = (_U32 * max(1, self.n))()
+        lib().crum_plan_order(self.handle, ctypes.cast(arr, _P), self.n)
+        return [arr[i] for i in range(self.n)]
 
     def groups(self):
         n = _U32()

@@ -32,6 +32,7 @@ PARAMS = {
     "pack_depth": C.CRUM_PARAM_PACK_DEPTH,
     "diff_priority": C.CRUM_PARAM_DIFF_PRIORITY,
     "crc_variant": C.CRUM_PARAM_CRC_VARIANT,
+    "plan_order": C.CRUM_PARAM_PLAN_ORDER,
 }
 
 

@@ -284,6 +284,12 @@ int crum_ctx_set_param(crum_ctx* c, int param, uint64_t v)
         c->piece_shift = (uint32_t)v;
         return CRUM_OK;
     }
+    if (param == CRUM_PARAM_PLAN_ORDER) {
+        if (v > 1)
+            return CRUM_EINVAL;
+        c->plan_order = (int)v;
+        return CRUM_OK;
+    }
     if (param == CRUM_PARAM_CRC_VARIANT) {
         if (v > (uint64_t)kCrcVariantAuto)
             return CRUM_EINVAL;
@@ -346,6 +352,7 @@ int crum_ctx_get_param(crum_ctx* c, int param, uint64_t* v)
     case CRUM_PARAM_PACK_DEPTH: *v = (uint64_t)c->pack_depth; return CRUM_OK;
     case CRUM_PARAM_DIFF_PRIORITY: *v = (uint64_t)c->diff_prio; return CRUM_OK;
     case CRUM_PARAM_CRC_VARIANT: *v = (uint64_t)c->crc_variant; return CRUM_OK;
+    case CRUM_PARAM_PLAN_ORDER: *v = (uint64_t)c->plan_order; return CRUM_OK;
     default: return CRUM_EINVAL;
     }
 }

@@ -103,6 +103,7 @@ struct crum_ctx {
     int pack_depth = 4;
     int diff_prio = 0;
     int crc_variant = crum::kCrcVariantAuto;
+    int plan_order = 0;
     bool eager = true;
     uint32_t timing_mask = 0;  // bit c: time launches of class c
     bool partial_call = false;  // a call stopped part-way through its enqueue
@@ -131,6 +132,7 @@ inline uint32_t ctx_piece_shift(const crum_ctx* c) { return c->piece_shift; }
 inline int ctx_pack_depth(const crum_ctx* c) { return c->pack_depth; }
 inline int ctx_diff_prio(const crum_ctx* c) { return c->diff_prio; }
 inline int ctx_crc_variant(const crum_ctx* c) { return c->crc_variant; }
+inline int ctx_plan_order(const crum_ctx* c) { return c->plan_order; }
 
 }  // namespace crum
 

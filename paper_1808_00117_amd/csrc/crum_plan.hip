@@ -20,6 +20,7 @@ using namespace crum;
 struct crum_plan {
     crum_ctx* ctx = nullptr;
     uint32_t n_reqs = 0;
+    std::vector<uint32_t> order;  // position -> index of the request in the caller's list
     uint32_t n_regs = 0;
     std::vector<uint32_t> group_q;  // group g holds requests [group_q[g], group_q[g+1])
     uint8_t* d_mem = nullptr;
@@ -66,6 +67,25 @@ void plan_free(crum_plan* p)
     delete p;
 }
 
+// Status records of requests in processing order q, written at the caller's
+// index order[q] (40 bytes each, as k_plan_status writes them).
+__global__ void k_plan_status_ordered(const DevReqOut* __restrict__ out, uint32_t n,
+                                      const uint32_t* __restrict__ order,
+                                      uint8_t* __restrict__ dst)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n)
+        return;
+    const DevReqOut& O = out[q];
+    uint8_t* d = dst + 40ull * order[q];
+    *reinterpret_cast<int32_t*>(d) = O.code;
+    *reinterpret_cast<uint32_t*>(d + 4) = O.first_bad;
+    *reinterpret_cast<uint64_t*>(d + 8) = O.n_dirty;
+    *reinterpret_cast<uint64_t*>(d + 16) = O.total_pages;
+    *reinterpret_cast<uint64_t*>(d + 24) = O.image_bytes;
+    *reinterpret_cast<uint64_t*>(d + 32) = O.img_base;
+}
+
 }  // namespace
 
 extern "C" {
@@ -96,14 +116,31 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
     if (total_regs > 0xFFFFFFFFull || ctx_check_ranges(all.data(), (uint32_t)all.size()) != CRUM_OK)
         return CRUM_EINVAL;
 
-    // ---- flatten: requests padded to 64-page boundaries in one page space
+    // ---- processing order: the caller's, or smallest scanned bytes first
+    std::vector<uint32_t> order(n_reqs);
+    for (uint32_t q = 0; q < n_reqs; ++q)
+        order[q] = q;
+    if (ctx_plan_order(c) == 1) {
+        std::vector<uint64_t> bytes(n_reqs, 0);
+        for (uint32_t q = 0; q < n_reqs; ++q)
+            for (uint32_t i = 0; i < reqs[q].n_regions; ++i)
+                bytes[q] += reqs[q].regions[i].len;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](uint32_t a, uint32_t b) { return bytes[a] < bytes[b]; });
+    }
+    bool reordered = false;
+    for (uint32_t q = 0; q < n_reqs; ++q)
+        reordered |= order[q] != q;
+
+    // ---- flatten (in processing order): requests padded to 64-page
+    // boundaries in one page space
     std::vector<DevRegion> dregs(std::max<uint64_t>(1, total_regs));
     std::vector<DevRequest> dreq(std::max<uint32_t>(1, n_reqs));
     std::vector<uint64_t> req_unit0(n_reqs + 1, 0), req_bytes(n_reqs, 0);
     uint64_t page = 0, unit = 0, ri = 0, max_np_shift = 0;
     const uint32_t pc_shift = ctx_piece_shift(c);
     for (uint32_t q = 0; q < n_reqs; ++q) {
-        const crum_request& r = reqs[q];
+        const crum_request& r = reqs[order[q]];
         const uint32_t ps = (uint32_t)ctx_log2(r.page_size);
         const uint32_t us = std::min<uint32_t>(ps, ctx_unit_shift_max(c));
         DevRequest& Q = dreq[q];
@@ -149,6 +186,7 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
     crum_plan* p = new crum_plan();
     p->ctx = c;
     p->n_reqs = n_reqs;
+    p->order = order;
     p->n_regs = (uint32_t)total_regs;
     p->staging = static_cast<uint8_t*>(d_staging);
     p->staging_bytes = staging_bytes;
@@ -193,6 +231,7 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
     const size_t o_part = take(4 * std::max<uint64_t>(np_shift ? G << np_shift : 0, 1));
     const size_t o_bounds = take(8 * std::max<size_t>(n_groups, 1));
     const size_t o_status = take(40ull * std::max<uint32_t>(n_reqs, 1));
+    const size_t o_order = take(4ull * std::max<uint32_t>(n_reqs, 1));
     DeviceGuardC g(ctx_device(c));
     auto fail = [&](int code) {
         plan_free(p);
@@ -210,8 +249,11 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
     if (hipMemcpy(M + o_regs, dregs.data(), sizeof(DevRegion) * dregs.size(),
                   hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(M + o_reqs, dreq.data(), sizeof(DevRequest) * dreq.size(),
-                  hipMemcpyHostToDevice) != hipSuccess)
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        (n_reqs && hipMemcpy(M + o_order, order.data(), 4ull * n_reqs,
+                             hipMemcpyHostToDevice) != hipSuccess))
         return fail(CRUM_EHIP);
+    const uint32_t* d_order = reinterpret_cast<const uint32_t*>(M + o_order);
     const DevRegion* d_regs = reinterpret_cast<const DevRegion*>(M + o_regs);
     const DevRequest* d_reqs = reinterpret_cast<const DevRequest*>(M + o_reqs);
     DevReqOut* d_out = reinterpret_cast<DevReqOut*>(M + o_out);
@@ -264,8 +306,15 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
         if (e == hipSuccess)
             e = launch_header(d_regs, d_reqs, q0, q1, d_out, d_bitmap, d_crcs, p->staging,
                               capacity, tabs, s);
-        if (e == hipSuccess && gi + 1 == n_groups)
-            e = launch_plan_status(d_out, n_reqs, p->d_status, s);
+        if (e == hipSuccess && gi + 1 == n_groups) {
+            if (!reordered) {
+                e = launch_plan_status(d_out, n_reqs, p->d_status, s);
+            } else {
+                hipLaunchKernelGGL(k_plan_status_ordered, dim3((n_reqs + 255) / 256), dim3(256),
+                                   0, s, d_out, n_reqs, d_order, p->d_status);
+                e = hipGetLastError();
+            }
+        }
         hipGraph_t graph = nullptr;
         const hipError_t e2 = hipStreamEndCapture(s, &graph);
         if (e != hipSuccess || e2 != hipSuccess || !graph) {
@@ -336,6 +385,15 @@ int crum_plan_groups(crum_plan* p, uint32_t* n_groups, uint32_t* first_request, 
     if (first_request)
         for (uint32_t i = 0; i <= n && i < cap; ++i)
             first_request[i] = p->group_q[i];
+    return CRUM_OK;
+}
+
+int crum_plan_order(crum_plan* p, uint32_t* order, uint32_t cap)
+{
+    if (!p || (cap && !order))
+        return CRUM_EINVAL;
+    for (uint32_t i = 0; i < p->n_reqs && i < cap; ++i)
+        order[i] = p->order[i];
     return CRUM_OK;
 }
 

@@ -252,3 +252,50 @@ def test_autotune_keeps_images(tmp_path):
         assert autotune.load("test", path) == best
     finally:
         crum.crum_ctx_destroy(ctx)
+
+
+def test_smallest_first_order(ctx):
+    """With CRUM_PARAM_PLAN_ORDER 1 the requests run smallest first: statuses
+    stay in the caller's order, every image equals the oracle's, groups
+    follow the processing order, and a capacity shortfall hits the largest
+    requests (the last in processing order)."""
+    import torch
+    import paper_1808_00117_amd as crum
+    from paper_1808_00117_amd.api import regions_of
+    host = make_requests(21, 16, max_regions=3, page_sizes=(4 * KiB,))
+    expected = [oracle.snapshot(r, P, seq=s)[1] for r, P, s in host]
+    size = [sum(c.size for c, _, _ in r) for r, _, _ in host]
+    dev = [upload(regs) for regs, _, _ in host]
+    crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_PLAN_ORDER, 1)
+    saved = [crum.crum_ctx_get_param(ctx.ctx, p) for p in
+             (crum.CRUM_PARAM_CHUNK_BYTES, crum.CRUM_PARAM_CHUNK_MAX_BYTES)]
+    crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_CHUNK_BYTES, 1)
+    crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_CHUNK_MAX_BYTES, 1)
+    try:
+        reqs = [(regions_of(d), P, 0, s) for d, (_, P, s) in zip(dev, host)]
+        full = sum((e.size + 4095) // 4096 * 4096 for e in expected)
+        for cap in (full, full // 2):
+            staging = torch.empty(cap, dtype=torch.uint8, device="cuda")
+            himg = torch.empty(cap, dtype=torch.uint8, pin_memory=True)
+            status = torch.zeros(40 * len(host), dtype=torch.uint8, pin_memory=True)
+            plan = crum.Plan(ctx.ctx, reqs, staging.data_ptr(), cap, himg.data_ptr(), cap)
+            order = plan.order()
+            assert sorted(order) == list(range(len(host)))
+            assert [size[q] for q in order] == sorted(size)
+            assert plan.launch(torch.cuda.current_stream().cuda_stream, status.data_ptr()) == 0
+            torch.cuda.synchronize()
+            sts = crum.read_request_statuses(status.data_ptr(), len(host))
+            codes = [sts[q][0] for q in order]
+            if cap == full:
+                assert all(c == 0 for c in codes)
+            else:
+                k = codes.index(-2)
+                assert k >= 1 and all(c == -2 for c in codes[k:])
+            for q, (code, _, D, G, b, off) in enumerate(sts):
+                if code == 0:
+                    assert np.array_equal(himg[off:off + b].numpy(), expected[q]), q
+            plan.destroy()
+    finally:
+        crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_PLAN_ORDER, 0)
+        crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_CHUNK_BYTES, saved[0])
+        crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_CHUNK_MAX_BYTES, saved[1])
