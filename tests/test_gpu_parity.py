@@ -464,3 +464,34 @@ def test_random_tables(snap, snap_small_chunks, seed):
         assert torch.equal(c.cpu(), torch.from_numpy(hc))
         if s is not None:
             assert torch.equal(s, c)
+
+
+def test_snapshot_orders_after_stream_work(snap):
+    """Quiesce: work enqueued on the caller's stream before the snapshot
+    (here a kernel that rewrites pages, with no host synchronization in
+    between) is seen by the snapshot, on a non-default stream."""
+    import torch
+    import synth
+    P = 16 * KiB
+    host = host_case((64,), P, set(), seed=77)  # current == shadow: nothing dirty yet
+    dev = upload(host)
+    torch.cuda.synchronize()
+    cur = dev[0][0]
+    st_stream = torch.cuda.Stream()
+    rewritten = [3, 17, 40, 63]
+    with torch.cuda.stream(st_stream):
+        for p in rewritten:
+            synth.fill_dev(cur.data_ptr() + p * P, P, 4321, p, 0, st_stream.cuda_stream)
+        cap = oracle.prefix_bytes(1, 64) + 64 * P + 4 * 64 + 8
+        staging = torch.empty(cap, dtype=torch.uint8, device="cuda")
+        h = torch.empty(cap, dtype=torch.uint8, pin_memory=True)
+        rc = snap.snapshot(dev, P, staging, h, seq=5, stream=st_stream, sync=False)
+    assert rc == 0
+    st_stream.synchronize()
+    st = snap.status()
+    expect_cur = host[0][0].copy()
+    for p in rewritten:
+        expect_cur[p * P:(p + 1) * P] = synth.fill_host(P, 4321, p, 0)
+    st_o, img_o, _ = oracle.snapshot([(expect_cur, host[0][1], host[0][2])], P, seq=5)
+    assert st.code == 0 and st.n_dirty == len(rewritten) == st_o.n_dirty
+    assert np.array_equal(h[:st.image_bytes].numpy(), img_o)
