@@ -49,7 +49,9 @@ def parse_args():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="many",
-                    choices=["many", "plain", "batched", "served", "managed", "persist"])
+                    choices=["many", "plain", "batched", "served", "managed", "persist", "lazy"])
+    ap.add_argument("--lazy-step", type=int, default=8 << 20,
+                    help="lazy: bytes per touch of the sequential sweep")
     ap.add_argument("--persist-dir", default=None,
                     help="persist: directory for the checkpoint files ($TMPDIR/crum_persist)")
     ap.add_argument("--app-ms", type=float, default=500.0,
@@ -795,6 +797,179 @@ def bench_persist(args):
     print(json.dumps(result), flush=True)
 
 
+def bench_lazy(args):
+    """On-demand restore of the 16 GiB many-allocations image (section 4.2's
+    read-fault readahead, with touches announced by the caller) against the
+    full restore.  The targets are the shadow buffers, which hold the old
+    bytes of the dirty pages; restoring makes them equal to the current
+    buffers, and applying the page mutation again (an XOR) resets them.
+    Measured: time to the first restored access (open + a touch of one
+    dirty page, which fetches that 64 KiB page),
+    a sequential sweep of every region in --lazy-step touches plus finish,
+    and 1024 random 64 KiB touches."""
+    import numpy as np
+
+    import paper_1808_00117_amd as crum
+    import paper_1808_00117_amd.hip as H
+    import synth
+    from synth import scenarios as sc
+
+    crum.lib()
+    scn = sc.many_allocs()
+    P, N, D, G, R = scn.page_size, scn.total_bytes, scn.n_dirty, scn.total_pages, len(scn.regions)
+    pairs = materialize_raw(scn, H)
+    table = crum.region_table([(c.ptr, s.ptr, r.nbytes, r.id)
+                               for (c, s), r in zip(pairs, scn.regions)])
+    targets = crum.region_table([(s.ptr, 0, r.nbytes, r.id)
+                                 for (c, s), r in zip(pairs, scn.regions)])
+    ib = crum.crum_image_bytes(R, G, D, P)
+    staging = H.DeviceBuffer(ib)
+    himg = H.PinnedBuffer(ib)
+    status = H.PinnedBuffer(64)
+    settle = settle_copy_engines(H, staging.ptr, himg.ptr, min(256 << 20, ib))
+    ctx = crum.crum_ctx_create(0)
+    s1 = H.Stream()
+    assert crum.crum_snapshot(ctx, table, P, 0, 5, staging.ptr, ib, himg.ptr, ib, s1.handle,
+                              status.ptr) == 0
+    s1.synchronize()
+    st = crum.read_status(status.ptr)
+    assert st.code == 0 and st.n_dirty == D and st.image_bytes == ib, st
+    d_pages = []
+    for r in scn.regions:
+        pg = np.ascontiguousarray(r.dirty_pages, np.int64)
+        buf = H.DeviceBuffer(max(pg.nbytes, 8))
+        if pg.size:
+            H.memcpy_htod(buf.ptr, pg.ctypes.data, pg.nbytes)
+        d_pages.append((buf, pg))
+
+    def reset():
+        """Old bytes back into the dirty pages of the targets."""
+        for (c, sh), r, (buf, pg) in zip(pairs, scn.regions, d_pages):
+            if pg.size:
+                synth.mutate_dev(sh.ptr, r.nbytes, P, buf.ptr, int(pg.size), int(pg.max()),
+                                 r.mut_kind, scn.mut_seed, r.fill_region, 0)
+        H.device_synchronize()
+
+    def n_differing():
+        """Pages where the targets differ from the current buffers (a snapshot
+        kept on the device)."""
+        assert crum.crum_snapshot(ctx, table, P, 0, 6, staging.ptr, ib, 0, 0, s1.handle,
+                                  status.ptr) == 0
+        s1.synchronize()
+        return crum.read_status(status.ptr).n_dirty
+
+    def ok(code_addr=status.ptr):
+        st_ = crum.read_status(code_addr)
+        assert st_.code == 0, st_
+
+    assert n_differing() == D
+    # the first access: the first dirty page of the largest region (a fault
+    # whose window is that one page)
+    ri_first = int(np.argmax([r.nbytes if r.dirty_pages.size else 0 for r in scn.regions]))
+    pg_first = int(scn.regions[ri_first].dirty_pages[0])
+    trials = 2 if args.quick else 4
+    full, first, open_ms, sweep, rand = [], [], [], [], []
+    stats = {}
+    rng = np.random.default_rng(11)
+    sizes = np.array([r.nbytes for r in scn.regions], np.float64)
+    for t in range(trials + 1):
+        # full restore
+        reset()
+        t0 = time.perf_counter()
+        assert crum.crum_restore(ctx, targets, himg.ptr, ib, crum.CRUM_VERIFY, staging.ptr, ib,
+                                 s1.handle, status.ptr) == 0
+        s1.synchronize()
+        t1 = time.perf_counter()
+        ok()
+        if t == 0:
+            assert n_differing() == 0
+        else:
+            full.append(t1 - t0)
+        # on demand: first access, then a sequential sweep and finish
+        reset()
+        t0 = time.perf_counter()
+        lz = crum.Lazy(ctx, targets, himg.ptr, ib, crum.CRUM_VERIFY, 2 << 20, staging.ptr, ib,
+                       s1.handle, status.ptr)
+        s1.synchronize()
+        t_open = time.perf_counter()
+        ok()
+        assert lz.touch(ri_first, pg_first * P, P, s1.handle, status.ptr) == 1
+        s1.synchronize()
+        t1 = time.perf_counter()
+        for ri, r in enumerate(scn.regions):
+            for off in range(0, r.nbytes, args.lazy_step):
+                lz.touch(ri, off, min(args.lazy_step, r.nbytes - off), s1.handle, 0)
+        lz.finish(s1.handle, status.ptr)
+        s1.synchronize()
+        t2 = time.perf_counter()
+        ok()
+        sw = lz.stats()
+        lz.close()
+        if t == 0:
+            assert n_differing() == 0
+            stats["sweep"] = sw
+        else:
+            open_ms.append(t_open - t0)
+            first.append(t1 - t0)
+            sweep.append(t2 - t0)
+        # on demand: random single-page accesses
+        reset()
+        lz = crum.Lazy(ctx, targets, himg.ptr, ib, crum.CRUM_VERIFY, 2 << 20, staging.ptr, ib,
+                       s1.handle, status.ptr)
+        s1.synchronize()
+        picks = []
+        for _ in range(1024):
+            ri = int(rng.choice(R, p=sizes / sizes.sum()))
+            picks.append((ri, int(rng.integers(0, scn.regions[ri].nbytes // P)) * P))
+        t0 = time.perf_counter()
+        for ri, off in picks:
+            lz.touch(ri, off, P, s1.handle, 0)
+        s1.synchronize()
+        t1 = time.perf_counter()
+        rs = lz.stats()
+        lz.finish(s1.handle, status.ptr)
+        s1.synchronize()
+        ok()
+        lz.close()
+        if t == 0:
+            assert n_differing() == 0
+        else:
+            rand.append(t1 - t0)
+            stats["random"] = rs
+    ms = lambda v: round(1e3 * statistics.median(v), 3)  # noqa: E731
+    sw = stats["sweep"]
+    result = {
+        "metric": "restart latency: time until the first access of a restored image can run",
+        "value": ms(first), "unit": "ms", "n_gpus": 1, "steps": trials, "warmup": 1,
+        "ms_per_step": ms(first), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic (seeded SplitMix64 bytes, PCG64 scenario)",
+        "config": {"workload": "on-demand restore of the image of 64 allocations scaled to "
+                               "16 GiB, 64 KiB pages, clustered dirty runs",
+                   "image_bytes": ib, "dirty_pages": D, "small_region_bytes": 2 << 20,
+                   "sweep_step_bytes": args.lazy_step, "verify": True, "settle": settle},
+        "full_restore_ms": ms(full),
+        "on_demand": {
+            "open_ms": ms(open_ms),
+            "first_access_ms": ms(first),
+            "first_access": f"region {ri_first} page {pg_first}: one 64 KiB page fetched",
+            "sweep_plus_finish_ms": ms(sweep),
+            "sweep": {"faults": sw["faults"], "copies": sw["copies"],
+                      "pages_fetched_by_touches_and_finish": sw["pages_fetched"],
+                      "image_gbs": round(ib / (statistics.median(sweep)) / 1e9, 2)},
+            "random_1024_pages": {"ms": ms(rand), "faults": stats["random"]["faults"],
+                                  "copies": stats["random"]["copies"],
+                                  "bytes_fetched": stats["random"]["bytes_fetched"],
+                                  "fraction_of_image_pages": round(
+                                      stats["random"]["pages_fetched"] / max(D, 1), 4)},
+        },
+        "checked": "targets equal the current buffers after every first trial (snapshot "
+                   "finds 0 differing pages)",
+    }
+    crum.crum_ctx_destroy(ctx)
+    print(json.dumps(result), flush=True)
+
+
 def fill_managed_host(buf, scn, region_index, pages, threads=16):
     """Write the generator bytes of the listed pages from host threads."""
     from concurrent.futures import ThreadPoolExecutor
@@ -977,6 +1152,8 @@ def main():
         return bench_managed(args)
     if args.config == "persist":
         return bench_persist(args)
+    if args.config == "lazy":
+        return bench_lazy(args)
     import numpy as np
 
     import paper_1808_00117_amd as crum

@@ -359,6 +359,86 @@ int crum_ctx_timing(crum_ctx* ctx, int which, uint64_t* launches, double* total_
 int crum_ctx_timing_reset(crum_ctx* ctx);
 
 /* ---------------------------------------------------------------------------
+ * On-demand restore (section 4.2: unified-memory data is brought into the
+ * application's copy on read faults; a small region is read whole at its
+ * first fault, a large one one page at the first fault and twice as many
+ * pages at each later fault of the same region).  The device takes no page
+ * faults here, so the caller announces each access with crum_lazy_touch
+ * before work that reads or writes the range.
+ *
+ * The packed pages of the image are absent until fetched; every other page
+ * of the regions is taken to hold its bytes already (as in crum_restore).  A
+ * touch is a fault when its range covers an absent page.  The fault's window
+ * starts at the first absent page the range covers and spans
+ * max(2^f, pages to the end of the range) pages, f being the number of
+ * earlier faults of the region, clipped at the region's end; a region of at
+ * most small_bytes bytes has the whole region as its window.  Every absent
+ * image page of the window is fetched: its packed bytes are copied from
+ * h_image into d_staging (at their image offsets), CRC-checked with
+ * CRUM_VERIFY, and written to the page (and its shadow with
+ * CRUM_UPDATE_SHADOW), in runs of consecutive packed pages, one copy per run.
+ *
+ * Verification is per fetched run: a run that fails is not written, and
+ * neither is anything fetched after it; pages written before stay written.
+ * The session then reports CRUM_ECRC (first_bad: lowest failing slot) for
+ * every later call.  A session whose image failed the device-side checks of
+ * open reports CRUM_EFORMAT for every call and writes nothing.  After a call
+ * returns CRUM_EHIP the session is unusable; close it.
+ * -------------------------------------------------------------------------*/
+typedef struct crum_lazy crum_lazy;
+
+typedef struct {
+    uint64_t pages_total;   /* D: packed pages in the image */
+    uint64_t pages_fetched; /* pages whose fetch has been enqueued */
+    uint64_t faults;        /* touches that found an absent page */
+    uint64_t copies;        /* host-to-device copies (runs) enqueued */
+    uint64_t bytes_fetched; /* packed-page bytes copied */
+} crum_lazy_info;
+
+/* Start an on-demand restore.  The host checks the header and region table
+ * as crum_restore does (returning CRUM_EFORMAT, CRUM_EMISMATCH or, for
+ * staging_bytes below image_bytes, CRUM_ENOSPC, written to *h_status, with
+ * nothing enqueued and *out NULL), and that the bitmap holds n_dirty bits
+ * below total_pages.  Then enqueues on `stream` the upload of the image
+ * prefix and CRC array into d_staging, their device-side checks (meta_crc,
+ * crcs_crc, bitmap, pads: CRUM_EFORMAT in *h_status) and the slot list; no
+ * page is fetched.  h_image (pinned host memory) and d_staging must stay
+ * valid and unchanged until crum_lazy_close.  The session keeps the ctx's CRC
+ * tables and the launch shapes in force at open; the ctx must outlive it.
+ * Returns CRUM_OK, CRUM_EINVAL (bad argument, h_image NULL), an image error
+ * above, or CRUM_EHIP. */
+int crum_lazy_open(crum_ctx* ctx, const crum_region* regions, uint32_t n_regions,
+                   const void* h_image, uint64_t image_bytes, uint32_t flags,
+                   uint64_t small_bytes, void* d_staging, uint64_t staging_bytes, void* stream,
+                   crum_status* h_status, crum_lazy** out);
+
+/* Announce an access to bytes [offset, offset + len) of region `region`
+ * (len > 0, within the region).  Makes `stream` wait for every fetch
+ * enqueued before, so work after the call on `stream` sees the pages.  On a
+ * fault, enqueues the fetch of its window on `stream` and, when h_status
+ * (pinned) is not NULL, the session's status into it; *n_fetched (may be
+ * NULL) receives the pages fetched.  A touch that is not a fault enqueues
+ * only the wait and leaves *h_status as it is.  Returns CRUM_OK, CRUM_EINVAL
+ * or CRUM_EHIP. */
+int crum_lazy_touch(crum_lazy* lazy, uint32_t region, uint64_t offset, uint64_t len,
+                    void* stream, crum_status* h_status, uint64_t* n_fetched);
+
+/* Fetch every page still absent (the rest of a full restore) on `stream`
+ * after the earlier fetches; the session's status into *h_status (pinned). */
+int crum_lazy_finish(crum_lazy* lazy, void* stream, crum_status* h_status);
+
+/* Counters of the session so far (host values, no wait). */
+int crum_lazy_stats(crum_lazy* lazy, crum_lazy_info* out);
+
+/* Which pages have been fetched: bit g % 64 of words[g / 64] is set once the
+ * fetch of global page g has been enqueued (pages numbered across regions in
+ * table order); n_words words are written. */
+int crum_lazy_fetched(crum_lazy* lazy, uint64_t* words, uint64_t n_words);
+
+/* Wait for the session's enqueued work and free it. NULL is ignored. */
+void crum_lazy_close(crum_lazy* lazy);
+
+/* ---------------------------------------------------------------------------
  * Persisting images: phase two of the paper's checkpoint (section 3.3), where
  * a forked child writes the image to storage while the application resumes.
  * Here the image is already in pinned host memory when the snapshot ends, so

@@ -77,6 +77,12 @@ class crum_write_status(ctypes.Structure):
 CRUM_WRITE_DIRECT, CRUM_WRITE_SYNC = 1, 2
 
 
+class crum_lazy_info(ctypes.Structure):
+    _fields_ = [("pages_total", ctypes.c_uint64), ("pages_fetched", ctypes.c_uint64),
+                ("faults", ctypes.c_uint64), ("copies", ctypes.c_uint64),
+                ("bytes_fetched", ctypes.c_uint64)]
+
+
 class crum_request_status(ctypes.Structure):
     _fields_ = [("status", crum_status), ("image_offset", ctypes.c_uint64)]
 
@@ -114,6 +120,13 @@ _SIGS = {
     "crum_writer_submit": (_I, [_P, ctypes.c_char_p, _P, _U64, ctypes.POINTER(_U64)]),
     "crum_writer_poll": (_I, [_P, _U64, _I, _P]),
     "crum_writer_destroy": (None, [_P]),
+    "crum_lazy_open": (_I, [_P, _P, _U32, _P, _U64, _U32, _U64, _P, _U64, _P, _P,
+                            ctypes.POINTER(_P)]),
+    "crum_lazy_touch": (_I, [_P, _U32, _U64, _U64, _P, _P, ctypes.POINTER(_U64)]),
+    "crum_lazy_finish": (_I, [_P, _P, _P]),
+    "crum_lazy_stats": (_I, [_P, _P]),
+    "crum_lazy_fetched": (_I, [_P, _P, _U64]),
+    "crum_lazy_close": (None, [_P]),
 }
 
 _lib = None
@@ -419,5 +432,75 @@ class Writer:
     def __del__(self):
         try:
             self.destroy()
+        except Exception:
+            pass
+
+
+class ImageError(Exception):
+    """An image refused by the host-side checks; .code is the CRUM_ code."""
+
+    def __init__(self, code: int):
+        super().__init__(CODE_NAMES.get(code, code))
+        self.code = code
+
+
+class Lazy:
+    """Owns a crum_lazy session (on-demand restore of an image).
+
+    Raises ValueError for argument errors; an image error found on the host
+    (EFORMAT, EMISMATCH, ENOSPC) is raised as ImageError with the status."""
+
+    def __init__(self, ctx: int, regions, h_image: int, image_bytes: int, flags: int,
+                 small_bytes: int, d_staging: int, staging_bytes: int, stream: int,
+                 h_status: int):
+        self._table = regions if isinstance(regions, ctypes.Array) else region_table(regions)
+        n = len(regions)
+        h = _P()
+        rc = lib().crum_lazy_open(ctx, ctypes.cast(self._table, _P) if n else None, n,
+                                  h_image or None, image_bytes, flags, small_bytes, d_staging,
+                                  staging_bytes, stream or None, h_status, ctypes.byref(h))
+        self.handle = h.value or 0
+        if rc in (CRUM_EFORMAT, CRUM_EMISMATCH, CRUM_ENOSPC):
+            raise ImageError(rc)
+        if rc != CRUM_OK:
+            raise ValueError(f"crum_lazy_open: {CODE_NAMES.get(rc, rc)}")
+
+    def touch(self, region: int, offset: int, length: int, stream: int, h_status: int = 0) -> int:
+        """Returns the number of pages the access fetched (0: not a fault)."""
+        n = _U64()
+        rc = lib().crum_lazy_touch(self.handle, region, offset, length, stream or None,
+                                   h_status or None, ctypes.byref(n))
+        if rc != CRUM_OK:
+            raise ValueError(f"crum_lazy_touch: {CODE_NAMES.get(rc, rc)}")
+        return n.value
+
+    def finish(self, stream: int, h_status: int) -> None:
+        rc = lib().crum_lazy_finish(self.handle, stream or None, h_status)
+        if rc != CRUM_OK:
+            raise ValueError(f"crum_lazy_finish: {CODE_NAMES.get(rc, rc)}")
+
+    def stats(self) -> dict:
+        st = crum_lazy_info()
+        rc = lib().crum_lazy_stats(self.handle, ctypes.byref(st))
+        if rc != CRUM_OK:
+            raise ValueError(f"crum_lazy_stats: {CODE_NAMES.get(rc, rc)}")
+        return {f: getattr(st, f) for f, _ in crum_lazy_info._fields_}
+
+    def fetched(self, n_words: int):
+        """The fetched-page bitmap as a list of n_words ints."""
+        arr = (ctypes.c_uint64 * max(1, n_words))()
+        rc = lib().crum_lazy_fetched(self.handle, ctypes.cast(arr, _P), n_words)
+        if rc != CRUM_OK:
+            raise ValueError(f"crum_lazy_fetched: {CODE_NAMES.get(rc, rc)}")
+        return list(arr)[:n_words]
+
+    def close(self) -> None:
+        if self.handle:
+            lib().crum_lazy_close(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass

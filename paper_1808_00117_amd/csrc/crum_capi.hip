@@ -132,9 +132,46 @@ hipError_t ensure_pinned(crum_ctx* c, size_t bytes)
     return e;
 }
 
+hipError_t ensure_events(std::vector<hipEvent_t>& v, size_t n)
+{
+    while (v.size() < n) {
+        hipEvent_t e;
+        hipError_t err = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+        if (err != hipSuccess)
+            return err;
+        v.push_back(e);
+    }
+    return hipSuccess;
+}
+
+#define CRUM_TRY(expr)                          \
+    do {                                        \
+        hipError_t e_ = (expr);                 \
+        if (e_ != hipSuccess)                   \
+            return CRUM_EHIP;                   \
+    } while (0)
+
+}  // namespace
+
+namespace crum {
+
+static uint32_t rd32(const uint8_t* p)
+{
+    uint32_t v;
+    std::memcpy(&v, p, 4);
+    return v;
+}
+
+static uint64_t rd64(const uint8_t* p)
+{
+    uint64_t v;
+    std::memcpy(&v, p, 8);
+    return v;
+}
+
 // Flatten one table into DevRegion entries (single request, request 0).
-void flatten(const crum_region* regs, uint32_t n, uint32_t ps, uint32_t us_max,
-             uint32_t region_flags, DevRegion* out, uint64_t* n_pages, uint64_t* n_units)
+void flatten_regions(const crum_region* regs, uint32_t n, uint32_t ps, uint32_t us_max,
+                     uint32_t region_flags, DevRegion* out, uint64_t* n_pages, uint64_t* n_units)
 {
     uint64_t page = 0, unit = 0;
     const uint32_t us = std::min<uint32_t>(ps, us_max);
@@ -157,26 +194,51 @@ void flatten(const crum_region* regs, uint32_t n, uint32_t ps, uint32_t us_max,
     *n_units = unit;
 }
 
-hipError_t ensure_events(std::vector<hipEvent_t>& v, size_t n)
+int parse_image_prefix(const uint8_t* h, uint64_t avail, uint64_t image_bytes,
+                       const crum_region* regions, uint32_t n_regions, ImageInfo* out)
 {
-    while (v.size() < n) {
-        hipEvent_t e;
-        hipError_t err = hipEventCreateWithFlags(&e, hipEventDisableTiming);
-        if (err != hipSuccess)
-            return err;
-        v.push_back(e);
+    *out = ImageInfo{};
+    if (image_bytes < 64 || avail < 64)
+        return CRUM_EFORMAT;
+    if (std::memcmp(h, "CRUMIMG1", 8) != 0 || rd32(h + 8) != 1 || !page_size_ok(rd32(h + 12)) ||
+        (rd32(h + 20) & ~1u))
+        return CRUM_EFORMAT;
+    ImageInfo& I = *out;
+    I.page_size = rd32(h + 12);
+    I.ps = (uint32_t)log2_exact(I.page_size);
+    I.R = rd32(h + 16);
+    I.G = rd64(h + 24);
+    I.D = rd64(h + 32);
+    I.seq = rd64(h + 40);
+    I.data_off = rd64(h + 48);
+    if (I.G > 0xFFFFFF00ull || I.D > I.G)
+        return CRUM_EFORMAT;
+    I.W = (I.G + 63) / 64;
+    const uint64_t prefix_end = 64 + 32 * I.R + 8 * I.W;
+    if (I.data_off != round_up(prefix_end, 4096) ||
+        I.data_off + (I.D << I.ps) + round_up(4 * I.D, 8) != image_bytes)
+        return CRUM_EFORMAT;
+    if (I.R != n_regions)
+        return CRUM_EMISMATCH;
+    if (avail < 64 + 32 * I.R)
+        return CRUM_EFORMAT;
+    uint64_t chain = 0;
+    bool mismatch = false;
+    for (uint64_t i = 0; i < I.R; ++i) {
+        const uint8_t* e = h + 64 + 32 * i;
+        const uint64_t len = rd64(e + 8);
+        if (rd64(e + 24) != 0 || len % I.page_size || rd64(e + 16) != chain)
+            return CRUM_EFORMAT;
+        chain += len >> I.ps;
+        if (rd64(e) != regions[i].id || len != regions[i].len)
+            mismatch = true;
     }
-    return hipSuccess;
+    if (chain != I.G)
+        return CRUM_EFORMAT;
+    return mismatch ? CRUM_EMISMATCH : CRUM_OK;
 }
 
-#define CRUM_TRY(expr)                          \
-    do {                                        \
-        hipError_t e_ = (expr);                 \
-        if (e_ != hipSuccess)                   \
-            return CRUM_EHIP;                   \
-    } while (0)
-
-}  // namespace
+}  // namespace crum
 
 extern "C" {
 
@@ -458,8 +520,8 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     const uint32_t us = std::min<uint32_t>(ps, c->unit_shift_max);
     std::vector<DevRegion> dregs(std::max<uint32_t>(1, n_regions));
     uint64_t n_pages = 0, n_units = 0;
-    flatten(regions, n_regions, ps, c->unit_shift_max, (flags & CRUM_UPDATE_SHADOW) ? 1u : 0u,
-            dregs.data(), &n_pages, &n_units);
+    flatten_regions(regions, n_regions, ps, c->unit_shift_max,
+                    (flags & CRUM_UPDATE_SHADOW) ? 1u : 0u, dregs.data(), &n_pages, &n_units);
     const Layout L =
         make_layout(n_regions, 1, n_units, W, W * 64, np_shift ? G << np_shift : 0, n_chunks);
     CRUM_TRY(ensure_scratch(c, L.total));
@@ -673,19 +735,6 @@ static int restore_fail(crum_status* st, int code, uint64_t D, uint64_t G, uint6
     return code;
 }
 
-static uint32_t rd32(const uint8_t* p)
-{
-    uint32_t v;
-    std::memcpy(&v, p, 4);
-    return v;
-}
-
-static uint64_t rd64(const uint8_t* p)
-{
-    uint64_t v;
-    std::memcpy(&v, p, 8);
-    return v;
-}
 
 int crum_restore(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
                  const void* h_image, uint64_t image_bytes, uint32_t flags, void* d_staging,
@@ -712,39 +761,15 @@ int crum_restore(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
         CRUM_TRY(hipMemcpy(hdr_copy.data(), d_staging, want, hipMemcpyDeviceToHost));
         h = hdr_copy.data();
     }
-    if (std::memcmp(h, "CRUMIMG1", 8) != 0 || rd32(h + 8) != 1 || !page_size_ok(rd32(h + 12)) ||
-        (rd32(h + 20) & ~1u))
-        return restore_fail(h_status, CRUM_EFORMAT, 0, 0, image_bytes);
-    const uint32_t page_size = rd32(h + 12);
-    const uint32_t ps = (uint32_t)log2_exact(page_size);
-    const uint64_t R = rd32(h + 16), G = rd64(h + 24), D = rd64(h + 32), seq = rd64(h + 40);
-    const uint64_t data_off = rd64(h + 48);
-    if (G > 0xFFFFFF00ull || D > G)
-        return restore_fail(h_status, CRUM_EFORMAT, D, G, image_bytes);
-    const uint64_t W = (G + 63) / 64;
-    const uint64_t prefix_end = 64 + 32 * R + 8 * W;
-    if (data_off != round_up(prefix_end, 4096) ||
-        data_off + (D << ps) + round_up(4 * D, 8) != image_bytes)
-        return restore_fail(h_status, CRUM_EFORMAT, D, G, image_bytes);
-    if (R != n_regions)
-        return restore_fail(h_status, CRUM_EMISMATCH, D, G, image_bytes);
-    if (hdr_copy.size() && hdr_copy.size() < 64 + 32 * R)
-        return restore_fail(h_status, CRUM_EFORMAT, D, G, image_bytes);
-    uint64_t chain = 0;
-    bool mismatch = false;
-    for (uint64_t i = 0; i < R; ++i) {
-        const uint8_t* e = h + 64 + 32 * i;
-        const uint64_t len = rd64(e + 8);
-        if (rd64(e + 24) != 0 || len % page_size || rd64(e + 16) != chain)
-            return restore_fail(h_status, CRUM_EFORMAT, D, G, image_bytes);
-        chain += len >> ps;
-        if (rd64(e) != regions[i].id || len != regions[i].len)
-            mismatch = true;
-    }
-    if (chain != G)
-        return restore_fail(h_status, CRUM_EFORMAT, D, G, image_bytes);
-    if (mismatch)
-        return restore_fail(h_status, CRUM_EMISMATCH, D, G, image_bytes);
+    ImageInfo info;
+    const int rc = parse_image_prefix(h, hdr_copy.size() ? hdr_copy.size() : image_bytes,
+                                      image_bytes, regions, n_regions, &info);
+    const uint64_t G = info.G, D = info.D;
+    if (rc != CRUM_OK)
+        return restore_fail(h_status, rc, D, G, image_bytes);
+    const uint32_t ps = info.ps;
+    const uint64_t R = info.R, W = info.W, seq = info.seq, data_off = info.data_off;
+    const uint32_t page_size = info.page_size;
     if (staging_bytes < image_bytes)
         return restore_fail(h_status, CRUM_ENOSPC, D, G, image_bytes);
 
@@ -753,7 +778,8 @@ int crum_restore(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     const uint32_t np_shift = ps > pc_shift ? ps - pc_shift : 0;
     std::vector<DevRegion> dregs(std::max<uint32_t>(1, n_regions));
     uint64_t n_pages = 0, n_units = 0;
-    flatten(regions, n_regions, ps, c->unit_shift_max, 0, dregs.data(), &n_pages, &n_units);
+    flatten_regions(regions, n_regions, ps, c->unit_shift_max, 0, dregs.data(), &n_pages,
+                    &n_units);
     const Layout L = make_layout(n_regions, 1, 0, W, W * 64, np_shift ? D << np_shift : 0, 1);
     CRUM_TRY(ensure_scratch(c, L.total));
     CRUM_TRY(ensure_pinned(c, L.upload_end));

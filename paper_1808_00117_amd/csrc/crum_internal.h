@@ -77,6 +77,26 @@ inline int check_ranges(const crum_region* regs, uint32_t n)
 }
 
 
+// One region table as DevRegion entries of request 0: global first page and
+// first diff unit of each region (table order), diff unit
+// 2^min(ps, us_max), region_flags in every entry.
+void flatten_regions(const crum_region* regs, uint32_t n, uint32_t ps, uint32_t us_max,
+                     uint32_t region_flags, DevRegion* out, uint64_t* n_pages, uint64_t* n_units);
+
+// Fields of an image header that passed the host-side checks.
+struct ImageInfo {
+    uint32_t page_size = 0, ps = 0;
+    uint64_t R = 0, G = 0, D = 0, seq = 0, data_off = 0, W = 0;
+};
+
+// Host-side checks of an image's header and region table against the
+// caller's table: magic, version, page size, flags, sizes and offsets, the
+// chaining of first_page, then count, lengths and ids.  `avail` bytes are
+// readable at h.  Returns CRUM_OK, CRUM_EFORMAT or CRUM_EMISMATCH; G and D
+// are filled once the header fields are read.
+int parse_image_prefix(const uint8_t* h, uint64_t avail, uint64_t image_bytes,
+                       const crum_region* regions, uint32_t n_regions, ImageInfo* out);
+
 }  // namespace crum
 
 struct crum_ctx {

@@ -262,3 +262,90 @@ def test_persist_16gib_image(tmp_path):
         staging.free()
         for b in bufs:
             b.free()
+
+
+def test_lazy_restore_16gib():
+    """On-demand restore of the 16 GiB many-allocations image into the shadow
+    buffers (which hold the old bytes of the dirty pages), swept region by
+    region in 8 MiB touches as bench.py does: the fetched pages equal the
+    oracle's read-fault model at every 256th touch and at the end, sampled
+    pages hold the generator's bytes (restored) or the mutated bytes (not yet
+    fetched), and after finish the shadows equal the current buffers (a
+    snapshot finds no differing page)."""
+    import bench
+    import paper_1808_00117_amd as crum
+    import paper_1808_00117_amd.hip as H
+    from oracle.lazy import LazyModel
+    from synth import scenarios as sc
+
+    scn = sc.many_allocs()
+    P, G, D, R = scn.page_size, scn.total_pages, scn.n_dirty, len(scn.regions)
+    W = (G + 63) // 64
+    log(f"[fullsize] lazy restore many_allocs D={D}")
+    pairs = bench.materialize_raw(scn, H)
+    table = crum.region_table([(c.ptr, s.ptr, r.nbytes, r.id)
+                               for (c, s), r in zip(pairs, scn.regions)])
+    targets = crum.region_table([(s.ptr, 0, r.nbytes, r.id)
+                                 for (c, s), r in zip(pairs, scn.regions)])
+    ib = crum.crum_image_bytes(R, G, D, P)
+    cap = crum.crum_image_bytes(R, G, G, P)
+    staging = H.DeviceBuffer(cap)
+    himg = H.PinnedBuffer(cap)
+    status = H.PinnedBuffer(64)
+    ctx = crum.crum_ctx_create(0)
+    s = H.Stream()
+    lz = None
+    try:
+        assert crum.crum_snapshot(ctx, table, P, 0, 12, staging.ptr, cap, himg.ptr, cap,
+                                  s.handle, status.ptr) == 0
+        s.synchronize()
+        assert crum.read_status(status.ptr).n_dirty == D
+        small = 2 << 20
+        lz = crum.Lazy(ctx, targets, himg.ptr, ib, crum.CRUM_VERIFY, small, staging.ptr, cap,
+                       s.handle, status.ptr)
+        s.synchronize()
+        assert crum.read_status(status.ptr).code == 0
+        model = LazyModel([r.nbytes for r in scn.regions], P, scn.dirty_global(), small)
+        counts, starts = page_index(scn)
+        rng = np.random.default_rng(17)
+        want_dirty = scn.dirty_global()
+        buf = np.empty(P, np.uint8)
+        step, k = 8 << 20, 0
+        for ri, r in enumerate(scn.regions):
+            for off in range(0, r.nbytes, step):
+                ln = min(step, r.nbytes - off)
+                assert lz.touch(ri, off, ln, s.handle, 0) == model.touch(ri, off, ln)
+                k += 1
+                if k % 256 == 1:
+                    s.synchronize()
+                    assert lz.fetched(W) == model.fetched_bitmap(G), k
+                    for g in rng.choice(want_dirty, size=4, replace=False):
+                        g = int(g)
+                        ri2 = int(np.searchsorted(starts, g, side="right") - 1)
+                        H.memcpy_dtoh(buf.ctypes.data,
+                                      pairs[ri2][1].ptr + (g - int(starts[ri2])) * P, P)
+                        restored = g in model.fetched
+                        want = sc.host_page(scn, ri2, g - int(starts[ri2]), not restored)
+                        assert np.array_equal(buf, want), (k, g, restored)
+        s.synchronize()
+        assert lz.fetched(W) == model.fetched_bitmap(G)
+        lz.finish(s.handle, status.ptr)
+        s.synchronize()
+        assert crum.read_status(status.ptr).code == 0
+        st = lz.stats()
+        assert st["pages_fetched"] == D and st["faults"] == sum(model.faults.values())
+        lz.close()
+        lz = None
+        assert crum.crum_snapshot(ctx, table, P, 0, 13, staging.ptr, cap, 0, 0, s.handle,
+                                  status.ptr) == 0
+        s.synchronize()
+        assert crum.read_status(status.ptr).n_dirty == 0
+    finally:
+        if lz is not None:
+            lz.close()
+        crum.crum_ctx_destroy(ctx)
+        for c, sh in pairs:
+            c.free()
+            sh.free()
+        staging.free()
+        himg.free()
