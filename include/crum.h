@@ -418,8 +418,9 @@ int crum_lazy_open(crum_ctx* ctx, const crum_region* regions, uint32_t n_regions
  * fault, enqueues the fetch of its window on `stream` and, when h_status
  * (pinned) is not NULL, the session's status into it; *n_fetched (may be
  * NULL) receives the pages fetched.  A touch that is not a fault enqueues
- * only the wait and leaves *h_status as it is.  Returns CRUM_OK, CRUM_EINVAL
- * or CRUM_EHIP. */
+ * at most the wait (none on the stream of the session's last fetch) and
+ * leaves *h_status as it is.  Streams given to a session must stay alive
+ * until it is closed.  Returns CRUM_OK, CRUM_EINVAL or CRUM_EHIP. */
 int crum_lazy_touch(crum_lazy* lazy, uint32_t region, uint64_t offset, uint64_t len,
                     void* stream, crum_status* h_status, uint64_t* n_fetched);
 

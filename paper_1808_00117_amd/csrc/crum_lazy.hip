@@ -20,9 +20,9 @@
 // slot -> page list; the host keeps the bitmap with per-word slot prefixes to
 // map a page range to its slots, and one bit per page for "fetched".
 //
-// The host-to-device copies run on the session's own copy stream, and the
-// caller's stream waits for each touch's copies before its checks and
-// scatters: the copies of the next fault then overlap the kernels of this
+// The host-to-device copies run on the context's side stream (creating a
+// stream per session costs more than the rest of open), and the caller's
+// stream waits for each touch's copies before its checks and scatters: the copies of the next fault then overlap the kernels of this
 // one.  Every run has its own slots of the staging buffer, so a copy never
 // overwrites bytes a kernel still reads.
 #include "crum.h"
@@ -58,8 +58,9 @@ struct crum_lazy {
     size_t o_regs = 0, o_req = 0, o_out = 0, o_glob = 0, o_prefix = 0, o_list = 0,
            o_partials = 0, o_crcs = 0, upload_end = 0;
     uint8_t* h_up = nullptr;  // pinned upload of the tables
-    hipStream_t copy = nullptr;
+    hipStream_t copy = nullptr;  // the context's side stream
     hipEvent_t ev_done = nullptr;    // the last call's work on the caller's stream
+    hipStream_t done_stream = nullptr;  // the stream ev_done was last recorded on
     hipEvent_t ev_copied = nullptr;  // the last touch's copies
 };
 
@@ -82,8 +83,6 @@ void lazy_free(crum_lazy* z)
         (void)hipEventDestroy(z->ev_done);
     if (z->ev_copied)
         (void)hipEventDestroy(z->ev_copied);
-    if (z->copy)
-        (void)hipStreamDestroy(z->copy);
     delete z;
 }
 
@@ -194,20 +193,33 @@ hipError_t fetch_window(crum_lazy* z, uint64_t g0, uint64_t g1, hipStream_t s, u
     return hipSuccess;
 }
 
-// Status of the session after the work enqueued so far, into h_status.
+// Status of the session after the work enqueued so far, into h_status (the
+// status is cumulative, so nothing is enqueued without a destination).
 hipError_t enqueue_status(crum_lazy* z, crum_status* h_status, hipStream_t s)
 {
+    if (!h_status)
+        return hipSuccess;
     DevReqOut* out = reinterpret_cast<DevReqOut*>(z->d_mem + z->o_out);
     DevGlobal* glob = reinterpret_cast<DevGlobal*>(z->d_mem + z->o_glob);
     hipError_t e = launch_restore_finish(out, 1, glob, s);
     if (e != hipSuccess)
         return e;
-    if (h_status) {
-        e = hipMemcpyAsync(h_status, out, sizeof(crum_status), hipMemcpyDeviceToHost, s);
-        if (e != hipSuccess)
-            return e;
-    }
-    return hipSuccess;
+    return hipMemcpyAsync(h_status, out, sizeof(crum_status), hipMemcpyDeviceToHost, s);
+}
+
+// Order `s` after the session's earlier work: nothing to do on the stream
+// that work was enqueued on.
+hipError_t wait_done(crum_lazy* z, hipStream_t s)
+{
+    return s == z->done_stream ? hipSuccess : hipStreamWaitEvent(s, z->ev_done, 0);
+}
+
+hipError_t record_done(crum_lazy* z, hipStream_t s)
+{
+    hipError_t e = hipEventRecord(z->ev_done, s);
+    if (e == hipSuccess)
+        z->done_stream = s;
+    return e;
 }
 
 }  // namespace
@@ -256,6 +268,7 @@ int crum_lazy_open(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     crum_lazy* z = new crum_lazy();
     z->ctx = c;
     z->device = ctx_device(c);
+    z->copy = ctx_side_stream(c);
     z->regions.assign(regions, regions + n_regions);
     z->faults.assign(n_regions, 0);
     uint64_t page = 0;
@@ -292,8 +305,7 @@ int crum_lazy_open(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     if (hipMalloc(reinterpret_cast<void**>(&z->d_mem), off) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&z->h_up), z->upload_end, 0) != hipSuccess ||
         hipEventCreateWithFlags(&z->ev_done, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&z->ev_copied, hipEventDisableTiming) != hipSuccess ||
-        hipStreamCreateWithFlags(&z->copy, hipStreamNonBlocking) != hipSuccess) {
+        hipEventCreateWithFlags(&z->ev_copied, hipEventDisableTiming) != hipSuccess) {
         lazy_free(z);
         return CRUM_EHIP;
     }
@@ -347,7 +359,7 @@ int crum_lazy_open(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
                     stream) != hipSuccess ||
         launch_list(img_bitmap, d_prefix, 0, W, d_list, stream) != hipSuccess ||
         enqueue_status(z, h_status, stream) != hipSuccess ||
-        hipEventRecord(z->ev_done, stream) != hipSuccess ||
+        record_done(z, stream) != hipSuccess ||
         // page copies start after everything the caller enqueued before
         // open (the image may have been drained on `stream`)
         hipStreamWaitEvent(z->copy, z->ev_done, 0) != hipSuccess)
@@ -369,7 +381,7 @@ int crum_lazy_touch(crum_lazy* z, uint32_t region, uint64_t offset, uint64_t len
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     DeviceGuard g(z->device);
     // the caller's work after this call sees every fetch enqueued before it
-    CRUM_TRY_C(hipStreamWaitEvent(stream, z->ev_done, 0));
+    CRUM_TRY_C(wait_done(z, stream));
 
     const uint32_t ps = z->info.ps;
     const uint64_t base = z->first_page[region];
@@ -404,7 +416,7 @@ int crum_lazy_touch(crum_lazy* z, uint32_t region, uint64_t offset, uint64_t len
     uint64_t pages = 0, runs = 0;
     CRUM_TRY_C(fetch_window(z, w0, w1, stream, &pages, &runs));
     CRUM_TRY_C(enqueue_status(z, h_status, stream));
-    CRUM_TRY_C(hipEventRecord(z->ev_done, stream));
+    CRUM_TRY_C(record_done(z, stream));
     ++z->faults[region];
     z->st.faults += 1;
     z->st.pages_fetched += pages;
@@ -421,11 +433,11 @@ int crum_lazy_finish(crum_lazy* z, void* stream_, crum_status* h_status)
         return CRUM_EINVAL;
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     DeviceGuard g(z->device);
-    CRUM_TRY_C(hipStreamWaitEvent(stream, z->ev_done, 0));
+    CRUM_TRY_C(wait_done(z, stream));
     uint64_t pages = 0, runs = 0;
     CRUM_TRY_C(fetch_window(z, 0, z->info.G, stream, &pages, &runs));
     CRUM_TRY_C(enqueue_status(z, h_status, stream));
-    CRUM_TRY_C(hipEventRecord(z->ev_done, stream));
+    CRUM_TRY_C(record_done(z, stream));
     z->st.pages_fetched += pages;
     z->st.copies += runs;
     z->st.bytes_fetched += pages << z->info.ps;
