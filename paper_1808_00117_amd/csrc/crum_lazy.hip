@@ -24,7 +24,9 @@
 // stream per session costs more than the rest of open), and the caller's
 // stream waits for each touch's copies before its checks and scatters: the copies of the next fault then overlap the kernels of this
 // one.  Every run has its own slots of the staging buffer, so a copy never
-// overwrites bytes a kernel still reads.
+// overwrites bytes a kernel still reads.  The checks and scatter of a short
+// run cut its pages into smaller pieces, so that it still spreads over many
+// waves (the piece CRCs are combined as for large pages).
 #include "crum.h"
 #include "crum_dev.h"
 #include "crum_internal.h"
@@ -104,11 +106,31 @@ uint64_t slot_of(const crum_lazy* z, uint64_t g)
     return z->prefix[w] + (uint64_t)__builtin_popcountll(below);
 }
 
+// Waves a run's checks and scatter should spread over: a wave works through
+// its piece one 1 KiB step after another, so a run of a few 64 KiB pages in
+// whole-page pieces takes tens of microseconds; pieces are made smaller (down
+// to 4 KiB) until the run has about this many.
+constexpr uint64_t kRunWaves = 1024;
+
+// Log2 of the piece size for a run of n slots: the context's piece size (at
+// most a page), halved while the run has fewer than kRunWaves pieces.  A
+// halved run has fewer than 2 * kRunWaves pieces.
+uint32_t run_piece_shift(const crum_lazy* z, uint64_t n)
+{
+    const uint32_t ps = z->info.ps;
+    uint32_t pcs = std::min(z->pc_shift, ps);
+    while (pcs > kPieceShiftMin && (n << (ps - pcs)) < kRunWaves)
+        --pcs;
+    return pcs;
+}
+
 // Checks and scatter of slots [k0, k1), whose packed pages are in staging.
 hipError_t run_kernels(crum_lazy* z, uint64_t k0, uint64_t k1, hipStream_t s)
 {
     const uint32_t ps = z->info.ps;
     const uint64_t n = k1 - k0;
+    const uint32_t pcs = run_piece_shift(z, n);
+    const uint32_t nps = ps > pcs ? ps - pcs : 0;
     uint8_t* M = z->d_mem;
     const DevRegion* regs = reinterpret_cast<const DevRegion*>(M + z->o_regs);
     const DevRequest* req = reinterpret_cast<const DevRequest*>(M + z->o_req);
@@ -121,19 +143,19 @@ hipError_t run_kernels(crum_lazy* z, uint64_t k0, uint64_t k1, hipStream_t s)
     hipError_t e;
     if (z->flags & CRUM_VERIFY) {
         const SlotRange sr{k0, k1, nullptr, 0, n};
-        e = launch_pack(kModeVerify, regs, nr, req, out, list, sr, z->np_shift, z->pc_shift,
+        e = launch_pack(kModeVerify, regs, nr, req, out, list, sr, nps, pcs,
                         nullptr, z->staging, crcs, partials, ctx_tables(z->ctx), glob,
                         z->pack_blocks, z->depth, z->variant, s);
         if (e != hipSuccess)
             return e;
-        e = launch_finalize(kModeVerify, regs, nr, req, out, list, sr, z->np_shift, z->pc_shift,
+        e = launch_finalize(kModeVerify, regs, nr, req, out, list, sr, nps, pcs,
                             partials, crcs, z->staging, glob, s);
         if (e != hipSuccess)
             return e;
     }
     // the scatter numbers slots from the list pointer and finds a slot's
     // packed page from the staging pointer, so both start at slot k0
-    return launch_scatter(regs, nr, req, out, list + k0, n, z->np_shift, z->pc_shift,
+    return launch_scatter(regs, nr, req, out, list + k0, n, nps, pcs,
                           z->staging + (k0 << ps), (z->flags & CRUM_UPDATE_SHADOW) ? 1 : 0, glob,
                           z->pack_blocks, s);
 }
@@ -300,7 +322,7 @@ int crum_lazy_open(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     z->upload_end = off;
     z->o_prefix = take(&off, 4 * std::max<uint64_t>(W, 1));
     z->o_list = take(&off, 4 * std::max<uint64_t>(W * 64, 1));
-    z->o_partials = take(&off, 4 * std::max<uint64_t>(D << z->np_shift, 1));
+    z->o_partials = take(&off, 4 * std::max<uint64_t>(D << z->np_shift, 2 * kRunWaves));
     z->o_crcs = take(&off, 4 * std::max<uint64_t>(D, 1));
     if (hipMalloc(reinterpret_cast<void**>(&z->d_mem), off) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&z->h_up), z->upload_end, 0) != hipSuccess ||

@@ -105,7 +105,7 @@ def check_state(s, model, total_pages):
         g += new.size // P
 
 
-@pytest.mark.parametrize("P,flags", [(4 * KiB, 2), (4 * KiB, 0), (256 * KiB, 2)])
+@pytest.mark.parametrize("P,flags", [(4 * KiB, 2), (4 * KiB, 0), (64 * KiB, 2), (256 * KiB, 2)])
 def test_touch_sequence_matches_model(env, P, flags):
     crum, ctx, status = env
     counts = (30, 3, 90, 1, 40)
@@ -183,9 +183,9 @@ def test_update_shadow_writes_fetched_pages_only(env):
     s.lz.close()
 
 
-def test_corrupt_page_stops_the_session(env):
+@pytest.mark.parametrize("P", [4 * KiB, 64 * KiB])
+def test_corrupt_page_stops_the_session(env, P):
     crum, ctx, status = env
-    P = 4 * KiB
     regs, img = make_case((64,), P, 1.0, seed=5)   # every page in the image: slot = page
     bad = img.copy()
     data_off = 4096
