@@ -320,6 +320,34 @@ def materialize_raw(scn, H):
     return pairs
 
 
+def read_ceiling(H, scn, pairs, stream, reps: int = 7) -> dict:
+    """Practical HBM read rate of this GPU: the plain two-stream read kernel
+    of the generator library over the largest region and its shadow (the
+    diff's traffic without its bookkeeping), median of `reps` launches timed
+    with HIP events."""
+    import synth
+    i = max(range(len(scn.regions)), key=lambda k: scn.regions[k].nbytes)
+    nb = scn.regions[i].nbytes // 16384 * 16384
+    blocks = 2048
+    out = H.DeviceBuffer(4 * blocks * 256)
+    e0, e1 = H.Event(), H.Event()
+    v = []
+    for r in range(reps + 2):
+        e0.record(stream)
+        synth.read2_dev(pairs[i][0].ptr, pairs[i][1].ptr, nb, out.ptr, blocks * 256, blocks,
+                        stream.handle)
+        e1.record(stream)
+        ms = e0.elapsed_ms(e1)
+        if r >= 2:
+            v.append(ms)
+    out.free()
+    ms = statistics.median(v)
+    gbs = 2 * nb / (ms * 1e-3) / 1e9
+    return {"kernel": "synth_read2_kernel: one wave per 16 KiB unit, 4 non-temporal 16-byte "
+                      "loads per buffer in flight", "bytes": 2 * nb, "ms": round(ms, 4),
+            "achieved": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def percentile(v, q):
     v = sorted(v)
     return v[min(len(v) - 1, int(round(q * (len(v) - 1))))]
@@ -1215,6 +1243,7 @@ def main():
         k, v = kv.split("=")
         autotune.apply(ctx, {k: int(v)})
     s1, s2 = H.Stream(), H.Stream()
+    ceiling = read_ceiling(H, scn, pair_sets[0], s1) if args.config == "many" else None
 
     # co-runner: an application stream of fp32 SAXPY passes (y = a*x + y over
     # 4096x4096 elements), one kernel per pass, captured once as a graph of
@@ -1466,6 +1495,8 @@ def main():
             "avg_launch_ms": round(diff_ms / max(n_diff, 1), 4),
             "launches": n_diff,
             "measured_with": "co-runner active" if corun_on else "alone",
+            "practical_ceiling": ceiling,
+            "frac_of_ceiling": round(diff_gbs / ceiling["achieved"], 4) if ceiling else None,
         },
         "roofline_alone": {"kernel": "k_diff", "achieved": round(diff_alone_gbs, 1),
                            "frac": round(diff_alone_gbs / HBM_PEAK_GBS, 4),

@@ -37,6 +37,16 @@
 
 namespace crum {
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Pointers into global memory.  Region and staging pointers reach the kernels
+// inside structs or after arithmetic the compiler cannot follow, so it would
+// use flat instructions; a flat access counts against the LDS/scalar counter
+// as well, so every wait for an LDS table lookup would also wait for each
+// load and store in flight.  Casting keeps them global.
+typedef const u32x4 __attribute__((address_space(1)))* gcv4;
+typedef u32x4 __attribute__((address_space(1)))* gv4;
+
 // ------------------------------------------------------------ CRC tables
 
 void build_crc_tables(CrcTables* h)
@@ -257,12 +267,12 @@ __device__ __forceinline__ uint32_t lane_combine(const uint32_t* __restrict__ ld
 // `alt` (the shadow) instead of `cur`.  That keeps re-reads off the host link
 // when the current bytes live in host memory.  alt == nullptr: always cur.
 struct PieceSrc {
-    const uint4* cur;
-    const uint4* alt;
+    gcv4 cur;
+    gcv4 alt;
     uint32_t dirty;
     uint32_t ush;
     __device__ __forceinline__ bool is_dirty(uint32_t t) const { return (dirty >> (t >> ush)) & 1u; }
-    __device__ __forceinline__ const uint4* at(uint32_t t) const
+    __device__ __forceinline__ gcv4 at(uint32_t t) const
     {
         return (alt && !is_dirty(t)) ? alt : cur;
     }
@@ -270,14 +280,14 @@ struct PieceSrc {
 
 // lds: the pack layout (kPackLdsWords); V: the CRC step variant.
 template <bool STORE, int U, int V>
-__device__ __forceinline__ uint32_t piece_steps(const PieceSrc& src, uint4* __restrict__ dst,
-                                                uint4* __restrict__ sh, uint32_t* t_io,
+__device__ __forceinline__ uint32_t piece_steps(const PieceSrc& src, gv4 __restrict__ dst,
+                                                gv4 __restrict__ sh, uint32_t* t_io,
                                                 uint32_t steps, uint32_t lane,
                                                 const uint32_t* __restrict__ lds, uint32_t s)
 {
     uint32_t t = *t_io;
     for (; t + U <= steps; t += U) {
-        uint4 w[U];
+        u32x4 w[U];
 #pragma unroll
         for (int u = 0; u < U; ++u)
             w[u] = src.at(t + u)[(t + u) * 64 + lane];
@@ -295,7 +305,8 @@ __device__ __forceinline__ uint32_t piece_steps(const PieceSrc& src, uint4* __re
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            s = shift1k_v<V>(lds, s) ^ word_crc_v<V>(lds, w[u]);
+            s = shift1k_v<V>(lds, s) ^
+                word_crc_v<V>(lds, make_uint4(w[u].x, w[u].y, w[u].z, w[u].w));
     }
     *t_io = t;
     return s;
@@ -306,8 +317,8 @@ __device__ __forceinline__ uint32_t piece_steps(const PieceSrc& src, uint4* __re
 // before it folds them into its CRC.  All lanes return the same value.
 // gz: z[0] of the shift tables in global memory (the butterfly's shifts).
 template <bool STORE, int DEPTH, int V>
-__device__ __forceinline__ uint32_t wave_piece_crc(const PieceSrc& src, uint4* __restrict__ dst,
-                                                   uint4* __restrict__ sh, uint32_t steps,
+__device__ __forceinline__ uint32_t wave_piece_crc(const PieceSrc& src, gv4 __restrict__ dst,
+                                                   gv4 __restrict__ sh, uint32_t steps,
                                                    uint32_t lane,
                                                    const uint32_t* __restrict__ lds,
                                                    const uint32_t* __restrict__ gz)
@@ -346,14 +357,9 @@ __device__ __forceinline__ uint32_t find_region(const DevRegion* __restrict__ re
 // by the lane; loads are 1 KiB apart so each one is coalesced across the wave.
 // NT marks the loads non-temporal: the streamed bytes are not kept in the
 // caches, which stay available to co-running work.
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
 template <int LOADS, bool NT>
-__device__ __forceinline__ uint32_t xor_or(const uint4* __restrict__ a_,
-                                           const uint4* __restrict__ b_)
+__device__ __forceinline__ uint32_t xor_or(gcv4 __restrict__ a, gcv4 __restrict__ b)
 {
-    const u32x4* a = reinterpret_cast<const u32x4*>(a_);
-    const u32x4* b = reinterpret_cast<const u32x4*>(b_);
     u32x4 va[LOADS], vb[LOADS];
 #pragma unroll
     for (int j = 0; j < LOADS; ++j) {
@@ -404,8 +410,8 @@ __global__ __launch_bounds__(256) void k_diff(const DevRegion* __restrict__ regs
         uint32_t x = 1;
         if (R.shadow != nullptr) {
             const uint64_t off = (u - R.first_unit) << us;
-            const uint4* a = reinterpret_cast<const uint4*>(R.cur + off) + lane;
-            const uint4* b = reinterpret_cast<const uint4*>(R.shadow + off) + lane;
+            const gcv4 a = (gcv4)(R.cur + off) + lane;
+            const gcv4 b = (gcv4)(R.shadow + off) + lane;
             x = us == 12 ? xor_or<4, NT>(a, b) : us == 13 ? xor_or<8, NT>(a, b)
                                                           : xor_or<16, NT>(a, b);
         }
@@ -690,7 +696,7 @@ __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs
         const uint32_t steps = 1u << (pb_shift - 10);
         uint32_t raw;
         if (MODE == kModePack) {
-            PieceSrc src{reinterpret_cast<const uint4*>(R.cur + page_off + piece_off), nullptr,
+            PieceSrc src{(gcv4)(R.cur + page_off + piece_off), nullptr,
                          ~0u, 0};
             if (unit_flags && R.shadow) {
                 // the piece's diff units: clean ones are read from the shadow
@@ -700,17 +706,17 @@ __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs
                 uint32_t m = 0;
                 for (uint32_t j = 0; j < n_u; ++j)
                     m |= (unit_flags[u0 + j] ? 1u : 0u) << j;
-                src.alt = reinterpret_cast<const uint4*>(R.shadow + page_off + piece_off);
+                src.alt = (gcv4)(R.shadow + page_off + piece_off);
                 src.dirty = m;
                 src.ush = us - 10;
             }
-            uint4* sh = ((R.flags & 1u) && R.shadow)
-                            ? reinterpret_cast<uint4*>(R.shadow + page_off + piece_off)
+            gv4 sh = ((R.flags & 1u) && R.shadow)
+                            ? (gv4)(R.shadow + page_off + piece_off)
                             : nullptr;
-            raw = wave_piece_crc<true, DEPTH, V>(src, reinterpret_cast<uint4*>(slot_ptr), sh,
+            raw = wave_piece_crc<true, DEPTH, V>(src, (gv4)slot_ptr, sh,
                                                  steps, lane, lds, gz);
         } else {
-            const PieceSrc src{reinterpret_cast<const uint4*>(slot_ptr), nullptr, ~0u, 0};
+            const PieceSrc src{(gcv4)slot_ptr, nullptr, ~0u, 0};
             raw = wave_piece_crc<false, DEPTH, V>(src, nullptr, nullptr, steps, lane, lds, gz);
         }
         if (lane != 0)
@@ -1211,15 +1217,14 @@ __global__ __launch_bounds__(256) void k_scatter(const DevRegion* __restrict__ r
             continue;
         const uint64_t page_off = (g - R.first_page) << ps;
         const uint64_t piece_off = (uint64_t)piece << pb_shift;
-        const uint4* src = reinterpret_cast<const uint4*>(
-            staging + O.img_base + Q.data_off + ((k - O.slot_base) << ps) + piece_off);
-        uint4* dst = reinterpret_cast<uint4*>(const_cast<uint8_t*>(R.cur) + page_off + piece_off);
-        uint4* sh = (update_shadow && R.shadow)
-                        ? reinterpret_cast<uint4*>(R.shadow + page_off + piece_off)
-                        : nullptr;
+        const gcv4 src =
+            (gcv4)(staging + O.img_base + Q.data_off + ((k - O.slot_base) << ps) + piece_off);
+        const gv4 dst = (gv4)(R.cur + page_off + piece_off);
+        const gv4 sh = (update_shadow && R.shadow) ? (gv4)(R.shadow + page_off + piece_off)
+                                                   : nullptr;
         const uint32_t n16 = 1u << (pb_shift - 4);
         for (uint32_t i = lane; i < n16; i += 64 * 4) {
-            uint4 w[4];
+            u32x4 w[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 if (i + 64 * u < n16)

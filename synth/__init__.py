@@ -23,6 +23,7 @@ from .lib import (  # noqa: F401
     mutate_dev,
     saxpy_loop_dev,
     copy_dev,
+    read2_dev,
     mutate_frac_dev,
     clobber_frac_dev,
 )

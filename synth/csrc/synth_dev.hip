@@ -122,6 +122,42 @@ __global__ void synth_copy_kernel(uint4* __restrict__ dst, const uint4* __restri
         dst[i] = src[i];
 }
 
+// Reference streaming read of two equal buffers: one wave per 16 KiB unit
+// (units handed out grid-stride), four non-temporal 16-byte loads of each
+// buffer in flight per lane, OR of the XOR, one word written per thread.  The
+// plainest form of the diff's memory traffic, timed as the practical read
+// ceiling of the GPU.
+typedef uint32_t synth_u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void synth_read2_kernel(const synth_u32x4* __restrict__ a,
+                                                          const synth_u32x4* __restrict__ b,
+                                                          uint64_t n_units,
+                                                          uint32_t* __restrict__ out)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t wave = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint64_t n_waves = (uint64_t)gridDim.x * 4;
+    uint32_t acc = 0;
+    for (uint64_t u = wave; u < n_units; u += n_waves) {
+        const synth_u32x4* pa = a + u * 1024 + lane;
+        const synth_u32x4* pb = b + u * 1024 + lane;
+        for (int j = 0; j < 16; j += 4) {
+            synth_u32x4 va[4], vb[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                va[k] = __builtin_nontemporal_load(pa + (j + k) * 64);
+                vb[k] = __builtin_nontemporal_load(pb + (j + k) * 64);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const synth_u32x4 x = va[k] ^ vb[k];
+                acc |= x.x | x.y | x.z | x.w;
+            }
+        }
+    }
+    out[(uint64_t)blockIdx.x * blockDim.x + threadIdx.x] = acc;
+}
+
 // y <- a*x + y, repeated `iters` times over n elements (the co-running
 // compute kernel of the many-allocations workload).
 __global__ void synth_saxpy_loop_kernel(float* __restrict__ y, const float* __restrict__ x,
@@ -208,6 +244,18 @@ int synth_copy_dev(void* dst, const void* src, uint64_t nbytes, void* stream)
         return 0;
     hipLaunchKernelGGL(synth_copy_kernel, dim3(4096), dim3(256), 0, (hipStream_t)stream,
                        (uint4*)dst, (const uint4*)src, nbytes >> 4);
+    return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+// blocks workgroups of 256 threads; out holds blocks * 256 words.
+int synth_read2_dev(const void* a, const void* b, uint64_t nbytes, uint32_t* out,
+                    uint64_t out_words, int blocks, void* stream)
+{
+    if (((uintptr_t)a & 15) || ((uintptr_t)b & 15) || (nbytes & 16383) || blocks <= 0 ||
+        out_words < (uint64_t)blocks * 256)
+        return -1;
+    hipLaunchKernelGGL(synth_read2_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                       (const synth_u32x4*)a, (const synth_u32x4*)b, nbytes >> 14, out);
     return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 
