@@ -279,6 +279,30 @@ def test_argument_errors_and_empty_image(env):
     s.lz.close()
 
 
+def test_empty_region_table(env):
+    """An image of no regions: open succeeds, every touch is an argument
+    error, finish has nothing to fetch."""
+    import torch
+    crum, ctx, status = env
+    P = 4 * KiB
+    st, img, _ = oracle.snapshot([], P)
+    assert st.code == oracle.OK and st.total_pages == 0
+    h = torch.from_numpy(img.copy()).pin_memory()
+    stg = torch.empty(img.size, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+    lz = crum.Lazy(ctx, [], h.data_ptr(), img.size, crum.CRUM_VERIFY, 0, stg.data_ptr(),
+                   img.size, stream.cuda_stream, status.data_ptr())
+    stream.synchronize()
+    assert crum.read_status(status.data_ptr()).code == 0
+    with pytest.raises(ValueError):
+        lz.touch(0, 0, 1, stream.cuda_stream)
+    lz.finish(stream.cuda_stream, status.data_ptr())
+    stream.synchronize()
+    assert crum.read_status(status.data_ptr()).code == 0
+    assert lz.fetched(0) == [] and lz.stats()["pages_total"] == 0
+    lz.close()
+
+
 def test_touch_orders_other_streams(env):
     """A page fetched on one stream and touched (no fault) on another: work
     queued after the second touch on the second stream sees the page."""
