@@ -1,0 +1,141 @@
+/* A C99 client of the library's C ABI: no Python, no torch.  Two regions
+ * (one with a shadow, one without), a snapshot with the image drained to
+ * pinned memory, a verified restore into fresh buffers holding the shadow's
+ * bytes, then a snapshot with shadow update and one more that must find
+ * nothing dirty.  Prints one line and exits 0 when every check holds. */
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <hip/hip_runtime_api.h>
+
+#include "crum.h"
+
+#define PAGE 4096u
+#define N0 40u /* pages of region 0 (has a shadow) */
+#define N1 9u  /* pages of region 1 (no shadow: all dirty) */
+
+static int fail(const char* what, long v)
+{
+    printf("abi_roundtrip: FAIL %s (%ld)\n", what, v);
+    return 1;
+}
+
+#define HIPOK(x)                                    \
+    do {                                            \
+        if ((x) != hipSuccess)                      \
+            return fail(#x, (long)hipGetLastError()); \
+    } while (0)
+
+int main(void)
+{
+    const size_t b0 = (size_t)N0 * PAGE, b1 = (size_t)N1 * PAGE;
+    uint8_t* h_cur0 = malloc(b0);
+    uint8_t* h_sh0 = malloc(b0);
+    uint8_t* h_cur1 = malloc(b1);
+    uint8_t* h_back = malloc(b0 > b1 ? b0 : b1);
+    if (!h_cur0 || !h_sh0 || !h_cur1 || !h_back)
+        return fail("malloc", 0);
+    uint32_t x = 12345u;
+    for (size_t i = 0; i < b0; ++i) {
+        x = x * 1664525u + 1013904223u;
+        h_cur0[i] = (uint8_t)(x >> 24);
+    }
+    for (size_t i = 0; i < b1; ++i) {
+        x = x * 1664525u + 1013904223u;
+        h_cur1[i] = (uint8_t)(x >> 24);
+    }
+    memcpy(h_sh0, h_cur0, b0);
+    unsigned n_changed = 0;
+    for (unsigned p = 0; p < N0; p += 3) { /* pages 0, 3, 6, ... differ */
+        h_sh0[(size_t)p * PAGE + (p * 97u) % PAGE] ^= 0x5a;
+        ++n_changed;
+    }
+
+    void *cur0, *sh0, *cur1, *t0, *t1, *staging;
+    HIPOK(hipMalloc(&cur0, b0));
+    HIPOK(hipMalloc(&sh0, b0));
+    HIPOK(hipMalloc(&cur1, b1));
+    HIPOK(hipMalloc(&t0, b0));
+    HIPOK(hipMalloc(&t1, b1));
+    HIPOK(hipMemcpy(cur0, h_cur0, b0, hipMemcpyHostToDevice));
+    HIPOK(hipMemcpy(sh0, h_sh0, b0, hipMemcpyHostToDevice));
+    HIPOK(hipMemcpy(cur1, h_cur1, b1, hipMemcpyHostToDevice));
+
+    uint64_t cap = 0;
+    if (crum_image_bytes(2, N0 + N1, N0 + N1, PAGE, &cap) != CRUM_OK)
+        return fail("crum_image_bytes", 0);
+    HIPOK(hipMalloc(&staging, cap));
+    void* h_image = NULL;
+    crum_status* st = NULL;
+    HIPOK(hipHostMalloc(&h_image, cap, 0));
+    HIPOK(hipHostMalloc((void**)&st, sizeof(*st), 0));
+    hipStream_t s;
+    HIPOK(hipStreamCreate(&s));
+
+    crum_ctx* ctx = NULL;
+    int rc = crum_ctx_create(0, &ctx);
+    if (rc != CRUM_OK)
+        return fail("crum_ctx_create", rc);
+    crum_region regs[2] = {{cur0, sh0, b0, 71}, {cur1, NULL, b1, 72}};
+    rc = crum_snapshot(ctx, regs, 2, PAGE, 0, 9, staging, cap, h_image, cap, s, st);
+    if (rc != CRUM_OK)
+        return fail("crum_snapshot", rc);
+    HIPOK(hipStreamSynchronize(s));
+    if (st->code != CRUM_OK || st->n_dirty != n_changed + N1 || st->total_pages != N0 + N1)
+        return fail("snapshot status", (long)st->n_dirty);
+    const uint64_t image_bytes = st->image_bytes;
+
+    /* restore into buffers that hold the shadow's bytes (and garbage) */
+    HIPOK(hipMemcpy(t0, h_sh0, b0, hipMemcpyHostToDevice));
+    HIPOK(hipMemset(t1, 0xee, b1));
+    crum_region targets[2] = {{t0, NULL, b0, 71}, {t1, NULL, b1, 72}};
+    rc = crum_restore(ctx, targets, 2, h_image, image_bytes, CRUM_VERIFY, staging, cap, s, st);
+    if (rc != CRUM_OK)
+        return fail("crum_restore", rc);
+    HIPOK(hipStreamSynchronize(s));
+    if (st->code != CRUM_OK)
+        return fail("restore status", st->code);
+    HIPOK(hipMemcpy(h_back, t0, b0, hipMemcpyDeviceToHost));
+    if (memcmp(h_back, h_cur0, b0) != 0)
+        return fail("region 0 restored bytes", 0);
+    HIPOK(hipMemcpy(h_back, t1, b1, hipMemcpyDeviceToHost));
+    if (memcmp(h_back, h_cur1, b1) != 0)
+        return fail("region 1 restored bytes", 0);
+
+    /* a wrong id is refused before anything is enqueued */
+    targets[1].id = 99;
+    rc = crum_restore(ctx, targets, 2, h_image, image_bytes, CRUM_VERIFY, staging, cap, s, st);
+    if (rc != CRUM_EMISMATCH || st->code != CRUM_EMISMATCH)
+        return fail("restore with a wrong id", rc);
+
+    /* shadow update, then nothing is dirty */
+    rc = crum_snapshot(ctx, regs, 1, PAGE, CRUM_UPDATE_SHADOW, 10, staging, cap, h_image, cap, s,
+                       st);
+    HIPOK(hipStreamSynchronize(s));
+    if (rc != CRUM_OK || st->code != CRUM_OK || st->n_dirty != n_changed)
+        return fail("snapshot with shadow update", rc);
+    rc = crum_snapshot(ctx, regs, 1, PAGE, 0, 11, staging, cap, h_image, cap, s, st);
+    HIPOK(hipStreamSynchronize(s));
+    if (rc != CRUM_OK || st->code != CRUM_OK || st->n_dirty != 0)
+        return fail("snapshot after shadow update", (long)st->n_dirty);
+
+    crum_ctx_destroy(ctx);
+    HIPOK(hipStreamDestroy(s));
+    hipFree(cur0);
+    hipFree(sh0);
+    hipFree(cur1);
+    hipFree(t0);
+    hipFree(t1);
+    hipFree(staging);
+    hipHostFree(h_image);
+    hipHostFree(st);
+    free(h_cur0);
+    free(h_sh0);
+    free(h_cur1);
+    free(h_back);
+    printf("abi_roundtrip: ok (%u + %u dirty pages, image %llu bytes)\n", n_changed, N1,
+           (unsigned long long)image_bytes);
+    return 0;
+}
