@@ -604,7 +604,7 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
                                      c->pack_depth, c->crc_variant, stream));
                 CRUM_TRY(launch_finalize(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                          np_shift, pc_shift, d_partials, d_crcs, staging, d_glob,
-                                         stream));
+                                         c->d_tabs, stream));
             }
             CRUM_TRY(hipEventRecord(c->ev_chunk[ci], stream));
         }
@@ -677,7 +677,7 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
                                      c->pack_depth, c->crc_variant, stream));
                 CRUM_TRY(launch_finalize(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                          np_shift, pc_shift, d_partials, d_crcs, staging, d_glob,
-                                         stream));
+                                         c->d_tabs, stream));
             }
             if (himg) {
                 CRUM_TRY(ensure_events(c->ev_chunk, ci + 1));
@@ -839,7 +839,7 @@ int crum_restore(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
                              stream));
         CRUM_TRY(launch_finalize(kModeVerify, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                  np_shift, pc_shift, d_partials, d_crcs, staging, d_glob,
-                                 stream));
+                                 c->d_tabs, stream));
     }
     {
         Span sp(c, kTScatter, stream);

@@ -145,7 +145,7 @@ hipError_t launch_finalize(int mode, const DevRegion* regs, uint32_t n_regs,
                            const DevRequest* reqs, const DevReqOut* out, const uint32_t* list,
                            SlotRange range, uint32_t np_shift, uint32_t piece_shift,
                            const uint32_t* partials, uint32_t* crc_out, uint8_t* staging,
-                           DevGlobal* glob, hipStream_t s);
+                           DevGlobal* glob, const CrcTables* tabs, hipStream_t s);
 // One workgroup per request of [q0, q1).  Requests with ENOSPC get only their
 // prefix (header, table, bitmap), and only when it fits within `capacity`.
 hipError_t launch_header(const DevRegion* regs, const DevRequest* reqs, uint32_t q0, uint32_t q1,

@@ -835,7 +835,8 @@ __global__ __launch_bounds__(256) void k_finalize(const DevRegion* __restrict__ 
                                                   const uint32_t* __restrict__ partials,
                                                   uint32_t* __restrict__ crc_out,
                                                   uint8_t* __restrict__ staging,
-                                                  DevGlobal* __restrict__ glob)
+                                                  DevGlobal* __restrict__ glob,
+                                                  const CrcTables* __restrict__ tabs)
 {
     if (MODE == kModeVerify && glob->fmt_bad)
         return;
@@ -857,7 +858,7 @@ __global__ __launch_bounds__(256) void k_finalize(const DevRegion* __restrict__ 
     if (MODE == kModePack && O.code != 0)
         return;
     const uint32_t np = 1u << (ps - piece_shift);
-    const uint32_t K = gf2_xpow8n(1ull << piece_shift);
+    const uint32_t K = tabs->xp[piece_shift];  // x^(8 * piece bytes)
     uint32_t s = 0;
     for (uint32_t j = 0; j < np; ++j)
         s = gf2_mulmod(s, K) ^ partials[(i << np_shift) + j];
@@ -877,7 +878,7 @@ hipError_t launch_finalize(int mode, const DevRegion* regs, uint32_t n_regs,
                            const DevRequest* reqs, const DevReqOut* out, const uint32_t* list,
                            SlotRange range, uint32_t np_shift, uint32_t piece_shift,
                            const uint32_t* partials, uint32_t* crc_out, uint8_t* staging,
-                           DevGlobal* glob, hipStream_t s)
+                           DevGlobal* glob, const CrcTables* tabs, hipStream_t s)
 {
     if (range.max_slots == 0 || np_shift == 0)
         return hipSuccess;
@@ -885,11 +886,11 @@ hipError_t launch_finalize(int mode, const DevRegion* regs, uint32_t n_regs,
     if (mode == kModePack)
         hipLaunchKernelGGL(k_finalize<kModePack>, dim3(nb), dim3(256), 0, s, regs, n_regs, reqs,
                            out, list, range, np_shift, piece_shift, partials, crc_out, staging,
-                           glob);
+                           glob, tabs);
     else
         hipLaunchKernelGGL(k_finalize<kModeVerify>, dim3(nb), dim3(256), 0, s, regs, n_regs,
                            reqs, out, list, range, np_shift, piece_shift, partials, crc_out,
-                           staging, glob);
+                           staging, glob, tabs);
     return hipGetLastError();
 }
 
@@ -930,8 +931,9 @@ __device__ uint32_t wg_crc(const uint8_t* __restrict__ p, uint64_t n, uint64_t z
     const uint32_t* Z4096 = lds + kSliceWords + 6 * 1024;
     const uint64_t steps = (n + 4095) / 4096;
     const int64_t pad = (int64_t)(steps * 4096 - n);
-    uint32_t s = 0;
-    for (uint64_t j = 0; j < steps; ++j) {
+    // thread tid's 16 bytes of 4 KiB step j, the step's zero padding (and
+    // the word at zero_off) read as zero
+    auto load_step = [&](uint64_t j) {
         const int64_t v = (int64_t)((j * 256 + tid) * 16) - pad;
         uint32_t w[4];
 #pragma unroll
@@ -941,8 +943,23 @@ __device__ uint32_t wg_crc(const uint8_t* __restrict__ p, uint64_t n, uint64_t z
                        ? *reinterpret_cast<const uint32_t*>(p + r)
                        : 0u;
         }
-        s = shiftz(Z4096, s) ^ word_crc(lds, make_uint4(w[0], w[1], w[2], w[3]));
+        return make_uint4(w[0], w[1], w[2], w[3]);
+    };
+    // four steps' loads in flight before they are folded, in step order
+    constexpr int U = 4;
+    uint32_t s = 0;
+    uint64_t j = 0;
+    for (; j + U <= steps; j += U) {
+        uint4 w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            w[u] = load_step(j + u);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            s = shiftz(Z4096, s) ^ word_crc(lds, w[u]);
     }
+    for (; j < steps; ++j)
+        s = shiftz(Z4096, s) ^ word_crc(lds, load_step(j));
     s = lane_combine(lds, s, lane);
     for (uint32_t k = wave; k < 3; ++k)
         s = shiftz(Z1024, s);

@@ -149,7 +149,7 @@ hipError_t run_kernels(crum_lazy* z, uint64_t k0, uint64_t k1, hipStream_t s)
         if (e != hipSuccess)
             return e;
         e = launch_finalize(kModeVerify, regs, nr, req, out, list, sr, nps, pcs,
-                            partials, crcs, z->staging, glob, s);
+                            partials, crcs, z->staging, glob, ctx_tables(z->ctx), s);
         if (e != hipSuccess)
             return e;
     }

@@ -302,7 +302,7 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
                             shape.pack_blocks, ctx_pack_depth(c), ctx_crc_variant(c), s);
         if (e == hipSuccess)
             e = launch_finalize(kModePack, d_regs, p->n_regs, d_reqs, d_out, d_list, sr, np_shift,
-                                pc_shift, d_part, d_crcs, p->staging, d_glob, s);
+                                pc_shift, d_part, d_crcs, p->staging, d_glob, tabs, s);
         if (e == hipSuccess)
             e = launch_header(d_regs, d_reqs, q0, q1, d_out, d_bitmap, d_crcs, p->staging,
                               capacity, tabs, s);
