@@ -321,6 +321,10 @@ void crum_ctx_destroy(crum_ctx* c)
         (void)hipFree(c->d_scratch);
     if (c->h_pin)
         (void)hipHostFree(c->h_pin);
+    if (c->lazy_d)
+        (void)hipFree(c->lazy_d);
+    if (c->lazy_h)
+        (void)hipHostFree(c->lazy_h);
     delete c;
 }
 

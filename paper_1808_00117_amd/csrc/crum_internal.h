@@ -129,6 +129,13 @@ struct crum_ctx {
     bool partial_call = false;  // a call stopped part-way through its enqueue
     std::vector<hipEvent_t> pool;
     size_t pool_used = 0;
+    // scratch of on-demand restore sessions, lent to one open session at a
+    // time (allocating per session costs more than the rest of opening one)
+    uint8_t* lazy_d = nullptr;
+    size_t lazy_d_cap = 0;
+    uint8_t* lazy_h = nullptr;  // pinned
+    size_t lazy_h_cap = 0;
+    bool lazy_busy = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> spans[crum::kTimingClasses];
 };
 

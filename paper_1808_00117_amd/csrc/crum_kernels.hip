@@ -86,14 +86,42 @@ constexpr int kNibOff = kSliceWords;
 constexpr int kZ5Off = kNibOff + 20 * 2 * 16;
 constexpr int kPackLdsWords = kZ5Off + 4 * 256;
 
+// Every kernel of this file runs 256-thread workgroups.
+constexpr int kBlock = 256;
+
+// Copy WORDS 4-byte words (16-byte aligned at both ends) from global memory
+// into LDS: each thread issues all of its 16-byte loads before its first LDS
+// store.  A word-per-iteration loop waits for every load in turn, which cost
+// each workgroup tens of memory round trips before its first useful step.
+template <int WORDS>
+__device__ __forceinline__ void stage_words(uint32_t* __restrict__ dst,
+                                            const uint32_t* __restrict__ src)
+{
+    static_assert(WORDS % 4 == 0, "whole 16-byte vectors");
+    constexpr int V = WORDS / 4;
+    constexpr int N = (V + kBlock - 1) / kBlock;
+    const uint4* s = reinterpret_cast<const uint4*>(src);
+    uint4* d = reinterpret_cast<uint4*>(dst);
+    uint4 v[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const int i = (int)threadIdx.x + kBlock * k;
+        if (V % kBlock == 0 || i < V)
+            v[k] = s[i];
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const int i = (int)threadIdx.x + kBlock * k;
+        if (V % kBlock == 0 || i < V)
+            d[i] = v[k];
+    }
+}
+
 __device__ __forceinline__ void load_pack_tables(uint32_t* lds, const CrcTables* tabs)
 {
-    for (int i = threadIdx.x; i < kSliceWords; i += blockDim.x)
-        lds[i] = (&tabs->t[0][0])[i];
-    for (int i = threadIdx.x; i < 20 * 2 * 16; i += blockDim.x)
-        lds[kNibOff + i] = (&tabs->nib[0][0][0])[i];
-    for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x)
-        lds[kZ5Off + i] = (&tabs->z[5][0][0])[i];
+    stage_words<kSliceWords>(lds, &tabs->t[0][0]);
+    stage_words<20 * 2 * 16>(lds + kNibOff, &tabs->nib[0][0][0]);
+    stage_words<4 * 256>(lds + kZ5Off, &tabs->z[5][0][0]);
     __syncthreads();
 }
 
@@ -137,11 +165,11 @@ __device__ __forceinline__ uint32_t shiftz(const uint32_t* __restrict__ Z, uint3
            Z[768 + (s >> 24)];
 }
 
-__device__ __forceinline__ void load_tables(uint32_t* lds, const CrcTables* tabs, int words)
+// The slicing tables and all shift tables (t and z are contiguous in CrcTables).
+__device__ __forceinline__ void load_all_tables(uint32_t* lds, const CrcTables* tabs)
 {
-    const uint32_t* src = &tabs->t[0][0];
-    for (int i = threadIdx.x; i < words; i += blockDim.x)
-        lds[i] = src[i];
+    static_assert(offsetof(CrcTables, z) == sizeof(uint32_t) * kSliceWords, "t then z");
+    stage_words<kAllTabWords>(lds, &tabs->t[0][0]);
     __syncthreads();
 }
 
@@ -652,7 +680,7 @@ __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs
                                               const CrcTables* __restrict__ tabs,
                                               DevGlobal* __restrict__ glob)
 {
-    __shared__ uint32_t lds[kPackLdsWords];
+    __shared__ __attribute__((aligned(16))) uint32_t lds[kPackLdsWords];
     if (MODE == kModeVerify && glob->fmt_bad)
         return;
     uint64_t slot0, slot1;
@@ -1004,14 +1032,14 @@ __global__ __launch_bounds__(256) void k_header(const DevRegion* __restrict__ re
                                                 uint64_t capacity,
                                                 const CrcTables* __restrict__ tabs)
 {
-    __shared__ uint32_t lds[kAllTabWords];
+    __shared__ __attribute__((aligned(16))) uint32_t lds[kAllTabWords];
     __shared__ uint32_t red[4];
     __shared__ uint32_t s_shadowed;
     const DevRequest& Q = reqs[q0 + blockIdx.x];
     const DevReqOut& O = out[q0 + blockIdx.x];
     if (O.code != 0 && O.img_base + Q.data_off > capacity)
         return;  // no room even for the prefix
-    load_tables(lds, tabs, kAllTabWords);
+    load_all_tables(lds, tabs);
     const uint32_t tid = threadIdx.x;
     uint8_t* img = staging + O.img_base;
     const uint64_t R = Q.n_regions;
@@ -1135,11 +1163,11 @@ __global__ __launch_bounds__(256) void k_restore_check(const DevRequest* __restr
                                                        const CrcTables* __restrict__ tabs,
                                                        DevGlobal* __restrict__ glob)
 {
-    __shared__ uint32_t lds[kAllTabWords];
+    __shared__ __attribute__((aligned(16))) uint32_t lds[kAllTabWords];
     __shared__ uint32_t red[4];
     __shared__ unsigned long long s_pop;
     __shared__ uint32_t s_bad;
-    load_tables(lds, tabs, kAllTabWords);
+    load_all_tables(lds, tabs);
     const uint32_t tid = threadIdx.x;
     const DevRequest& Q = reqs[blockIdx.x];
     const DevReqOut& O = out[blockIdx.x];

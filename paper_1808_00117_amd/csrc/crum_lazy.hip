@@ -60,6 +60,7 @@ struct crum_lazy {
     size_t o_regs = 0, o_req = 0, o_out = 0, o_glob = 0, o_prefix = 0, o_list = 0,
            o_partials = 0, o_crcs = 0, upload_end = 0;
     uint8_t* h_up = nullptr;  // pinned upload of the tables
+    bool borrowed = false;    // d_mem and h_up are the context's lazy scratch
     hipStream_t copy = nullptr;  // the context's side stream
     hipEvent_t ev_done = nullptr;    // the last call's work on the caller's stream
     hipStream_t done_stream = nullptr;  // the stream ev_done was last recorded on
@@ -77,10 +78,14 @@ size_t take(size_t* off, size_t bytes)
 
 void lazy_free(crum_lazy* z)
 {
-    if (z->d_mem)
-        (void)hipFree(z->d_mem);
-    if (z->h_up)
-        (void)hipHostFree(z->h_up);
+    if (z->borrowed) {
+        z->ctx->lazy_busy = false;
+    } else {
+        if (z->d_mem)
+            (void)hipFree(z->d_mem);
+        if (z->h_up)
+            (void)hipHostFree(z->h_up);
+    }
     if (z->ev_done)
         (void)hipEventDestroy(z->ev_done);
     if (z->ev_copied)
@@ -324,9 +329,42 @@ int crum_lazy_open(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     z->o_list = take(&off, 4 * std::max<uint64_t>(W * 64, 1));
     z->o_partials = take(&off, 4 * std::max<uint64_t>(D << z->np_shift, 2 * kRunWaves));
     z->o_crcs = take(&off, 4 * std::max<uint64_t>(D, 1));
-    if (hipMalloc(reinterpret_cast<void**>(&z->d_mem), off) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&z->h_up), z->upload_end, 0) != hipSuccess ||
-        hipEventCreateWithFlags(&z->ev_done, hipEventDisableTiming) != hipSuccess ||
+    if (!c->lazy_busy) {
+        // the context's scratch: free while no session holds it, so a
+        // session that closed has finished with it (close waits)
+        z->borrowed = true;
+        c->lazy_busy = true;
+        if (c->lazy_d_cap < off) {
+            if (c->lazy_d)
+                (void)hipFree(c->lazy_d);
+            c->lazy_d = nullptr;
+            c->lazy_d_cap = 0;
+            const size_t cap = round_up(off + off / 4, 1 << 20);
+            if (hipMalloc(reinterpret_cast<void**>(&c->lazy_d), cap) == hipSuccess)
+                c->lazy_d_cap = cap;
+        }
+        if (c->lazy_h_cap < z->upload_end) {
+            if (c->lazy_h)
+                (void)hipHostFree(c->lazy_h);
+            c->lazy_h = nullptr;
+            c->lazy_h_cap = 0;
+            const size_t cap = round_up(z->upload_end + z->upload_end / 4, 1 << 16);
+            if (hipHostMalloc(reinterpret_cast<void**>(&c->lazy_h), cap, 0) == hipSuccess)
+                c->lazy_h_cap = cap;
+        }
+        z->d_mem = c->lazy_d_cap >= off ? c->lazy_d : nullptr;
+        z->h_up = c->lazy_h_cap >= z->upload_end ? c->lazy_h : nullptr;
+        if (!z->d_mem || !z->h_up) {
+            lazy_free(z);
+            return CRUM_EHIP;
+        }
+    } else if (hipMalloc(reinterpret_cast<void**>(&z->d_mem), off) != hipSuccess ||
+               hipHostMalloc(reinterpret_cast<void**>(&z->h_up), z->upload_end, 0) !=
+                   hipSuccess) {
+        lazy_free(z);
+        return CRUM_EHIP;
+    }
+    if (hipEventCreateWithFlags(&z->ev_done, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&z->ev_copied, hipEventDisableTiming) != hipSuccess) {
         lazy_free(z);
         return CRUM_EHIP;

@@ -279,6 +279,35 @@ def test_argument_errors_and_empty_image(env):
     s.lz.close()
 
 
+def test_sessions_at_once_on_one_context(env):
+    """Two sessions open together on one context (the first uses the
+    context's scratch, the second its own), interleaved touches, both end as
+    the oracle's restore; a third session afterwards reuses the scratch."""
+    crum, ctx, status = env
+    P = 4 * KiB
+    cases = [make_case((30, 12), P, 0.4, seed=81), make_case((7, 50), P, 0.4, seed=82),
+             make_case((64,), P, 0.3, seed=83)]
+    a = Session(crum, ctx, status, *cases[0], P, crum.CRUM_VERIFY, 0)
+    b = Session(crum, ctx, status, *cases[1], P, crum.CRUM_VERIFY, 0)
+    ma = LazyModel([30 * P, 12 * P], P, image_pages(cases[0][1], 2, 42), 0)
+    mb = LazyModel([7 * P, 50 * P], P, image_pages(cases[1][1], 2, 57), 0)
+    for r, off, ln in [(0, 0, 3 * P), (1, 5 * P, P), (0, 20 * P, 4 * P), (1, 0, 12 * P)]:
+        assert a.touch(r, off, ln) == ma.touch(r, off, ln)
+        assert b.touch(1 - r, off % (7 * P), P) == mb.touch(1 - r, off % (7 * P), P)
+        check_state(a, ma, 42)
+        check_state(b, mb, 57)
+    for s, m, (regs, _) in ((a, ma, cases[0]), (b, mb, cases[1])):
+        s.finish()
+        assert s.st().code == 0
+        for i, (new, _, _) in enumerate(regs):
+            assert np.array_equal(s.host(i), new)
+        s.lz.close()
+    c = Session(crum, ctx, status, *cases[2], P, crum.CRUM_VERIFY, 0)
+    c.finish()
+    assert c.st().code == 0 and np.array_equal(c.host(0), cases[2][0][0][0])
+    c.lz.close()
+
+
 def test_empty_region_table(env):
     """An image of no regions: open succeeds, every touch is an argument
     error, finish has nothing to fetch."""
