@@ -231,6 +231,7 @@ def cpu_baseline(scn, budget_s: float):
         del img
     gbs = total * n_runs / t_acc / 1e9
     return {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "host": host_cpu(),
             "sample": f"{len(regs)} whole regions in table order, {total / 2**30:.2f} GiB "
                       f"scanned, {dirty} dirty {P // 1024} KiB pages, snapshotted "
                       f"{n_runs}x single-threaded ({t_acc:.1f} s)"}
@@ -318,6 +319,25 @@ def materialize_raw(scn, H):
         pairs.append((cur, sh))
     H.device_synchronize()
     return pairs
+
+
+def host_cpu() -> dict:
+    """The host the CPU baseline ran on: CPU model and the hardware threads
+    this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        threads = os.cpu_count()
+    return {"cpu_model": model, "threads_available": threads}
 
 
 def read_ceiling(H, scn, pairs, stream, reps: int = 7) -> dict:
