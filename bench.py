@@ -1166,7 +1166,8 @@ def bench_managed(args):
                    "image_bytes": image_bytes, "settle": settle},
         "diff": {"achieved_gbs": round(2 * N * args.steps / (diff_ms * 1e-3) / 1e9, 1),
                  "launches": n_diff},
-        "drain": {"achieved_gbs": round(image_bytes * args.steps / (drain_ms * 1e-3) / 1e9, 2)},
+        "drain": {"achieved_gbs": round(image_bytes * args.steps / (drain_ms * 1e-3) / 1e9, 2)
+                  if drain_ms else None},
         "residency": {"pointer_attributes": {k: v for k, v in attrs.items()
                                              if k in ("type", "isManaged", "allocationFlags")},
                       "before": res_before, "after": res_after,
@@ -1335,7 +1336,8 @@ def main():
     crum.crum_ctx_set_timing(ctx, False)
     n_da, da_ms = crum.crum_ctx_timing(ctx, 0)
     _, dr_alone_ms = crum.crum_ctx_timing(ctx, 2)
-    drain_alone_gbs = image_bytes * n_alone / (dr_alone_ms * 1e-3) / 1e9
+    # no drain copies in the direct order (the kernels write the host image)
+    drain_alone_gbs = image_bytes * n_alone / (dr_alone_ms * 1e-3) / 1e9 if dr_alone_ms else None
     diff_alone_gbs = diff_bytes_step * n_alone / (da_ms * 1e-3) / 1e9
     checked_ms = float("nan") if args.quick else median_ms(lambda: run_snapshot(eager=False))
     corun_on = args.config == "many" and not args.no_corunner
@@ -1421,7 +1423,7 @@ def main():
     n_diff, diff_ms = timing["diff"]
     diff_gbs = diff_bytes_step * args.steps / (diff_ms * 1e-3) / 1e9
     n_dr, drain_ms = timing["drain"]
-    drain_gbs = image_bytes * n_breakdown / (drain_ms * 1e-3) / 1e9
+    drain_gbs = image_bytes * n_breakdown / (drain_ms * 1e-3) / 1e9 if drain_ms else None
     n_pk, pack_ms = timing["pack"]
     pack_bytes = 2 * D * P + 4 * D
     pack_gbs = pack_bytes * n_breakdown / (pack_ms * 1e-3) / 1e9
@@ -1492,8 +1494,11 @@ def main():
             "dirty_pages": D,
             "image_bytes": image_bytes,
             "staging_capacity": cap,
-            "order": ("chunk-pipelined" if N > crum.crum_ctx_get_param(
-                ctx, crum.CRUM_PARAM_CHUNK_BYTES) else "diff-first (the pages make one chunk)"),
+            "order": ("direct (image built in the pinned host image)"
+                      if cap <= crum.crum_ctx_get_param(ctx, crum.CRUM_PARAM_DIRECT_BYTES)
+                      else "chunk-pipelined" if N > crum.crum_ctx_get_param(
+                          ctx, crum.CRUM_PARAM_CHUNK_BYTES)
+                      else "diff-first (the pages make one chunk)"),
             "co_runner": (f"fp32 SAXPY 4096x4096: graphs of {PASSES} single-pass kernels "
                           f"issued continuously on a second stream by a second host thread "
                           f"({sax_graphs[0]} graphs during the timed steps)") if corun_on else None,
@@ -1522,18 +1527,23 @@ def main():
                            "frac": round(diff_alone_gbs / HBM_PEAK_GBS, 4),
                            "avg_launch_ms": round(da_ms / max(n_da, 1), 4),
                            "what": "same snapshot steps without the co-runner"},
-        "drain": {"achieved": round(drain_gbs, 2), "peak": LINK_PEAK_GBS, "unit": "GB/s",
-                  "frac": round(drain_gbs / LINK_PEAK_GBS, 4), "copies": n_dr,
-                  "reference": link_ref},
+        "drain": {"achieved": round(drain_gbs, 2) if drain_gbs else None,
+                  "peak": LINK_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(drain_gbs / LINK_PEAK_GBS, 4) if drain_gbs else None,
+                  "copies": n_dr, "reference": link_ref,
+                  "what": None if drain_gbs else "no drain copies: the image was built in "
+                                                   "the pinned host image (direct order)"},
         "pack": {"achieved": round(pack_gbs, 1), "unit": "GB/s",
-                 "algorithmic_bytes_per_step": pack_bytes},
+                 "algorithmic_bytes_per_step": pack_bytes,
+                 "what": None if drain_gbs else "direct order: the pack's stores cross the "
+                                                "host link into the pinned image"},
         "header": {"avg_launch_ms": round(header_ms / max(n_hd, 1), 4)},
         "breakdown_timed": "in the timed steps" if breakdown_in_timed else
                            f"separate pass of {n_breakdown} snapshots after the timed steps",
         "overlap": {
             "snapshot_ms_alone": round(snap_alone_ms, 3),
             "snapshot_ms_alone_each": alone_list,
-            "drain_gbs_alone": round(drain_alone_gbs, 2),
+            "drain_gbs_alone": round(drain_alone_gbs, 2) if drain_alone_gbs else None,
             "snapshot_ms_with_corunner": round(p50, 3) if corun_on else None,
             "snapshot_ms_diff_first_order": round(checked_ms, 3),
             "saxpy_gbs_alone": round(sax_alone_gbs, 1) if corun_on else None,

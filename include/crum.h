@@ -123,11 +123,15 @@ int crum_image_bytes(uint32_t n_regions, uint64_t total_pages, uint64_t n_dirty,
  * processed in chunks and each chunk is drained while later chunks are
  * diffed; otherwise the whole diff
  * and the capacity check run first, then pack chunks with their drain behind
- * them.  With CRUM_UPDATE_SHADOW, every dirty page is also copied into its
- * shadow, but only when the status is CRUM_OK.
+ * them.  A third order applies when an image with every page dirty is at most
+ * CRUM_PARAM_DIRECT_BYTES and h_image is host memory the device maps at the
+ * same address (hipHostMalloc): the pack and header kernels write the image
+ * straight into h_image, d_staging is not written, and the calling thread
+ * does not wait at all.  With CRUM_UPDATE_SHADOW, every dirty page is also
+ * copied into its shadow, but only when the status is CRUM_OK.
  *
  * d_staging: device buffer of staging_bytes, at least data_off bytes, 16-byte
- * aligned; receives the image.  h_image: pinned host buffer of h_image_bytes,
+ * aligned; receives the image (except in the direct order).  h_image: pinned host buffer of h_image_bytes,
  * or NULL to keep the image on the device only.  If the image does not fit
  * either capacity, status CRUM_ENOSPC: nothing is packed, no shadow changes,
  * n_dirty/image_bytes and the bitmap (at d_staging + 64 + 32R) are valid.
@@ -321,13 +325,16 @@ void crum_server_destroy(crum_server* server);
  *   their compute units relative to co-running kernels, 0..3 (0).
  * CRUM_PARAM_PLAN_ORDER: processing order of a plan's requests, 0 = the
  *   caller's, 1 = smallest scanned bytes first (0).
+ * CRUM_PARAM_DIRECT_BYTES: snapshots whose image with every page dirty is at
+ *   most this many bytes are built straight in the pinned host image (see
+ *   crum_snapshot); 0 turns the direct order off (128 MiB).
  * CRUM_PARAM_CRC_VARIANT: how the pack and verify kernels' CRC step splits
  *   its table lookups between 256-entry byte tables (bank conflicts) and
  *   16-entry nibble tables (conflict-free, more ALU work): 0 = byte tables
  *   only, 1..5 = mixes, 6 = byte tables for pack and mix 3 for verify, the
  *   fastest of each on MI355X (6).
- * Values of 0 are rejected (CRUM_EINVAL) except for the two on/off switches
- * and the priority. */
+ * Values of 0 are rejected (CRUM_EINVAL) except for the two on/off switches,
+ * the priority and the direct-order size. */
 enum {
     CRUM_PARAM_DIFF_BLOCKS = 1,
     CRUM_PARAM_PACK_BLOCKS = 2,
@@ -341,7 +348,8 @@ enum {
     CRUM_PARAM_PACK_DEPTH = 10,
     CRUM_PARAM_DIFF_PRIORITY = 11,
     CRUM_PARAM_CRC_VARIANT = 12,
-    CRUM_PARAM_PLAN_ORDER = 13
+    CRUM_PARAM_PLAN_ORDER = 13,
+    CRUM_PARAM_DIRECT_BYTES = 14
 };
 int crum_ctx_set_param(crum_ctx* ctx, int param, uint64_t value);
 int crum_ctx_get_param(crum_ctx* ctx, int param, uint64_t* value);

@@ -33,6 +33,7 @@ PARAMS = {
     "diff_priority": C.CRUM_PARAM_DIFF_PRIORITY,
     "crc_variant": C.CRUM_PARAM_CRC_VARIANT,
     "plan_order": C.CRUM_PARAM_PLAN_ORDER,
+    "direct_bytes": C.CRUM_PARAM_DIRECT_BYTES,
 }
 
 

@@ -350,6 +350,10 @@ int crum_ctx_set_param(crum_ctx* c, int param, uint64_t v)
         c->piece_shift = (uint32_t)v;
         return CRUM_OK;
     }
+    if (param == CRUM_PARAM_DIRECT_BYTES) {
+        c->direct_bytes = v;
+        return CRUM_OK;
+    }
     if (param == CRUM_PARAM_PLAN_ORDER) {
         if (v > 1)
             return CRUM_EINVAL;
@@ -419,6 +423,7 @@ int crum_ctx_get_param(crum_ctx* c, int param, uint64_t* v)
     case CRUM_PARAM_DIFF_PRIORITY: *v = (uint64_t)c->diff_prio; return CRUM_OK;
     case CRUM_PARAM_CRC_VARIANT: *v = (uint64_t)c->crc_variant; return CRUM_OK;
     case CRUM_PARAM_PLAN_ORDER: *v = (uint64_t)c->plan_order; return CRUM_OK;
+    case CRUM_PARAM_DIRECT_BYTES: *v = c->direct_bytes; return CRUM_OK;
     default: return CRUM_EINVAL;
     }
 }
@@ -464,6 +469,11 @@ int crum_ctx_timing(crum_ctx* c, int which, uint64_t* launches, double* total_ms
     return CRUM_OK;
 }
 
+static bool himg_ok_for_direct(const crum_ctx* c, const void* h_image, uint64_t worst)
+{
+    return h_image && c->direct_bytes && worst <= c->direct_bytes;
+}
+
 int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
                   uint32_t page_size, uint32_t flags, uint64_t seq, void* d_staging,
                   uint64_t staging_bytes, void* h_image, uint64_t h_image_bytes, void* stream_,
@@ -495,9 +505,20 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     // Otherwise, or when the pages make a single chunk (nothing to overlap),
     // the whole diff and the capacity check come before any write.
     const uint64_t worst = data_off + (G << ps) + round_up(4 * G, 8);
-    bool eager = c->eager && capacity >= worst && G > 0;
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     DeviceGuard g(c->device);
+    // Small images may be built straight in the pinned host image (the pack
+    // and header kernels write it over the host link): no staging, no drain
+    // copy, and the host never waits on a dirty count.  Only for host memory
+    // that the device maps at the same address.
+    bool direct = false;
+    if (himg_ok_for_direct(c, h_image, worst)) {
+        hipPointerAttribute_t a{};
+        direct = hipPointerGetAttributes(&a, h_image) == hipSuccess &&
+                 a.type == hipMemoryTypeHost && a.devicePointer == h_image;
+        (void)hipGetLastError();
+    }
+    bool eager = !direct && c->eager && capacity >= worst && G > 0;
 
     // ---- chunk plan (page ranges aligned to bitmap words)
     std::vector<uint64_t> cuts{0};
@@ -573,6 +594,44 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     CRUM_TRY(hipStreamWaitEvent(stream, c->ev_done, 0));
     CRUM_TRY(hipMemcpyAsync(S, P, L.upload_end, hipMemcpyHostToDevice, stream));
     CRUM_TRY(hipEventRecord(c->ev_upload, stream));
+
+    if (direct) {
+        // ---- direct order: diff, scan (with the capacity check), list, then
+        // pack and header into the host image; slot counts stay on the device
+        {
+            Span sp(c, kTDiff, stream);
+            CRUM_TRY(launch_diff(d_regs, n_regions, 0, n_units, d_flags, c->shape.diff_blocks,
+                                 c->diff_nt, c->diff_prio, stream));
+        }
+        {
+            Span sp(c, kTScan, stream);
+            CRUM_TRY(launch_bitmap(d_regs, n_regions, 0, W, d_flags, d_bitmap, stream));
+            CRUM_TRY(launch_scan(d_bitmap, 0, W, W, d_prefix, d_bounds, 1, d_reqs, 0, 1, d_out,
+                                 d_glob, capacity, 0, stream));
+            CRUM_TRY(launch_list(d_bitmap, d_prefix, 0, W, d_list, stream));
+        }
+        {
+            Span sp(c, kTPack, stream);
+            SlotRange sr{0, 0, d_bounds, 0, G};
+            CRUM_TRY(launch_pack(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
+                                 np_shift, pc_shift, d_flags, himg, d_crcs, d_partials,
+                                 c->d_tabs, d_glob, c->shape.pack_blocks, c->pack_depth,
+                                 c->crc_variant, stream));
+            CRUM_TRY(launch_finalize(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
+                                     np_shift, pc_shift, d_partials, d_crcs, himg, d_glob,
+                                     c->d_tabs, stream));
+        }
+        {
+            Span sp(c, kTHeader, stream);
+            CRUM_TRY(launch_header(d_regs, d_reqs, 0, 1, d_out, d_bitmap, d_crcs, himg, capacity,
+                                   c->d_tabs, stream));
+        }
+        CRUM_TRY(hipMemcpyAsync(h_status, d_out, sizeof(crum_status), hipMemcpyDeviceToHost,
+                                stream));
+        CRUM_TRY(hipEventRecord(c->ev_done, stream));
+        c->partial_call = false;
+        return CRUM_OK;
+    }
 
     uint64_t D = 0, image_bytes = 0;
     if (eager) {

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.gpu_util import gpu_snapshot, log, to_dev, upload
+from tests.gpu_util import gpu_snapshot, image_capacity, log, to_dev, upload
 
 pytestmark = pytest.mark.gpu
 
@@ -20,6 +20,9 @@ def snap():
     crum.lib()  # the HIP library must be present; no fallback exists
     from paper_1808_00117_amd.api import Snapshotter
     s = Snapshotter(0)
+    # the staging orders (pipelined and diff-first); the direct order that
+    # small images take by default has its own context below
+    crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_DIRECT_BYTES, 0)
     yield s
     s.close()
 
@@ -30,9 +33,21 @@ def snap_small_chunks():
     import paper_1808_00117_amd as crum
     from paper_1808_00117_amd.api import Snapshotter
     s = Snapshotter(0)
+    crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_DIRECT_BYTES, 0)
     crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_CHUNK_BYTES, 1)
     crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_CHUNK_MAX_BYTES, 1)
     crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_DRAIN_CHUNK_BYTES, 1)
+    yield s
+    s.close()
+
+
+@pytest.fixture(scope="module")
+def snap_direct():
+    """A context that builds every image straight in the pinned host image."""
+    import paper_1808_00117_amd as crum
+    from paper_1808_00117_amd.api import Snapshotter
+    s = Snapshotter(0)
+    crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_DIRECT_BYTES, 1 << 40)
     yield s
     s.close()
 
@@ -94,14 +109,58 @@ CASES = [
 
 
 @pytest.mark.parametrize("name,counts,P,dirty,nulls", CASES, ids=[c[0] for c in CASES])
-def test_snapshot_parity_edges(snap, snap_small_chunks, name, counts, P, dirty, nulls):
+def test_snapshot_parity_edges(snap, snap_small_chunks, snap_direct, name, counts, P, dirty,
+                               nulls):
     G = sum(counts)
     if dirty == "all":
         dirty = set(range(G))
     log(f"[parity] {name} counts={counts} P={P} dirty={len(dirty)}")
     for where in ("first", "last", "random"):
         regs = host_case(counts, P, dirty, seed=G + P, null_shadow=nulls, where=where)
-        check_parity(snap, regs, P, others=(snap_small_chunks,))
+        check_parity(snap, regs, P, others=(snap_small_chunks, snap_direct))
+
+
+def test_direct_order_writes_only_the_host_image(snap_direct):
+    """The direct order builds the image in pinned host memory: it equals the
+    oracle's, and the device staging buffer is left as it was."""
+    import torch
+    P = 4 * KiB
+    host = host_case((30, 50), P, set(range(0, 80, 4)), seed=91)
+    st_o, img_o, _ = oracle.snapshot(host, P, seq=5)
+    dev = upload(host)
+    cap = image_capacity(dev, P)
+    staging = torch.full((cap,), 0x5C, dtype=torch.uint8, device="cuda")
+    h = torch.empty(cap, dtype=torch.uint8, pin_memory=True)
+    rc, st = snap_direct.snapshot(dev, P, staging, h, seq=5)
+    assert rc == 0 and st.code == 0 and st.image_bytes == st_o.image_bytes
+    assert np.array_equal(h[: st.image_bytes].numpy(), img_o)
+    assert bool((staging == 0x5C).all())
+
+
+def test_direct_order_enospc_and_shadow_update(snap_direct):
+    import torch
+    P = 4 * KiB
+    host = host_case((32,), P, set(range(10)), seed=93)
+    dev = upload(host)
+    need = oracle.snapshot(host, P)[0].image_bytes
+    staging = torch.empty(need, dtype=torch.uint8, device="cuda")
+    h = torch.full((need,), 0xA5, dtype=torch.uint8, pin_memory=True)
+    sh_before = dev[0][1].clone()
+    # one page short: ENOSPC, only the prefix is written, the shadow is kept
+    rc, st = snap_direct.snapshot(dev, P, staging, h[: need - P], flags=1)
+    assert rc == 0 and st.code == -2 and st.n_dirty == 10 and st.image_bytes == need
+    assert torch.equal(dev[0][1], sh_before)
+    data_off = oracle.prefix_bytes(1, 32)
+    assert bool((h[data_off:] == 0xA5).all())
+    # the prefix holds the valid bitmap of the ten dirty pages
+    bm = h[64 + 32:64 + 32 + 8].numpy().view(np.uint64)[0]
+    assert int(bm) == (1 << 10) - 1
+    # room for the image: OK, the shadow takes the dirty pages, then nothing is dirty
+    rc, st = snap_direct.snapshot(dev, P, staging, h, flags=1)
+    assert rc == 0 and st.code == 0 and st.n_dirty == 10
+    assert torch.equal(dev[0][0], dev[0][1])
+    rc, st = snap_direct.snapshot(dev, P, staging, h)
+    assert rc == 0 and st.code == 0 and st.n_dirty == 0
 
 
 def test_snapshot_parity_random_sets(snap, snap_small_chunks):
