@@ -384,7 +384,9 @@ int crum_ctx_timing_reset(crum_ctx* ctx);
  * image page of the window is fetched: its packed bytes are copied from
  * h_image into d_staging (at their image offsets), CRC-checked with
  * CRUM_VERIFY, and written to the page (and its shadow with
- * CRUM_UPDATE_SHADOW), in runs of consecutive packed pages, one copy per run.
+ * CRUM_UPDATE_SHADOW), in runs of consecutive packed pages, one copy per run
+ * (runs of up to 2 MiB are read in place from h_image when the device maps
+ * it at the same address, as hipHostMalloc memory is).
  *
  * Verification is per fetched run: a run that fails is not written, and
  * neither is anything fetched after it; pages written before stay written.
@@ -399,7 +401,7 @@ typedef struct {
     uint64_t pages_total;   /* D: packed pages in the image */
     uint64_t pages_fetched; /* pages whose fetch has been enqueued */
     uint64_t faults;        /* touches that found an absent page */
-    uint64_t copies;        /* host-to-device copies (runs) enqueued */
+    uint64_t copies;        /* runs of packed pages fetched (copied, or read in place) */
     uint64_t bytes_fetched; /* packed-page bytes copied */
 } crum_lazy_info;
 

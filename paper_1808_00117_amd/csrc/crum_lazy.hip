@@ -13,7 +13,9 @@
 // image pages of the window are fetched in runs of consecutive slots: one
 // host-to-device copy of the run's packed pages into the staging buffer (at
 // their offsets in the image layout), the CRC check of the run (with
-// CRUM_VERIFY) and the scatter of the run into the regions.
+// CRUM_VERIFY) and the scatter of the run into the regions.  Runs of up to
+// 2 MiB skip the copy: when the host image is device-mapped pinned memory,
+// their check and scatter read the packed pages from it in place.
 //
 // Open uploads only the image prefix (header, table, bitmap) and the CRC
 // array, checks them on the device as a full restore does and builds the
@@ -61,6 +63,7 @@ struct crum_lazy {
            o_partials = 0, o_crcs = 0, upload_end = 0;
     uint8_t* h_up = nullptr;  // pinned upload of the tables
     bool borrowed = false;    // d_mem and h_up are the context's lazy scratch
+    bool host_mapped = false; // the device maps h_image at the same address
     hipStream_t copy = nullptr;  // the context's side stream
     hipEvent_t ev_done = nullptr;    // the last call's work on the caller's stream
     hipStream_t done_stream = nullptr;  // the stream ev_done was last recorded on
@@ -129,8 +132,14 @@ uint32_t run_piece_shift(const crum_lazy* z, uint64_t n)
     return pcs;
 }
 
-// Checks and scatter of slots [k0, k1), whose packed pages are in staging.
-hipError_t run_kernels(crum_lazy* z, uint64_t k0, uint64_t k1, hipStream_t s)
+// Runs of at most this many packed bytes are checked and scattered straight
+// from the pinned host image (the kernels read it over the host link): a
+// copy to staging and the wait for it cost more than the transfer itself.
+constexpr uint64_t kInPlaceRunBytes = 2ull << 20;
+
+// Checks and scatter of slots [k0, k1), whose packed pages are at their
+// image offsets from `src` (the staging buffer, or the host image itself).
+hipError_t run_kernels(crum_lazy* z, uint64_t k0, uint64_t k1, uint8_t* src, hipStream_t s)
 {
     const uint32_t ps = z->info.ps;
     const uint64_t n = k1 - k0;
@@ -149,25 +158,25 @@ hipError_t run_kernels(crum_lazy* z, uint64_t k0, uint64_t k1, hipStream_t s)
     if (z->flags & CRUM_VERIFY) {
         const SlotRange sr{k0, k1, nullptr, 0, n};
         e = launch_pack(kModeVerify, regs, nr, req, out, list, sr, nps, pcs,
-                        nullptr, z->staging, crcs, partials, ctx_tables(z->ctx), glob,
+                        nullptr, src, crcs, partials, ctx_tables(z->ctx), glob,
                         z->pack_blocks, z->depth, z->variant, s);
         if (e != hipSuccess)
             return e;
         e = launch_finalize(kModeVerify, regs, nr, req, out, list, sr, nps, pcs,
-                            partials, crcs, z->staging, glob, ctx_tables(z->ctx), s);
+                            partials, crcs, src, glob, ctx_tables(z->ctx), s);
         if (e != hipSuccess)
             return e;
     }
     // the scatter numbers slots from the list pointer and finds a slot's
-    // packed page from the staging pointer, so both start at slot k0
-    return launch_scatter(regs, nr, req, out, list + k0, n, nps, pcs,
-                          z->staging + (k0 << ps), (z->flags & CRUM_UPDATE_SHADOW) ? 1 : 0, glob,
-                          z->pack_blocks, s);
+    // packed page from the source pointer, so both start at slot k0
+    return launch_scatter(regs, nr, req, out, list + k0, n, nps, pcs, src + (k0 << ps),
+                          (z->flags & CRUM_UPDATE_SHADOW) ? 1 : 0, glob, z->pack_blocks, s);
 }
 
-// Fetch every absent image page of global pages [g0, g1): the runs' copies
-// on the copy stream, then on `s` a wait for them and each run's kernels.
-// Returns the pages enqueued in *pages and the runs in *runs.
+// Fetch every absent image page of global pages [g0, g1): the copies of the
+// runs that are not read in place on the copy stream, then on `s` a wait for
+// them and each run's kernels.  Returns the pages enqueued in *pages and the
+// runs in *runs.
 hipError_t fetch_window(crum_lazy* z, uint64_t g0, uint64_t g1, hipStream_t s, uint64_t* pages,
                         uint64_t* runs)
 {
@@ -198,21 +207,31 @@ hipError_t fetch_window(crum_lazy* z, uint64_t g0, uint64_t g1, hipStream_t s, u
     if (rs.empty())
         return hipSuccess;
     const ImageInfo& I = z->info;
+    uint8_t* host = const_cast<uint8_t*>(z->h_image);  // read only
+    auto in_place = [&](const std::pair<uint64_t, uint64_t>& r) {
+        return z->host_mapped && ((r.second - r.first) << I.ps) <= kInPlaceRunBytes;
+    };
+    bool copied = false;
+    hipError_t e = hipSuccess;
     for (const auto& r : rs) {
+        if (in_place(r))
+            continue;
         const uint64_t off = I.data_off + (r.first << I.ps);
-        hipError_t e = hipMemcpyAsync(z->staging + off, z->h_image + off,
-                                      (r.second - r.first) << I.ps, hipMemcpyHostToDevice,
-                                      z->copy);
+        e = hipMemcpyAsync(z->staging + off, z->h_image + off, (r.second - r.first) << I.ps,
+                           hipMemcpyHostToDevice, z->copy);
+        if (e != hipSuccess)
+            return e;
+        copied = true;
+    }
+    if (copied) {
+        e = hipEventRecord(z->ev_copied, z->copy);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(s, z->ev_copied, 0);
         if (e != hipSuccess)
             return e;
     }
-    hipError_t e = hipEventRecord(z->ev_copied, z->copy);
-    if (e == hipSuccess)
-        e = hipStreamWaitEvent(s, z->ev_copied, 0);
-    if (e != hipSuccess)
-        return e;
     for (const auto& r : rs) {
-        e = run_kernels(z, r.first, r.second, s);
+        e = run_kernels(z, r.first, r.second, in_place(r) ? host : z->staging, s);
         if (e != hipSuccess)
             return e;
     }
@@ -306,6 +325,12 @@ int crum_lazy_open(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     z->info = I;
     z->h_image = h;
     z->image_bytes = image_bytes;
+    {
+        hipPointerAttribute_t a{};
+        z->host_mapped = hipPointerGetAttributes(&a, h_image) == hipSuccess &&
+                         a.type == hipMemoryTypeHost && a.devicePointer == h_image;
+        (void)hipGetLastError();
+    }
     z->staging = static_cast<uint8_t*>(d_staging);
     z->flags = flags;
     z->small_bytes = small_bytes;
