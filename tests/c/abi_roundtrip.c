@@ -1,8 +1,9 @@
 /* A C99 client of the library's C ABI: no Python, no torch.  Two regions
- * (one with a shadow, one without), a snapshot with the image drained to
- * pinned memory, a verified restore into fresh buffers holding the shadow's
- * bytes, then a snapshot with shadow update and one more that must find
- * nothing dirty.  Prints one line and exits 0 when every check holds. */
+ * (one with a shadow, one without), a snapshot with the image in pinned
+ * memory, a verified restore into fresh buffers holding the shadow's bytes,
+ * an on-demand restore of the same image (one touch, then finish), then a
+ * snapshot with shadow update and one more that must find nothing dirty.
+ * Prints one line and exits 0 when every check holds. */
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -109,6 +110,40 @@ int main(void)
     rc = crum_restore(ctx, targets, 2, h_image, image_bytes, CRUM_VERIFY, staging, cap, s, st);
     if (rc != CRUM_EMISMATCH || st->code != CRUM_EMISMATCH)
         return fail("restore with a wrong id", rc);
+
+    /* on-demand restore of the same image into buffers holding old bytes:
+     * one touch of region 0's page 3 (dirty) fetches exactly that page, then
+     * finish fetches the rest */
+    targets[1].id = 72;
+    HIPOK(hipMemcpy(t0, h_sh0, b0, hipMemcpyHostToDevice));
+    HIPOK(hipMemset(t1, 0xee, b1));
+    crum_lazy* lz = NULL;
+    rc = crum_lazy_open(ctx, targets, 2, h_image, image_bytes, CRUM_VERIFY, 0, staging, cap, s,
+                        st, &lz);
+    if (rc != CRUM_OK)
+        return fail("crum_lazy_open", rc);
+    uint64_t fetched = 0;
+    rc = crum_lazy_touch(lz, 0, 3u * PAGE + 5u, 1, s, st, &fetched);
+    HIPOK(hipStreamSynchronize(s));
+    if (rc != CRUM_OK || st->code != CRUM_OK || fetched != 1)
+        return fail("crum_lazy_touch", (long)fetched);
+    HIPOK(hipMemcpy(h_back, t0, b0, hipMemcpyDeviceToHost));
+    if (memcmp(h_back + 3u * PAGE, h_cur0 + 3u * PAGE, PAGE) != 0 ||
+        memcmp(h_back + 6u * PAGE, h_sh0 + 6u * PAGE, PAGE) != 0)
+        return fail("page 3 fetched alone", 0);
+    rc = crum_lazy_finish(lz, s, st);
+    HIPOK(hipStreamSynchronize(s));
+    crum_lazy_info info;
+    if (rc != CRUM_OK || st->code != CRUM_OK || crum_lazy_stats(lz, &info) != CRUM_OK ||
+        info.pages_fetched != n_changed + N1 || info.faults != 1)
+        return fail("crum_lazy_finish", rc);
+    crum_lazy_close(lz);
+    HIPOK(hipMemcpy(h_back, t0, b0, hipMemcpyDeviceToHost));
+    if (memcmp(h_back, h_cur0, b0) != 0)
+        return fail("region 0 after the on-demand restore", 0);
+    HIPOK(hipMemcpy(h_back, t1, b1, hipMemcpyDeviceToHost));
+    if (memcmp(h_back, h_cur1, b1) != 0)
+        return fail("region 1 after the on-demand restore", 0);
 
     /* shadow update, then nothing is dirty */
     rc = crum_snapshot(ctx, regs, 1, PAGE, CRUM_UPDATE_SHADOW, 10, staging, cap, h_image, cap, s,

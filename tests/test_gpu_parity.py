@@ -163,7 +163,7 @@ def test_direct_order_enospc_and_shadow_update(snap_direct):
     assert rc == 0 and st.code == 0 and st.n_dirty == 0
 
 
-def test_snapshot_parity_random_sets(snap, snap_small_chunks):
+def test_snapshot_parity_random_sets(snap, snap_small_chunks, snap_direct):
     rng = np.random.default_rng(77)
     for trial in range(6):
         counts = tuple(int(x) for x in rng.integers(0, 200, int(rng.integers(1, 8))))
@@ -173,7 +173,7 @@ def test_snapshot_parity_random_sets(snap, snap_small_chunks):
                                                replace=False)) if G else set()
         log(f"[parity] random trial={trial} counts={counts} P={P} D={len(dirty)}")
         check_parity(snap, host_case(counts, P, dirty, seed=trial), P, seq=trial,
-                     others=(snap_small_chunks,))
+                     others=(snap_small_chunks, snap_direct))
 
 
 def test_many_regions(snap):
