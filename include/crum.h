@@ -393,7 +393,8 @@ int crum_ctx_timing_reset(crum_ctx* ctx);
  * The session then reports CRUM_ECRC (first_bad: lowest failing slot) for
  * every later call.  A session whose image failed the device-side checks of
  * open reports CRUM_EFORMAT for every call and writes nothing.  After a call
- * returns CRUM_EHIP the session is unusable; close it.
+ * returns CRUM_EHIP the session is unusable; close it.  Like a context, a
+ * session is not thread-safe: calls on one session must not overlap.
  * -------------------------------------------------------------------------*/
 typedef struct crum_lazy crum_lazy;
 

@@ -52,6 +52,40 @@ def test_size_helpers_reject_bad_arguments():
         crum.crum_image_bytes(1, 10, 1, 1000)
 
 
+def test_null_handles_are_rejected_without_a_gpu():
+    """Entry points given no context, session, plan, server or writer return
+    CRUM_EINVAL before any HIP call (so this runs on the CPU) and the
+    destroy/close calls ignore NULL."""
+    import ctypes
+
+    import paper_1808_00117_amd as crum
+    lib = crum.lib()
+    E = crum.CRUM_EINVAL
+    out = ctypes.c_void_p(123)
+    st = (ctypes.c_uint8 * 64)()
+    assert lib.crum_lazy_open(None, None, 0, None, 0, 0, 0, None, 0, None, st,
+                              ctypes.byref(out)) == E
+    assert out.value is None  # *out cleared
+    assert lib.crum_lazy_open(None, None, 0, None, 0, 0, 0, None, 0, None, None, None) == E
+    n = ctypes.c_uint64(7)
+    assert lib.crum_lazy_touch(None, 0, 0, 1, None, None, ctypes.byref(n)) == E
+    assert n.value == 0
+    assert lib.crum_lazy_finish(None, None, st) == E
+    info = crum.crum_lazy_info()
+    assert lib.crum_lazy_stats(None, ctypes.byref(info)) == E
+    assert lib.crum_lazy_fetched(None, None, 0) == E
+    lib.crum_lazy_close(None)
+    assert lib.crum_snapshot(None, None, 0, 4096, 0, 0, None, 0, None, 0, None, st) == E
+    assert lib.crum_restore(None, None, 0, None, 0, 0, None, 0, None, st) == E
+    assert lib.crum_ctx_set_param(None, crum.CRUM_PARAM_DIRECT_BYTES, 0) == E
+    v = ctypes.c_uint64()
+    assert lib.crum_ctx_get_param(None, crum.CRUM_PARAM_DIRECT_BYTES, ctypes.byref(v)) == E
+    lib.crum_ctx_destroy(None)
+    lib.crum_plan_destroy(None)
+    lib.crum_server_destroy(None)
+    lib.crum_writer_destroy(None)
+
+
 def test_product_package_does_not_import_the_oracle():
     pkg = os.path.join(ROOT, "paper_1808_00117_amd")
     for dirpath, _, files in os.walk(pkg):
