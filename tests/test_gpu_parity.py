@@ -352,6 +352,20 @@ def test_invalid_arguments_are_synchronous(snap):
     assert rc == crum.CRUM_EINVAL
     rc = snap.snapshot(ok, P, staging, h, flags=0x80, sync=False)
     assert rc == crum.CRUM_EINVAL
+    # more pages than the image numbers (over 0xFFFFFF00): two 8 TiB region
+    # descriptors, refused on the host before any of their memory is touched
+    big = 8 << 40
+    fake = [(1 << 46, 0, big, 1), ((1 << 46) + big, 0, big, 2)]
+    assert snap.snapshot(fake, P, staging, h, sync=False) == crum.CRUM_EINVAL
+    # one page short of the limit passes the count check but not the capacity
+    # check of the staging buffer, still before anything is enqueued
+    n_max = 0xFFFFFF00
+    fake = [(1 << 46, 0, n_max * P, 1)]
+    assert snap.snapshot(fake, P, staging, h, sync=False) == crum.CRUM_EINVAL
+    # page sizes outside [4 KiB, 1 GiB] or not a power of two
+    for pg in (1 << 31, 2048, 3 * 4096):
+        assert snap.snapshot([(cur.data_ptr(), sh.data_ptr(), 0, 1)], pg, staging, h,
+                             sync=False) == crum.CRUM_EINVAL
 
 
 def test_empty_table(snap):
