@@ -30,6 +30,11 @@ def _ptr(t) -> int:
         return 0
     if isinstance(t, int):
         return t
+    if t.numel() == 0:
+        # torch reports address 0 for any empty tensor; an empty view still
+        # names a buffer, and a shadow given for a zero-length region must
+        # stay a shadow (None is the way to say "no shadow")
+        return t.untyped_storage().data_ptr() + t.storage_offset() * t.element_size()
     return t.data_ptr()
 
 
