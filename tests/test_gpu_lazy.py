@@ -350,3 +350,57 @@ def test_touch_orders_other_streams(env):
     other.synchronize()
     assert np.array_equal(out.cpu().numpy(), regs[0][0])
     s.lz.close()
+
+
+def test_property_sessions(env):
+    """Drawn sessions (0-5 regions of 0-60 pages, 4-64 KiB pages, dirty
+    density, small-region size, with or without verification and shadow
+    update, 0-25 touches of drawn ranges): after every touch the fetched
+    pages equal the model's, and after finish the regions (and shadows)
+    equal the oracle's restore.  Derandomized."""
+    from hypothesis import HealthCheck, given, settings
+    from hypothesis import strategies as st
+    crum, ctx, status = env
+
+    @settings(max_examples=20, deadline=None, derandomize=True,
+              suppress_health_check=list(HealthCheck))
+    @given(counts=st.lists(st.integers(0, 60), min_size=0, max_size=5),
+           pshift=st.sampled_from([12, 14, 16]),
+           density=st.sampled_from([0.0, 0.1, 0.5, 1.0]),
+           small_pages=st.sampled_from([0, 1, 4, 1000]),
+           flags=st.sampled_from([0, 2, 3]),
+           seed=st.integers(0, 2**31 - 1),
+           touches=st.lists(st.tuples(st.integers(0, 4), st.floats(0, 1), st.floats(0, 1)),
+                            max_size=25))
+    def run(counts, pshift, density, small_pages, flags, seed, touches):
+        P = 1 << pshift
+        regs, img = make_case(tuple(counts), P, density, seed)
+        G = sum(counts)
+        small = small_pages * P
+        s = Session(crum, ctx, status, regs, img, P, flags, small, shadows=bool(flags & 1))
+        assert s.st().code == 0
+        model = LazyModel([n * P for n in counts], P, image_pages(img, len(counts), G), small)
+        for r, a, b in touches:
+            if not counts or counts[r % len(counts)] == 0:
+                continue
+            r %= len(counts)
+            size = counts[r] * P
+            off = min(int(a * size), size - 1)
+            ln = max(1, min(int(b * 3 * P), size - off))
+            assert s.touch(r, off, ln) == model.touch(r, off, ln)
+            assert s.lz.fetched((G + 63) // 64) == model.fetched_bitmap(G)
+        s.finish()
+        assert s.st().code == 0
+        model.finish()
+        check_state(s, model, G)
+        if flags & 1:
+            g = 0
+            for i, (new, _, _) in enumerate(regs):
+                sh = s.shadows[i].cpu().numpy()
+                for p in range(counts[i]):
+                    want = new[p * P:(p + 1) * P] if g + p in model.fetched else 0
+                    assert np.all(sh[p * P:(p + 1) * P] == want)
+                g += counts[i]
+        s.lz.close()
+
+    run()

@@ -598,3 +598,45 @@ def test_snapshot_orders_after_stream_work(snap):
     st_o, img_o, _ = oracle.snapshot([(expect_cur, host[0][1], host[0][2])], P, seq=5)
     assert st.code == 0 and st.n_dirty == len(rewritten) == st_o.n_dirty
     assert np.array_equal(h[:st.image_bytes].numpy(), img_o)
+
+
+def test_restore_parity_property(snap):
+    """Drawn images restored with and without verification and shadow update
+    into buffers holding their old bytes: the regions (and shadows) equal the
+    oracle's restore of the same image, byte for byte.  Derandomized."""
+    import torch
+    from hypothesis import HealthCheck, given, settings
+    from hypothesis import strategies as st
+
+    @settings(max_examples=20, deadline=None, derandomize=True,
+              suppress_health_check=list(HealthCheck))
+    @given(counts=st.lists(st.integers(0, 100), min_size=0, max_size=5),
+           pshift=st.sampled_from([12, 13, 16, 18]),
+           density=st.sampled_from([0.0, 0.05, 0.5, 1.0]),
+           flags=st.sampled_from([0, 1, 2, 3]),
+           seed=st.integers(0, 2**31 - 1))
+    def run(counts, pshift, density, flags, seed):
+        P = 1 << pshift
+        rng = np.random.default_rng(seed)
+        G = sum(counts)
+        dirty = {g for g in range(G) if rng.random() < density}
+        host = host_case(tuple(counts), P, dirty, seed=seed)
+        st_o, img, _ = oracle.snapshot(host, P, seq=seed & 0xFF)
+        assert st_o.code == oracle.OK
+        # restore targets start from the old bytes (the shadows), with fresh shadows
+        tgt_host = [(sh.copy(), np.zeros_like(sh), rid) for _, sh, rid in host]
+        res = oracle.restore([(c, s if flags & 1 else None, rid) for c, s, rid in tgt_host],
+                             img, flags)
+        assert res.code == oracle.OK
+        dev = upload([(sh, None, rid) for _, sh, rid in host])
+        dev = [(c, torch.zeros_like(c) if flags & 1 else None, rid) for c, _, rid in dev]
+        staging = torch.empty(max(img.size, 16), dtype=torch.uint8, device="cuda")
+        rc, st = snap.restore(dev, torch.from_numpy(img).pin_memory(), img.size, staging,
+                              flags=flags)
+        assert rc == 0 and st.code == 0, st
+        for (c, s, _), (hc, hs, _) in zip(dev, tgt_host):
+            assert np.array_equal(c.cpu().numpy(), hc)
+            if flags & 1:
+                assert np.array_equal(s.cpu().numpy(), hs)
+
+    run()
