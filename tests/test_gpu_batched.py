@@ -299,3 +299,35 @@ def test_smallest_first_order(ctx):
         crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_PLAN_ORDER, 0)
         crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_CHUNK_BYTES, saved[0])
         crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_CHUNK_MAX_BYTES, saved[1])
+
+
+def test_batched_property(ctx):
+    """Drawn request sets (0-10 requests of 0-4 regions, page sizes, one or
+    many groups, caller's or smallest-first order): every request's image is
+    the oracle's, byte for byte, at a 4 KiB-aligned offset.  Derandomized."""
+    import paper_1808_00117_amd as crum
+    from hypothesis import HealthCheck, given, settings
+    from hypothesis import strategies as st
+
+    @settings(max_examples=15, deadline=None, derandomize=True,
+              suppress_health_check=list(HealthCheck))
+    @given(seed=st.integers(0, 2**31 - 1), n=st.integers(0, 10),
+           max_regions=st.integers(0, 4),
+           sizes=st.sampled_from([(4 * KiB,), (64 * KiB,), (4 * KiB, 16 * KiB, 64 * KiB)]),
+           small_groups=st.booleans(), order=st.sampled_from([0, 1]))
+    def run(seed, n, max_regions, sizes, small_groups, order):
+        host = make_requests(seed, n, max_regions=max_regions, page_sizes=sizes)
+        crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_PLAN_ORDER, order)
+        try:
+            _, results, _ = run_plan(ctx, host, small_groups=small_groups)
+        finally:
+            crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_PLAN_ORDER, 0)
+        sts, imgs = results[0]
+        for q, ((code, _, D, G, ib, off), img) in enumerate(zip(sts, imgs)):
+            regs, P, seq = host[q]
+            st_o, img_o, _ = oracle.snapshot(regs, P, seq=seq)
+            assert code == 0 and off % 4096 == 0 and (D, G, ib) == \
+                (st_o.n_dirty, st_o.total_pages, st_o.image_bytes), q
+            assert np.array_equal(img, img_o), f"request {q} differs from the oracle"
+
+    run()
