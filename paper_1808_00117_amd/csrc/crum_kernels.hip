@@ -948,9 +948,9 @@ __device__ __forceinline__ uint32_t xpow8n_wave(uint64_t n, const uint32_t* __re
 // "shift by 4096 bytes" step, the wave butterfly combines lanes and each wave
 // is shifted by the 1 KiB stripes that follow it.  lds: slicing tables and
 // all seven shift levels.  All threads return the value.
-__device__ uint32_t wg_crc(const uint8_t* __restrict__ p, uint64_t n, uint64_t zero_off,
-                           const uint32_t* __restrict__ lds, const uint32_t* __restrict__ xp,
-                           uint32_t* red)
+__device__ __forceinline__ uint32_t wg_crc(const uint8_t* __restrict__ p, uint64_t n,
+                                          uint64_t zero_off, const uint32_t* __restrict__ lds,
+                                          const uint32_t* __restrict__ xp, uint32_t* red)
 {
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u;
@@ -959,6 +959,8 @@ __device__ uint32_t wg_crc(const uint8_t* __restrict__ p, uint64_t n, uint64_t z
     const uint32_t* Z4096 = lds + kSliceWords + 6 * 1024;
     const uint64_t steps = (n + 4095) / 4096;
     const int64_t pad = (int64_t)(steps * 4096 - n);
+    typedef const uint32_t __attribute__((address_space(1)))* gcu32;
+    const gcu32 g = (gcu32)p;
     // thread tid's 16 bytes of 4 KiB step j, the step's zero padding (and
     // the word at zero_off) read as zero
     auto load_step = [&](uint64_t j) {
@@ -967,14 +969,12 @@ __device__ uint32_t wg_crc(const uint8_t* __restrict__ p, uint64_t n, uint64_t z
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int64_t r = v + 4 * i;
-            w[i] = (r >= 0 && (uint64_t)r != zero_off)
-                       ? *reinterpret_cast<const uint32_t*>(p + r)
-                       : 0u;
+            w[i] = (r >= 0 && (uint64_t)r != zero_off) ? g[r >> 2] : 0u;
         }
         return make_uint4(w[0], w[1], w[2], w[3]);
     };
-    // four steps' loads in flight before they are folded, in step order
-    constexpr int U = 4;
+    // eight steps' loads in flight before they are folded, in step order
+    constexpr int U = 8;
     uint32_t s = 0;
     uint64_t j = 0;
     for (; j + U <= steps; j += U) {
@@ -1002,12 +1002,12 @@ __device__ uint32_t wg_crc(const uint8_t* __restrict__ p, uint64_t n, uint64_t z
 
 // ------------------------------------------------------------ k_header
 
-// dst[i] = src[i] for i < n by one workgroup, 8 loads in flight per thread.
+// dst[i] = src[i] for i < n by one workgroup, 16 loads in flight per thread.
 template <typename T>
 __device__ __forceinline__ void copy_words(T* __restrict__ dst, const T* __restrict__ src,
                                            uint64_t n)
 {
-    constexpr uint32_t U = 8;
+    constexpr uint32_t U = 16;
     const uint64_t stride = (uint64_t)blockDim.x * U;
     uint64_t i = threadIdx.x;
     for (; i + (U - 1) * blockDim.x < n; i += stride) {
