@@ -578,6 +578,7 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     const DevRequest* d_reqs = reinterpret_cast<const DevRequest*>(S + L.reqs);
     DevReqOut* d_out = reinterpret_cast<DevReqOut*>(S + L.out);
     DevGlobal* d_glob = reinterpret_cast<DevGlobal*>(S + L.glob);
+    const uint32_t hdr_blocks = header_blocks(n_regions, W, G);
     uint8_t* d_flags = S + L.flags;
     uint64_t* d_bitmap = reinterpret_cast<uint64_t*>(S + L.bitmap);
     uint32_t* d_prefix = reinterpret_cast<uint32_t*>(S + L.prefix);
@@ -623,8 +624,8 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
         }
         {
             Span sp(c, kTHeader, stream);
-            CRUM_TRY(launch_header(d_regs, d_reqs, 0, 1, d_out, d_bitmap, d_crcs, himg, capacity,
-                                   c->d_tabs, stream));
+            CRUM_TRY(launch_header(d_regs, d_reqs, 0, 1, hdr_blocks, d_out, d_bitmap, d_crcs,
+                                   himg, capacity, c->d_tabs, stream));
         }
         CRUM_TRY(hipMemcpyAsync(h_status, d_out, sizeof(crum_status), hipMemcpyDeviceToHost,
                                 stream));
@@ -709,8 +710,8 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
         if (o.code != CRUM_OK) {
             // ENOSPC: header, table and bitmap only; nothing packed or drained
             Span sp(c, kTHeader, stream);
-            CRUM_TRY(launch_header(d_regs, d_reqs, 0, 1, d_out, d_bitmap, d_crcs, staging,
-                                   capacity, c->d_tabs, stream));
+            CRUM_TRY(launch_header(d_regs, d_reqs, 0, 1, hdr_blocks, d_out, d_bitmap, d_crcs,
+                                   staging, capacity, c->d_tabs, stream));
             sp.end();
             CRUM_TRY(hipMemcpyAsync(h_status, d_out, sizeof(crum_status), hipMemcpyDeviceToHost,
                                     stream));
@@ -761,8 +762,8 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     // ---- header (with the CRC array), then the prefix and tail of the drain
     {
         Span sp(c, kTHeader, stream);
-        CRUM_TRY(launch_header(d_regs, d_reqs, 0, 1, d_out, d_bitmap, d_crcs, staging, capacity,
-                               c->d_tabs, stream));
+        CRUM_TRY(launch_header(d_regs, d_reqs, 0, 1, hdr_blocks, d_out, d_bitmap, d_crcs,
+                               staging, capacity, c->d_tabs, stream));
     }
     if (himg) {
         CRUM_TRY(hipEventRecord(c->ev_hdr, stream));
@@ -888,7 +889,8 @@ int crum_restore(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
         CRUM_TRY(hipMemcpyAsync(staging, h_image, image_bytes, hipMemcpyHostToDevice, stream));
     {
         Span sp(c, kTScan, stream);
-        CRUM_TRY(launch_restore_check(d_reqs, 1, d_out, staging, c->d_tabs, d_glob, stream));
+        CRUM_TRY(launch_restore_check(d_reqs, 1, header_blocks(n_regions, W, D), d_out, staging,
+                                      c->d_tabs, d_glob, stream));
         CRUM_TRY(launch_scan(img_bitmap, 0, W, W, d_prefix, nullptr, 1, d_reqs, 0, 1, d_out,
                              d_glob, 0, 1, stream));
         CRUM_TRY(launch_list(img_bitmap, d_prefix, 0, W, d_list, stream));

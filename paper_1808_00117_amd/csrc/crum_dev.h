@@ -58,7 +58,10 @@ struct DevReqOut {
     uint64_t image_bytes;
     uint64_t slot_base;  // global slot of the request's first packed page
     uint64_t img_base;   // byte offset of the request's image in staging
-    uint64_t pad[2];
+    // header / image-check kernels: CRC shares of crcs_crc and meta_crc,
+    // arrivals, and a flag or count; zero before those kernels run (the final
+    // scan clears them for a snapshot, the host for a restore)
+    uint32_t acc[4];
 };
 static_assert(sizeof(DevReqOut) == 64, "DevReqOut layout");
 
@@ -146,20 +149,24 @@ hipError_t launch_finalize(int mode, const DevRegion* regs, uint32_t n_regs,
                            SlotRange range, uint32_t np_shift, uint32_t piece_shift,
                            const uint32_t* partials, uint32_t* crc_out, uint8_t* staging,
                            DevGlobal* glob, const CrcTables* tabs, hipStream_t s);
-// One workgroup per request of [q0, q1).  Requests with ENOSPC get only their
-// prefix (header, table, bitmap), and only when it fits within `capacity`.
+// Workgroups per request for launch_header and launch_restore_check, from
+// the request's region count, bitmap words and (a bound on) its CRC count.
+uint32_t header_blocks(uint64_t n_regions, uint64_t n_words, uint64_t n_crcs);
+// `blocks` workgroups per request of [q0, q1).  Requests with ENOSPC get only
+// their prefix (header, table, bitmap), and only when it fits within
+// `capacity`.
 hipError_t launch_header(const DevRegion* regs, const DevRequest* reqs, uint32_t q0, uint32_t q1,
-                         const DevReqOut* out, const uint64_t* bitmap, const uint32_t* crcs,
-                         uint8_t* staging, uint64_t capacity, const CrcTables* tabs,
-                         hipStream_t s);
+                         uint32_t blocks, DevReqOut* out, const uint64_t* bitmap,
+                         const uint32_t* crcs, uint8_t* staging, uint64_t capacity,
+                         const CrcTables* tabs, hipStream_t s);
 // Resets the launch-wide counters (graph-safe: a kernel, not a memset).
 hipError_t launch_plan_init(DevGlobal* glob, hipStream_t s);
 // Compact per-request results: {code, first_bad, n_dirty, total_pages,
 // image_bytes, image_offset} (40 bytes each) for requests [0, n).
 hipError_t launch_plan_status(const DevReqOut* out, uint32_t n, uint8_t* dst, hipStream_t s);
-hipError_t launch_restore_check(const DevRequest* reqs, uint32_t n_reqs, const DevReqOut* out,
-                                const uint8_t* staging, const CrcTables* tabs, DevGlobal* glob,
-                                hipStream_t s);
+hipError_t launch_restore_check(const DevRequest* reqs, uint32_t n_reqs, uint32_t blocks,
+                                DevReqOut* out, const uint8_t* staging, const CrcTables* tabs,
+                                DevGlobal* glob, hipStream_t s);
 hipError_t launch_scatter(const DevRegion* regs, uint32_t n_regs, const DevRequest* reqs,
                           const DevReqOut* out, const uint32_t* list, uint64_t n_slots,
                           uint32_t np_shift, uint32_t piece_shift, const uint8_t* staging,

@@ -46,6 +46,11 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // load and store in flight.  Casting keeps them global.
 typedef const u32x4 __attribute__((address_space(1)))* gcv4;
 typedef u32x4 __attribute__((address_space(1)))* gv4;
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef const u32x2 __attribute__((address_space(1)))* gcv2;
+typedef u32x2 __attribute__((address_space(1)))* gv2;
+typedef const uint32_t __attribute__((address_space(1)))* gcu32;
+typedef uint32_t __attribute__((address_space(1)))* gu32;
 
 // ------------------------------------------------------------ CRC tables
 
@@ -584,6 +589,7 @@ __global__ __launch_bounds__(1024) void k_scan(const uint64_t* __restrict__ bitm
         O.n_dirty = D;
         O.total_pages = Q.n_pages;
         O.slot_base = p0;
+        O.acc[0] = O.acc[1] = O.acc[2] = O.acc[3] = 0;
         if (!restore_mode) {
             const uint64_t ib = Q.data_off + (D << Q.page_shift) + ((4 * D + 7) & ~7ull);
             O.code = 0;
@@ -924,9 +930,6 @@ hipError_t launch_finalize(int mode, const DevRegion* regs, uint32_t n_regs,
 
 // ------------------------------------------------------------ block CRC
 
-// Standard CRC-32C of n bytes at p (p 16-byte aligned) computed by one
-// 256-thread workgroup; the 4 bytes at zero_off (a multiple of 4, or ~0) are
-// read as zero.  T is the slicing table in LDS.  All threads return it.
 // x^(8n) mod P from the table xp[i] = x^(8 * 2^i): the product of the
 // entries for the set bits of n, reduced across the wave.  Every lane returns
 // it; all lanes of the wave must call.
@@ -940,174 +943,345 @@ __device__ __forceinline__ uint32_t xpow8n_wave(uint64_t n, const uint32_t* __re
     return v;
 }
 
-// Standard CRC-32C of n bytes at p (p and n multiples of 4) by one
-// 256-thread workgroup; the 4 bytes at zero_off (a multiple of 4, or ~0) are
-// read as zero.  The message is taken as left-padded with zero bytes to a
-// multiple of 4096 (which leaves a zero-initialised CRC unchanged); thread t
-// reads 16-byte words t, t+256, ... and keeps a Horner accumulator with a
-// "shift by 4096 bytes" step, the wave butterfly combines lanes and each wave
-// is shifted by the 1 KiB stripes that follow it.  lds: slicing tables and
-// all seven shift levels.  All threads return the value.
-__device__ __forceinline__ uint32_t wg_crc(const uint8_t* __restrict__ p, uint64_t n,
-                                          uint64_t zero_off, const uint32_t* __restrict__ lds,
-                                          const uint32_t* __restrict__ xp, uint32_t* red)
+// x^(8 n_w) for one n per wave of a 256-thread workgroup, the four computed
+// in parallel, into pw[w]; the caller synchronises before reading them.
+__device__ __forceinline__ void wave_powers(uint64_t n0, uint64_t n1, uint64_t n2, uint64_t n3,
+                                            const uint32_t* __restrict__ xp, uint32_t* pw)
+{
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint64_t n = wave == 0 ? n0 : wave == 1 ? n1 : wave == 2 ? n2 : n3;
+    const uint32_t v = xpow8n_wave(n, xp, lane);
+    if (lane == 0)
+        pw[wave] = v;
+}
+
+// Standard CRC-32C of an n-byte message from its raw CRC (zero initial
+// value, no final inversion) and x^(8n): the all-ones initial value carried
+// through the n bytes, plus the final inversion.
+__device__ __forceinline__ uint32_t crc_from_raw(uint32_t raw, uint32_t x8n)
+{
+    return raw ^ gf2_mulmod(0xFFFFFFFFu, x8n) ^ 0xFFFFFFFFu;
+}
+
+// Raw CRC of the 4 KiB steps [j0, j1) of a message by one 256-thread
+// workgroup.  load(j) gives thread t's 16-byte word t of step j (the caller
+// left-pads the message with zero bytes to whole steps, which leaves a raw
+// CRC unchanged); use(j, w) is called on it in step order (a store of the
+// word, or nothing).  Thread t keeps a Horner accumulator with a "shift by
+// 4 KiB" step over its words, the wave butterfly combines lanes and each wave
+// is shifted by the 1 KiB stripes that follow it.  Eight steps' loads are in
+// flight before they are folded.  lds: slicing tables and all seven shift
+// levels.  Uniform over the workgroup; all threads return the value.
+template <typename Load, typename Use>
+__device__ __forceinline__ uint32_t wg_crc_steps(Load load, Use use, uint64_t j0, uint64_t j1,
+                                                 const uint32_t* __restrict__ lds, uint32_t* red)
 {
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u;
     const uint32_t wave = tid >> 6;
     const uint32_t* Z1024 = lds + kSliceWords + 5 * 1024;
     const uint32_t* Z4096 = lds + kSliceWords + 6 * 1024;
-    const uint64_t steps = (n + 4095) / 4096;
-    const int64_t pad = (int64_t)(steps * 4096 - n);
-    typedef const uint32_t __attribute__((address_space(1)))* gcu32;
-    const gcu32 g = (gcu32)p;
-    // thread tid's 16 bytes of 4 KiB step j, the step's zero padding (and
-    // the word at zero_off) read as zero
-    auto load_step = [&](uint64_t j) {
-        const int64_t v = (int64_t)((j * 256 + tid) * 16) - pad;
-        uint32_t w[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t r = v + 4 * i;
-            w[i] = (r >= 0 && (uint64_t)r != zero_off) ? g[r >> 2] : 0u;
-        }
-        return make_uint4(w[0], w[1], w[2], w[3]);
-    };
-    // eight steps' loads in flight before they are folded, in step order
     constexpr int U = 8;
     uint32_t s = 0;
-    uint64_t j = 0;
-    for (; j + U <= steps; j += U) {
+    uint64_t j = j0;
+    for (; j + U <= j1; j += U) {
         uint4 w[U];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            w[u] = load_step(j + u);
+            w[u] = load(j + u);
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int u = 0; u < U; ++u) {
+            use(j + u, w[u]);
             s = shiftz(Z4096, s) ^ word_crc(lds, w[u]);
+        }
     }
-    for (; j < steps; ++j)
-        s = shiftz(Z4096, s) ^ word_crc(lds, load_step(j));
+    for (; j < j1; ++j) {
+        const uint4 w = load(j);
+        use(j, w);
+        s = shiftz(Z4096, s) ^ word_crc(lds, w);
+    }
     s = lane_combine(lds, s, lane);
     for (uint32_t k = wave; k < 3; ++k)
         s = shiftz(Z1024, s);
     if (lane == 0)
         red[wave] = s;
-    const uint32_t fix = gf2_mulmod(0xFFFFFFFFu, xpow8n_wave(n, xp, lane)) ^ 0xFFFFFFFFu;
     __syncthreads();
     const uint32_t raw = red[0] ^ red[1] ^ red[2] ^ red[3];
     __syncthreads();
-    return raw ^ fix;
+    return raw;
 }
+
+// A message of n bytes cut into S = ceil(n / 4096) steps of 4 KiB after
+// left-padding with zeros; workgroup b of nb takes steps [S b / nb,
+// S (b + 1) / nb).  Its raw CRC times x^(8 * bytes after its steps) is its
+// share of the message's raw CRC, and the shares XOR to the whole.
+struct StepSplit {
+    uint64_t steps, j0, j1;
+    int64_t pad;  // zero bytes in front of the message
+    __device__ StepSplit(uint64_t n, uint32_t b, uint32_t nb)
+    {
+        steps = (n + 4095) >> 12;
+        pad = (int64_t)(steps * 4096 - n);
+        j0 = steps * b / nb;
+        j1 = steps * (b + 1) / nb;
+    }
+    // message offset of thread t's first byte of step j (negative: padding)
+    __device__ int64_t at(uint64_t j) const
+    {
+        return (int64_t)((j * 256 + threadIdx.x) * 16) - pad;
+    }
+};
+
+// This workgroup's share of the raw CRC of the message split by sp: the raw
+// CRC of its steps times x_after = x^(8 * bytes after them), zero when it
+// has no steps.  load and use as for wg_crc_steps.  Uniform over the
+// workgroup.
+template <typename Load, typename Use>
+__device__ __forceinline__ uint32_t wg_crc_share(const StepSplit& sp, Load load, Use use,
+                                                 uint32_t x_after,
+                                                 const uint32_t* __restrict__ lds, uint32_t* red)
+{
+    if (sp.j0 >= sp.j1)
+        return 0;
+    return gf2_mulmod(wg_crc_steps(load, use, sp.j0, sp.j1, lds, red), x_after);
+}
+
+// Workgroups a request's header or image check uses: about two 4 KiB steps
+// each over the longer of its two CRC messages, at most the nb launched.
+__device__ __forceinline__ uint32_t active_blocks(uint64_t bytes_a, uint64_t bytes_b, uint32_t nb)
+{
+    const uint64_t steps = ((bytes_a > bytes_b ? bytes_a : bytes_b) + 4095) >> 12;
+    const uint64_t want = (steps + 1) / 2;
+    return want < 1 ? 1u : want < nb ? (uint32_t)want : nb;
+}
+
+// Called once by every workgroup of a request after its atomics: true in
+// exactly one of them, the last to arrive, which then sees every other
+// workgroup's atomics.  Not called when a request has one workgroup.
+__device__ __forceinline__ bool last_arrival(uint32_t* count, uint32_t nb, uint32_t* s_flag)
+{
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0)
+        *s_flag = atomicAdd(count, 1u) == nb - 1 ? 1u : 0u;
+    __syncthreads();
+    const bool last = *s_flag != 0;
+    __syncthreads();
+    if (last)
+        __threadfence();
+    return last;
+}
+
+// acc[0..3] read at L2 (device-scope atomics) by threads 0-3 at once, into
+// LDS for the workgroup.
+__device__ __forceinline__ void read_accs(uint32_t* acc, uint32_t* s_vals)
+{
+    if (threadIdx.x < 4)
+        s_vals[threadIdx.x] = atomicAdd(&acc[threadIdx.x], 0u);
+    __syncthreads();
+}
+
+// 0xFFFFFFFF * x^(8 * 60): the all-ones initial value carried to the end of
+// the header's first 60 bytes.
+constexpr uint32_t kInitOver60 = gf2_shift(0xFFFFFFFFu, 60);
 
 // ------------------------------------------------------------ k_header
 
-// dst[i] = src[i] for i < n by one workgroup, 16 loads in flight per thread.
-template <typename T>
-__device__ __forceinline__ void copy_words(T* __restrict__ dst, const T* __restrict__ src,
-                                           uint64_t n)
-{
-    constexpr uint32_t U = 16;
-    const uint64_t stride = (uint64_t)blockDim.x * U;
-    uint64_t i = threadIdx.x;
-    for (; i + (U - 1) * blockDim.x < n; i += stride) {
-        T v[U];
-#pragma unroll
-        for (uint32_t u = 0; u < U; ++u)
-            v[u] = src[i + u * blockDim.x];
-#pragma unroll
-        for (uint32_t u = 0; u < U; ++u)
-            dst[i + u * blockDim.x] = v[u];
-    }
-    for (; i < n; i += blockDim.x)
-        dst[i] = src[i];
-}
-
+// nb workgroups launched per request of [q0, q0 + gridDim.x / nb), of which
+// the first active_blocks() work.  Each writes its share of the prefix
+// (header, region table, bitmap) and of the CRC array into the image while
+// folding the same words into its shares of the raw meta_crc and crcs_crc
+// (read from the sources, never back from the image, which may sit in host
+// memory).  In the meta message the header's last two words (meta_crc,
+// crcs_crc) count as zero; crcs_crc is added at the end by linearity.  With
+// several workgroups O.acc collects the shares and the arrivals (zero on
+// entry: the final scan clears it) and the last to arrive writes the two CRC
+// words; a single workgroup keeps its shares in registers.
 __global__ __launch_bounds__(256) void k_header(const DevRegion* __restrict__ regs,
                                                 const DevRequest* __restrict__ reqs,
-                                                const DevReqOut* __restrict__ out,
+                                                DevReqOut* __restrict__ out,
                                                 const uint64_t* __restrict__ bitmap,
                                                 const uint32_t* __restrict__ crcs,
                                                 uint8_t* __restrict__ staging, uint32_t q0,
-                                                uint64_t capacity,
+                                                uint32_t nb, uint64_t capacity,
                                                 const CrcTables* __restrict__ tabs)
 {
     __shared__ __attribute__((aligned(16))) uint32_t lds[kAllTabWords];
     __shared__ uint32_t red[4];
-    __shared__ uint32_t s_shadowed;
-    const DevRequest& Q = reqs[q0 + blockIdx.x];
-    const DevReqOut& O = out[q0 + blockIdx.x];
+    __shared__ uint32_t s_word;
+    __shared__ uint32_t s_hdr[16];
+    __shared__ uint32_t s_pw[4];
+    __shared__ uint32_t s_acc[4];
+    const uint32_t q = q0 + blockIdx.x / nb, b = blockIdx.x % nb;
+    const DevRequest& Q = reqs[q];
+    DevReqOut& O = out[q];
     if (O.code != 0 && O.img_base + Q.data_off > capacity)
         return;  // no room even for the prefix
-    load_all_tables(lds, tabs);
     const uint32_t tid = threadIdx.x;
     uint8_t* img = staging + O.img_base;
     const uint64_t R = Q.n_regions;
-    const uint64_t prefix_end = 64 + 32 * R + 8 * Q.n_words;
+    const uint64_t table_end = 64 + 32 * R;
+    const uint64_t prefix_end = table_end + 8 * Q.n_words;
     const uint64_t D = O.n_dirty;
     const uint64_t first_page0 = Q.first_word * 64;
-    if (tid == 0)
-        s_shadowed = 0;
-    __syncthreads();
-    for (uint64_t i = tid; i < R; i += blockDim.x) {
-        const DevRegion& G = regs[Q.first_region + i];
-        uint64_t* e = reinterpret_cast<uint64_t*>(img + 64 + 32 * i);
-        e[0] = G.id;
-        e[1] = G.len;
-        e[2] = G.first_page - first_page0;
-        e[3] = 0;
-        if (G.shadow)
-            atomicOr(&s_shadowed, 1u);
-    }
-    copy_words(reinterpret_cast<uint64_t*>(img + 64 + 32 * R), bitmap + Q.first_word,
-               Q.n_words);
-    for (uint64_t o = prefix_end + 8 * tid; o < Q.data_off; o += 8 * blockDim.x)
-        *reinterpret_cast<uint64_t*>(img + o) = 0;
     const bool ok = O.code == 0;
-    if (ok) {
-        uint32_t* dst = reinterpret_cast<uint32_t*>(img + Q.data_off + (D << Q.page_shift));
-        copy_words(dst, crcs + O.slot_base, D);
-        if (tid == 0 && (D & 1))
-            dst[D] = 0;
-    }
-    __syncthreads();
-    uint32_t* h32 = reinterpret_cast<uint32_t*>(img);
-    uint64_t* h64 = reinterpret_cast<uint64_t*>(img);
+    const uint32_t ne = active_blocks(prefix_end, ok ? 4 * D : 0, nb);
+    if (b >= ne)
+        return;
+    const StepSplit m(prefix_end, b, ne);
+    const StepSplit c(ok ? 4 * D : 0, b, ne);
+    // the shares' shifts, and for the last workgroup x^(8 * 4D) and
+    // x^(8 * (prefix_end - 60)) (crcs_crc's place in the meta message)
+    wave_powers((c.steps - c.j1) * 4096, (m.steps - m.j1) * 4096, 4 * D, prefix_end - 60,
+                tabs->xp, s_pw);
+    load_all_tables(lds, tabs);
+
+    // header words (the two CRC words zero), in the workgroups whose steps
+    // hold some of its bytes: padded positions [m.pad, m.pad + 64)
+    const bool has_hdr = m.j0 < m.j1 && m.j0 * 4096 < (uint64_t)m.pad + 64 &&
+                         m.j1 * 4096 > (uint64_t)m.pad;
+    uint32_t shadowed = 0;
+    if (has_hdr)
+        for (uint64_t i = tid; i < R; i += blockDim.x)
+            shadowed |= regs[Q.first_region + i].shadow ? 1u : 0u;
+    const int any_shadow = __syncthreads_or((int)shadowed);
     if (tid == 0) {
-        h64[0] = 0x31474D494D555243ull;  // "CRUMIMG1"
-        h32[2] = 1;
-        h32[3] = 1u << Q.page_shift;
-        h32[4] = (uint32_t)R;
-        h32[5] = s_shadowed ? 0u : 1u;
-        h64[3] = Q.n_pages;
-        h64[4] = D;
-        h64[5] = Q.seq;
-        h64[6] = Q.data_off;
-        h32[14] = 0;
-        h32[15] = 0;
+        s_hdr[0] = 0x4D555243u;  // "CRUM"
+        s_hdr[1] = 0x31474D49u;  // "IMG1"
+        s_hdr[2] = 1;
+        s_hdr[3] = 1u << Q.page_shift;
+        s_hdr[4] = (uint32_t)R;
+        s_hdr[5] = any_shadow ? 0u : 1u;
+        s_hdr[6] = (uint32_t)Q.n_pages;
+        s_hdr[7] = (uint32_t)(Q.n_pages >> 32);
+        s_hdr[8] = (uint32_t)D;
+        s_hdr[9] = (uint32_t)(D >> 32);
+        s_hdr[10] = (uint32_t)Q.seq;
+        s_hdr[11] = (uint32_t)(Q.seq >> 32);
+        s_hdr[12] = (uint32_t)Q.data_off;
+        s_hdr[13] = (uint32_t)(Q.data_off >> 32);
+        s_hdr[14] = 0;
+        s_hdr[15] = 0;
     }
-    uint32_t crcs_crc = 0;
-    if (ok)
-        crcs_crc = wg_crc(img + Q.data_off + (D << Q.page_shift), 4 * D, ~0ull, lds, tabs->xp,
-                          red);
-    if (tid == 0)
-        h32[15] = crcs_crc;
-    __threadfence_block();
     __syncthreads();
-    const uint32_t meta = wg_crc(img, prefix_end, ~0ull, lds, tabs->xp, red);
-    if (tid == 0)
-        h32[14] = meta;
+    const uint64_t gt = (uint64_t)b * blockDim.x + tid, gstride = (uint64_t)ne * blockDim.x;
+    for (uint64_t o = prefix_end + 8 * gt; o < Q.data_off; o += 8 * gstride)
+        *reinterpret_cast<uint64_t*>(img + o) = 0;
+
+    // prefix word at byte r: header, region table entries {id, len, first
+    // page within the request, 0}, then the bitmap
+    const gcu32 bm32 = (gcu32)(bitmap + Q.first_word);
+    auto prefix_word = [&](uint64_t r) -> uint32_t {
+        if (r < 64)
+            return s_hdr[r >> 2];
+        if (r < table_end) {
+            const uint64_t t = r - 64;
+            const DevRegion& G = regs[Q.first_region + (t >> 5)];
+            const uint32_t k = (uint32_t)(t >> 2) & 7u;
+            const uint64_t v = k < 2 ? G.id : k < 4 ? G.len : k < 6 ? G.first_page - first_page0 : 0;
+            return (uint32_t)(v >> (32 * (k & 1)));
+        }
+        return bm32[(r - table_end) >> 2];
+    };
+    // m.pad is a multiple of 8, so each thread's 16 bytes are two aligned
+    // 8-byte pairs; the pair at 56 is the two CRC words, written last
+    auto m_load = [&](uint64_t j) {
+        const int64_t v = m.at(j);
+        uint32_t w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t r = v + 4 * i;
+            w[i] = r >= 0 ? prefix_word((uint64_t)r) : 0u;
+        }
+        return make_uint4(w[0], w[1], w[2], w[3]);
+    };
+    auto m_use = [&](uint64_t j, uint4 w) {
+        const int64_t v = m.at(j);
+        if (v >= 0 && v != 56)
+            *(gv2)(img + v) = u32x2{w.x, w.y};
+        if (v + 8 >= 0 && v + 8 != 56)
+            *(gv2)(img + v + 8) = u32x2{w.z, w.w};
+    };
+    const uint32_t m_share = wg_crc_share(m, m_load, m_use, s_pw[1], lds, red);
+    uint32_t c_share = 0;
+    if (ok) {
+        const uint64_t crcs_off = Q.data_off + (D << Q.page_shift);
+        const gcu32 src = (gcu32)(crcs + O.slot_base);
+        uint8_t* dst = img + crcs_off;
+        const bool even = (D & 1) == 0;  // then c.pad, and every v, is a multiple of 8
+        auto c_load = [&](uint64_t j) {
+            const int64_t v = c.at(j);
+            uint32_t w[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                w[i] = v + 4 * i >= 0 ? src[(v >> 2) + i] : 0u;
+            return make_uint4(w[0], w[1], w[2], w[3]);
+        };
+        auto c_use = [&](uint64_t j, uint4 w) {
+            const int64_t v = c.at(j);
+            if (even) {
+                if (v >= 0)
+                    *(gv2)(dst + v) = u32x2{w.x, w.y};
+                if (v + 8 >= 0)
+                    *(gv2)(dst + v + 8) = u32x2{w.z, w.w};
+            } else {
+                const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (v + 4 * i >= 0)
+                        ((gu32)dst)[(v >> 2) + i] = ws[i];
+            }
+        };
+        c_share = wg_crc_share(c, c_load, c_use, s_pw[0], lds, red);
+        if (b == 0 && tid == 0 && !even)
+            ((gu32)dst)[D] = 0;
+    }
+
+    uint32_t c_raw = c_share, m_raw = m_share;
+    if (ne > 1) {
+        if (tid == 0) {
+            if (c_share)
+                atomicXor(&O.acc[0], c_share);
+            if (m_share)
+                atomicXor(&O.acc[1], m_share);
+        }
+        if (!last_arrival(&O.acc[2], ne, &s_word))
+            return;
+        read_accs(O.acc, s_acc);
+        c_raw = s_acc[0];
+        m_raw = s_acc[1];
+    }
+    if (tid == 0) {
+        const uint32_t crcs_crc = ok ? crc_from_raw(c_raw, s_pw[2]) : 0u;
+        // raw meta with crcs_crc in place, then the initial value and inversion
+        const uint32_t meta = m_raw ^ gf2_mulmod(crcs_crc ^ kInitOver60, s_pw[3]) ^ 0xFFFFFFFFu;
+        *(gv2)(img + 56) = u32x2{meta, crcs_crc};
+    }
+}
+
+// Workgroups per request for the header and image-check kernels: about two
+// 4 KiB CRC steps each over the larger of the prefix and the CRC array, at
+// most 128.
+uint32_t header_blocks(uint64_t n_regions, uint64_t n_words, uint64_t n_crcs)
+{
+    const uint64_t prefix = 64 + 32 * n_regions + 8 * n_words;
+    const uint64_t bytes = prefix > 4 * n_crcs ? prefix : 4 * n_crcs;
+    const uint64_t steps = (bytes + 4095) >> 12;
+    const uint64_t nb = (steps + 1) / 2;
+    return (uint32_t)(nb < 1 ? 1 : nb > 128 ? 128 : nb);
 }
 
 hipError_t launch_header(const DevRegion* regs, const DevRequest* reqs, uint32_t q0, uint32_t q1,
-                         const DevReqOut* out, const uint64_t* bitmap, const uint32_t* crcs,
-                         uint8_t* staging, uint64_t capacity, const CrcTables* tabs,
-                         hipStream_t s)
+                         uint32_t blocks, DevReqOut* out, const uint64_t* bitmap,
+                         const uint32_t* crcs, uint8_t* staging, uint64_t capacity,
+                         const CrcTables* tabs, hipStream_t s)
 {
     if (q1 <= q0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_header, dim3(q1 - q0), dim3(256), 0, s, regs, reqs, out, bitmap, crcs,
-                       staging, q0, capacity, tabs);
+    if (blocks == 0 || (uint64_t)(q1 - q0) * blocks > 0x7FFFFFFFull)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_header, dim3((q1 - q0) * blocks), dim3(256), 0, s, regs, reqs, out,
+                       bitmap, crcs, staging, q0, blocks, capacity, tabs);
     return hipGetLastError();
 }
 
@@ -1156,70 +1330,127 @@ hipError_t launch_plan_status(const DevReqOut* out, uint32_t n, uint8_t* dst, hi
 
 // Device-side image checks that need the bytes: meta_crc, crcs_crc, bitmap
 // population and unused bits, zero pads.  The host has already checked the
-// header fields, lengths and the region table.
+// header fields, lengths and the region table.  nb workgroups launched per
+// request, of which the first active_blocks() work; each takes a share of the
+// bitmap, the pad and the two CRC messages.  With several, O.acc (zero on
+// entry: the host uploads it cleared) collects the CRC shares, the arrivals
+// and the population, and the last workgroup to arrive compares.
 __global__ __launch_bounds__(256) void k_restore_check(const DevRequest* __restrict__ reqs,
-                                                       const DevReqOut* __restrict__ out,
+                                                       DevReqOut* __restrict__ out,
                                                        const uint8_t* __restrict__ staging,
+                                                       uint32_t nb,
                                                        const CrcTables* __restrict__ tabs,
                                                        DevGlobal* __restrict__ glob)
 {
     __shared__ __attribute__((aligned(16))) uint32_t lds[kAllTabWords];
     __shared__ uint32_t red[4];
-    __shared__ unsigned long long s_pop;
-    __shared__ uint32_t s_bad;
-    load_all_tables(lds, tabs);
+    __shared__ uint32_t s_pop;
+    __shared__ uint32_t s_word;
+    __shared__ uint32_t s_pw[4];
+    __shared__ uint32_t s_acc[4];
     const uint32_t tid = threadIdx.x;
-    const DevRequest& Q = reqs[blockIdx.x];
-    const DevReqOut& O = out[blockIdx.x];
+    const uint32_t q = blockIdx.x / nb, b = blockIdx.x % nb;
+    const DevRequest& Q = reqs[q];
+    DevReqOut& O = out[q];
     const uint8_t* img = staging + O.img_base;
+    const gcu32 img32 = (gcu32)img;
     const uint64_t R = Q.n_regions;
     const uint64_t prefix_end = 64 + 32 * R + 8 * Q.n_words;
-    const uint32_t* h32 = reinterpret_cast<const uint32_t*>(img);
     const uint64_t D = reinterpret_cast<const uint64_t*>(img)[4];
-    if (tid == 0) {
+    const uint64_t crcs_off = Q.data_off + (D << Q.page_shift);
+    const uint32_t ne = active_blocks(prefix_end, 4 * D, nb);
+    if (b >= ne)
+        return;
+    const StepSplit c(4 * D, b, ne);
+    const StepSplit m(prefix_end, b, ne);
+    wave_powers((c.steps - c.j1) * 4096, (m.steps - m.j1) * 4096, 4 * D, prefix_end, tabs->xp,
+                s_pw);
+    if (tid == 0)
         s_pop = 0;
-        s_bad = 0;
-    }
-    __syncthreads();
+    load_all_tables(lds, tabs);
+
+    const uint64_t gt = (uint64_t)b * blockDim.x + tid, gstride = (uint64_t)ne * blockDim.x;
     const uint64_t* bm = reinterpret_cast<const uint64_t*>(img + 64 + 32 * R);
-    unsigned long long pop = 0;
-    uint32_t bad = 0;
-    for (uint64_t w = tid; w < Q.n_words; w += blockDim.x) {
+    uint32_t pop = 0, bad = 0;
+    for (uint64_t w = gt; w < Q.n_words; w += gstride) {
         const uint64_t word = bm[w];
-        pop += __popcll(word);
+        pop += (uint32_t)__popcll(word);
         if (w == Q.n_words - 1 && (Q.n_pages & 63)) {
             if (word >> (Q.n_pages & 63))
                 bad = 1;
         }
     }
-    for (uint64_t o = prefix_end + 8 * tid; o < Q.data_off; o += 8 * blockDim.x)
+    for (uint64_t o = prefix_end + 8 * gt; o < Q.data_off; o += 8 * gstride)
         if (*reinterpret_cast<const uint64_t*>(img + o))
             bad = 1;
-    if (tid == 0) {
-        const uint64_t tail = Q.data_off + (D << Q.page_shift) + 4 * D;
-        for (uint64_t o = tail; o < O.image_bytes; ++o)
+    if (gt == 0) {
+        for (uint64_t o = crcs_off + 4 * D; o < O.image_bytes; ++o)
             if (img[o])
                 bad = 1;
     }
-    atomicAdd(&s_pop, pop);
     if (bad)
-        atomicOr(&s_bad, 1u);
-    const uint32_t crcs =
-        wg_crc(img + Q.data_off + (D << Q.page_shift), 4 * D, ~0ull, lds, tabs->xp, red);
-    const uint32_t meta = wg_crc(img, prefix_end, 56, lds, tabs->xp, red);
+        atomicOr(&glob->fmt_bad, 1u);
+    if (pop)
+        atomicAdd(&s_pop, pop);
+
+    auto no_use = [](uint64_t, uint4) {};
+    const gcu32 c32 = (gcu32)(img + crcs_off);
+    auto c_load = [&](uint64_t j) {
+        const int64_t v = c.at(j);
+        uint32_t w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            w[i] = v + 4 * i >= 0 ? c32[(v >> 2) + i] : 0u;
+        return make_uint4(w[0], w[1], w[2], w[3]);
+    };
+    const uint32_t c_share = wg_crc_share(c, c_load, no_use, s_pw[0], lds, red);
+    auto m_load = [&](uint64_t j) {
+        const int64_t v = m.at(j);
+        uint32_t w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t r = v + 4 * i;
+            w[i] = r >= 0 && r != 56 ? img32[r >> 2] : 0u;  // meta_crc itself reads as zero
+        }
+        return make_uint4(w[0], w[1], w[2], w[3]);
+    };
+    const uint32_t m_share = wg_crc_share(m, m_load, no_use, s_pw[1], lds, red);
     __syncthreads();
+    uint32_t c_raw = c_share, m_raw = m_share, total_pop = s_pop;
+    if (ne > 1) {
+        if (tid == 0) {
+            if (c_share)
+                atomicXor(&O.acc[0], c_share);
+            if (m_share)
+                atomicXor(&O.acc[1], m_share);
+            if (s_pop)
+                atomicAdd(&O.acc[3], s_pop);
+        }
+        if (!last_arrival(&O.acc[2], ne, &s_word))
+            return;
+        read_accs(O.acc, s_acc);
+        c_raw = s_acc[0];
+        m_raw = s_acc[1];
+        total_pop = s_acc[3];
+    }
     if (tid == 0) {
-        if (s_bad || s_pop != D || crcs != h32[15] || meta != h32[14])
+        const uint32_t crcs = crc_from_raw(c_raw, s_pw[2]);
+        const uint32_t meta = crc_from_raw(m_raw, s_pw[3]);
+        if ((uint64_t)total_pop != D || crcs != img32[15] || meta != img32[14])
             atomicOr(&glob->fmt_bad, 1u);
     }
 }
 
-hipError_t launch_restore_check(const DevRequest* reqs, uint32_t n_reqs, const DevReqOut* out,
-                                const uint8_t* staging, const CrcTables* tabs, DevGlobal* glob,
-                                hipStream_t s)
+hipError_t launch_restore_check(const DevRequest* reqs, uint32_t n_reqs, uint32_t blocks,
+                                DevReqOut* out, const uint8_t* staging, const CrcTables* tabs,
+                                DevGlobal* glob, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_restore_check, dim3(n_reqs), dim3(256), 0, s, reqs, out, staging, tabs,
-                       glob);
+    if (n_reqs == 0)
+        return hipSuccess;
+    if (blocks == 0 || (uint64_t)n_reqs * blocks > 0x7FFFFFFFull)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_restore_check, dim3(n_reqs * blocks), dim3(256), 0, s, reqs, out,
+                       staging, blocks, tabs, glob);
     return hipGetLastError();
 }
 

@@ -438,7 +438,8 @@ int crum_lazy_open(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
         hipMemcpyAsync(z->staging, h, I.data_off, hipMemcpyHostToDevice, stream) != hipSuccess ||
         hipMemcpyAsync(z->staging + pages_end, h + pages_end, image_bytes - pages_end,
                        hipMemcpyHostToDevice, stream) != hipSuccess ||
-        launch_restore_check(d_req, 1, d_out, z->staging, ctx_tables(c), d_glob, stream) !=
+        launch_restore_check(d_req, 1, header_blocks(n_regions, W, D), d_out, z->staging,
+                             ctx_tables(c), d_glob, stream) !=
             hipSuccess ||
         launch_scan(img_bitmap, 0, W, W, d_prefix, nullptr, 1, d_req, 0, 1, d_out, d_glob, 0, 1,
                     stream) != hipSuccess ||

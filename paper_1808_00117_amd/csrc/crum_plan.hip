@@ -276,6 +276,10 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
         const uint64_t w0 = q0 < n_reqs ? dreq[q0].first_word : W;
         const uint64_t w1 = q1 < n_reqs ? dreq[q1].first_word : W;
         const uint64_t u0 = req_unit0[q0], u1 = req_unit0[q1];
+        uint32_t hdr_blocks = 1;
+        for (uint32_t q = q0; q < q1; ++q)
+            hdr_blocks = std::max(hdr_blocks, header_blocks(dreq[q].n_regions, dreq[q].n_words,
+                                                            dreq[q].n_pages));
         hipStream_t s = p->cap_stream;
         if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return fail(CRUM_EHIP);
@@ -304,8 +308,8 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
             e = launch_finalize(kModePack, d_regs, p->n_regs, d_reqs, d_out, d_list, sr, np_shift,
                                 pc_shift, d_part, d_crcs, p->staging, d_glob, tabs, s);
         if (e == hipSuccess)
-            e = launch_header(d_regs, d_reqs, q0, q1, d_out, d_bitmap, d_crcs, p->staging,
-                              capacity, tabs, s);
+            e = launch_header(d_regs, d_reqs, q0, q1, hdr_blocks, d_out, d_bitmap, d_crcs,
+                              p->staging, capacity, tabs, s);
         if (e == hipSuccess && gi + 1 == n_groups) {
             if (!reordered) {
                 e = launch_plan_status(d_out, n_reqs, p->d_status, s);

@@ -15,7 +15,7 @@
 #include <stdint.h>
 
 #ifndef CRUM_HD
-#define CRUM_HD __host__ __device__ inline
+#define CRUM_HD __host__ __device__ constexpr inline
 #endif
 
 namespace crum {

@@ -216,6 +216,41 @@ def test_many_regions(snap):
     check_parity(snap, host_case((1,) * R, P, dirty, seed=9), P)
 
 
+@pytest.mark.parametrize("n_dirty", [5001, 5000], ids=["odd_D", "even_D"])
+def test_header_split_over_workgroups(snap, snap_small_chunks, snap_direct, n_dirty):
+    """A prefix of three 4 KiB steps and a CRC array of five, so the header and
+    image-check kernels spread both CRCs over several workgroups (an odd and an
+    even page count change the CRC array's alignment): the images equal the
+    oracle's in every order, a verified restore reproduces the regions, and
+    bit flips in late CRC entries and a late bitmap word, outside the first
+    workgroup's steps, are rejected."""
+    import torch
+    P = 4 * KiB
+    counts = (1,) * 300 + (12000,)
+    G = sum(counts)
+    W = (G + 63) // 64
+    rng = np.random.default_rng(n_dirty)
+    dirty = set(int(x) for x in rng.choice(G, size=n_dirty, replace=False))
+    log(f"[parity] header split over workgroups, D={n_dirty}")
+    host = host_case(counts, P, dirty, seed=n_dirty)
+    dev, img = check_parity(snap, host, P, others=(snap_small_chunks, snap_direct))
+    staging = torch.empty(img.size, dtype=torch.uint8, device="cuda")
+    targets = [(sh.clone(), None, rid) for _, sh, rid in dev]
+    rc, st = snap.restore(targets, torch.from_numpy(img).pin_memory(), img.size, staging,
+                          flags=2)
+    assert rc == 0 and st.code == 0, st
+    for (t, _, _), (c, _, _) in zip(targets, dev):
+        assert torch.equal(t, c)
+    crc_off = oracle.prefix_bytes(len(counts), G) + n_dirty * P
+    for pos in (crc_off + 4 * n_dirty - 3, crc_off + 4 * 3000,
+                64 + 32 * len(counts) + 8 * (W - 2)):
+        bad = img.copy()
+        bad[pos] ^= 0x10
+        rc, st = snap.restore(targets, torch.from_numpy(bad).pin_memory(), bad.size, staging,
+                              flags=2)
+        assert st.code in (-4, -6), (pos, st)
+
+
 def test_multi_chunk_drain(snap, snap_small_chunks):
     # D*P well above the first 8 MiB drain chunk: several pack/drain chunks
     P = 64 * KiB
