@@ -608,8 +608,7 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
             Span sp(c, kTScan, stream);
             CRUM_TRY(launch_bitmap(d_regs, n_regions, 0, W, d_flags, d_bitmap, stream));
             CRUM_TRY(launch_scan(d_bitmap, 0, W, W, d_prefix, d_bounds, 1, d_reqs, 0, 1, d_out,
-                                 d_glob, capacity, 0, stream));
-            CRUM_TRY(launch_list(d_bitmap, d_prefix, 0, W, d_list, stream));
+                                 d_glob, capacity, 0, d_list, stream));
         }
         {
             Span sp(c, kTPack, stream);
@@ -650,15 +649,11 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
                 CRUM_TRY(launch_bitmap(d_regs, n_regions, w0, w1, d_flags, d_bitmap, stream));
                 CRUM_TRY(launch_scan(d_bitmap, w0, w1, W, d_prefix, d_bounds + ci,
                                      ci + 1 == n_chunks, d_reqs, 0, 1, d_out, d_glob, capacity,
-                                     0, stream));
+                                     0, d_list, stream));
             }
             CRUM_TRY(hipMemcpyAsync(rb + 128 + 8 * ci, d_bounds + ci, 8, hipMemcpyDeviceToHost,
                                     stream));
             CRUM_TRY(hipEventRecord(c->ev_cnt[ci], stream));
-            {
-                Span sp(c, kTScan, stream);
-                CRUM_TRY(launch_list(d_bitmap, d_prefix, w0, w1, d_list, stream));
-            }
             {
                 Span sp(c, kTPack, stream);
                 SlotRange sr{0, 0, d_bounds, (uint32_t)ci, g1 - g0};
@@ -700,7 +695,7 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
             Span sp(c, kTScan, stream);
             CRUM_TRY(launch_bitmap(d_regs, n_regions, 0, W, d_flags, d_bitmap, stream));
             CRUM_TRY(launch_scan(d_bitmap, 0, W, W, d_prefix, d_bounds, 1, d_reqs, 0, 1, d_out,
-                                 d_glob, capacity, 0, stream));
+                                 d_glob, capacity, 0, nullptr, stream));
         }
         CRUM_TRY(hipMemcpyAsync(rb, d_out, 128, hipMemcpyDeviceToHost, stream));
         CRUM_TRY(hipEventRecord(c->ev_count, stream));
@@ -892,8 +887,7 @@ int crum_restore(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
         CRUM_TRY(launch_restore_check(d_reqs, 1, header_blocks(n_regions, W, D), d_out, staging,
                                       c->d_tabs, d_glob, stream));
         CRUM_TRY(launch_scan(img_bitmap, 0, W, W, d_prefix, nullptr, 1, d_reqs, 0, 1, d_out,
-                             d_glob, 0, 1, stream));
-        CRUM_TRY(launch_list(img_bitmap, d_prefix, 0, W, d_list, stream));
+                             d_glob, 0, 1, d_list, stream));
     }
     if (flags & CRUM_VERIFY) {
         Span sp(c, kTVerify, stream);

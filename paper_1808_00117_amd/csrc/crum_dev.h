@@ -123,11 +123,13 @@ hipError_t launch_bitmap(const DevRegion* regs, uint32_t n_regs, uint64_t w0, ui
 // to *bounds_out when non-null.  With `final`, also fills the results of
 // requests [q0, q1) (whose words must all have been scanned), lays their
 // images out from glob->img_next and applies the capacity check: a group that
-// does not fit, and every later group, gets CRUM_ENOSPC.
+// does not fit, and every later group, gets CRUM_ENOSPC.  With `list`, also
+// writes the slot list of the words (as launch_list): inside the scan kernel
+// when the range takes one pass, else by a launch_list behind it.
 hipError_t launch_scan(const uint64_t* bitmap, uint64_t w0, uint64_t w1, uint64_t n_words_total,
                        uint32_t* prefix, uint64_t* bounds_out, int final, const DevRequest* reqs,
                        uint32_t q0, uint32_t q1, DevReqOut* out, DevGlobal* glob,
-                       uint64_t capacity, int restore_mode, hipStream_t s);
+                       uint64_t capacity, int restore_mode, uint32_t* list, hipStream_t s);
 hipError_t launch_list(const uint64_t* bitmap, const uint32_t* prefix, uint64_t w0, uint64_t w1,
                        uint32_t* list, hipStream_t s);
 // Pack, verify and scatter work on (slot, piece) items: a page of 2^ps bytes

@@ -516,6 +516,12 @@ hipError_t launch_bitmap(const DevRegion* regs, uint32_t n_regs, uint64_t w0, ui
 
 // ------------------------------------------------------------ k_scan
 
+// A range of at most this many bitmap words gets its slot list from k_scan
+// itself (the k_list work, from LDS, with no second launch).  One workgroup
+// writes the list at about 5 ns a word, so past this a separate k_list (about
+// 5 us plus a launch gap) is faster.
+constexpr uint64_t kScanListWords = 512;
+
 __global__ __launch_bounds__(1024) void k_scan(const uint64_t* __restrict__ bitmap, uint64_t w0,
                                                uint64_t w1, uint64_t n_words_total,
                                                uint32_t* __restrict__ prefix,
@@ -523,10 +529,13 @@ __global__ __launch_bounds__(1024) void k_scan(const uint64_t* __restrict__ bitm
                                                const DevRequest* __restrict__ reqs, uint32_t q0,
                                                uint32_t q1, DevReqOut* __restrict__ out,
                                                DevGlobal* __restrict__ glob, uint64_t capacity,
-                                               int restore_mode)
+                                               int restore_mode, uint32_t* __restrict__ list)
 {
     constexpr int V = 4;  // words per thread per pass
+    static_assert(kScanListWords <= 1024 * V, "a fused list range takes one pass");
     __shared__ uint32_t wave_tot[16];
+    __shared__ uint64_t s_words[kScanListWords];  // with `list`: the words and their
+    __shared__ uint32_t s_pre[kScanListWords];    // prefixes, for the list below
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
     uint32_t carry = (uint32_t)glob->running;
     for (uint64_t base = w0; base < w1; base += 1024 * V) {
@@ -535,7 +544,10 @@ __global__ __launch_bounds__(1024) void k_scan(const uint64_t* __restrict__ bitm
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             const uint64_t w = base + (uint64_t)tid * V + v;
-            c[v] = w < w1 ? (uint32_t)__popcll(bitmap[w]) : 0u;
+            const uint64_t word = w < w1 ? bitmap[w] : 0ull;
+            if (list && w < w1)
+                s_words[w - w0] = word;
+            c[v] = (uint32_t)__popcll(word);
             local += c[v];
         }
         uint32_t incl = local;
@@ -558,12 +570,37 @@ __global__ __launch_bounds__(1024) void k_scan(const uint64_t* __restrict__ bitm
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             const uint64_t w = base + (uint64_t)tid * V + v;
-            if (w < w1)
+            if (w < w1) {
                 prefix[w] = excl;
+                if (list)
+                    s_pre[w - w0] = excl;
+            }
             excl += c[v];
         }
         carry += blk;
         __syncthreads();
+    }
+    if (list) {
+        // the k_list step: wave wv takes words 4wv .. 4wv + 3, then 64 further
+        // on, ... (four LDS reads in flight); the lane of each set bit writes
+        // its page at the word's prefix plus the set bits below it
+        const uint64_t n = w1 - w0;
+        for (uint64_t i0 = 4 * wv; i0 < n; i0 += 64) {
+            uint64_t m[4];
+            uint32_t pre[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                m[u] = i0 + u < n ? s_words[i0 + u] : 0ull;
+                pre[u] = i0 + u < n ? s_pre[i0 + u] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(m[u] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[u], 0u));
+                if ((m[u] >> lane) & 1u)
+                    list[pre[u] + below] = (uint32_t)((w0 + i0 + u) * 64 + lane);
+            }
+        }
     }
     __threadfence_block();
     __syncthreads();
@@ -617,11 +654,16 @@ __global__ __launch_bounds__(1024) void k_scan(const uint64_t* __restrict__ bitm
 hipError_t launch_scan(const uint64_t* bitmap, uint64_t w0, uint64_t w1, uint64_t n_words_total,
                        uint32_t* prefix, uint64_t* bounds_out, int final, const DevRequest* reqs,
                        uint32_t q0, uint32_t q1, DevReqOut* out, DevGlobal* glob,
-                       uint64_t capacity, int restore_mode, hipStream_t s)
+                       uint64_t capacity, int restore_mode, uint32_t* list, hipStream_t s)
 {
+    const bool fused = list && w1 - w0 <= kScanListWords;
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, bitmap, w0, w1, n_words_total, prefix,
-                       bounds_out, final, reqs, q0, q1, out, glob, capacity, restore_mode);
-    return hipGetLastError();
+                       bounds_out, final, reqs, q0, q1, out, glob, capacity, restore_mode,
+                       fused ? list : nullptr);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && list && !fused)
+        e = launch_list(bitmap, prefix, w0, w1, list, s);
+    return e;
 }
 
 // ------------------------------------------------------------ k_list

@@ -442,8 +442,7 @@ int crum_lazy_open(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
                              ctx_tables(c), d_glob, stream) !=
             hipSuccess ||
         launch_scan(img_bitmap, 0, W, W, d_prefix, nullptr, 1, d_req, 0, 1, d_out, d_glob, 0, 1,
-                    stream) != hipSuccess ||
-        launch_list(img_bitmap, d_prefix, 0, W, d_list, stream) != hipSuccess ||
+                    d_list, stream) != hipSuccess ||
         enqueue_status(z, h_status, stream) != hipSuccess ||
         record_done(z, stream) != hipSuccess ||
         // page copies start after everything the caller enqueued before

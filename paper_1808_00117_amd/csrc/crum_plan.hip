@@ -293,12 +293,10 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
             e = launch_bitmap(d_regs, p->n_regs, w0, w1, d_flags, d_bitmap, s);
         if (e == hipSuccess)
             e = launch_scan(d_bitmap, w0, w1, W, d_prefix, d_bounds + gi, 1, d_reqs, q0, q1,
-                            d_out, d_glob, capacity, 0, s);
+                            d_out, d_glob, capacity, 0, d_list, s);
         if (e == hipSuccess)
             e = hipMemcpyAsync(p->h_rb + 8 * gi, &d_glob->staging_used, 8,
                                hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess)
-            e = launch_list(d_bitmap, d_prefix, w0, w1, d_list, s);
         SlotRange sr{0, 0, d_bounds, (uint32_t)gi, (w1 - w0) * 64};
         if (e == hipSuccess)
             e = launch_pack(kModePack, d_regs, p->n_regs, d_reqs, d_out, d_list, sr, np_shift,
