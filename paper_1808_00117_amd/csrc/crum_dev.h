@@ -166,6 +166,9 @@ hipError_t launch_plan_init(DevGlobal* glob, hipStream_t s);
 // Compact per-request results: {code, first_bad, n_dirty, total_pages,
 // image_bytes, image_offset} (40 bytes each) for requests [0, n).
 hipError_t launch_plan_status(const DevReqOut* out, uint32_t n, uint8_t* dst, hipStream_t s);
+// The image checks that need its bytes (bitmap population and unused bits,
+// zero pads, crcs_crc, meta_crc), `blocks` workgroups per request; a failure
+// sets glob->fmt_bad.  out[q].acc must be zero.
 hipError_t launch_restore_check(const DevRequest* reqs, uint32_t n_reqs, uint32_t blocks,
                                 DevReqOut* out, const uint8_t* staging, const CrcTables* tabs,
                                 DevGlobal* glob, hipStream_t s);

@@ -10,15 +10,17 @@
 //   k_scan    one workgroup: exclusive prefix sum of popcount(word) -> slot of
 //             each word's first dirty page, continuing a running total so the
 //             page space can be processed in chunks; at the end, per-request
-//             dirty counts, image offsets and the capacity check.
+//             dirty counts, image offsets and the capacity check.  A short
+//             range also gets the k_list step here.
 //   k_list    per word: ballot compaction, lane with bit set writes its page
 //             index at prefix + popcount(bits below the lane).
 //   k_pack    per dirty page (or piece of up to 64 KiB): copy into the
 //             image's page area, optionally into the shadow, and CRC-32C on
 //             the way; k_finalize combines the piece CRCs of larger pages.
-//   k_header  per request: header, region table, bitmap, CRC array, pads,
-//             crcs_crc, meta_crc.
-// Restore: k_restore_check, k_scan, k_list, k_pack (verify), k_scatter.
+//   k_header  per request, over one or more workgroups: header, region
+//             table, bitmap, CRC array, pads, crcs_crc, meta_crc.
+// Restore: k_restore_check (the image's own checks, also over one or more
+// workgroups), k_scan, k_list, k_pack (verify), k_scatter.
 //
 // CRC-32C on the device.  The polynomial arithmetic is in gf2.h.  A wave
 // processes a piece of n = 64*T 16-byte words; lane l takes words l, l+64,
