@@ -394,6 +394,46 @@ def test_enospc_leaves_shadow_and_canary(snap):
     assert st.code == -2
 
 
+def test_enospc_prefix_split_over_workgroups(snap, snap_direct):
+    """ENOSPC with a prefix of three 4 KiB steps, so the header kernel writes it
+    from several workgroups: the prefix equals the oracle image's apart from
+    the two CRC words, crcs_crc is zero (nothing packed) and meta_crc is the
+    CRC-32C of the prefix with meta_crc read as zero; nothing past the prefix
+    is written."""
+    import torch
+    P = 4 * KiB
+    counts = (1,) * 300 + (12000,)
+    G = sum(counts)
+    rng = np.random.default_rng(77)
+    dirty = set(int(x) for x in rng.choice(G, size=2001, replace=False))
+    host = host_case(counts, P, dirty, seed=77)
+    st_o, img_o, _ = oracle.snapshot(host, P)
+    need = st_o.image_bytes
+    data_off = oracle.prefix_bytes(len(counts), G)
+    prefix_end = 64 + 32 * len(counts) + 8 * ((G + 63) // 64)
+    assert prefix_end > 2 * 4096
+    dev = upload(host)
+    log("[parity] ENOSPC with a three-step prefix")
+    for ctx, in_host in ((snap, False), (snap_direct, True)):
+        big = torch.full((need,), 0xA5, dtype=torch.uint8, device="cuda")
+        h = torch.full((need,), 0xA5, dtype=torch.uint8, pin_memory=True)
+        if in_host:
+            rc, st = ctx.snapshot(dev, P, big, h[: need - P])
+        else:
+            rc, st = ctx.snapshot(dev, P, big[: need - P], h)
+        assert rc == 0 and st.code == -2 and st.n_dirty == 2001, st
+        img = h.numpy() if in_host else big.cpu().numpy()
+        assert np.array_equal(img[:56], img_o[:56])
+        assert np.array_equal(img[64:data_off], img_o[64:data_off])
+        crcs_crc = int(img[60:64].view(np.uint32)[0])
+        meta = int(img[56:60].view(np.uint32)[0])
+        assert crcs_crc == 0
+        zeroed = img[:prefix_end].copy()
+        zeroed[56:60] = 0
+        assert meta == oracle.crc32c(zeroed)
+        assert bool((img[data_off:] == 0xA5).all())
+
+
 def test_invalid_arguments_are_synchronous(snap):
     import torch
     import paper_1808_00117_amd as crum
