@@ -193,6 +193,44 @@ def test_snapshot_parity_property(snap, snap_small_chunks, snap_direct):
     run()
 
 
+def test_split_header_parity_property(snap, snap_small_chunks, snap_direct):
+    """Drawn tables whose prefix (100-700 one-page regions plus one of up to
+    20 000 pages) and CRC array span one to about twenty 4 KiB steps, so the
+    header and image-check kernels run on drawn numbers of workgroups with
+    drawn step boundaries: every order gives the oracle's image and a verified
+    restore of it reproduces the regions.  Derandomized."""
+    import torch
+    from hypothesis import given, settings, HealthCheck
+    from hypothesis import strategies as st
+
+    @settings(max_examples=10, deadline=None, derandomize=True,
+              suppress_health_check=list(HealthCheck))
+    @given(n_small=st.integers(100, 700),
+           big=st.integers(0, 20000),
+           pshift=st.sampled_from([12, 14]),
+           dirty_seed=st.integers(0, 2**31 - 1),
+           density=st.sampled_from([0.0, 0.05, 0.4, 1.0]))
+    def run(n_small, big, pshift, dirty_seed, density):
+        P = 1 << pshift
+        counts = (1,) * n_small + (big,)
+        G = sum(counts)
+        rng = np.random.default_rng(dirty_seed)
+        dirty = {g for g in range(G) if rng.random() < density}
+        log(f"[parity] split header: {n_small} + {big} pages of {P}, D={len(dirty)}")
+        regs = host_case(counts, P, dirty, seed=dirty_seed)
+        dev, img = check_parity(snap, regs, P, seq=dirty_seed & 0xFFFF,
+                                others=(snap_small_chunks, snap_direct))
+        targets = [(sh.clone(), None, rid) for _, sh, rid in dev]
+        staging = torch.empty(img.size, dtype=torch.uint8, device="cuda")
+        rc, st_r = snap.restore(targets, torch.from_numpy(img).pin_memory(), img.size, staging,
+                                flags=2)
+        assert rc == 0 and st_r.code == 0, st_r
+        for (t, _, _), (c, _, _) in zip(targets, dev):
+            assert torch.equal(t, c)
+
+    run()
+
+
 def test_snapshot_parity_random_sets(snap, snap_small_chunks, snap_direct):
     rng = np.random.default_rng(77)
     for trial in range(6):
