@@ -87,6 +87,11 @@ def lib():
                                    ctypes.c_uint64, ctypes.POINTER(_Status)]
         L.orc_parse.restype = ctypes.c_int
         L.orc_parse.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(_Header)]
+        L.orc_snapshot_stream.restype = ctypes.c_int
+        L.orc_snapshot_stream.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                          ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                          ctypes.c_uint64, ctypes.POINTER(_Status)]
         L.orc_restore.restype = ctypes.c_int
         L.orc_restore.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
                                   ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(_Status)]
@@ -162,6 +167,41 @@ def snapshot(regions, page_size: int, flags: int = 0, seq: int = 0,
                        ctypes.byref(st))
     s = _status(st)
     img = image[: s.image_bytes].copy() if s.code == OK else np.zeros(0, np.uint8)
+    return s, img, bitmap[:W].copy()
+
+
+class _StreamRegion(ctypes.Structure):
+    _fields_ = [("len", ctypes.c_uint64), ("id", ctypes.c_uint64),
+                ("has_shadow", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+def snapshot_stream(regions, page_size: int, src_fn: int, src_user: int, seq: int = 0,
+                    image_cap: Optional[int] = None):
+    """The snapshot with region bytes handed in one page at a time.
+
+    regions: sequence of (len, id, has_shadow); src_fn: address of a C
+    function ``int src(void* user, uint32_t region, uint64_t page, uint8_t*
+    cur, uint8_t* shadow_or_NULL)`` (for example ``synth.lib.PageSource``);
+    src_user: its first argument.  Returns (Status, image, bitmap) like
+    :func:`snapshot`.  The default capacity holds the image whatever D is;
+    the buffer is reserved with np.empty, so only the image's own bytes are
+    ever touched."""
+    G = sum(int(ln) // page_size for ln, _, _ in regions) if page_size else 0
+    W = (G + 63) // 64
+    full = prefix_bytes(len(regions), G) + G * page_size + ((4 * G + 7) // 8) * 8
+    if image_cap is None:
+        image_cap = full
+    image = np.empty(max(1, min(image_cap, full)), dtype=np.uint8)
+    bitmap = np.zeros(max(1, W), dtype=np.uint64)
+    arr = (_StreamRegion * max(1, len(regions)))()
+    for i, (ln, rid, has_sh) in enumerate(regions):
+        arr[i] = _StreamRegion(ln, rid, 1 if has_sh else 0, 0)
+    st = _Status()
+    lib().orc_snapshot_stream(arr if regions else None, len(regions), page_size, seq, src_fn,
+                              src_user, image.ctypes.data, min(image_cap, full),
+                              bitmap.ctypes.data, W, ctypes.byref(st))
+    s = _status(st)
+    img = image[: s.image_bytes] if s.code == OK else np.zeros(0, np.uint8)
     return s, img, bitmap[:W].copy()
 
 

@@ -28,6 +28,9 @@
  *     regions): parse and check the image, check the destination table,
  *     optionally verify every page CRC before writing anything, then copy
  *     packed page k to the k-th set bit's page.
+ *  8. The snapshot of steps 1-4 and 6 again with the region bytes handed in
+ *     one page at a time by a caller's source (orc_snapshot_stream), for
+ *     workloads of tens of GB that cannot be held twice in host memory.
  *
  * Status codes: 0 OK, -1 EINVAL, -2 ENOSPC, -3 ECRC, -4 EFORMAT, -6 EMISMATCH.
  */
@@ -346,6 +349,157 @@ int orc_snapshot(const orc_region* r, uint32_t nr, uint32_t page_size, uint32_t 
     free(bitmap);
     st->code = ORC_OK;
     return ORC_OK;
+}
+
+/* -------------------------------------------------------- streamed input */
+
+/*
+ * The same snapshot with the region bytes supplied one page at a time by the
+ * caller instead of as whole buffers, for workloads too large to hold twice
+ * in host memory (tens of GB).  Nothing else changes: the same definition,
+ * in the same order.  The source fills `cur` with page `page` of region
+ * `region` and, when `shadow` is not NULL, the shadow's copy of that page;
+ * it returns 0, or nonzero to abort (status EINVAL).  A region without a
+ * shadow has every page dirty and is never asked for shadow bytes.  There is
+ * no shadow update: the source owns the bytes.
+ *
+ * Two passes over the pages, as the definition reads: first the diff of
+ * every page (building the bitmap), then the dirty pages again in ascending
+ * order, each copied into the image with its CRC.
+ */
+typedef int (*orc_page_fn)(void* user, uint32_t region, uint64_t page, uint8_t* cur,
+                           uint8_t* shadow);
+
+typedef struct {
+    uint64_t len;
+    uint64_t id;
+    uint32_t has_shadow;
+    uint32_t reserved;
+} orc_stream_region;
+
+int orc_snapshot_stream(const orc_stream_region* r, uint32_t nr, uint32_t page_size,
+                        uint64_t seq, orc_page_fn src, void* user, uint8_t* image,
+                        uint64_t image_cap, uint64_t* bitmap_out, uint64_t bitmap_out_words,
+                        orc_status* st)
+{
+    memset(st, 0, sizeof(*st));
+    if (!page_size_ok(page_size) || (nr > 0 && r == NULL) || src == NULL || image == NULL) {
+        st->code = ORC_EINVAL;
+        return ORC_EINVAL;
+    }
+    for (uint32_t i = 0; i < nr; ++i) {
+        if (r[i].len % page_size != 0) {
+            st->code = ORC_EINVAL;
+            return ORC_EINVAL;
+        }
+    }
+    const uint64_t P = page_size;
+
+    /* flatten: first page of each region, total G */
+    uint64_t G = 0;
+    uint64_t* first = (uint64_t*)calloc(nr ? nr : 1, sizeof(uint64_t));
+    for (uint32_t i = 0; i < nr; ++i) {
+        first[i] = G;
+        G += r[i].len / P;
+    }
+    const uint64_t W = (G + 63) / 64;
+    const uint64_t prefix_end = 64 + 32 * (uint64_t)nr + 8 * W;
+    const uint64_t data_off = round_up(prefix_end, 4096);
+    uint8_t* cur = (uint8_t*)malloc(P);
+    uint8_t* sh = (uint8_t*)malloc(P);
+    uint64_t* bitmap = (uint64_t*)calloc(W ? W : 1, sizeof(uint64_t));
+    int rc = ORC_OK;
+    if (image_cap < data_off)
+        rc = ORC_EINVAL;
+
+    /* diff: one bit per page */
+    uint64_t D = 0;
+    for (uint32_t i = 0; i < nr && rc == ORC_OK; ++i) {
+        for (uint64_t p = 0; p < r[i].len / P; ++p) {
+            const uint64_t g = first[i] + p;
+            if (src(user, i, p, cur, r[i].has_shadow ? sh : NULL) != 0) {
+                rc = ORC_EINVAL;
+                break;
+            }
+            const int dirty = !r[i].has_shadow || memcmp(cur, sh, P) != 0;
+            if (dirty) {
+                bitmap[g / 64] |= (uint64_t)1 << (g % 64);
+                D += 1;
+            }
+        }
+    }
+    const uint64_t total = data_off + D * P + round_up(4 * D, 8);
+    if (rc == ORC_OK) {
+        st->n_dirty = D;
+        st->total_pages = G;
+        st->image_bytes = total;
+        if (bitmap_out) {
+            for (uint64_t w = 0; w < W && w < bitmap_out_words; ++w)
+                bitmap_out[w] = bitmap[w];
+        }
+        if (total > image_cap)
+            rc = ORC_ENOSPC;
+    }
+
+    if (rc == ORC_OK) {
+        /* header, region table, bitmap, zero pad */
+        memset(image, 0, data_off);
+        memcpy(image, "CRUMIMG1", 8);
+        put_u32(image + 8, 1);
+        put_u32(image + 12, page_size);
+        put_u32(image + 16, nr);
+        uint32_t img_flags = 1;
+        for (uint32_t i = 0; i < nr; ++i)
+            if (r[i].has_shadow)
+                img_flags = 0;
+        put_u32(image + 20, img_flags);
+        put_u64(image + 24, G);
+        put_u64(image + 32, D);
+        put_u64(image + 40, seq);
+        put_u64(image + 48, data_off);
+        for (uint32_t i = 0; i < nr; ++i) {
+            uint8_t* e = image + 64 + 32 * (uint64_t)i;
+            put_u64(e, r[i].id);
+            put_u64(e + 8, r[i].len);
+            put_u64(e + 16, first[i]);
+            put_u64(e + 24, 0);
+        }
+        for (uint64_t w = 0; w < W; ++w)
+            put_u64(image + 64 + 32 * (uint64_t)nr + 8 * w, bitmap[w]);
+
+        /* pages in ascending g, and their CRCs */
+        uint8_t* pages = image + data_off;
+        uint8_t* crcs = pages + D * P;
+        uint64_t k = 0;
+        for (uint32_t i = 0; i < nr && rc == ORC_OK; ++i) {
+            for (uint64_t p = 0; p < r[i].len / P; ++p) {
+                const uint64_t g = first[i] + p;
+                if (!((bitmap[g / 64] >> (g % 64)) & 1u))
+                    continue;
+                if (src(user, i, p, pages + k * P, NULL) != 0) {
+                    rc = ORC_EINVAL;
+                    break;
+                }
+                put_u32(crcs + 4 * k, orc_crc32c(pages + k * P, P));
+                k += 1;
+            }
+        }
+        if (rc == ORC_OK) {
+            memset(crcs + 4 * D, 0, round_up(4 * D, 8) - 4 * D);
+            put_u32(image + 60, orc_crc32c(crcs, 4 * D));
+            put_u32(image + 56, 0);
+            put_u32(image + 56, orc_crc32c(image, prefix_end));
+        }
+    }
+    free(first);
+    free(cur);
+    free(sh);
+    free(bitmap);
+    if (rc == ORC_EINVAL) {
+        memset(st, 0, sizeof(*st));
+    }
+    st->code = rc;
+    return rc;
 }
 
 /* ------------------------------------------------------------------- parse */

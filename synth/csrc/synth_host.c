@@ -110,3 +110,59 @@ void synth_mutate_host(uint8_t* region_bytes, uint64_t page_size, const int64_t*
         synth_mutate_page_host(region_bytes + (uint64_t)pages[i] * page_size, page_size, kind, ms,
                                region, (uint64_t)pages[i]);
 }
+
+/*
+ * Page source for a streamed-input snapshot: page `page` of region `region`
+ * of a scenario, regenerated on the host.  The current bytes are generator
+ * output; the shadow's copy equals them, with the mutation rule above applied
+ * when the page is in the region's (sorted) list of mutated pages.  Returns 0,
+ * or -1 for a page or region out of range.  Generation only: nothing here
+ * compares, packs or checksums.
+ */
+typedef struct {
+    uint64_t nbytes;
+    uint64_t fill_seed;
+    uint64_t fill_region;
+    const int64_t* mutated; /* sorted page indices whose shadow differs */
+    uint64_t n_mutated;
+    int32_t mut_kind;
+    int32_t has_shadow;
+} synth_src_region;
+
+typedef struct {
+    uint64_t page_size;
+    uint64_t mut_seed;
+    uint64_t n_regions;
+    const synth_src_region* regions;
+} synth_src;
+
+static int sorted_contains(const int64_t* a, uint64_t n, int64_t v)
+{
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (a[mid] < v)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo < n && a[lo] == v;
+}
+
+int synth_page_source(void* user, uint32_t region, uint64_t page, uint8_t* cur, uint8_t* shadow)
+{
+    const synth_src* s = (const synth_src*)user;
+    if (region >= s->n_regions)
+        return -1;
+    const synth_src_region* r = &s->regions[region];
+    const uint64_t P = s->page_size;
+    if ((page + 1) * P > r->nbytes)
+        return -1;
+    synth_fill_host(cur, P, r->fill_seed, r->fill_region, page * P);
+    if (shadow) {
+        memcpy(shadow, cur, P);
+        if (r->has_shadow && sorted_contains(r->mutated, r->n_mutated, (int64_t)page))
+            synth_mutate_page_host(shadow, P, r->mut_kind, s->mut_seed, r->fill_region, page);
+    }
+    return 0;
+}

@@ -130,6 +130,38 @@ def mutate_host(buf: np.ndarray, page_size: int, pages, kind: int, ms: int, regi
                                  kind, ms, region)
 
 
+class _SrcRegion(ctypes.Structure):
+    _fields_ = [("nbytes", ctypes.c_uint64), ("fill_seed", ctypes.c_uint64),
+                ("fill_region", ctypes.c_uint64), ("mutated", ctypes.c_void_p),
+                ("n_mutated", ctypes.c_uint64), ("mut_kind", ctypes.c_int32),
+                ("has_shadow", ctypes.c_int32)]
+
+
+class _Src(ctypes.Structure):
+    _fields_ = [("page_size", ctypes.c_uint64), ("mut_seed", ctypes.c_uint64),
+                ("n_regions", ctypes.c_uint64), ("regions", ctypes.c_void_p)]
+
+
+class PageSource:
+    """A scenario as a C page source (``synth_page_source``): ``fn`` is the
+    function's address and ``user`` the address of its argument block, valid
+    while this object lives.  Region i of the scenario is source region i."""
+
+    def __init__(self, scn):
+        self._lists = [np.ascontiguousarray(r.dirty_pages, dtype=np.int64) for r in scn.regions]
+        self._regs = (_SrcRegion * max(1, len(scn.regions)))()
+        for i, (r, lst) in enumerate(zip(scn.regions, self._lists)):
+            self._regs[i] = _SrcRegion(r.nbytes, r.fill_seed, r.fill_region,
+                                       lst.ctypes.data if lst.size else None, lst.size,
+                                       r.mut_kind, 1 if r.has_shadow else 0)
+        self._src = _Src(scn.page_size, scn.mut_seed, len(scn.regions),
+                         ctypes.cast(self._regs, ctypes.c_void_p))
+        self.fn = ctypes.cast(host_lib().synth_page_source, ctypes.c_void_p).value
+        self.user = ctypes.addressof(self._src)
+        self.regions = [(r.nbytes, r.id, bool(r.has_shadow)) for r in scn.regions]
+        self.page_size = scn.page_size
+
+
 def _check(rc: int, what: str) -> None:
     if rc != 0:
         raise RuntimeError(f"{what} failed with code {rc}")
