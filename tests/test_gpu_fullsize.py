@@ -1,13 +1,13 @@
 """GPU parity at the benchmark workloads' full sizes, in the launch
 configuration bench.py times (default context shapes, the chunk-pipelined
-order where the capacity allows it).  The oracle cannot take 16-71 GB whole,
-so these tests check what it can compute one page at a time and properties
-that hold at any size:
+order where the capacity allows it).  The regions are tens of GB, so the
+oracle takes their bytes one page at a time (``oracle.snapshot_stream`` over
+the scenario regenerated on the host by ``synth.lib.PageSource``) and its
+whole image is compared with the GPU's byte for byte: header, region table,
+bitmap, every packed page, every CRC, both checksums.  Besides:
 
 * the bitmap equals the scenario's chosen dirty set (each chosen page differs
   from its shadow by construction, every other page is equal);
-* sampled packed pages equal the generator bytes regenerated on the host, and
-  their CRCs equal the oracle's CRC-32C of those bytes;
 * the oracle's parser accepts the image (magic, layout, popcount, both
   checksums, length);
 * the diff-first order gives the same image byte for byte;
@@ -57,6 +57,28 @@ def check_image(img, scn, n_samples, rng, seq):
         assert int(crcs[k]) == oracle.crc32c(page), f"crc of slot {k}"
 
 
+def oracle_image(scn, seq):
+    """The oracle's image of a scenario, region bytes streamed page by page."""
+    from synth.lib import PageSource
+    src = PageSource(scn)
+    st, img, _ = oracle.snapshot_stream(src.regions, scn.page_size, src.fn, src.user, seq=seq)
+    assert st.code == oracle.OK and st.n_dirty == scn.n_dirty, st
+    return img
+
+
+def assert_same_image(got, want, what):
+    """Byte-for-byte equality; on failure, name the first differing byte's
+    part of the image."""
+    if got.size == want.size and np.array_equal(got, want):
+        return
+    n = min(got.size, want.size)
+    diff = np.flatnonzero(got[:n] != want[:n])
+    first = int(diff[0]) if diff.size else n
+    raise AssertionError(f"{what}: images differ (sizes {got.size}/{want.size}, "
+                         f"first differing byte {first}, {diff.size} bytes differ)")
+
+
+@pytest.mark.timeout(900)
 def test_many_allocs_16gib():
     """The 16 GiB many-allocations workload (64 regions, 64 KiB pages)."""
     import bench
@@ -90,6 +112,11 @@ def test_many_allocs_16gib():
         assert np.array_equal(images[0], images[1]), "the two orders disagree"
         rng = np.random.default_rng(16)
         check_image(images[0], scn, 64, rng, seq=11)
+        log("[fullsize] many_allocs: oracle image (streamed)")
+        want = oracle_image(scn, 11)
+        assert_same_image(images[0], want, "pipelined order vs oracle")
+        assert_same_image(images[1], want, "diff-first order vs oracle")
+        del want
         # overwrite 8 dirty pages on the device, restore, check them and a clean page
         counts, starts = page_index(scn)
         want = scn.dirty_global()
@@ -116,6 +143,7 @@ def test_many_allocs_16gib():
         himg.free()
 
 
+@pytest.mark.timeout(900)
 def test_managed_32gib():
     """The 32 GiB managed workload, 70 % of pages written by host threads and
     30 % prefetched and written by a kernel."""
@@ -157,6 +185,8 @@ def test_managed_32gib():
         st = crum.read_status(status.ptr)
         assert st.code == 0 and st.n_dirty == D and st.image_bytes == ib, st
         check_image(himg.numpy(ib), scn, 24, np.random.default_rng(32), seq=3)
+        log("[fullsize] managed: oracle image (streamed)")
+        assert_same_image(himg.numpy(ib), oracle_image(scn, 3), "managed image vs oracle")
     finally:
         crum.crum_ctx_destroy(ctx)
         cur.free()
@@ -165,10 +195,11 @@ def test_managed_32gib():
         himg.free()
 
 
+@pytest.mark.timeout(1200)
 def test_batched_256_requests():
     """The 256-request batch (71 GB scanned) in one plan launch with the
-    package's tuned shapes: every request's status, and sampled requests'
-    images against their scenarios."""
+    package's tuned shapes: every request's status, and every request's image
+    against the oracle's, byte for byte."""
     import bench
     import paper_1808_00117_amd as crum
     import paper_1808_00117_amd.hip as H
@@ -205,6 +236,11 @@ def test_batched_256_requests():
             off, b = sts[q][5], sts[q][4]
             check_image(himg.numpy(off + b)[off:], reqs[q], 4, rng, seq=9)
         plan.destroy()
+        log("[fullsize] batched: oracle images (streamed), 256 requests")
+        for q in range(len(reqs)):
+            off, b = sts[q][5], sts[q][4]
+            assert_same_image(himg.numpy(off + b)[off:], oracle_image(reqs[q], 9),
+                              f"request {q} vs oracle")
     finally:
         crum.crum_ctx_destroy(ctx)
         for pr in pairs:
