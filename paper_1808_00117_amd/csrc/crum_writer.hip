@@ -106,7 +106,7 @@ void finish(crum_writer* w, Job& j)
     if (close(j.fd_buf) != 0 && !err)
         err = errno;
     std::lock_guard<std::mutex> lk(w->mu);
-    j.st.code = err ? CRUM_EIO : CRUM_OK;
+    j.st.code = err ? (int32_t)CRUM_EIO : (int32_t)CRUM_OK;
     j.st.err = err;
     j.st.bytes = err ? 0 : j.bytes;
     j.st.direct = j.direct_used.load() ? 1u : 0u;

@@ -1,0 +1,58 @@
+"""Host code under sanitizers (CPU, gcc): the serving loop's scheduling core
+with a stub backend, the image writer, and the CPU oracle, each built with
+AddressSanitizer + UndefinedBehaviorSanitizer, and the two multi-threaded
+ones also with ThreadSanitizer.  Each program checks its own results and
+exits non-zero on the first failed check or sanitizer report."""
+import os
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+INC = os.path.join(ROOT, "include")
+CSRC = os.path.join(ROOT, "paper_1808_00117_amd", "csrc")
+C = os.path.join(ROOT, "tests", "c")
+
+SAN = {"asan": ["-fsanitize=address,undefined", "-fno-sanitize-recover=all"],
+       "tsan": ["-fsanitize=thread"]}
+
+
+def build(cmd):
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+
+
+def run(cmd, **kw):
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
+               TSAN_OPTIONS="halt_on_error=1", UBSAN_OPTIONS="halt_on_error=1")
+    r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=600, **kw)
+    assert r.returncode == 0, r.stdout + r.stderr
+    return r.stdout
+
+
+@pytest.mark.parametrize("san", ["asan", "tsan"])
+def test_serve_core(tmp_path, san):
+    exe = str(tmp_path / "serve_core")
+    build(["g++", "-std=c++17", "-g", "-O1", "-fno-omit-frame-pointer", *SAN[san], "-Wall",
+           "-Wextra", "-Werror", "-I" + INC, "-I" + CSRC, os.path.join(C, "serve_core_test.cpp"),
+           "-o", exe, "-lpthread"])
+    assert "serve core: ok" in run([exe, "2"])
+
+
+@pytest.mark.parametrize("san", ["asan", "tsan"])
+def test_writer(tmp_path, san):
+    exe = str(tmp_path / "writer")
+    build(["g++", "-std=c++17", "-g", "-O1", "-fno-omit-frame-pointer", *SAN[san], "-Wall",
+           "-Werror", "-I" + INC, "-x", "c++", os.path.join(CSRC, "crum_writer.hip"), "-x",
+           "none", os.path.join(C, "writer_sanitize.cpp"), "-o", exe, "-lpthread"])
+    d = tmp_path / "files"
+    d.mkdir()
+    assert "writer sanitize: ok" in run([exe, str(d)])
+
+
+def test_oracle(tmp_path):
+    exe = str(tmp_path / "oracle")
+    build(["gcc", "-std=c11", "-g", "-O1", "-fno-omit-frame-pointer", *SAN["asan"], "-Wall",
+           "-Wextra", "-Werror", os.path.join(C, "oracle_sanitize.c"),
+           os.path.join(ROOT, "oracle", "crum_oracle.c"), "-o", exe])
+    assert "oracle sanitize: ok" in run([exe, "40"])
