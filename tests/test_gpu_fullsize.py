@@ -238,6 +238,8 @@ def test_batched_256_requests():
         plan.destroy()
         log("[fullsize] batched: oracle images (streamed), 256 requests")
         for q in range(len(reqs)):
+            if q % 32 == 0:
+                log(f"[fullsize] batched: oracle image of request {q}")
             off, b = sts[q][5], sts[q][4]
             assert_same_image(himg.numpy(off + b)[off:], oracle_image(reqs[q], 9),
                               f"request {q} vs oracle")
