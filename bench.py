@@ -48,8 +48,12 @@ def parse_args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="many",
-                    choices=["many", "plain", "batched", "served", "managed", "persist", "lazy"])
+    ap.add_argument("--config", default="headline",
+                    choices=["headline", "many", "plain", "batched", "served", "managed",
+                             "persist", "lazy"],
+                    help="headline (default): the batched 256-request workload, batched vs "
+                         "plain, then the 16 GiB many-allocations snapshot beside its "
+                         "co-runner (diff roofline, drain, pack, restore) and the CPU oracle")
     ap.add_argument("--lazy-step", type=int, default=8 << 20,
                     help="lazy: bytes per touch of the sequential sweep")
     ap.add_argument("--persist-dir", default=None,
@@ -75,8 +79,12 @@ def parse_args():
     ap.add_argument("--cold", action="store_true",
                     help="plain workload: rotate over 8 independent (current, shadow) pairs "
                          "(1 GiB working set, larger than the 256 MB last-level cache)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="target CPU time of the oracle baseline leg (0 disables it)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="wall time of each CPU oracle baseline leg, one thread and all "
+                         "threads (0 disables them)")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="threads of the all-core oracle leg (0: every usable hardware "
+                         "thread, at most 16)")
     ap.add_argument("--quick", action="store_true",
                     help="skip the untimed reference phases (for profiler runs)")
     ap.add_argument("--pmc-calibrate", action="store_true",
@@ -199,12 +207,17 @@ def load_traffic(workload: str, launches_bytes: float):
     return d.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(scn, budget_s: float):
-    """Time the CPU oracle (single-threaded, as it stands) on a bounded
-    sample of the same workload: whole regions in table order up to 1 GiB,
-    regenerated on the host (untimed), snapshotted repeatedly until about
-    `budget_s` seconds of oracle time have accrued."""
-    import numpy as np
+def cpu_baseline(scn, budget_s: float, threads: int = 0) -> dict:
+    """Time the CPU oracle (as it stands: plain single-threaded C) on a
+    bounded sample of the same workload: whole regions in table order up to
+    1 GiB, regenerated on the host (untimed).  Two legs of about `budget_s`
+    seconds each: one thread snapshotting the sample repeatedly, then
+    `threads` threads (default: every hardware thread this process may use,
+    at most 16) each snapshotting the same sample repeatedly and independently
+    (the oracle call releases the GIL; the inputs are only read).  Reported as
+    scanned GB/s: sample bytes x snapshots / wall time."""
+    import threading
+
     import oracle
     from synth import scenarios as sc
 
@@ -221,20 +234,43 @@ def cpu_baseline(scn, budget_s: float):
     P = scn.page_size
     G = total // P
     cap = oracle.prefix_bytes(len(regs), G) + dirty * P + ((4 * dirty + 7) // 8) * 8
-    t_acc, n_runs = 0.0, 0
-    while t_acc < budget_s or n_runs == 0:
+    oracle.crc32c(b"")  # the oracle's CRC table is built before any thread starts
+
+    def leg(n_threads):
+        counts = [0] * n_threads
+        stop_at = [0.0]
+
+        def worker(k):
+            while True:
+                st, img, _ = oracle.snapshot(regs, P, image_cap=cap)
+                assert st.code == oracle.OK and st.n_dirty == dirty
+                del img
+                counts[k] += 1
+                if time.perf_counter() >= stop_at[0]:
+                    return
         t0 = time.perf_counter()
-        st, img, _ = oracle.snapshot(regs, P, image_cap=cap)
-        t_acc += time.perf_counter() - t0
-        n_runs += 1
-        assert st.code == oracle.OK and st.n_dirty == dirty
-        del img
-    gbs = total * n_runs / t_acc / 1e9
-    return {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "host": host_cpu(),
-            "sample": f"{len(regs)} whole regions in table order, {total / 2**30:.2f} GiB "
-                      f"scanned, {dirty} dirty {P // 1024} KiB pages, snapshotted "
-                      f"{n_runs}x single-threaded ({t_acc:.1f} s)"}
+        stop_at[0] = t0 + budget_s
+        ths = [threading.Thread(target=worker, args=(k,)) for k in range(n_threads)]
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+        wall = time.perf_counter() - t0
+        return total * sum(counts) / wall / 1e9, sum(counts), wall
+
+    host = host_cpu()
+    if threads <= 0:
+        threads = max(1, min(16, host["threads_available"] or 1))
+    one_gbs, one_n, one_s = leg(1)
+    all_gbs, all_n, all_s = leg(threads)
+    sample = (f"{len(regs)} whole regions in table order, {total / 2**30:.2f} GiB scanned, "
+              f"{dirty} dirty {P // 1024} KiB pages")
+    return {"value": round(all_gbs, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "host": host,
+            "sample": f"{sample}; {threads} threads each snapshotting the sample independently, "
+                      f"{all_n} snapshots in {all_s:.1f} s",
+            "single_core": {"value": round(one_gbs, 3), "unit": "GB/s", "cores": 1,
+                            "sample": f"{sample}; {one_n} snapshots in {one_s:.1f} s"}}
 
 
 def settle_copy_engines(H, dev_ptr: int, host_ptr: int, nbytes: int = 256 << 20,
@@ -337,7 +373,18 @@ def host_cpu() -> dict:
         threads = len(os.sched_getaffinity(0))
     except (AttributeError, OSError):
         threads = os.cpu_count()
-    return {"cpu_model": model, "threads_available": threads}
+    out = {"cpu_model": model, "threads_available": threads, "nproc": os.cpu_count()}
+    try:
+        import subprocess
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        f = dict((k.strip(), v.strip()) for k, v in
+                 (ln.split(":", 1) for ln in txt.splitlines() if ":" in ln))
+        out["lscpu"] = {k: f.get(k) for k in ("Model name", "Socket(s)", "Core(s) per socket",
+                                              "Thread(s) per core", "CPU(s)")}
+        out["physical_cores"] = int(f["Socket(s)"]) * int(f["Core(s) per socket"])
+    except Exception:
+        pass
+    return out
 
 
 def read_ceiling(H, scn, pairs, stream, reps: int = 7) -> dict:
@@ -373,12 +420,16 @@ def percentile(v, q):
     return v[min(len(v) - 1, int(round(q * (len(v) - 1))))]
 
 
-def bench_batched(args):
+def bench_batched(args) -> dict:
     """Batched workload: 256 requests (1-32 allocations each, request totals
     log-uniform 1 MiB-2 GiB, 4 KiB or 64 KiB pages, dirty fraction U(1%, 50%)
     in runs of mean 16) snapshotted by one plan launch (captured graphs, one
     per group of requests), against 256 one-at-a-time plain snapshots of the
-    same requests into the same host offsets; images compared byte for byte."""
+    same requests into the same host offsets; images compared byte for byte.
+    Three plans are timed: the grouped plan (tuned shapes, caller's order),
+    the same plan smallest request first, and a one-graph plan (a single group
+    holding all 256 requests: one persistent diff, one drain).  Returns the
+    result dict."""
     import numpy as np
 
     import paper_1808_00117_amd as crum
@@ -495,6 +546,20 @@ def bench_batched(args):
     batched_image = h_images.numpy(cap)[: max(o + b for o, b in zip(offsets, sizes))].copy()
     plan.destroy()
 
+    # one graph for the whole batch: a single group (one persistent diff
+    # over every unit of the 256 requests, one scan, one pack, one drain)
+    crum.crum_ctx_set_param(ctx, crum.CRUM_PARAM_CHUNK_BYTES, N)
+    crum.crum_ctx_set_param(ctx, crum.CRUM_PARAM_CHUNK_MAX_BYTES, N)
+    plan = make_plan()
+    mk_1, lat_1, sts_1, n_groups_1 = timed(plan)
+    img_1 = h_images.numpy(cap)
+    same_1 = all(np.array_equal(img_1[st[5]:st[5] + b], batched_image[o:o + b])
+                 for st, o, b in zip(sts_1, offsets, sizes))
+    assert same_1 and n_groups_1 == 1, "one-graph images differ from the grouped plan's"
+    plan.destroy()
+    autotune.apply(ctx, {"chunk_bytes": params["chunk_bytes"],
+                         "chunk_max_bytes": params["chunk_max_bytes"]})
+
     # the same plan with the smallest requests first: same images, each at
     # its own offset
     crum.crum_ctx_set_param(ctx, crum.CRUM_PARAM_PLAN_ORDER, 1)
@@ -556,15 +621,26 @@ def bench_batched(args):
                    "groups": n_groups, "params": params, "tuned": bool(tuned),
                    "settle": settle},
         "batched": {"makespan_ms": round(mk_ms, 2),
+                    "gbs": round(N / statistics.median(mk) / 1e9, 2),
+                    "groups": n_groups,
                     "makespans_ms": [round(1e3 * v, 1) for v in mk],
                     "latency_ms": {"p50": round(percentile(lat_b, 0.5), 2),
                                    "p99": round(percentile(lat_b, 0.99), 2)},
                     "drain_gbs": round(sum(sizes) / statistics.median(mk) / 1e9, 2)},
         "batched_smallest_first": {
             "makespan_ms": round(1e3 * statistics.median(mk_s), 2),
+            "gbs": round(N / statistics.median(mk_s) / 1e9, 2),
             "latency_ms": {"p50": round(percentile(lat_s, 0.5), 2),
                            "p99": round(percentile(lat_s, 0.99), 2)},
             "groups": n_groups_s, "same_images": same_s},
+        "batched_one_graph": {
+            "makespan_ms": round(1e3 * statistics.median(mk_1), 2),
+            "gbs": round(N / statistics.median(mk_1) / 1e9, 2),
+            "latency_ms": {"p50": round(percentile(lat_1, 0.5), 2),
+                           "p99": round(percentile(lat_1, 0.99), 2)},
+            "groups": n_groups_1, "same_images": same_1,
+            "what": "all 256 requests in one captured graph (one persistent diff, one "
+                    "scan, one pack), drained by one copy when the graph ends"},
         "plain": {"makespan_ms": round(1e3 * t_plain, 2),
                   "gbs": round(N / t_plain / 1e9, 2),
                   "latency_ms": {"p50": round(1e3 * percentile(lat_p, 0.5), 2),
@@ -573,6 +649,78 @@ def bench_batched(args):
     }
     crum.crum_ctx_destroy(ctx)
     crum.crum_ctx_destroy(pctx)
+    for pr in pairs:
+        for c, sh in pr:
+            c.free()
+            if sh:
+                sh.free()
+    for b in (staging, h_images, status, pstage, pstatus):
+        b.free()
+    return result
+
+
+HEADLINE_METRIC = ("snapshot GB/s (diff+CRC+compact+drain) and p99 latency, batched vs plain")
+
+
+def bench_headline(args):
+    """The default line.  Headline: the batched workload (256 snapshot
+    requests, 71 GB scanned), one plan launch per step against the same 256
+    requests snapshotted one at a time by the plain path: GB/s, makespan and
+    p50/p99 request latency of both, images equal byte for byte.  Then the
+    16 GiB many-allocations snapshot beside its SAXPY co-runner, which gives
+    the diff kernel's roofline (HIP events around each launch over its timed
+    snapshots), the drain against the host link, the pack, verify and
+    scatter rates, and a verified restore; then the CPU oracle on one thread
+    and on all threads.  One JSON line."""
+    b = bench_batched(args)
+    log(f"[bench] batched leg: {b['value']} GB/s, p99 {b['batched']['latency_ms']['p99']} ms "
+        f"vs plain {b['plain']['latency_ms']['p99']} ms")
+    m = bench_many(args, with_cpu=False)
+    cpu = None
+    if args.cpu_seconds > 0:
+        from synth import scenarios as sc
+        log("[bench] CPU oracle baseline ...")
+        cpu = cpu_baseline(sc.many_allocs(), args.cpu_seconds, args.cpu_threads)
+    bat, pl = b["batched"], b["plain"]
+    roof = dict(m["roofline"])
+    roof["workload"] = ("the 16 GiB many-allocations snapshot (64 regions, 64 KiB pages) "
+                        "beside the SAXPY co-runner: its own timed snapshots in this run")
+    many = {k: m[k] for k in ("value", "unit", "ms_per_step", "latency_ms", "config", "restore",
+                              "roofline_alone", "drain", "pack", "header", "breakdown_timed",
+                              "overlap")}
+    many["metric"] = m["metric"]
+    many["steps"] = m["steps"]
+    result = {
+        "metric": HEADLINE_METRIC,
+        "value": b["value"],
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": b["steps"],
+        "warmup": b["warmup"],
+        "ms_per_step": b["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": b["data"],
+        "config": dict(b["config"], parallelism="single GPU",
+                       step="one plan launch snapshotting all 256 requests, ending when "
+                            "every image has landed in pinned host memory"),
+        "latency_ms": bat["latency_ms"],
+        "batched": bat,
+        "batched_smallest_first": b["batched_smallest_first"],
+        "batched_one_graph": b["batched_one_graph"],
+        "plain": pl,
+        "bit_exact_vs_plain": b["bit_exact_vs_plain"],
+        "vs_plain": {"gbs_ratio": round(b["value"] / pl["gbs"], 3),
+                     "p50_ratio": round(bat["latency_ms"]["p50"] / pl["latency_ms"]["p50"], 3),
+                     "p99_ratio": round(bat["latency_ms"]["p99"] / pl["latency_ms"]["p99"], 3)},
+        "roofline": roof,
+        "drain": m["drain"],
+        "pack": m["pack"],
+        "many_allocs": many,
+        "cpu_baseline": cpu,
+    }
     print(json.dumps(result), flush=True)
 
 
@@ -1193,8 +1341,11 @@ def main():
               "multi-GPU runs are not part of this build (each GPU would snapshot its own "
               "regions independently).", file=sys.stderr)
         sys.exit(2)
+    if args.config == "headline":
+        return bench_headline(args)
     if args.config == "batched":
-        return bench_batched(args)
+        print(json.dumps(bench_batched(args)), flush=True)
+        return
     if args.config == "served":
         return bench_served(args)
     if args.config == "managed":
@@ -1203,6 +1354,15 @@ def main():
         return bench_persist(args)
     if args.config == "lazy":
         return bench_lazy(args)
+    print(json.dumps(bench_many(args)), flush=True)
+
+
+def bench_many(args, with_cpu: bool = True) -> dict:
+    """The single-request workloads (`--config many`, the 16 GiB
+    many-allocations snapshot beside a SAXPY co-runner, or `--config plain`,
+    the 64 MiB one): K timed snapshots, the diff kernel's roofline, the
+    drain against the host link, pack and header times, and a verified
+    restore of the last image.  Returns the result dict."""
     import numpy as np
 
     import paper_1808_00117_amd as crum
@@ -1468,6 +1628,10 @@ def main():
         if n_v else None,
         "scatter_gbs": round(2 * D * P * n_sc / max(scatter_ms * 1e-3, 1e-12) / 1e9, 1)
         if n_sc else None,
+        "verify_frac": round((D * P + 4 * D) * n_v / max(verify_ms * 1e-3, 1e-12) / 1e9 /
+                             HBM_PEAK_GBS, 4) if n_v else None,
+        "scatter_frac": round(2 * D * P * n_sc / max(scatter_ms * 1e-3, 1e-12) / 1e9 /
+                              HBM_PEAK_GBS, 4) if n_sc else None,
         "what": "H2D of the image from pinned memory, CRC verify of every page, scatter",
     }
 
@@ -1533,7 +1697,9 @@ def main():
                   "copies": n_dr, "reference": link_ref,
                   "what": None if drain_gbs else "no drain copies: the image was built in "
                                                    "the pinned host image (direct order)"},
-        "pack": {"achieved": round(pack_gbs, 1), "unit": "GB/s",
+        "pack": {"achieved": round(pack_gbs, 1), "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                 "frac": round(pack_gbs / HBM_PEAK_GBS, 4), "launches": n_pk,
+                 "avg_launch_ms": round(pack_ms / max(n_pk, 1), 4),
                  "algorithmic_bytes_per_step": pack_bytes,
                  "what": None if drain_gbs else "direct order: the pack's stores cross the "
                                                 "host link into the pinned image"},
@@ -1550,13 +1716,20 @@ def main():
             "saxpy_gbs_with_snapshot": round(sax_with, 1) if sax_with else None,
         },
     }
-    if args.cpu_seconds > 0:
+    if args.cpu_seconds > 0 and with_cpu:
         log("[bench] CPU oracle baseline ...")
-        result["cpu_baseline"] = cpu_baseline(scn, args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(scn, args.cpu_seconds, args.cpu_threads)
     else:
         result["cpu_baseline"] = None
     crum.crum_ctx_destroy(ctx)
-    print(json.dumps(result), flush=True)
+    for pairs in pair_sets:
+        for c, s in pairs:
+            c.free()
+            if s:
+                s.free()
+    for b in (staging, h_image, status, x, y):
+        b.free()
+    return result
 
 
 if __name__ == "__main__":

@@ -327,7 +327,8 @@ void crum_server_destroy(crum_server* server);
  *   caller's, 1 = smallest scanned bytes first (0).
  * CRUM_PARAM_DIRECT_BYTES: snapshots whose image with every page dirty is at
  *   most this many bytes are built straight in the pinned host image (see
- *   crum_snapshot); 0 turns the direct order off (128 MiB).
+ *   crum_snapshot), an opt-in alternative to the staged drain; 0 turns the
+ *   direct order off (0: every image is drained by hipMemcpyAsync).
  * CRUM_PARAM_CRC_VARIANT: how the pack and verify kernels' CRC step splits
  *   its table lookups between 256-entry byte tables (bank conflicts) and
  *   16-entry nibble tables (conflict-free, more ALU work): 0 = byte tables

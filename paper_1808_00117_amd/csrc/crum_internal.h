@@ -124,7 +124,7 @@ struct crum_ctx {
     int diff_prio = 0;
     int crc_variant = crum::kCrcVariantAuto;
     int plan_order = 0;
-    uint64_t direct_bytes = 128ull << 20;  // worst-case images up to this size go straight to the host
+    uint64_t direct_bytes = 0;  // opt-in: worst-case images up to this size go straight to the host
     bool eager = true;
     uint32_t timing_mask = 0;  // bit c: time launches of class c
     bool partial_call = false;  // a call stopped part-way through its enqueue

@@ -94,3 +94,15 @@ def test_autotune_search_and_cache(tmp_path, monkeypatch):
     assert autotune.load("missing", path) is None
     assert autotune.load("batched", str(tmp_path / "none.json")) is None
     assert set(json.load(open(path))["test-device|hip0"]) == {"batched", "other"}
+
+
+def test_cpu_baseline_reports_one_and_all_threads():
+    """The CPU baseline times the unchanged oracle on one thread and on
+    several threads over the same host-regenerated sample."""
+    import bench
+    from synth import scenarios as sc
+    res = bench.cpu_baseline(sc.plain(nbytes=2 << 20), 0.2, threads=2)
+    assert res["kind"] == "oracle" and res["cores"] == 2 and res["unit"] == "GB/s"
+    assert res["value"] > 0 and res["single_core"]["cores"] == 1
+    assert res["single_core"]["value"] > 0
+    assert res["host"]["threads_available"] >= 1
