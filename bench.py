@@ -675,7 +675,7 @@ def bench_headline(args):
     b = bench_batched(args)
     log(f"[bench] batched leg: {b['value']} GB/s, p99 {b['batched']['latency_ms']['p99']} ms "
         f"vs plain {b['plain']['latency_ms']['p99']} ms")
-    m = bench_many(args, with_cpu=False)
+    m = bench_many(argparse.Namespace(**dict(vars(args), config="many")), with_cpu=False)
     cpu = None
     if args.cpu_seconds > 0:
         from synth import scenarios as sc
@@ -1323,8 +1323,122 @@ def bench_managed(args):
         "parity": "bitmap exact; 24 sampled pages and CRCs equal to host-regenerated bytes; "
                   "image checksums verified by the oracle parser",
     }
+    untracked_image = img.copy()
+    result["tracked"] = managed_tracked_leg(args, scn, cur, sh, table, ctx, staging, himg, cap,
+                                            status, s1, untracked_image, t_total / args.steps)
     crum.crum_ctx_destroy(ctx)
     print(json.dumps(result), flush=True)
+
+
+def managed_tracked_leg(args, scn, cur, sh, table, ctx, staging, himg, cap, status, s1,
+                        untracked_image, untracked_s):
+    """Host write tracking (paper section 3.2, Algorithm 1) on the managed
+    workload.  The host-written pages are written through a tracker's view
+    and flushed into the managed region; the snapshot then reads only the
+    candidate pages: those flushed since the last snapshot, and every
+    device-written page (the device's writes are not tracked).
+
+    Set-up (untimed): the view gets the shadow's bytes of every host page and
+    is flushed (the state at the last snapshot); the device pages are written
+    again by their kernel; the pending set is cleared.  Then the application
+    writes each host page that changed since (the scenario's dirty host pages,
+    with their current bytes) through the view, and a flush moves them into
+    the region.  The managed region then holds exactly the bytes of the
+    untracked runs, and the tracked image must equal theirs byte for byte."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    import paper_1808_00117_amd as crum
+    import synth
+    from synth import scenarios as sc
+
+    r = scn.regions[0]
+    P, G, N, D = scn.page_size, scn.total_pages, scn.total_bytes, scn.n_dirty
+    W = (G + 63) // 64
+    dev_pages = np.asarray(scn.meta["device_pages"], np.int64)
+    host_pages = np.setdiff1d(np.arange(G), dev_pages)
+    dirty_host = np.intersect1d(r.dirty_pages, host_pages)
+    threads = 16
+    t0 = time.perf_counter()
+    tr = crum.Tracker(N, P)
+    try:
+        v = tr.view()
+        dirty_set = set(int(x) for x in r.dirty_pages)
+
+        def write_shadow(p):
+            page = v[p * P:(p + 1) * P]
+            synth.fill_host(P, r.fill_seed, r.fill_region, p * P, out=page)
+            if p in dirty_set:
+                sc._mutate_one(page, P, p, r.mut_kind, scn.mut_seed, r.fill_region)
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(write_shadow, (int(p) for p in host_pages)))
+        tr.flush(cur.ptr, threads)
+        fill_managed_device(cur, scn, 0, dev_pages)
+        tr.pending(clear=True)
+        f0 = tr.stats()["faults"]
+        t_setup = time.perf_counter() - t0
+
+        # the application's writes since the last snapshot, then the flush of
+        # Algorithm 1 before the next call into the GPU runtime
+        t0 = time.perf_counter()
+
+        def write_current(p):
+            synth.fill_host(P, r.fill_seed, r.fill_region, p * P, out=v[p * P:(p + 1) * P])
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(write_current, (int(p) for p in dirty_host)))
+        t_writes = time.perf_counter() - t0
+        faults = tr.stats()["faults"] - f0
+        t0 = time.perf_counter()
+        n_flushed = tr.flush(cur.ptr, threads)
+        t_flush = time.perf_counter() - t0
+        pend = tr.pending(clear=False)
+        pend_pages = np.flatnonzero(np.unpackbits(pend.view(np.uint8), bitorder="little"))
+        assert np.array_equal(pend_pages, dirty_host), "pending set differs from the writes"
+        cand = pend.copy()
+        for p in dev_pages:
+            cand[p >> 6] |= np.uint64(1) << np.uint64(p & 63)
+        n_cand = int(np.unpackbits(cand.view(np.uint8)).sum())
+        image_bytes = untracked_image.size
+
+        def snap():
+            rc = crum.crum_snapshot_tracked(ctx, table, P, 0, 3, cand, staging.ptr, cap,
+                                            himg.ptr, cap, s1.handle, status.ptr)
+            assert rc == 0, rc
+            s1.synchronize()
+            st = crum.read_status(status.ptr)
+            assert st.code == 0 and st.n_dirty == D and st.image_bytes == image_bytes, st
+
+        snap()
+        same = bool(np.array_equal(himg.numpy(image_bytes), untracked_image))
+        assert same, "tracked image differs from the untracked one"
+        for _ in range(args.warmup):
+            snap()
+        lat = []
+        for _ in range(args.steps):
+            t = time.perf_counter()
+            snap()
+            lat.append(time.perf_counter() - t)
+        ms = 1e3 * statistics.median(lat)
+        return {
+            "what": "host-written pages written through a write-protected view and flushed "
+                    "into the managed region (Algorithm 1); the snapshot reads only pages "
+                    "flushed since the last snapshot and the device-written pages",
+            "candidate_pages": n_cand, "of_pages": G,
+            "candidate_bytes_read": n_cand * P, "pages_flushed": int(n_flushed),
+            "write_faults": int(faults),
+            "snapshot_ms": round(ms, 2),
+            "snapshot_ms_untracked": round(1e3 * untracked_s, 2),
+            "speedup": round(1e3 * untracked_s / ms, 3),
+            "gbs": round(N / (ms * 1e-3) / 1e9, 2),
+            "app_writes_ms": round(1e3 * t_writes, 1),
+            "flush_ms": round(1e3 * t_flush, 1),
+            "flush_gbs": round(n_flushed * P / max(t_flush, 1e-9) / 1e9, 2),
+            "setup_s": round(t_setup, 1),
+            "same_image_as_untracked": same,
+        }
+    finally:
+        tr.destroy()
 
 
 def main():

@@ -157,6 +157,79 @@ int crum_restore(crum_ctx* ctx, const crum_region* regions, uint32_t n_regions,
                  const void* h_image, uint64_t image_bytes, uint32_t flags, void* d_staging,
                  uint64_t staging_bytes, void* stream, crum_status* h_status);
 
+/* ---------------------------------------------------------------------------
+ * Host write tracking (section 3.2, Algorithm 1, and section 3.2.1: the
+ * application writes a shadow of each unified-memory region on the host; a
+ * write to a write-protected page faults and marks the page dirty, and at
+ * each call into the GPU runtime the dirty pages are flushed to the real
+ * region, write-protected again and marked clean; a new region starts with
+ * every page dirty).
+ *
+ * crum_track_create maps a host view of `bytes` bytes (anonymous memory that
+ * the GPU never maps) cut into pages of page_size bytes (a power of two in
+ * [4 KiB, 1 GiB], a multiple of the OS page size, dividing bytes).  The
+ * application writes its data through crum_track_view.  Every page starts
+ * dirty and writable.  A write to a clean (read-only) page is caught by a
+ * SIGSEGV handler that the first tracker installs (once per process, before
+ * any handler installed later; faults outside every view go to the handler
+ * that was installed before it, or take the default action): the page is made
+ * writable and marked dirty, and the write completes.
+ *
+ * crum_track_flush copies every dirty page to the same offset of dst (the real
+ * region: for example a hipMallocManaged allocation, read and written by the
+ * host here), on up to n_threads host threads, after making it read-only and
+ * clearing its dirty bit; each flushed page is added to the pending set.
+ * *n_flushed (may be NULL) receives the pages flushed.
+ *
+ * The pending set holds the pages flushed since it was last cleared:
+ * crum_track_pending copies it as a bitmap (bit p % 64 of words[p / 64] for
+ * page p; n_words words are written, words past the view's pages as zero)
+ * and, with clear, empties it.  A caller that updates the shadows at each
+ * snapshot (CRUM_UPDATE_SHADOW) clears the pending set at the same time; the
+ * pages outside it are then equal to their shadows unless something other
+ * than the view (the GPU) wrote them, and those go into the candidate set of
+ * crum_snapshot_tracked as well.
+ *
+ * Flushes of one tracker are serialised; writes to the view may run on any
+ * thread, also during a flush (a page written while it is copied stays
+ * dirty).  No write to the view may run during crum_track_destroy.  Returns
+ * CRUM_OK or CRUM_EINVAL (bad argument, mmap or mprotect failure, more than
+ * 64 trackers at once).  Host code only: no HIP call is made.
+ * -------------------------------------------------------------------------*/
+typedef struct crum_track crum_track;
+
+typedef struct {
+    uint64_t pages;          /* pages of the view */
+    uint64_t dirty_pages;    /* written since the last flush */
+    uint64_t pending_pages;  /* flushed since the pending set was last cleared */
+    uint64_t faults;         /* write faults taken so far */
+    uint64_t flushed_pages;  /* pages copied by all flushes so far */
+} crum_track_info;
+
+int crum_track_create(uint64_t bytes, uint32_t page_size, crum_track** out);
+void* crum_track_view(crum_track* track);
+int crum_track_flush(crum_track* track, void* dst, uint32_t n_threads, uint64_t* n_flushed);
+int crum_track_pending(crum_track* track, uint64_t* words, uint64_t n_words, int clear);
+/* The dirty set (written since the last flush), as crum_track_pending. */
+int crum_track_dirty(crum_track* track, uint64_t* words, uint64_t n_words);
+int crum_track_stats(crum_track* track, crum_track_info* out);
+void crum_track_destroy(crum_track* track);
+
+/* Snapshot with a candidate set (section 3.2: only pages written since the
+ * last flush can differ from it).  As crum_snapshot, except that a page whose
+ * bit in h_candidates (host memory, bit g % 64 of word g / 64 for global page
+ * g, at least ceil(G/64) words in n_words) is clear is taken to equal its
+ * shadow: neither copy of it is read, and it is not dirty.  The image equals
+ * crum_snapshot's whenever every page that differs from its shadow has its
+ * bit set; regions without a shadow ignore the set (all their pages are
+ * dirty).  The bitmap is read before the call returns.  Returns as
+ * crum_snapshot; CRUM_EINVAL also for h_candidates NULL or n_words too small. */
+int crum_snapshot_tracked(crum_ctx* ctx, const crum_region* regions, uint32_t n_regions,
+                          uint32_t page_size, uint32_t flags, uint64_t seq,
+                          const uint64_t* h_candidates, uint64_t n_words, void* d_staging,
+                          uint64_t staging_bytes, void* h_image, uint64_t h_image_bytes,
+                          void* stream, crum_status* h_status);
+
 /* ---------------------------------------------------------------- batched
  * Many snapshot requests in one plan (the batched pattern).  Each request is a
  * region table with its own page size, flags (CRUM_UPDATE_SHADOW) and seq,

@@ -128,6 +128,15 @@ _SIGS = {
     "crum_lazy_stats": (_I, [_P, _P]),
     "crum_lazy_fetched": (_I, [_P, _P, _U64]),
     "crum_lazy_close": (None, [_P]),
+    "crum_track_create": (_I, [_U64, _U32, ctypes.POINTER(_P)]),
+    "crum_track_view": (_P, [_P]),
+    "crum_track_flush": (_I, [_P, _P, _U32, ctypes.POINTER(_U64)]),
+    "crum_track_pending": (_I, [_P, _P, _U64, _I]),
+    "crum_track_dirty": (_I, [_P, _P, _U64]),
+    "crum_track_stats": (_I, [_P, _P]),
+    "crum_track_destroy": (None, [_P]),
+    "crum_snapshot_tracked": (_I, [_P, _P, _U32, _U32, _U32, _U64, _P, _U64, _P, _U64, _P,
+                                   _U64, _P, _P]),
 }
 
 _lib = None
@@ -193,6 +202,84 @@ def crum_snapshot(ctx: int, regions, page_size: int, flags: int, seq: int, d_sta
     return lib().crum_snapshot(ctx, ctypes.cast(arr, _P) if n else None, n, page_size, flags,
                                seq, d_staging, staging_bytes, h_image or None, h_image_bytes,
                                stream or None, h_status)
+
+
+def crum_snapshot_tracked(ctx: int, regions, page_size: int, flags: int, seq: int,
+                          candidates, d_staging: int, staging_bytes: int, h_image: int,
+                          h_image_bytes: int, stream: int, h_status: int) -> int:
+    """candidates: a uint64 numpy array (the candidate bitmap, host memory)."""
+    import numpy as np
+    arr = regions if isinstance(regions, ctypes.Array) else region_table(regions)
+    n = len(regions)
+    cand = np.ascontiguousarray(candidates, dtype=np.uint64)
+    return lib().crum_snapshot_tracked(ctx, ctypes.cast(arr, _P) if n else None, n, page_size,
+                                       flags, seq, cand.ctypes.data if cand.size else None,
+                                       cand.size, d_staging, staging_bytes, h_image or None,
+                                       h_image_bytes, stream or None, h_status)
+
+
+class crum_track_info(ctypes.Structure):
+    _fields_ = [("pages", ctypes.c_uint64), ("dirty_pages", ctypes.c_uint64),
+                ("pending_pages", ctypes.c_uint64), ("faults", ctypes.c_uint64),
+                ("flushed_pages", ctypes.c_uint64)]
+
+
+class Tracker:
+    """Owns a crum_track: a host view of `nbytes` whose writes are tracked
+    per page of `page_size` bytes."""
+
+    def __init__(self, nbytes: int, page_size: int):
+        h = _P()
+        rc = lib().crum_track_create(nbytes, page_size, ctypes.byref(h))
+        if rc != CRUM_OK:
+            raise RuntimeError(f"crum_track_create: {CODE_NAMES.get(rc, rc)}")
+        self.handle, self.nbytes, self.page_size = h.value, nbytes, page_size
+        self.n_pages = nbytes // page_size
+        self.ptr = lib().crum_track_view(self.handle)
+
+    def view(self):
+        """The view as a writable uint8 numpy array (no copy)."""
+        import numpy as np
+        return np.ctypeslib.as_array((ctypes.c_uint8 * self.nbytes).from_address(self.ptr))
+
+    def flush(self, dst: int, n_threads: int = 1) -> int:
+        n = _U64()
+        rc = lib().crum_track_flush(self.handle, dst, n_threads, ctypes.byref(n))
+        if rc != CRUM_OK:
+            raise RuntimeError(f"crum_track_flush: {CODE_NAMES.get(rc, rc)}")
+        return n.value
+
+    def _bits(self, fn, *extra):
+        import numpy as np
+        w = np.zeros(max(1, (self.n_pages + 63) // 64), np.uint64)
+        rc = fn(self.handle, w.ctypes.data, w.size, *extra)
+        if rc != CRUM_OK:
+            raise RuntimeError(CODE_NAMES.get(rc, rc))
+        return w
+
+    def pending(self, clear: bool = False):
+        return self._bits(lib().crum_track_pending, 1 if clear else 0)
+
+    def dirty(self):
+        return self._bits(lib().crum_track_dirty)
+
+    def stats(self) -> dict:
+        info = crum_track_info()
+        rc = lib().crum_track_stats(self.handle, ctypes.byref(info))
+        if rc != CRUM_OK:
+            raise RuntimeError(CODE_NAMES.get(rc, rc))
+        return {f: getattr(info, f) for f, _ in crum_track_info._fields_}
+
+    def destroy(self) -> None:
+        if self.handle:
+            lib().crum_track_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 def crum_restore(ctx: int, regions, h_image: int, image_bytes: int, flags: int,

@@ -19,13 +19,14 @@ namespace {
 
 // Scratch layout of one launch (offsets into ctx->d_scratch).
 struct Layout {
-    size_t regs = 0, reqs = 0, out = 0, glob = 0, upload_end = 0;
+    size_t regs = 0, reqs = 0, out = 0, glob = 0, cand = 0, upload_end = 0;
     size_t flags = 0, bitmap = 0, prefix = 0, list = 0, crcs = 0, partials = 0, bounds = 0,
            total = 0;
 };
 
 Layout make_layout(uint32_t n_regs, uint32_t n_reqs, uint64_t n_units, uint64_t n_words,
-                   uint64_t list_cap, uint64_t partial_cap, uint64_t n_chunks)
+                   uint64_t list_cap, uint64_t partial_cap, uint64_t n_chunks,
+                   uint64_t cand_words = 0)
 {
     Layout L;
     size_t off = 0;
@@ -38,6 +39,7 @@ Layout make_layout(uint32_t n_regs, uint32_t n_reqs, uint64_t n_units, uint64_t 
     L.reqs = take(64ull * n_reqs);
     L.out = take(64ull * n_reqs + 64);
     L.glob = L.out + 64ull * n_reqs;
+    L.cand = take(8 * cand_words);
     L.upload_end = off;
     L.flags = take(std::max<uint64_t>(n_units, 1));
     L.bitmap = take(8 * std::max<uint64_t>(n_words, 1));
@@ -474,10 +476,13 @@ static bool himg_ok_for_direct(const crum_ctx* c, const void* h_image, uint64_t 
     return h_image && c->direct_bytes && worst <= c->direct_bytes;
 }
 
-int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
-                  uint32_t page_size, uint32_t flags, uint64_t seq, void* d_staging,
-                  uint64_t staging_bytes, void* h_image, uint64_t h_image_bytes, void* stream_,
-                  crum_status* h_status)
+// The snapshot of crum_snapshot; h_cand (may be null) is the candidate
+// bitmap of crum_snapshot_tracked, cand_words long.
+static int snapshot_impl(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
+                         uint32_t page_size, uint32_t flags, uint64_t seq,
+                         const uint64_t* h_cand, uint64_t cand_words, void* d_staging,
+                         uint64_t staging_bytes, void* h_image, uint64_t h_image_bytes,
+                         void* stream_, crum_status* h_status)
 {
     // ---- synchronous argument checks (nothing enqueued on failure)
     if (!c || !h_status || (n_regions && !regions) || !d_staging ||
@@ -498,6 +503,8 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     const uint64_t W = (G + 63) / 64;
     const uint64_t data_off = round_up(64 + 32ull * n_regions + 8 * W, 4096);
     if (staging_bytes < data_off || (h_image && h_image_bytes < data_off))
+        return CRUM_EINVAL;
+    if (h_cand && cand_words < W)
         return CRUM_EINVAL;
     const uint64_t capacity = h_image ? std::min(staging_bytes, h_image_bytes) : staging_bytes;
     // When every page fits, ENOSPC cannot happen and the page space is
@@ -547,8 +554,8 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     uint64_t n_pages = 0, n_units = 0;
     flatten_regions(regions, n_regions, ps, c->unit_shift_max,
                     (flags & CRUM_UPDATE_SHADOW) ? 1u : 0u, dregs.data(), &n_pages, &n_units);
-    const Layout L =
-        make_layout(n_regions, 1, n_units, W, W * 64, np_shift ? G << np_shift : 0, n_chunks);
+    const Layout L = make_layout(n_regions, 1, n_units, W, W * 64, np_shift ? G << np_shift : 0,
+                                 n_chunks, h_cand ? W : 0);
     CRUM_TRY(ensure_scratch(c, L.total));
     const size_t rb_off = round_up(L.upload_end, 256);
     CRUM_TRY(ensure_pinned(c, rb_off + 128 + 8 * n_chunks));
@@ -572,8 +579,11 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     DevGlobal gl{};
     gl.crc_bad = kNoBad;
     std::memcpy(P + L.glob, &gl, sizeof(gl));
+    if (h_cand && W)
+        std::memcpy(P + L.cand, h_cand, 8 * W);
 
     uint8_t* S = c->d_scratch;
+    const uint64_t* d_cand = h_cand ? reinterpret_cast<const uint64_t*>(S + L.cand) : nullptr;
     const DevRegion* d_regs = reinterpret_cast<const DevRegion*>(S + L.regs);
     const DevRequest* d_reqs = reinterpret_cast<const DevRequest*>(S + L.reqs);
     DevReqOut* d_out = reinterpret_cast<DevReqOut*>(S + L.out);
@@ -602,7 +612,7 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
         {
             Span sp(c, kTDiff, stream);
             CRUM_TRY(launch_diff(d_regs, n_regions, 0, n_units, d_flags, c->shape.diff_blocks,
-                                 c->diff_nt, c->diff_prio, stream));
+                                 c->diff_nt, c->diff_prio, stream, d_cand));
         }
         {
             Span sp(c, kTScan, stream);
@@ -642,7 +652,8 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
             {
                 Span sp(c, kTDiff, stream);
                 CRUM_TRY(launch_diff(d_regs, n_regions, g0 << (ps - us), g1 << (ps - us), d_flags,
-                                     c->shape.diff_blocks, c->diff_nt, c->diff_prio, stream));
+                                     c->shape.diff_blocks, c->diff_nt, c->diff_prio, stream,
+                                     d_cand));
             }
             {
                 Span sp(c, kTScan, stream);
@@ -689,7 +700,7 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
         {
             Span sp(c, kTDiff, stream);
             CRUM_TRY(launch_diff(d_regs, n_regions, 0, n_units, d_flags, c->shape.diff_blocks,
-                                 c->diff_nt, c->diff_prio, stream));
+                                 c->diff_nt, c->diff_prio, stream, d_cand));
         }
         {
             Span sp(c, kTScan, stream);
@@ -782,6 +793,27 @@ int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
         c->partial_call = false;
     }
     return CRUM_OK;
+}
+
+int crum_snapshot(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
+                  uint32_t page_size, uint32_t flags, uint64_t seq, void* d_staging,
+                  uint64_t staging_bytes, void* h_image, uint64_t h_image_bytes, void* stream_,
+                  crum_status* h_status)
+{
+    return snapshot_impl(c, regions, n_regions, page_size, flags, seq, nullptr, 0, d_staging,
+                         staging_bytes, h_image, h_image_bytes, stream_, h_status);
+}
+
+int crum_snapshot_tracked(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
+                          uint32_t page_size, uint32_t flags, uint64_t seq,
+                          const uint64_t* h_candidates, uint64_t n_words, void* d_staging,
+                          uint64_t staging_bytes, void* h_image, uint64_t h_image_bytes,
+                          void* stream_, crum_status* h_status)
+{
+    if (!h_candidates)
+        return CRUM_EINVAL;
+    return snapshot_impl(c, regions, n_regions, page_size, flags, seq, h_candidates, n_words,
+                         d_staging, staging_bytes, h_image, h_image_bytes, stream_, h_status);
 }
 
 static int restore_fail(crum_status* st, int code, uint64_t D, uint64_t G, uint64_t n)

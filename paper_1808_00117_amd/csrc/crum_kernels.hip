@@ -417,10 +417,14 @@ __device__ __forceinline__ uint32_t xor_or(gcv4 __restrict__ a, gcv4 __restrict_
 // any byte of the unit differs from the shadow (or the region has none).
 // prio 1..3 raises the waves' issue priority on their compute unit above
 // that of co-running kernels' waves (0 leaves it at the default).
+// cand (may be null): a bitmap over global pages from host write tracking;
+// a page whose bit is clear is known to equal its shadow, so its units are
+// flagged clean without reading either copy.
 template <bool NT>
 __global__ __launch_bounds__(256) void k_diff(const DevRegion* __restrict__ regs,
                                               uint32_t n_regs, uint64_t u0, uint64_t u1,
-                                              uint8_t* __restrict__ unit_flags, uint32_t prio)
+                                              uint8_t* __restrict__ unit_flags, uint32_t prio,
+                                              const uint64_t* __restrict__ cand)
 {
     if (prio == 1)
         __builtin_amdgcn_s_setprio(1);
@@ -442,6 +446,14 @@ __global__ __launch_bounds__(256) void k_diff(const DevRegion* __restrict__ regs
         }
         const DevRegion& R = regs[r];
         const uint32_t us = R.unit_shift;
+        if (cand && R.shadow != nullptr) {
+            const uint64_t g = R.first_page + ((u - R.first_unit) >> (R.page_shift - us));
+            if (!((cand[g >> 6] >> (g & 63)) & 1ull)) {
+                if (lane == 0)
+                    unit_flags[u] = 0;
+                continue;
+            }
+        }
         uint32_t x = 1;
         if (R.shadow != nullptr) {
             const uint64_t off = (u - R.first_unit) << us;
@@ -458,7 +470,7 @@ __global__ __launch_bounds__(256) void k_diff(const DevRegion* __restrict__ regs
 
 hipError_t launch_diff(const DevRegion* regs, uint32_t n_regs, uint64_t u0, uint64_t u1,
                        uint8_t* unit_flags, int blocks, int nontemporal, int prio,
-                       hipStream_t s)
+                       hipStream_t s, const uint64_t* cand)
 {
     if (u1 <= u0)
         return hipSuccess;
@@ -466,10 +478,10 @@ hipError_t launch_diff(const DevRegion* regs, uint32_t n_regs, uint64_t u0, uint
     const uint64_t nb = need < (uint64_t)blocks ? need : (uint64_t)blocks;
     if (nontemporal)
         hipLaunchKernelGGL(k_diff<true>, dim3((unsigned)nb), dim3(256), 0, s, regs, n_regs, u0,
-                           u1, unit_flags, (uint32_t)prio);
+                           u1, unit_flags, (uint32_t)prio, cand);
     else
         hipLaunchKernelGGL(k_diff<false>, dim3((unsigned)nb), dim3(256), 0, s, regs, n_regs, u0,
-                           u1, unit_flags, (uint32_t)prio);
+                           u1, unit_flags, (uint32_t)prio, cand);
     return hipGetLastError();
 }
 

@@ -158,6 +158,38 @@ __global__ __launch_bounds__(256) void synth_read2_kernel(const synth_u32x4* __r
     out[(uint64_t)blockIdx.x * blockDim.x + threadIdx.x] = acc;
 }
 
+// Reference streaming copy (the read-and-write traffic of a pack without its
+// CRC): one wave per 16 KiB unit (units handed out grid-stride), DEPTH
+// non-temporal 16-byte loads per lane in flight (1 KiB apart, coalesced),
+// then the stores, non-temporal when NT_STORE.  Timed as the practical
+// copy ceiling of the GPU.
+template <int DEPTH, bool NT_STORE>
+__global__ __launch_bounds__(256) void synth_copy2_kernel(synth_u32x4* __restrict__ dst,
+                                                          const synth_u32x4* __restrict__ src,
+                                                          uint64_t n_units)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t wave = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint64_t n_waves = (uint64_t)gridDim.x * 4;
+    for (uint64_t u = wave; u < n_units; u += n_waves) {
+        const synth_u32x4* ps = src + u * 1024 + lane;
+        synth_u32x4* pd = dst + u * 1024 + lane;
+        for (int j = 0; j < 16; j += DEPTH) {
+            synth_u32x4 v[DEPTH];
+#pragma unroll
+            for (int k = 0; k < DEPTH; ++k)
+                v[k] = __builtin_nontemporal_load(ps + (j + k) * 64);
+#pragma unroll
+            for (int k = 0; k < DEPTH; ++k) {
+                if (NT_STORE)
+                    __builtin_nontemporal_store(v[k], pd + (j + k) * 64);
+                else
+                    pd[(j + k) * 64] = v[k];
+            }
+        }
+    }
+}
+
 // y <- a*x + y, repeated `iters` times over n elements (the co-running
 // compute kernel of the many-allocations workload).
 __global__ void synth_saxpy_loop_kernel(float* __restrict__ y, const float* __restrict__ x,
@@ -244,6 +276,28 @@ int synth_copy_dev(void* dst, const void* src, uint64_t nbytes, void* stream)
         return 0;
     hipLaunchKernelGGL(synth_copy_kernel, dim3(4096), dim3(256), 0, (hipStream_t)stream,
                        (uint4*)dst, (const uint4*)src, nbytes >> 4);
+    return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+// nbytes a multiple of 16 KiB; depth 4 or 16; blocks workgroups of 256.
+int synth_copy2_dev(void* dst, const void* src, uint64_t nbytes, int blocks, int depth,
+                    int nt_store, void* stream)
+{
+    if (((uintptr_t)dst & 15) || ((uintptr_t)src & 15) || (nbytes & 16383) || blocks <= 0 ||
+        (depth != 4 && depth != 16))
+        return -1;
+    const uint64_t n = nbytes >> 14;
+    synth_u32x4* d = (synth_u32x4*)dst;
+    const synth_u32x4* s = (const synth_u32x4*)src;
+    hipStream_t st = (hipStream_t)stream;
+    if (depth == 4 && nt_store)
+        hipLaunchKernelGGL((synth_copy2_kernel<4, true>), dim3(blocks), dim3(256), 0, st, d, s, n);
+    else if (depth == 4)
+        hipLaunchKernelGGL((synth_copy2_kernel<4, false>), dim3(blocks), dim3(256), 0, st, d, s, n);
+    else if (nt_store)
+        hipLaunchKernelGGL((synth_copy2_kernel<16, true>), dim3(blocks), dim3(256), 0, st, d, s, n);
+    else
+        hipLaunchKernelGGL((synth_copy2_kernel<16, false>), dim3(blocks), dim3(256), 0, st, d, s, n);
     return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 

@@ -87,6 +87,10 @@ def dev_lib():
         lib.synth_copy_dev.restype = ctypes.c_int
         lib.synth_copy_dev.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                        ctypes.c_void_p]
+        lib.synth_copy2_dev.restype = ctypes.c_int
+        lib.synth_copy2_dev.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                        ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_void_p]
         lib.synth_read2_dev.restype = ctypes.c_int
         lib.synth_read2_dev.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                         ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
@@ -203,6 +207,13 @@ def clobber_frac_dev(ptr: int, nbytes: int, page_size: int, sel_seed: int, frac:
 def copy_dev(dst: int, src: int, nbytes: int, stream: int = 0) -> None:
     """Plain device copy kernel (16-byte aligned pointers and size)."""
     _check(dev_lib().synth_copy_dev(dst, src, nbytes, stream), "synth_copy_dev")
+
+
+def copy2_dev(dst: int, src: int, nbytes: int, blocks: int, depth: int = 16,
+              nt_store: bool = False, stream: int = 0) -> None:
+    """Reference streaming copy (nbytes a multiple of 16 KiB)."""
+    _check(dev_lib().synth_copy2_dev(dst, src, nbytes, blocks, depth, 1 if nt_store else 0,
+                                     stream), "synth_copy2_dev")
 
 
 def read2_dev(a: int, b: int, nbytes: int, out: int, out_words: int, blocks: int,
