@@ -230,6 +230,28 @@ int crum_snapshot_tracked(crum_ctx* ctx, const crum_region* regions, uint32_t n_
                           uint64_t staging_bytes, void* h_image, uint64_t h_image_bytes,
                           void* stream, crum_status* h_status);
 
+/* Snapshot without allocation, for callers that cannot allocate: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Arguments, result and image as crum_snapshot's, always in its diff-first
+ * order (whole diff, capacity check, one pack launch, header), the image
+ * copied to h_image with one hipMemcpyAsync on `stream`; the calling thread
+ * waits for the dirty count.  The device scratch is a fixed array of
+ * CRUM_NOALLOC_SCRATCH_BYTES per device (held until the process ends), the
+ * host side a pinned buffer allocated by crum_ctx_create: no call allocates.
+ * Inputs whose scratch would not fit (more than CRUM_NOALLOC_MAX_REGIONS
+ * regions, or roughly 7 million pages of 4 KiB, 5 million of 64 KiB) return
+ * CRUM_ELIMIT with nothing enqueued.  Every call on one device shares that
+ * device's array: calls that overlap on one device (different contexts, or
+ * different threads) race; consecutive calls through one context are
+ * ordered.  Timing classes are not recorded by this call. */
+#define CRUM_NOALLOC_SCRATCH_BYTES (64ull << 20)
+#define CRUM_NOALLOC_MAX_REGIONS 2048u
+enum { CRUM_ELIMIT = -9 /* input larger than the fixed scratch of crum_snapshot_noalloc */ };
+int crum_snapshot_noalloc(crum_ctx* ctx, const crum_region* regions, uint32_t n_regions,
+                          uint32_t page_size, uint32_t flags, uint64_t seq, void* d_staging,
+                          uint64_t staging_bytes, void* h_image, uint64_t h_image_bytes,
+                          void* stream, crum_status* h_status);
+
 /* ---------------------------------------------------------------- batched
  * Many snapshot requests in one plan (the batched pattern).  Each request is a
  * region table with its own page size, flags (CRUM_UPDATE_SHADOW) and seq,

@@ -18,6 +18,8 @@ SO = os.path.join(HERE, "libcrum.so")
 CRUM_OK, CRUM_EINVAL, CRUM_ENOSPC, CRUM_ECRC = 0, -1, -2, -3
 CRUM_EFORMAT, CRUM_EHIP, CRUM_EMISMATCH = -4, -5, -6
 CRUM_EIO, CRUM_EAGAIN = -7, -8
+CRUM_ELIMIT = -9
+CRUM_NOALLOC_SCRATCH_BYTES, CRUM_NOALLOC_MAX_REGIONS = 64 << 20, 2048
 CRUM_UPDATE_SHADOW, CRUM_VERIFY = 1, 2
 CRUM_PARAM_DIFF_BLOCKS, CRUM_PARAM_PACK_BLOCKS = 1, 2
 CRUM_PARAM_CHUNK_BYTES, CRUM_PARAM_CHUNK_MAX_BYTES = 3, 4
@@ -29,7 +31,7 @@ CRUM_PARAM_DIRECT_BYTES = 14
 
 CODE_NAMES = {0: "CRUM_OK", -1: "CRUM_EINVAL", -2: "CRUM_ENOSPC", -3: "CRUM_ECRC",
               -4: "CRUM_EFORMAT", -5: "CRUM_EHIP", -6: "CRUM_EMISMATCH", -7: "CRUM_EIO",
-              -8: "CRUM_EAGAIN"}
+              -8: "CRUM_EAGAIN", -9: "CRUM_ELIMIT"}
 
 
 class crum_region(ctypes.Structure):
@@ -137,6 +139,8 @@ _SIGS = {
     "crum_track_destroy": (None, [_P]),
     "crum_snapshot_tracked": (_I, [_P, _P, _U32, _U32, _U32, _U64, _P, _U64, _P, _U64, _P,
                                    _U64, _P, _P]),
+    "crum_snapshot_noalloc": (_I, [_P, _P, _U32, _U32, _U32, _U64, _P, _U64, _P, _U64, _P,
+                                   _P]),
 }
 
 _lib = None
@@ -202,6 +206,17 @@ def crum_snapshot(ctx: int, regions, page_size: int, flags: int, seq: int, d_sta
     return lib().crum_snapshot(ctx, ctypes.cast(arr, _P) if n else None, n, page_size, flags,
                                seq, d_staging, staging_bytes, h_image or None, h_image_bytes,
                                stream or None, h_status)
+
+
+def crum_snapshot_noalloc(ctx: int, regions, page_size: int, flags: int, seq: int,
+                          d_staging: int, staging_bytes: int, h_image: int, h_image_bytes: int,
+                          stream: int, h_status: int) -> int:
+    """As crum_snapshot, through the entry point that allocates nothing."""
+    arr = regions if isinstance(regions, ctypes.Array) else region_table(regions)
+    n = len(regions)
+    return lib().crum_snapshot_noalloc(ctx, ctypes.cast(arr, _P) if n else None, n, page_size,
+                                       flags, seq, d_staging, staging_bytes, h_image or None,
+                                       h_image_bytes, stream or None, h_status)
 
 
 def crum_snapshot_tracked(ctx: int, regions, page_size: int, flags: int, seq: int,

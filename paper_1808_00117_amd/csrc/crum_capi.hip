@@ -291,7 +291,10 @@ int crum_ctx_create(int device, crum_ctx** out)
               hipEventCreateWithFlags(&c->ev_upload, hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&c->ev_count, hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming) == hipSuccess &&
-              hipEventCreateWithFlags(&c->ev_hdr, hipEventDisableTiming) == hipSuccess;
+              hipEventCreateWithFlags(&c->ev_hdr, hipEventDisableTiming) == hipSuccess &&
+              hipHostMalloc(reinterpret_cast<void**>(&c->na_pin), kNoAllocPinnedBytes, 0) ==
+                  hipSuccess &&
+              noalloc_scratch(device, &c->na_scratch) == CRUM_OK;
     if (!ok) {
         crum_ctx_destroy(c);
         return CRUM_EHIP;
@@ -323,6 +326,8 @@ void crum_ctx_destroy(crum_ctx* c)
         (void)hipFree(c->d_scratch);
     if (c->h_pin)
         (void)hipHostFree(c->h_pin);
+    if (c->na_pin)
+        (void)hipHostFree(c->na_pin);
     if (c->lazy_d)
         (void)hipFree(c->lazy_d);
     if (c->lazy_h)

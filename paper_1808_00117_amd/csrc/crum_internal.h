@@ -10,6 +10,13 @@
 namespace crum {
 
 constexpr int kTimingClasses = 7;
+// Pinned buffer of crum_snapshot_noalloc, allocated with the context: the
+// upload (region table, request, counters) and read-back below
+// kNoAllocSortOff, the argument check's interval sort above it.
+constexpr uint64_t kNoAllocSortOff = 160ull << 10;
+constexpr uint64_t kNoAllocPinnedBytes = 256ull << 10;
+// Address of crum_snapshot_noalloc's device scratch on `device` (current).
+int noalloc_scratch(int device, uint8_t** out);
 enum { kTDiff = 0, kTPack = 1, kTDrain = 2, kTScan = 3, kTHeader = 4, kTVerify = 5, kTScatter = 6 };
 
 struct DeviceGuard {
@@ -137,6 +144,9 @@ struct crum_ctx {
     uint8_t* lazy_h = nullptr;  // pinned
     size_t lazy_h_cap = 0;
     bool lazy_busy = false;
+    // crum_snapshot_noalloc: the device's static scratch and a pinned buffer
+    uint8_t* na_scratch = nullptr;
+    uint8_t* na_pin = nullptr;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> spans[crum::kTimingClasses];
 };
 

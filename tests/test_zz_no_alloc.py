@@ -1,0 +1,136 @@
+"""crum_snapshot_noalloc, the entry point for callers that cannot allocate,
+called through the C ABI: its image equals crum_snapshot's (and the
+oracle's) byte for byte on two calls in a row, the second with a smaller
+input, with the same status; inputs beyond its fixed scratch are refused
+with CRUM_ELIMIT before anything is enqueued."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.gpu_util import image_capacity, log, upload
+
+pytestmark = pytest.mark.gpu
+
+KiB = 1 << 10
+
+
+def host_case(counts, P, frac, seed, null_shadow=()):
+    rng = np.random.default_rng(seed)
+    regs = []
+    for rid, n in enumerate(counts):
+        cur = rng.integers(0, 256, n * P, dtype=np.uint8)
+        sh = cur.copy()
+        for i in rng.choice(n, size=int(n * frac), replace=False) if n else []:
+            sh[int(i) * P + int(rng.integers(0, P))] ^= np.uint8(1 + rng.integers(0, 255))
+        regs.append((cur, None if rid in null_shadow else sh, 300 + rid))
+    return regs
+
+
+def run(entry, ctx, dev, P, seq, cap):
+    import torch
+
+    import paper_1808_00117_amd as crum
+    from paper_1808_00117_amd.api import regions_of
+    staging = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    h = torch.zeros(cap, dtype=torch.uint8, pin_memory=True)
+    status = torch.zeros(64, dtype=torch.uint8, pin_memory=True)
+    rc = entry(ctx, regions_of(dev), P, 0, seq, staging.data_ptr(), cap, h.data_ptr(), cap,
+               torch.cuda.current_stream().cuda_stream, status.data_ptr())
+    assert rc == crum.CRUM_OK, rc
+    torch.cuda.synchronize()
+    st = crum.read_status(status.data_ptr())
+    img = h[: st.image_bytes].numpy().copy() if st.code == 0 else None
+    return st, img
+
+
+def test_noalloc_matches_snapshot_twice_then_smaller():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1808_00117_amd as crum
+    ctx_a = crum.crum_ctx_create(0)
+    ctx_b = crum.crum_ctx_create(0)
+    try:
+        cases = [
+            # a larger input first (several regions, 64 KiB pages, a region
+            # without shadow, ragged bitmap words), then a smaller one
+            ((130, 7, 300, 1), 64 * KiB, 0.2, 11, (1,)),
+            ((70,), 4 * KiB, 0.1, 12, ()),
+        ]
+        for k, (counts, P, frac, seed, nulls) in enumerate(cases):
+            host = host_case(counts, P, frac, seed, nulls)
+            st_o, img_o, _ = oracle.snapshot(host, P, seq=20 + k)
+            dev = upload(host)
+            cap = image_capacity(dev, P)
+            log(f"[noalloc] call {k}: regions {counts} P={P} D={st_o.n_dirty}")
+            st_n, img_n = run(crum.crum_snapshot_noalloc, ctx_a, dev, P, 20 + k, cap)
+            st_s, img_s = run(crum.crum_snapshot, ctx_b, dev, P, 20 + k, cap)
+            for st in (st_n, st_s):
+                assert st.code == 0 and st.n_dirty == st_o.n_dirty
+                assert st.image_bytes == st_o.image_bytes and st.total_pages == st_o.total_pages
+            assert np.array_equal(img_n, img_s), f"call {k}: no-alloc image differs"
+            assert np.array_equal(img_n, img_o), f"call {k}: image differs from the oracle"
+    finally:
+        crum.crum_ctx_destroy(ctx_a)
+        crum.crum_ctx_destroy(ctx_b)
+
+
+def test_noalloc_enospc_matches_snapshot():
+    """A capacity below the image: both entry points report ENOSPC with the
+    same counts, and leave the host image untouched."""
+    import torch
+
+    import paper_1808_00117_amd as crum
+    from paper_1808_00117_amd.api import regions_of
+    ctx = crum.crum_ctx_create(0)
+    try:
+        P = 4 * KiB
+        host = host_case((90,), P, 0.5, 13)
+        st_o, _, _ = oracle.snapshot(host, P, seq=1)
+        dev = upload(host)
+        cap = st_o.image_bytes - P
+        out = []
+        for entry in (crum.crum_snapshot_noalloc, crum.crum_snapshot):
+            staging = torch.empty(cap, dtype=torch.uint8, device="cuda")
+            h = torch.full((cap,), 0xA5, dtype=torch.uint8, pin_memory=True)
+            status = torch.zeros(64, dtype=torch.uint8, pin_memory=True)
+            rc = entry(ctx, regions_of(dev), P, 0, 1, staging.data_ptr(), cap, h.data_ptr(),
+                       cap, torch.cuda.current_stream().cuda_stream, status.data_ptr())
+            assert rc == 0
+            torch.cuda.synchronize()
+            st = crum.read_status(status.data_ptr())
+            assert st.code == crum.CRUM_ENOSPC and st.n_dirty == st_o.n_dirty
+            assert (h.numpy() == 0xA5).all()
+            out.append((st.n_dirty, st.image_bytes))
+        assert out[0] == out[1]
+    finally:
+        crum.crum_ctx_destroy(ctx)
+
+
+def test_noalloc_refuses_inputs_beyond_its_scratch():
+    """More regions than the fixed maximum (zero-length regions need no
+    memory), and a region of more pages than the scratch can number: both
+    CRUM_ELIMIT, with nothing enqueued."""
+    import torch
+
+    import paper_1808_00117_amd as crum
+    ctx = crum.crum_ctx_create(0)
+    try:
+        sb = 4 << 20  # above either input's image prefix
+        staging = torch.empty(sb, dtype=torch.uint8, device="cuda")
+        status = torch.zeros(64, dtype=torch.uint8, pin_memory=True)
+        s = torch.cuda.current_stream().cuda_stream
+        n = crum.CRUM_NOALLOC_MAX_REGIONS + 1
+        regs = [(0, 0, 0, i) for i in range(n)]
+        assert crum.crum_snapshot_noalloc(ctx, regs, 4096, 0, 1, staging.data_ptr(), sb, 0,
+                                          0, s, status.data_ptr()) == crum.CRUM_ELIMIT
+        # 8 Mi pages of 4 KiB: about 77 MB of scratch, above the 64 MiB array
+        big = torch.empty(32 << 30, dtype=torch.uint8, device="cuda")
+        assert crum.crum_snapshot_noalloc(ctx, [(big.data_ptr(), 0, 32 << 30, 1)], 4096, 0, 1,
+                                          staging.data_ptr(), sb, 0, 0, s,
+                                          status.data_ptr()) == crum.CRUM_ELIMIT
+        del big
+        torch.cuda.synchronize()
+    finally:
+        crum.crum_ctx_destroy(ctx)
