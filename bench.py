@@ -91,6 +91,8 @@ def parse_args():
                     help="run a 1 GiB plain copy kernel first (counter calibration)")
     ap.add_argument("--trace-summary", metavar="DIR",
                     help="summarise a rocprofv3 --kernel-trace --stats run of this script")
+    ap.add_argument("--pmc-table", metavar="DIR",
+                    help="per-kernel mean counter values of one rocprofv3 --pmc run")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
                          "this script and print the JSON that the roofline 'traffic' reads")
@@ -146,7 +148,46 @@ def pmc_summary(fetch_dir: str, write_dir: str, workload: str) -> dict:
                         "k_diff_bytes_per_launch": sum(diff) / len(diff) / factor}
     res["traffic_bytes_per_launch"] = round(res["FETCH_SIZE"]["k_diff_bytes_per_launch"] +
                                             res["WRITE_SIZE"]["k_diff_bytes_per_launch"])
+    # the snapshot pack (k_pack<0, ...>): counter bytes summed over its launches
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        pk = per_kernel(d, counter)
+        pack = [v for k, vs in pk.items() if "k_pack<0" in k for v in vs]
+        heads = sum(len(vs) for k, vs in pk.items() if "k_header" in k)
+        if pack:
+            res[counter]["k_pack_dispatches"] = len(pack)
+            res[counter]["k_pack_snapshots"] = heads
+            res[counter]["k_pack_bytes_total"] = sum(pack) / res[counter]["calibration_factor"]
     return res
+
+
+def pmc_table(d: str, kernels=("k_pack<0", "k_pack<1", "k_diff", "k_scatter")) -> str:
+    """Markdown table of a rocprofv3 --pmc run: per kernel (matched by name
+    prefix) the dispatch count and the mean of each counter per dispatch."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no counter_collection.csv under {d}")
+    acc = {}
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            name = r["Kernel_Name"]
+            key = next((k for k in kernels if k in name), None)
+            if key is None:
+                continue
+            per = acc.setdefault(key, {})
+            per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    counters = sorted({c for per in acc.values() for c in per})
+    out = ["| kernel | dispatches | " + " | ".join(counters) + " |",
+           "|---|---:|" + "---:|" * len(counters)]
+    for k in kernels:
+        if k not in acc:
+            continue
+        per = acc[k]
+        n = max(len(v) for v in per.values())
+        out.append(f"| `{k}` | {n} | " + " | ".join(
+            f"{statistics.mean(per[c]):.4g}" if c in per else "" for c in counters) + " |")
+    return "\n".join(out)
 
 
 def trace_summary(d: str, steps: int) -> str:
@@ -178,18 +219,55 @@ def trace_summary(d: str, steps: int) -> str:
             out.append(f"| {r['Name']} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                        f"{float(r['TotalDurationNs']) / 1e6:.2f} |")
     kt = find("*kernel_trace.csv")
+    t_lo = t_hi = None
     if kt:
         rows = [r for r in csv.DictReader(open(kt))]
         diff = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
                       for r in rows if "k_diff" in r["Kernel_Name"])
-        heads = sorted(int(r["Start_Timestamp"]) for r in rows if "k_header" in r["Kernel_Name"])
+        heads = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
+                       for r in rows if "k_header" in r["Kernel_Name"])
         if diff and len(heads) >= steps:
-            t0 = heads[-steps - 1] if len(heads) > steps else 0
+            t0 = heads[-steps - 1][0] if len(heads) > steps else 0
             sel = [(a, b) for a, b in diff if a > t0]
             avg = statistics.mean(b - a for a, b in sel) / 1e6
             out.append("")
             out.append(f"k_diff launches in the last {steps} snapshots (timed region): "
                        f"{len(sel)}, average duration {avg:.4f} ms")
+            t_lo, t_hi = t0, heads[-1][1]
+        packs = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
+                       for r in rows if "k_pack<0" in r["Kernel_Name"])
+        if packs and t_lo is not None:
+            sel = [(a, b) for a, b in packs if t_lo < a < t_hi]
+            if sel:
+                tot = sum(b - a for a, b in sel) / 1e6
+                out.append(f"k_pack (snapshot pack) launches in the timed snapshots: {len(sel)}, "
+                           f"summed duration {tot:.4f} ms ({tot / steps:.4f} ms per snapshot)")
+    mt = find("*memory_copy_trace.csv")
+    if mt and t_lo is not None:
+        rows = [r for r in csv.DictReader(open(mt))]
+        cols = list(rows[0].keys()) if rows else []
+        size_col = next((c for c in cols if "size" in c.lower() or "bytes" in c.lower()), None)
+        dir_col = next((c for c in cols if c.lower() in ("direction", "kind", "operation")), None)
+
+        def is_d2h(r):
+            v = " ".join(str(r.get(c, "")) for c in cols if c in ("Direction", "Kind",
+                                                                     "Operation"))
+            return "DEVICE_TO_HOST" in v.upper()
+        sel = [r for r in rows if is_d2h(r) and
+               t_lo < int(r["Start_Timestamp"]) and int(r["End_Timestamp"]) <= t_hi + 10**9]
+        if size_col:
+            sel = [r for r in sel if int(r[size_col]) >= 4096]
+        if sel:
+            dur = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in sel) / 1e9
+            line = (f"device-to-host copies of at least 4 KiB after the first timed snapshot "
+                    f"began ({dir_col}): {len(sel)} copies, summed duration "
+                    f"{dur * 1e3:.3f} ms")
+            if size_col:
+                nbytes = sum(int(r[size_col]) for r in sel)
+                gbs = nbytes / dur / 1e9
+                line += (f", {nbytes} bytes, {gbs:.2f} GB/s = {gbs / LINK_PEAK_GBS:.3f} of the "
+                         f"{LINK_PEAK_GBS:.1f} GB/s host link")
+            out.append(line)
     return "\n".join(out)
 
 
@@ -473,7 +551,8 @@ def bench_batched(args) -> dict:
         return time.perf_counter() - t
 
     cache = args.tune_cache or autotune.DEFAULT_CACHE
-    tuned = autotune.load("batched", cache)
+    tune_key = autotune.class_key("plan", N)
+    tuned = autotune.load(tune_key, cache)
 
     def mean_request_latency(plan):
         """Mean over requests of the time from launch start to the end of the
@@ -512,8 +591,9 @@ def bench_batched(args) -> dict:
                  "chunk_max_bytes": [64 << 20, 256 << 20, 1 << 30, 4 << 30],
                  "pack_blocks": [512, 1024, 2048],
                  "diff_blocks": [512, 1024, 2048]}
-        best, trials = autotune.search(ctx, trial, space, repeats=2, log=log)
-        autotune.save("batched", best, trials, cache)
+        best, trials, stats = autotune.search(ctx, trial, space, repeats=3, log=log)
+        autotune.save(tune_key, best, trials, cache, stats)
+        log(f"[autotune] {tune_key}: {stats}")
         tuned = best
     if tuned:
         autotune.apply(ctx, tuned)
@@ -619,6 +699,7 @@ def bench_batched(args) -> dict:
                                "U(1%,50%) in runs of mean 16",
                    "scanned_bytes": N, "dirty_pages": Dsum, "image_bytes": sum(sizes),
                    "groups": n_groups, "params": params, "tuned": bool(tuned),
+                   "tuning_class": tune_key,
                    "settle": settle},
         "batched": {"makespan_ms": round(mk_ms, 2),
                     "gbs": round(N / statistics.median(mk) / 1e9, 2),
@@ -1449,6 +1530,9 @@ def main():
         return
     if args.trace_summary:
         print(trace_summary(args.trace_summary, args.steps))
+        return
+    if args.pmc_table:
+        print(pmc_table(args.pmc_table))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the snapshot path has no cross-GPU step, and "

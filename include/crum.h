@@ -93,9 +93,24 @@ enum {
 };
 
 /* Create a context on HIP device `device`; builds the CRC tables, the side
- * stream and events.  Returns CRUM_OK, CRUM_EINVAL (bad device or out==NULL)
- * or CRUM_EHIP. */
-int crum_ctx_create(int device, crum_ctx** out);
+ * stream and events.  tuning_cache: path of the shape tuner's JSON cache, or
+ * NULL for the default shapes.  The entries for this device (its key is
+ * "cc<major>.<minor>-<CUs>cu|hip<runtime version>") and for the classes
+ * "snapshot|p<page size>|b<k>" (single snapshots of that page size scanning
+ * 2^k..2^(k+1) bytes) and "plan|b<k>" (plans whose requests scan that much)
+ * are loaded; a snapshot or plan of a loaded class then runs with that class's
+ * shapes, except for parameters set with crum_ctx_set_param, which always
+ * win.  Shapes change speed only, never an image.  Returns CRUM_OK,
+ * CRUM_EINVAL (bad device, out==NULL, a cache file that cannot be read or
+ * parsed) or CRUM_EHIP. */
+int crum_ctx_create(int device, const char* tuning_cache, crum_ctx** out);
+
+/* Number of tuned classes the context loaded for its device. */
+int crum_ctx_tuned_classes(crum_ctx* ctx, uint32_t* n_classes);
+
+/* Parse a tuning cache file as crum_ctx_create does, for the given device
+ * key: CRUM_OK and the number of classes found, or CRUM_EINVAL.  Host only. */
+int crum_tuning_check(const char* path, const char* device_key, uint32_t* n_classes);
 
 /* Destroy a context (waits for its outstanding work). NULL is ignored. */
 void crum_ctx_destroy(crum_ctx* ctx);
@@ -259,7 +274,8 @@ int crum_snapshot_noalloc(crum_ctx* ctx, const crum_region* regions, uint32_t n_
  * Requests are processed in the caller's order, or smallest scanned bytes
  * first when CRUM_PARAM_PLAN_ORDER is 1 (a request then waits only for
  * smaller ones), and grouped in that order (groups of whole requests,
- * scanned bytes per group starting at CRUM_PARAM_CHUNK_BYTES and doubling up
+ * scanned bytes per group starting at CRUM_PARAM_CHUNK_BYTES and growing by
+ * CRUM_PARAM_CHUNK_GROWTH up
  * to CRUM_PARAM_CHUNK_MAX_BYTES); each group's device work -- one persistent diff
  * over all units of its requests, bitmap, scan, compaction, pack with CRCs and
  * headers -- is captured once as a HIP graph at plan creation.  Request images
@@ -401,7 +417,7 @@ void crum_server_destroy(crum_server* server);
  *   pack, verify and scatter kernels (4 per compute unit).
  * CRUM_PARAM_CHUNK_BYTES / CRUM_PARAM_CHUNK_MAX_BYTES: scanned bytes of the
  *   first and of the largest chunk when the snapshot is pipelined by chunks
- *   (128 MiB / 4 GiB); chunks double in size up to the maximum.
+ *   (128 MiB / 4 GiB); chunks grow by CRUM_PARAM_CHUNK_GROWTH up to the maximum.
  * CRUM_PARAM_EAGER: 1 pipelines the snapshot by chunks whenever the staging
  *   and host capacities hold an image with every page dirty (so ENOSPC is
  *   impossible) and the pages span more than one chunk; 0 always runs the
@@ -412,7 +428,7 @@ void crum_server_destroy(crum_server* server);
  *   each wave compares min(page, 2^value) bytes per step.
  * CRUM_PARAM_DIFF_NONTEMPORAL: 1 marks the diff kernel's loads non-temporal (1).
  * CRUM_PARAM_PIECE_SHIFT: log2 of the largest piece of a page one wave packs,
- *   verifies or scatters, 12..16 (16); larger pages are split into pieces
+ *   verifies or scatters, 12..16 (14); larger pages are split into pieces
  *   whose CRCs are combined afterwards.
  * CRUM_PARAM_PACK_DEPTH: 16-byte loads each lane keeps in flight in the pack
  *   and verify kernels, 4, 8 or 16 (4).
@@ -429,7 +445,11 @@ void crum_server_destroy(crum_server* server);
  *   16-entry nibble tables (conflict-free, more ALU work): 0 = byte tables
  *   only, 1..5 = mixes, 6 = byte tables for pack and mix 3 for verify, the
  *   fastest of each on MI355X (6).
- * Values of 0 are rejected (CRUM_EINVAL) except for the two on/off switches,
+ * CRUM_PARAM_CHUNK_GROWTH: factor, 2..16, by which successive pipelined
+ *   chunks and plan groups grow, up to their maximum (4).
+ * CRUM_PARAM_PACK_NT_STORE: 1 writes the image with non-temporal stores in
+ *   the pack kernel (0).
+ * Values of 0 are rejected (CRUM_EINVAL) except for the on/off switches,
  * the priority and the direct-order size. */
 enum {
     CRUM_PARAM_DIFF_BLOCKS = 1,
@@ -445,7 +465,9 @@ enum {
     CRUM_PARAM_DIFF_PRIORITY = 11,
     CRUM_PARAM_CRC_VARIANT = 12,
     CRUM_PARAM_PLAN_ORDER = 13,
-    CRUM_PARAM_DIRECT_BYTES = 14
+    CRUM_PARAM_DIRECT_BYTES = 14,
+    CRUM_PARAM_CHUNK_GROWTH = 15,
+    CRUM_PARAM_PACK_NT_STORE = 16
 };
 int crum_ctx_set_param(crum_ctx* ctx, int param, uint64_t value);
 int crum_ctx_get_param(crum_ctx* ctx, int param, uint64_t* value);

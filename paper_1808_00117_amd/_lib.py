@@ -28,6 +28,7 @@ CRUM_PARAM_DIFF_UNIT_SHIFT, CRUM_PARAM_DIFF_NONTEMPORAL = 7, 8
 CRUM_PARAM_PIECE_SHIFT, CRUM_PARAM_PACK_DEPTH, CRUM_PARAM_DIFF_PRIORITY = 9, 10, 11
 CRUM_PARAM_CRC_VARIANT, CRUM_PARAM_PLAN_ORDER = 12, 13
 CRUM_PARAM_DIRECT_BYTES = 14
+CRUM_PARAM_CHUNK_GROWTH, CRUM_PARAM_PACK_NT_STORE = 15, 16
 
 CODE_NAMES = {0: "CRUM_OK", -1: "CRUM_EINVAL", -2: "CRUM_ENOSPC", -3: "CRUM_ECRC",
               -4: "CRUM_EFORMAT", -5: "CRUM_EHIP", -6: "CRUM_EMISMATCH", -7: "CRUM_EIO",
@@ -93,7 +94,9 @@ class crum_request_status(ctypes.Structure):
 _P = ctypes.c_void_p
 _U32, _U64, _I = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
 _SIGS = {
-    "crum_ctx_create": (_I, [_I, ctypes.POINTER(_P)]),
+    "crum_ctx_create": (_I, [_I, ctypes.c_char_p, ctypes.POINTER(_P)]),
+    "crum_ctx_tuned_classes": (_I, [_P, ctypes.POINTER(_U32)]),
+    "crum_tuning_check": (_I, [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(_U32)]),
     "crum_ctx_destroy": (None, [_P]),
     "crum_image_prefix_bytes": (_I, [_U32, _U64, ctypes.POINTER(_U64)]),
     "crum_image_bytes": (_I, [_U32, _U64, _U64, _U32, ctypes.POINTER(_U64)]),
@@ -169,12 +172,28 @@ def region_table(regions: Sequence) -> "ctypes.Array":
     return arr
 
 
-def crum_ctx_create(device: int = 0) -> int:
+def crum_ctx_create(device: int = 0, tuning_cache: Optional[str] = None) -> int:
     h = _P()
-    rc = lib().crum_ctx_create(device, ctypes.byref(h))
+    path = tuning_cache.encode() if tuning_cache else None
+    rc = lib().crum_ctx_create(device, path, ctypes.byref(h))
     if rc != CRUM_OK:
         raise RuntimeError(f"crum_ctx_create failed: {CODE_NAMES.get(rc, rc)}")
     return h.value
+
+
+def crum_ctx_tuned_classes(ctx: int) -> int:
+    n = _U32()
+    rc = lib().crum_ctx_tuned_classes(ctx, ctypes.byref(n))
+    if rc != CRUM_OK:
+        raise RuntimeError(CODE_NAMES.get(rc, rc))
+    return n.value
+
+
+def crum_tuning_check(path: str, device_key: str):
+    """(code, number of classes) of a tuning cache file for a device key."""
+    n = _U32()
+    rc = lib().crum_tuning_check(path.encode(), device_key.encode(), ctypes.byref(n))
+    return rc, n.value
 
 
 def crum_ctx_destroy(ctx: int) -> None:

@@ -3,8 +3,13 @@
 Searches the context parameters that shape the device work (diff unit size,
 non-temporal loads, diff and pack grid sizes, chunk or group sizes) by timing
 a caller-supplied workload, and keeps the winners in a JSON cache keyed by the
-device name, the HIP runtime version and the workload class, so later runs
-start from tuned shapes without searching again.
+device (compute capability, compute units, HIP runtime version) and by the
+workload class: ``snapshot|p<page size>|b<k>`` for single snapshots scanning
+2^k..2^(k+1) bytes, ``plan|b<k>`` for plans.  A candidate value is kept only
+when it beats the best so far by more than the run-to-run spread of the
+default shapes, so noise never becomes a tuned shape.  The library reads the
+same file (``crum_ctx_create``'s tuning_cache argument) and applies a class's
+shapes to the calls of that class, so C callers get them too.
 """
 from __future__ import annotations
 
@@ -34,7 +39,20 @@ PARAMS = {
     "crc_variant": C.CRUM_PARAM_CRC_VARIANT,
     "plan_order": C.CRUM_PARAM_PLAN_ORDER,
     "direct_bytes": C.CRUM_PARAM_DIRECT_BYTES,
+    "chunk_growth": C.CRUM_PARAM_CHUNK_GROWTH,
+    "pack_nt_store": C.CRUM_PARAM_PACK_NT_STORE,
 }
+
+
+def class_key(kind: str, nbytes: int, page_size: int = 0) -> str:
+    """Cache key of a workload class: kind "snapshot" (one page size) or
+    "plan", and k = floor(log2(scanned bytes))."""
+    k = max(0, int(nbytes).bit_length() - 1)
+    if kind == "snapshot":
+        return f"snapshot|p{int(page_size)}|b{k}"
+    if kind == "plan":
+        return f"plan|b{k}"
+    raise ValueError(kind)
 
 
 # hipDeviceAttribute_t values (hip_runtime_api.h, ROCm 7)
@@ -80,13 +98,17 @@ def load(workload: str, path: str = DEFAULT_CACHE) -> Optional[Dict[str, int]]:
     return dict(entry["params"]) if entry else None
 
 
-def save(workload: str, params: Dict[str, int], table: List, path: str = DEFAULT_CACHE) -> None:
+def save(workload: str, params: Dict[str, int], table: List, path: str = DEFAULT_CACHE,
+         stats: Optional[Dict[str, float]] = None) -> None:
     try:
         with open(path) as f:
             cache = json.load(f)
     except (OSError, ValueError):
         cache = {}
-    cache.setdefault(device_key(), {})[workload] = {"params": params, "trials": table}
+    entry = {"params": params, "trials": table}
+    if stats:
+        entry.update(stats)
+    cache.setdefault(device_key(), {})[workload] = entry
     tmp = path + ".tmp"
     with open(tmp, "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)
@@ -94,12 +116,16 @@ def save(workload: str, params: Dict[str, int], table: List, path: str = DEFAULT
 
 
 def search(ctx: int, run: Callable[[], float], space: Dict[str, Iterable[int]],
-           repeats: int = 2, log: Optional[Callable[[str], None]] = None):
+           repeats: int = 3, log: Optional[Callable[[str], None]] = None):
     """Coordinate search: starting from the context's current parameters,
     sweep one parameter at a time over its candidate values (others fixed at
-    their best so far), keeping the value with the lowest median time of
-    `repeats` runs of `run()` (which returns seconds and must rebuild any
-    state that depends on the parameters).  Returns (best params, trials)."""
+    their best so far), scoring each by the median of `repeats` runs of
+    `run()` (which returns seconds and must rebuild any state that depends on
+    the parameters).  The default shapes are measured first; the spread of
+    their runs (slowest minus fastest) is the noise margin, and a candidate
+    replaces the best so far only when it is faster by more than that margin.
+    Returns (best params, trials, stats) with stats = {default_s, best_s,
+    spread_s, gain}."""
     best = current(ctx)
     trials = []
 
@@ -107,20 +133,23 @@ def search(ctx: int, run: Callable[[], float], space: Dict[str, Iterable[int]],
         apply(ctx, params)
         ts = sorted(run() for _ in range(repeats))
         t = ts[len(ts) // 2]
-        trials.append({"params": dict(params), "seconds": t})
+        trials.append({"params": dict(params), "seconds": t, "runs": ts})
         if log:
             log(f"[autotune] {params} -> {t * 1e3:.2f} ms")
-        return t
+        return t, ts[-1] - ts[0]
 
-    best_t = measure(best)
+    default_t, spread = measure(best)
+    best_t = default_t
     for name, values in space.items():
         for v in values:
             if best.get(name) == v:
                 continue
             cand = dict(best)
             cand[name] = v
-            t = measure(cand)
-            if t < best_t:
+            t, _ = measure(cand)
+            if t < best_t - spread:
                 best, best_t = cand, t
     apply(ctx, best)
-    return best, trials
+    stats = {"default_s": default_t, "best_s": best_t, "spread_s": spread,
+             "gain": default_t / best_t if best_t else 1.0}
+    return best, trials, stats

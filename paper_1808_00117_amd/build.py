@@ -10,7 +10,7 @@ SO = os.path.join(HERE, "libcrum.so")
 SOURCES = [os.path.join(HERE, "csrc", f)
            for f in ("crum_kernels.hip", "crum_capi.hip", "crum_plan.hip", "crum_server.hip",
                      "crum_writer.hip", "crum_lazy.hip", "crum_track.hip",
-                     "crum_noalloc.hip")]
+                     "crum_noalloc.hip", "crum_tune.hip")]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
     "-Wno-unused-result",

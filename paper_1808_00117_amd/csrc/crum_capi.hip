@@ -263,7 +263,7 @@ int crum_image_bytes(uint32_t n_regions, uint64_t total_pages, uint64_t n_dirty,
     return CRUM_OK;
 }
 
-int crum_ctx_create(int device, crum_ctx** out)
+int crum_ctx_create(int device, const char* tuning_cache, crum_ctx** out)
 {
     if (!out)
         return CRUM_EINVAL;
@@ -273,9 +273,18 @@ int crum_ctx_create(int device, crum_ctx** out)
         return CRUM_EHIP;
     if (device < 0 || device >= n_dev)
         return CRUM_EINVAL;
+    std::vector<TunedClass> tuned;
+    if (tuning_cache) {
+        std::string key;
+        if (device_key(device, &key) != CRUM_OK)
+            return CRUM_EHIP;
+        if (tune_load(tuning_cache, key, &tuned) != CRUM_OK)
+            return CRUM_EINVAL;
+    }
     DeviceGuard g(device);
     crum_ctx* c = new crum_ctx();
     c->device = device;
+    c->tuned = std::move(tuned);
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
         cus > 0)
@@ -337,12 +346,51 @@ void crum_ctx_destroy(crum_ctx* c)
 
 int crum_ctx_set_param(crum_ctx* c, int param, uint64_t v)
 {
+    const int rc = crum::set_param_raw(c, param, v);
+    if (rc == CRUM_OK && param > 0 && param < 64)
+        c->explicit_params |= 1ull << param;
+    return rc;
+}
+
+int crum_ctx_tuned_classes(crum_ctx* c, uint32_t* n)
+{
+    if (!c || !n)
+        return CRUM_EINVAL;
+    *n = (uint32_t)c->tuned.size();
+    return CRUM_OK;
+}
+
+int crum_tuning_check(const char* path, const char* device_key, uint32_t* n_classes)
+{
+    if (!path || !device_key)
+        return CRUM_EINVAL;
+    std::vector<TunedClass> v;
+    const int rc = tune_load(path, device_key, &v);
+    if (rc == CRUM_OK && n_classes)
+        *n_classes = (uint32_t)v.size();
+    return rc;
+}
+
+}  // extern "C"
+
+namespace crum {
+
+int set_param_raw(crum_ctx* c, int param, uint64_t v)
+{
     if (!c)
         return CRUM_EINVAL;
-    if (param == CRUM_PARAM_EAGER || param == CRUM_PARAM_DIFF_NONTEMPORAL) {
+    if (param == CRUM_PARAM_EAGER || param == CRUM_PARAM_DIFF_NONTEMPORAL ||
+        param == CRUM_PARAM_PACK_NT_STORE) {
         if (v > 1)
             return CRUM_EINVAL;
-        (param == CRUM_PARAM_EAGER ? c->eager : c->diff_nt) = v != 0;
+        (param == CRUM_PARAM_EAGER ? c->eager
+         : param == CRUM_PARAM_DIFF_NONTEMPORAL ? c->diff_nt : c->pack_nt) = v != 0;
+        return CRUM_OK;
+    }
+    if (param == CRUM_PARAM_CHUNK_GROWTH) {
+        if (v < 2 || v > 16)
+            return CRUM_EINVAL;
+        c->chunk_growth = (uint32_t)v;
         return CRUM_OK;
     }
     if (param == CRUM_PARAM_DIFF_UNIT_SHIFT) {
@@ -412,6 +460,55 @@ int crum_ctx_set_param(crum_ctx* c, int param, uint64_t v)
     }
 }
 
+TunedScope::TunedScope(crum_ctx* c, int kind, uint32_t page_size, uint64_t bytes) : c_(c)
+{
+    const TunedClass* t = tune_find(c->tuned, kind, page_size, bytes);
+    if (!t)
+        return;
+    for (const auto& kv : t->params) {
+        if (n_ == 32)
+            break;
+        if (kv.first > 0 && kv.first < 64 && ((c->explicit_params >> kv.first) & 1u))
+            continue;
+        uint64_t old = 0;
+        if (crum_ctx_get_param(c, kv.first, &old) != CRUM_OK)
+            continue;
+        if (set_param_raw(c, kv.first, kv.second) == CRUM_OK) {
+            id_[n_] = kv.first;
+            old_[n_] = old;
+            ++n_;
+        }
+    }
+}
+
+TunedScope::~TunedScope()
+{
+    for (int i = n_ - 1; i >= 0; --i)
+        (void)set_param_raw(c_, id_[i], old_[i]);
+}
+
+// "cc<major>.<minor>-<CUs>cu|hip<runtime version>", as the shape tuner keys
+// its cache.
+int device_key(int device, std::string* out)
+{
+    int major = 0, minor = 0, cus = 0, ver = 0;
+    if (hipDeviceGetAttribute(&major, hipDeviceAttributeComputeCapabilityMajor, device) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&minor, hipDeviceAttributeComputeCapabilityMinor, device) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) !=
+            hipSuccess ||
+        hipRuntimeGetVersion(&ver) != hipSuccess)
+        return CRUM_EHIP;
+    *out = "cc" + std::to_string(major) + "." + std::to_string(minor) + "-" +
+           std::to_string(cus) + "cu|hip" + std::to_string(ver);
+    return CRUM_OK;
+}
+
+}  // namespace crum
+
+extern "C" {
+
 int crum_ctx_get_param(crum_ctx* c, int param, uint64_t* v)
 {
     if (!c || !v)
@@ -431,6 +528,8 @@ int crum_ctx_get_param(crum_ctx* c, int param, uint64_t* v)
     case CRUM_PARAM_CRC_VARIANT: *v = (uint64_t)c->crc_variant; return CRUM_OK;
     case CRUM_PARAM_PLAN_ORDER: *v = (uint64_t)c->plan_order; return CRUM_OK;
     case CRUM_PARAM_DIRECT_BYTES: *v = c->direct_bytes; return CRUM_OK;
+    case CRUM_PARAM_CHUNK_GROWTH: *v = c->chunk_growth; return CRUM_OK;
+    case CRUM_PARAM_PACK_NT_STORE: *v = c->pack_nt ? 1 : 0; return CRUM_OK;
     default: return CRUM_EINVAL;
     }
 }
@@ -519,6 +618,7 @@ static int snapshot_impl(crum_ctx* c, const crum_region* regions, uint32_t n_reg
     const uint64_t worst = data_off + (G << ps) + round_up(4 * G, 8);
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     DeviceGuard g(c->device);
+    const TunedScope tuned(c, 0, page_size, G << ps);
     // Small images may be built straight in the pinned host image (the pack
     // and header kernels write it over the host link): no staging, no drain
     // copy, and the host never waits on a dirty count.  Only for host memory
@@ -541,7 +641,7 @@ static int snapshot_impl(crum_ctx* c, const crum_region* regions, uint32_t n_reg
             const uint64_t pages = std::max<uint64_t>(64, (chunk_bytes >> ps) & ~63ull);
             gp = std::min(G, gp + pages);
             cuts.push_back(gp);
-            chunk_bytes = std::min<uint64_t>(chunk_bytes * 2,
+            chunk_bytes = std::min<uint64_t>(chunk_bytes * c->chunk_growth,
                                              std::max(c->chunk_max_bytes, c->chunk_bytes));
         }
         if (cuts.size() == 2)
@@ -631,7 +731,7 @@ static int snapshot_impl(crum_ctx* c, const crum_region* regions, uint32_t n_reg
             CRUM_TRY(launch_pack(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                  np_shift, pc_shift, d_flags, himg, d_crcs, d_partials,
                                  c->d_tabs, d_glob, c->shape.pack_blocks, c->pack_depth,
-                                 c->crc_variant, stream));
+                                 c->crc_variant, stream, c->pack_nt));
             CRUM_TRY(launch_finalize(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                      np_shift, pc_shift, d_partials, d_crcs, himg, d_glob,
                                      c->d_tabs, stream));
@@ -676,7 +776,7 @@ static int snapshot_impl(crum_ctx* c, const crum_region* regions, uint32_t n_reg
                 CRUM_TRY(launch_pack(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                      np_shift, pc_shift, d_flags, staging, d_crcs,
                                      d_partials, c->d_tabs, d_glob, c->shape.pack_blocks,
-                                     c->pack_depth, c->crc_variant, stream));
+                                     c->pack_depth, c->crc_variant, stream, c->pack_nt));
                 CRUM_TRY(launch_finalize(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                          np_shift, pc_shift, d_partials, d_crcs, staging, d_glob,
                                          c->d_tabs, stream));
@@ -749,7 +849,7 @@ static int snapshot_impl(crum_ctx* c, const crum_region* regions, uint32_t n_reg
                 CRUM_TRY(launch_pack(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                      np_shift, pc_shift, d_flags, staging, d_crcs,
                                      d_partials, c->d_tabs, d_glob, c->shape.pack_blocks,
-                                     c->pack_depth, c->crc_variant, stream));
+                                     c->pack_depth, c->crc_variant, stream, c->pack_nt));
                 CRUM_TRY(launch_finalize(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                          np_shift, pc_shift, d_partials, d_crcs, staging, d_glob,
                                          c->d_tabs, stream));

@@ -10,8 +10,13 @@ namespace crum {
 // loads, i.e. unit/1 KiB loads per array per lane.
 constexpr uint32_t kUnitShiftDefault = 14;
 // CRC piece: pages larger than this are split across waves and combined.
-constexpr uint32_t kPieceShift = 16;  // largest (and default) pack piece: 64 KiB
+constexpr uint32_t kPieceShift = 16;  // largest pack piece: 64 KiB
 constexpr uint32_t kPieceShiftMin = 12;
+// Default piece: 16 KiB.  Four times the waves of whole 64 KiB pages per
+// launch; on the 16 GiB workload's 23 117 dirty 64 KiB pages the pack ran at
+// 4.15-4.43 TB/s pipelined and 5.27-5.32 TB/s in one launch with 16 KiB
+// pieces, against 3.87-3.92 and 5.13-5.26 TB/s with 64 KiB ones.
+constexpr uint32_t kPieceShiftDefault = 14;
 // CRC step variants 0..5 (see launch_pack); kCrcVariantAuto picks the one
 // measured fastest per kernel: byte tables for pack, variant 3 for verify.
 constexpr int kCrcVariantAuto = 6;
@@ -142,12 +147,13 @@ hipError_t launch_list(const uint64_t* bitmap, const uint32_t* prefix, uint64_t 
 // lookups between byte and nibble tables.  Pack updates the shadows of regions whose flags bit 0
 // is set.  unit_flags (pack only, may be null): the diff's per-unit flags of
 // the same page space; units flagged clean are then read from the shadow.
+// nt_store (pack only): write the image with non-temporal stores.
 hipError_t launch_pack(int mode, const DevRegion* regs, uint32_t n_regs, const DevRequest* reqs,
                        const DevReqOut* out, const uint32_t* list, SlotRange range,
                        uint32_t np_shift, uint32_t piece_shift, const uint8_t* unit_flags,
                        uint8_t* staging, uint32_t* crc_out, uint32_t* partials,
                        const CrcTables* tabs, DevGlobal* glob, int blocks, int depth,
-                       int variant, hipStream_t s);
+                       int variant, hipStream_t s, int nt_store = 0);
 hipError_t launch_finalize(int mode, const DevRegion* regs, uint32_t n_regs,
                            const DevRequest* reqs, const DevReqOut* out, const uint32_t* list,
                            SlotRange range, uint32_t np_shift, uint32_t piece_shift,

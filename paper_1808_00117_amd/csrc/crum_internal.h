@@ -4,6 +4,7 @@
 #include "crum_dev.h"
 
 #include <algorithm>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -17,6 +18,24 @@ constexpr uint64_t kNoAllocSortOff = 160ull << 10;
 constexpr uint64_t kNoAllocPinnedBytes = 256ull << 10;
 // Address of crum_snapshot_noalloc's device scratch on `device` (current).
 int noalloc_scratch(int device, uint8_t** out);
+
+// Tuned shapes of one workload class from the shape tuner's cache: kind 0 =
+// single snapshots of page_size bytes, kind 1 = plans; the class holds calls
+// whose scanned bytes N satisfy 2^log2_bytes <= N < 2^(log2_bytes+1).
+struct TunedClass {
+    int kind = 0;
+    uint32_t page_size = 0;
+    uint32_t log2_bytes = 0;
+    std::vector<std::pair<int, uint64_t>> params;  // CRUM_PARAM_* id, value
+};
+// Reads the classes of `device_key` from the cache file (crum_tune.hip).
+int tune_load(const char* path, const std::string& device_key, std::vector<TunedClass>* out);
+const TunedClass* tune_find(const std::vector<TunedClass>& v, int kind, uint32_t page_size,
+                            uint64_t bytes);
+// crum_ctx_set_param without marking the parameter as set by the caller.
+int set_param_raw(crum_ctx* c, int param, uint64_t v);
+// The tuner's device key of `device` (crum_capi.hip).
+int device_key(int device, std::string* out);
 enum { kTDiff = 0, kTPack = 1, kTDrain = 2, kTScan = 3, kTHeader = 4, kTVerify = 5, kTScatter = 6 };
 
 struct DeviceGuard {
@@ -126,12 +145,18 @@ struct crum_ctx {
     uint32_t unit_shift_max = crum::kUnitShiftDefault;
     bool diff_nt = true;
     uint64_t drain_chunk_bytes = 8ull << 20;
-    uint32_t piece_shift = crum::kPieceShift;
+    uint32_t piece_shift = crum::kPieceShiftDefault;
     int pack_depth = 4;
     int diff_prio = 0;
     int crc_variant = crum::kCrcVariantAuto;
     int plan_order = 0;
     uint64_t direct_bytes = 0;  // opt-in: worst-case images up to this size go straight to the host
+    uint32_t chunk_growth = 4;  // growth factor of pipelined chunks and plan groups
+    bool pack_nt = false;       // non-temporal image stores in the pack
+    // tuned shapes per workload class (crum_ctx_create's tuning cache), applied
+    // to a call's parameters that crum_ctx_set_param has not set
+    std::vector<crum::TunedClass> tuned;
+    uint64_t explicit_params = 0;  // bit p: parameter p set by crum_ctx_set_param
     bool eager = true;
     uint32_t timing_mask = 0;  // bit c: time launches of class c
     bool partial_call = false;  // a call stopped part-way through its enqueue
@@ -171,6 +196,26 @@ inline int ctx_pack_depth(const crum_ctx* c) { return c->pack_depth; }
 inline int ctx_diff_prio(const crum_ctx* c) { return c->diff_prio; }
 inline int ctx_crc_variant(const crum_ctx* c) { return c->crc_variant; }
 inline int ctx_plan_order(const crum_ctx* c) { return c->plan_order; }
+inline uint32_t ctx_chunk_growth(const crum_ctx* c) { return c->chunk_growth; }
+inline int ctx_pack_nt(const crum_ctx* c) { return c->pack_nt ? 1 : 0; }
+
+// Applies the context's tuned shapes for one call's workload class, for the
+// duration of the call (a context is used by one thread at a time), to the
+// parameters the caller has not set explicitly; restores them afterwards.
+// No allocation.
+class TunedScope {
+public:
+    TunedScope(crum_ctx* c, int kind, uint32_t page_size, uint64_t bytes);
+    ~TunedScope();
+    TunedScope(const TunedScope&) = delete;
+    TunedScope& operator=(const TunedScope&) = delete;
+
+private:
+    crum_ctx* c_;
+    int n_ = 0;
+    int id_[32];
+    uint64_t old_[32];
+};
 
 }  // namespace crum
 

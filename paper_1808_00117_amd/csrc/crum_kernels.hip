@@ -88,7 +88,8 @@ constexpr int kAllTabWords = kSliceWords + 7 * 4 * 256;    // 44 KiB
 
 // LDS layout of the pack and verify kernels (words): slicing tables, nibble
 // tables, shift-by-1-KiB tables; 22.5 KiB.  The butterfly's shift tables
-// (used once per piece) are read from global memory.
+// (used once per piece) are read from global memory: holding nibble versions
+// of them in LDS as well (25 KiB) measured no faster.
 constexpr int kNibOff = kSliceWords;
 constexpr int kZ5Off = kNibOff + 20 * 2 * 16;
 constexpr int kPackLdsWords = kZ5Off + 4 * 256;
@@ -313,8 +314,10 @@ struct PieceSrc {
     }
 };
 
-// lds: the pack layout (kPackLdsWords); V: the CRC step variant.
-template <bool STORE, int U, int V>
+// lds: the pack layout (kPackLdsWords); V: the CRC step variant.  STORE: 0
+// reads only (verify), 1 copies into dst, 2 copies with non-temporal stores
+// (the image is streamed out and not read again by the kernels).
+template <int STORE, int U, int V>
 __device__ __forceinline__ uint32_t piece_steps(const PieceSrc& src, gv4 __restrict__ dst,
                                                 gv4 __restrict__ sh, uint32_t* t_io,
                                                 uint32_t steps, uint32_t lane,
@@ -328,8 +331,12 @@ __device__ __forceinline__ uint32_t piece_steps(const PieceSrc& src, gv4 __restr
             w[u] = src.at(t + u)[(t + u) * 64 + lane];
         if (STORE) {
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                dst[(t + u) * 64 + lane] = w[u];
+            for (int u = 0; u < U; ++u) {
+                if (STORE == 2)
+                    __builtin_nontemporal_store(w[u], dst + (t + u) * 64 + lane);
+                else
+                    dst[(t + u) * 64 + lane] = w[u];
+            }
             if (sh) {
                 // clean units already hold these bytes in the shadow
 #pragma unroll
@@ -351,7 +358,7 @@ __device__ __forceinline__ uint32_t piece_steps(const PieceSrc& src, gv4 __restr
 // sh, dirty units only) when STORE.  DEPTH: 16-byte loads each lane issues
 // before it folds them into its CRC.  All lanes return the same value.
 // gz: z[0] of the shift tables in global memory (the butterfly's shifts).
-template <bool STORE, int DEPTH, int V>
+template <int STORE, int DEPTH, int V>
 __device__ __forceinline__ uint32_t wave_piece_crc(const PieceSrc& src, gv4 __restrict__ dst,
                                                    gv4 __restrict__ sh, uint32_t steps,
                                                    uint32_t lane,
@@ -740,7 +747,7 @@ __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs
                                               uint32_t* __restrict__ crc_out,
                                               uint32_t* __restrict__ partials,
                                               const CrcTables* __restrict__ tabs,
-                                              DevGlobal* __restrict__ glob)
+                                              DevGlobal* __restrict__ glob, uint32_t nt_store)
 {
     __shared__ __attribute__((aligned(16))) uint32_t lds[kPackLdsWords];
     if (MODE == kModeVerify && glob->fmt_bad)
@@ -803,11 +810,13 @@ __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs
             gv4 sh = ((R.flags & 1u) && R.shadow)
                             ? (gv4)(R.shadow + page_off + piece_off)
                             : nullptr;
-            raw = wave_piece_crc<true, DEPTH, V>(src, (gv4)slot_ptr, sh,
-                                                 steps, lane, lds, gz);
+            raw = nt_store ? wave_piece_crc<2, DEPTH, V>(src, (gv4)slot_ptr, sh, steps, lane,
+                                                         lds, gz)
+                           : wave_piece_crc<1, DEPTH, V>(src, (gv4)slot_ptr, sh, steps, lane,
+                                                         lds, gz);
         } else {
             const PieceSrc src{(gcv4)slot_ptr, nullptr, ~0u, 0};
-            raw = wave_piece_crc<false, DEPTH, V>(src, nullptr, nullptr, steps, lane, lds, gz);
+            raw = wave_piece_crc<0, DEPTH, V>(src, nullptr, nullptr, steps, lane, lds, gz);
         }
         if (lane != 0)
             continue;
@@ -832,11 +841,12 @@ static void launch_pack_one(dim3 grid, hipStream_t s, const DevRegion* regs, uin
                             const DevRequest* reqs, const DevReqOut* out, const uint32_t* list,
                             SlotRange range, uint32_t np_shift, uint32_t piece_shift,
                             const uint8_t* unit_flags, uint8_t* staging, uint32_t* crc_out,
-                            uint32_t* partials, const CrcTables* tabs, DevGlobal* glob)
+                            uint32_t* partials, const CrcTables* tabs, DevGlobal* glob,
+                            uint32_t nt_store)
 {
     hipLaunchKernelGGL((k_pack<MODE, DEPTH, V>), grid, dim3(256), 0, s, regs, n_regs, reqs, out,
                        list, range, np_shift, piece_shift, unit_flags, staging, crc_out,
-                       partials, tabs, glob);
+                       partials, tabs, glob, nt_store);
 }
 
 template <int MODE, int DEPTH>
@@ -845,12 +855,12 @@ static void launch_pack_depth(int variant, dim3 grid, hipStream_t s, const DevRe
                               const uint32_t* list, SlotRange range, uint32_t np_shift,
                               uint32_t piece_shift, const uint8_t* unit_flags, uint8_t* staging,
                               uint32_t* crc_out, uint32_t* partials, const CrcTables* tabs,
-                              DevGlobal* glob)
+                              DevGlobal* glob, uint32_t nt_store)
 {
 #define CRUM_PACK_V(v)                                                                        \
     launch_pack_one<MODE, DEPTH, v>(grid, s, regs, n_regs, reqs, out, list, range, np_shift, \
                                     piece_shift, unit_flags, staging, crc_out, partials, tabs, \
-                                    glob)
+                                    glob, nt_store)
     switch (variant) {
     case 0: CRUM_PACK_V(0); break;
     case 1: CRUM_PACK_V(1); break;
@@ -868,20 +878,20 @@ static void launch_pack_mode(dim3 grid, int depth, int variant, hipStream_t s,
                              const DevReqOut* out, const uint32_t* list, SlotRange range,
                              uint32_t np_shift, uint32_t piece_shift, const uint8_t* unit_flags,
                              uint8_t* staging, uint32_t* crc_out, uint32_t* partials,
-                             const CrcTables* tabs, DevGlobal* glob)
+                             const CrcTables* tabs, DevGlobal* glob, uint32_t nt_store)
 {
     if (depth == 16)
         launch_pack_depth<MODE, 16>(variant, grid, s, regs, n_regs, reqs, out, list, range,
                                     np_shift, piece_shift, unit_flags, staging, crc_out,
-                                    partials, tabs, glob);
+                                    partials, tabs, glob, nt_store);
     else if (depth == 8)
         launch_pack_depth<MODE, 8>(variant, grid, s, regs, n_regs, reqs, out, list, range,
                                    np_shift, piece_shift, unit_flags, staging, crc_out, partials,
-                                   tabs, glob);
+                                   tabs, glob, nt_store);
     else
         launch_pack_depth<MODE, 4>(variant, grid, s, regs, n_regs, reqs, out, list, range,
                                    np_shift, piece_shift, unit_flags, staging, crc_out, partials,
-                                   tabs, glob);
+                                   tabs, glob, nt_store);
 }
 
 hipError_t launch_pack(int mode, const DevRegion* regs, uint32_t n_regs, const DevRequest* reqs,
@@ -889,7 +899,7 @@ hipError_t launch_pack(int mode, const DevRegion* regs, uint32_t n_regs, const D
                        uint32_t np_shift, uint32_t piece_shift, const uint8_t* unit_flags,
                        uint8_t* staging, uint32_t* crc_out, uint32_t* partials,
                        const CrcTables* tabs, DevGlobal* glob, int blocks, int depth,
-                       int variant, hipStream_t s)
+                       int variant, hipStream_t s, int nt_store)
 {
     const uint64_t max_items = range.max_slots << np_shift;
     if (max_items == 0)
@@ -904,11 +914,11 @@ hipError_t launch_pack(int mode, const DevRegion* regs, uint32_t n_regs, const D
     if (mode == kModePack)
         launch_pack_mode<kModePack>(grid, depth, variant, s, regs, n_regs, reqs, out, list,
                                     range, np_shift, piece_shift, unit_flags, staging, crc_out,
-                                    partials, tabs, glob);
+                                    partials, tabs, glob, nt_store ? 1u : 0u);
     else
         launch_pack_mode<kModeVerify>(grid, depth, variant, s, regs, n_regs, reqs, out, list,
                                       range, np_shift, piece_shift, nullptr, staging, crc_out,
-                                      partials, tabs, glob);
+                                      partials, tabs, glob, 0u);
     return hipGetLastError();
 }
 

@@ -115,6 +115,11 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
     }
     if (total_regs > 0xFFFFFFFFull || ctx_check_ranges(all.data(), (uint32_t)all.size()) != CRUM_OK)
         return CRUM_EINVAL;
+    uint64_t all_bytes = 0;
+    for (const crum_region& r : all)
+        all_bytes += r.len;
+    // the plan's shapes: the caller's parameters, or the tuned ones of its class
+    const TunedScope tuned(c, 1, 0, all_bytes);
 
     // ---- processing order: the caller's, or smallest scanned bytes first
     std::vector<uint32_t> order(n_reqs);
@@ -204,7 +209,7 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
             if (acc >= target || q + 1 == n_reqs) {
                 p->group_q.push_back(q + 1);
                 acc = 0;
-                target = std::min<uint64_t>(target * 2,
+                target = std::min<uint64_t>(target * ctx_chunk_growth(c),
                                             std::max(ctx_chunk_max_bytes(c), ctx_chunk_bytes(c)));
             }
         }
@@ -301,7 +306,8 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
         if (e == hipSuccess)
             e = launch_pack(kModePack, d_regs, p->n_regs, d_reqs, d_out, d_list, sr, np_shift,
                             pc_shift, d_flags, p->staging, d_crcs, d_part, tabs, d_glob,
-                            shape.pack_blocks, ctx_pack_depth(c), ctx_crc_variant(c), s);
+                            shape.pack_blocks, ctx_pack_depth(c), ctx_crc_variant(c), s,
+                            ctx_pack_nt(c));
         if (e == hipSuccess)
             e = launch_finalize(kModePack, d_regs, p->n_regs, d_reqs, d_out, d_list, sr, np_shift,
                                 pc_shift, d_part, d_crcs, p->staging, d_glob, tabs, s);

@@ -46,7 +46,7 @@ struct HipBackend {
     bool open(Slot& s, uint64_t staging_bytes)
     {
         DeviceGuard g(device);
-        if (crum_ctx_create(device, &s.ctx) != CRUM_OK ||
+        if (crum_ctx_create(device, nullptr, &s.ctx) != CRUM_OK ||
             hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
             hipMalloc(reinterpret_cast<void**>(&s.staging), staging_bytes) != hipSuccess ||
             hipHostMalloc(reinterpret_cast<void**>(&s.st), sizeof(crum_status), 0) != hipSuccess)

@@ -76,7 +76,7 @@ int main(void)
     HIPOK(hipStreamCreate(&s));
 
     crum_ctx* ctx = NULL;
-    int rc = crum_ctx_create(0, &ctx);
+    int rc = crum_ctx_create(0, NULL, &ctx);
     if (rc != CRUM_OK)
         return fail("crum_ctx_create", rc);
     crum_region regs[2] = {{cur0, sh0, b0, 71}, {cur1, NULL, b1, 72}};

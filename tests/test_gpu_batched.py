@@ -243,7 +243,7 @@ def test_autotune_keeps_images(tmp_path):
             return t
         space = {"pack_blocks": [8, 256], "chunk_bytes": [4096, 1 << 20],
                  "crc_variant": [0, 3], "diff_blocks": [16, 1024]}
-        best, trials = autotune.search(ctx, run, space, repeats=1)
+        best, trials, _ = autotune.search(ctx, run, space, repeats=1)
         assert len(trials) == 1 + sum(len(v) for v in space.values()) - sum(
             1 for k, v in space.items() if trials[0]["params"][k] in v)
         assert autotune.current(ctx) == best
@@ -331,3 +331,48 @@ def test_batched_property(ctx):
             assert np.array_equal(img, img_o), f"request {q} differs from the oracle"
 
     run()
+
+
+def test_tuning_cache_class_shapes_apply_and_explicit_params_win(tmp_path):
+    """A context created with a tuning cache runs a plan of a cached class
+    with that class's shapes (here one group per request, visible in the
+    plan's group layout), an explicitly set parameter wins over the cache,
+    and the images stay the oracle's."""
+    import json
+
+    import paper_1808_00117_amd as crum
+    from paper_1808_00117_amd import autotune
+    from paper_1808_00117_amd.api import Snapshotter
+    host = make_requests(41, 6)
+    total = sum(c.size for regs, _, _ in host for c, _, _ in regs)
+    key = autotune.class_key("plan", total)
+    path = tmp_path / "cache.json"
+    path.write_text(json.dumps({autotune.device_key(): {
+        key: {"params": {"chunk_bytes": 1, "chunk_max_bytes": 1}}}}))
+    s = Snapshotter(0)
+    crum.crum_ctx_destroy(s.ctx)
+    s.ctx = crum.crum_ctx_create(0, str(path))
+    try:
+        assert crum.crum_ctx_tuned_classes(s.ctx) == 1
+        dev, res, groups = run_plan(s, host)
+        # groups of one byte: a group closes at every request that scans any
+        expect, acc = 0, 0
+        for q, (regs, _, _) in enumerate(host):
+            acc += sum(c.size for c, _, _ in regs)
+            if acc >= 1 or q + 1 == len(host):
+                expect, acc = expect + 1, 0
+        assert expect > 1 and len(groups) - 1 == expect, groups
+        for q, (regs, P, seq) in enumerate(host):
+            st_o, img_o, _ = oracle.snapshot(regs, P, seq=seq)
+            assert np.array_equal(res[0][1][q], img_o), q
+        # the cache's shapes last for the call only
+        assert crum.crum_ctx_get_param(s.ctx, crum.CRUM_PARAM_CHUNK_BYTES) == 128 << 20
+        # an explicit value wins over the cached class
+        crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_CHUNK_BYTES, 1 << 40)
+        crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_CHUNK_MAX_BYTES, 1 << 40)
+        _, res2, groups2 = run_plan(s, host, dev=dev)
+        assert len(groups2) - 1 == 1, groups2
+        for q in range(len(host)):
+            assert np.array_equal(res2[0][1][q], res[0][1][q]), q
+    finally:
+        s.close()

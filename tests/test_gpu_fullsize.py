@@ -222,7 +222,7 @@ def test_batched_256_requests():
     ctx = crum.crum_ctx_create(0)
     s = H.Stream()
     try:
-        tuned = autotune.load("batched")
+        tuned = autotune.load(autotune.class_key("plan", sum(r.total_bytes for r in reqs)))
         if tuned:
             autotune.apply(ctx, tuned)
         plan = crum.Plan(ctx, [(t, r.page_size, 0, 9) for t, r in zip(tables, reqs)],

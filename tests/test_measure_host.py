@@ -9,10 +9,12 @@ import bench
 
 
 def write_csv(path, header, rows):
-    with open(path, "w") as f:
-        f.write(",".join(header) + "\n")
+    import csv
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(header)
         for r in rows:
-            f.write(",".join(str(x) for x in r) + "\n")
+            w.writerow(r)
 
 
 def test_pmc_summary_scales_by_the_copy_kernel(tmp_path):
@@ -60,6 +62,28 @@ def test_trace_summary_takes_the_last_steps(tmp_path):
     assert "6, average duration 0.0030 ms" in out
 
 
+def test_trace_summary_reports_timed_drain_copies(tmp_path):
+    """Device-to-host copies of at least 4 KiB that start after the last
+    untimed snapshot's header are summed into bytes, time and GB/s."""
+    hdr = ["Kernel_Name", "Start_Timestamp", "End_Timestamp"]
+    rows, copies = [], []
+    t = 0
+    for snap in range(3):  # 1 untimed + 2 timed
+        rows.append(("crum::k_diff<true>", t, t + 1000))
+        rows.append(("crum::k_pack<0, 4, 0>", t + 2000, t + 2500))
+        copies.append(("MEMORY_COPY_DEVICE_TO_HOST", t + 3000, t + 4000, 1 << 20))
+        copies.append(("MEMORY_COPY_DEVICE_TO_HOST", t + 4000, t + 4100, 40))
+        copies.append(("MEMORY_COPY_HOST_TO_DEVICE", t + 4100, t + 4200, 1 << 20))
+        rows.append(("crum::k_header", t + 5000, t + 5100))
+        t += 10000
+    write_csv(tmp_path / "run_kernel_trace.csv", hdr, rows)
+    write_csv(tmp_path / "run_memory_copy_trace.csv",
+              ["Direction", "Start_Timestamp", "End_Timestamp", "Size"], copies)
+    out = bench.trace_summary(str(tmp_path), 2)
+    assert "k_pack (snapshot pack) launches in the timed snapshots: 2" in out
+    assert "2 copies, summed duration 0.002 ms, 2097152 bytes, 1048.58 GB/s" in out
+
+
 def test_kernel_hash_ignores_comments(tmp_path, monkeypatch):
     src = tmp_path / "paper_1808_00117_amd" / "csrc"
     src.mkdir(parents=True)
@@ -81,10 +105,11 @@ def test_autotune_search_and_cache(tmp_path, monkeypatch):
     monkeypatch.setattr(autotune, "current", lambda ctx: dict(state))
     monkeypatch.setattr(autotune, "apply", lambda ctx, p: state.update(p))
     monkeypatch.setattr(autotune, "device_key", lambda: "test-device|hip0")
-    best, trials = autotune.search(
+    best, trials, stats = autotune.search(
         None, lambda: (state["a"] - 3) ** 2 + (state["b"] - 5) ** 2 + 1.0,
         {"a": [1, 2, 3, 4], "b": [2, 5, 8]}, repeats=3)
     assert best == {"a": 3, "b": 5} and state == best
+    assert stats["default_s"] == 21.0 and stats["best_s"] == 1.0 and stats["spread_s"] == 0
     assert trials[0]["params"] == {"a": 1, "b": 1}
     assert min(t["seconds"] for t in trials) == 1.0
     path = str(tmp_path / "cache.json")
@@ -94,6 +119,32 @@ def test_autotune_search_and_cache(tmp_path, monkeypatch):
     assert autotune.load("missing", path) is None
     assert autotune.load("batched", str(tmp_path / "none.json")) is None
     assert set(json.load(open(path))["test-device|hip0"]) == {"batched", "other"}
+
+
+def test_autotune_keeps_only_gains_above_the_noise(monkeypatch):
+    """The default shapes' runs spread over 0.2 s: a candidate 0.1 s faster
+    is noise and is not kept; one 0.5 s faster is."""
+    import itertools
+
+    from paper_1808_00117_amd import autotune
+    state = {"a": 0}
+    monkeypatch.setattr(autotune, "current", lambda ctx: dict(state))
+    monkeypatch.setattr(autotune, "apply", lambda ctx, p: state.update(p))
+    jitter = itertools.cycle([0.0, 0.1, 0.2])
+    base = {0: 10.0, 1: 9.9, 2: 9.5}
+    best, trials, stats = autotune.search(None, lambda: base[state["a"]] + next(jitter),
+                                          {"a": [1]}, repeats=3)
+    assert best == {"a": 0} and abs(stats["spread_s"] - 0.2) < 1e-9
+    best, trials, stats = autotune.search(None, lambda: base[state["a"]] + next(jitter),
+                                          {"a": [2]}, repeats=3)
+    assert best == {"a": 2} and stats["gain"] > 1.0
+
+
+def test_autotune_class_keys():
+    from paper_1808_00117_amd import autotune
+    assert autotune.class_key("snapshot", 17179869184, 65536) == "snapshot|p65536|b34"
+    assert autotune.class_key("snapshot", (1 << 26) + 5, 4096) == "snapshot|p4096|b26"
+    assert autotune.class_key("plan", 70977024000) == "plan|b36"
 
 
 def test_cpu_baseline_reports_one_and_all_threads():
