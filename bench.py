@@ -91,6 +91,9 @@ def parse_args():
                     help="run a 1 GiB plain copy kernel first (counter calibration)")
     ap.add_argument("--trace-summary", metavar="DIR",
                     help="summarise a rocprofv3 --kernel-trace --stats run of this script")
+    ap.add_argument("--image-bytes", type=int, default=0,
+                    help="--trace-summary: bytes of one timed snapshot's image, for the drain "
+                         "rate when the copy trace carries no sizes")
     ap.add_argument("--pmc-table", metavar="DIR",
                     help="per-kernel mean counter values of one rocprofv3 --pmc run")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -190,7 +193,7 @@ def pmc_table(d: str, kernels=("k_pack<0", "k_pack<1", "k_diff", "k_scatter")) -
     return "\n".join(out)
 
 
-def trace_summary(d: str, steps: int) -> str:
+def trace_summary(d: str, steps: int, image_bytes: int = 0) -> str:
     """Markdown summary of a rocprofv3 kernel-trace run of this script: the
     per-kernel stats table, and the k_diff launches of the last `steps`
     snapshots (the timed region), which is what the bench's avg_launch_ms
@@ -233,7 +236,8 @@ def trace_summary(d: str, steps: int) -> str:
             out.append("")
             out.append(f"k_diff launches in the last {steps} snapshots (timed region): "
                        f"{len(sel)}, average duration {avg:.4f} ms")
-            t_lo, t_hi = t0, heads[-1][1]
+            # from the first timed diff: the previous snapshot's copies are done
+            t_lo, t_hi = sel[0][0] - 1, heads[-1][1]
         packs = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
                        for r in rows if "k_pack<0" in r["Kernel_Name"])
         if packs and t_lo is not None:
@@ -259,14 +263,19 @@ def trace_summary(d: str, steps: int) -> str:
             sel = [r for r in sel if int(r[size_col]) >= 4096]
         if sel:
             dur = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in sel) / 1e9
-            line = (f"device-to-host copies of at least 4 KiB after the first timed snapshot "
-                    f"began ({dir_col}): {len(sel)} copies, summed duration "
-                    f"{dur * 1e3:.3f} ms")
-            if size_col:
-                nbytes = sum(int(r[size_col]) for r in sel)
+            span = (max(int(r["End_Timestamp"]) for r in sel) -
+                    min(int(r["Start_Timestamp"]) for r in sel)) / 1e9
+            what = "of at least 4 KiB " if size_col else ""
+            line = (f"device-to-host copies {what}from the first timed snapshot's diff on "
+                    f"({dir_col}): {len(sel)} copies, summed duration {dur * 1e3:.3f} ms, "
+                    f"first start to last end {span * 1e3:.3f} ms")
+            nbytes = sum(int(r[size_col]) for r in sel) if size_col else steps * image_bytes
+            if nbytes:
                 gbs = nbytes / dur / 1e9
-                line += (f", {nbytes} bytes, {gbs:.2f} GB/s = {gbs / LINK_PEAK_GBS:.3f} of the "
-                         f"{LINK_PEAK_GBS:.1f} GB/s host link")
+                line += (f"; {nbytes} bytes "
+                         f"({'from the trace' if size_col else f'{steps} images of {image_bytes} bytes'}): "
+                         f"{gbs:.2f} GB/s over the copies' durations = "
+                         f"{gbs / LINK_PEAK_GBS:.3f} of the {LINK_PEAK_GBS:.1f} GB/s host link")
             out.append(line)
     return "\n".join(out)
 
@@ -491,6 +500,31 @@ def read_ceiling(H, scn, pairs, stream, reps: int = 7) -> dict:
     return {"kernel": "synth_read2_kernel: one wave per 16 KiB unit, 4 non-temporal 16-byte "
                       "loads per buffer in flight", "bytes": 2 * nb, "ms": round(ms, 4),
             "achieved": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def copy_ceiling(H, src_ptr: int, dst_ptr: int, nbytes: int, stream, reps: int = 7) -> dict:
+    """Practical HBM copy rate of this GPU (read + write): the generator
+    library's streaming copy kernel (one wave per 16 KiB, 16 non-temporal
+    loads per lane in flight, non-temporal stores, 4096 workgroups) over
+    `nbytes` (rounded down to 16 KiB), median of `reps` launches timed with
+    HIP events.  The pack's traffic has the same read/write mix."""
+    import synth
+    nb = nbytes // 16384 * 16384
+    e0, e1 = H.Event(), H.Event()
+    v = []
+    for r in range(reps + 2):
+        e0.record(stream)
+        synth.lib.copy2_dev(dst_ptr, src_ptr, nb, 4096, 16, True, stream.handle)
+        e1.record(stream)
+        ms = e0.elapsed_ms(e1)
+        if r >= 2:
+            v.append(ms)
+    ms = statistics.median(v)
+    gbs = 2 * nb / (ms * 1e-3) / 1e9
+    return {"kernel": "synth_copy2_kernel<16, true>: one wave per 16 KiB unit, 16 "
+                      "non-temporal 16-byte loads per lane in flight, non-temporal stores",
+            "bytes": 2 * nb, "ms": round(ms, 4), "achieved": round(gbs, 1),
+            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def percentile(v, q):
@@ -1525,11 +1559,11 @@ def managed_tracked_leg(args, scn, cur, sh, table, ctx, staging, himg, cap, stat
 def main():
     args = parse_args()
     if args.pmc_summary:
-        wl = "many_allocs" if args.config == "many" else "plain"
+        wl = "plain" if args.config == "plain" else "many_allocs"
         print(json.dumps(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], wl), indent=1))
         return
     if args.trace_summary:
-        print(trace_summary(args.trace_summary, args.steps))
+        print(trace_summary(args.trace_summary, args.steps, args.image_bytes))
         return
     if args.pmc_table:
         print(pmc_table(args.pmc_table))
@@ -1623,6 +1657,11 @@ def bench_many(args, with_cpu: bool = True) -> dict:
         autotune.apply(ctx, {k: int(v)})
     s1, s2 = H.Stream(), H.Stream()
     ceiling = read_ceiling(H, scn, pair_sets[0], s1) if args.config == "many" else None
+    # the largest region's current bytes copied into staging: the pack's bytes
+    big = max(range(R), key=lambda k: scn.regions[k].nbytes)
+    c_ceiling = copy_ceiling(H, pair_sets[0][big][0].ptr, staging.ptr,
+                             min(D * P, scn.regions[big].nbytes), s1) \
+        if args.config == "many" else None
 
     # co-runner: an application stream of fp32 SAXPY passes (y = a*x + y over
     # 4096x4096 elements), one kernel per pass, captured once as a graph of
@@ -1898,6 +1937,9 @@ def bench_many(args, with_cpu: bool = True) -> dict:
         "pack": {"achieved": round(pack_gbs, 1), "unit": "GB/s", "peak": HBM_PEAK_GBS,
                  "frac": round(pack_gbs / HBM_PEAK_GBS, 4), "launches": n_pk,
                  "avg_launch_ms": round(pack_ms / max(n_pk, 1), 4),
+                 "practical_ceiling": c_ceiling,
+                 "frac_of_ceiling": round(pack_gbs / c_ceiling["achieved"], 4)
+                 if c_ceiling else None,
                  "algorithmic_bytes_per_step": pack_bytes,
                  "what": None if drain_gbs else "direct order: the pack's stores cross the "
                                                 "host link into the pinned image"},

@@ -449,6 +449,8 @@ void crum_server_destroy(crum_server* server);
  *   chunks and plan groups grow, up to their maximum (4).
  * CRUM_PARAM_PACK_NT_STORE: 1 writes the image with non-temporal stores in
  *   the pack kernel (0).
+ * CRUM_PARAM_PACK_PREFETCH: 1 makes each lane of the pack and verify kernels
+ *   issue its next loads before folding the current ones into its CRC (0).
  * Values of 0 are rejected (CRUM_EINVAL) except for the on/off switches,
  * the priority and the direct-order size. */
 enum {
@@ -467,7 +469,8 @@ enum {
     CRUM_PARAM_PLAN_ORDER = 13,
     CRUM_PARAM_DIRECT_BYTES = 14,
     CRUM_PARAM_CHUNK_GROWTH = 15,
-    CRUM_PARAM_PACK_NT_STORE = 16
+    CRUM_PARAM_PACK_NT_STORE = 16,
+    CRUM_PARAM_PACK_PREFETCH = 17
 };
 int crum_ctx_set_param(crum_ctx* ctx, int param, uint64_t value);
 int crum_ctx_get_param(crum_ctx* ctx, int param, uint64_t* value);

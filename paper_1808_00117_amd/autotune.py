@@ -41,6 +41,7 @@ PARAMS = {
     "direct_bytes": C.CRUM_PARAM_DIRECT_BYTES,
     "chunk_growth": C.CRUM_PARAM_CHUNK_GROWTH,
     "pack_nt_store": C.CRUM_PARAM_PACK_NT_STORE,
+    "pack_prefetch": C.CRUM_PARAM_PACK_PREFETCH,
 }
 
 

@@ -380,11 +380,13 @@ int set_param_raw(crum_ctx* c, int param, uint64_t v)
     if (!c)
         return CRUM_EINVAL;
     if (param == CRUM_PARAM_EAGER || param == CRUM_PARAM_DIFF_NONTEMPORAL ||
-        param == CRUM_PARAM_PACK_NT_STORE) {
+        param == CRUM_PARAM_PACK_NT_STORE || param == CRUM_PARAM_PACK_PREFETCH) {
         if (v > 1)
             return CRUM_EINVAL;
-        (param == CRUM_PARAM_EAGER ? c->eager
-         : param == CRUM_PARAM_DIFF_NONTEMPORAL ? c->diff_nt : c->pack_nt) = v != 0;
+        (param == CRUM_PARAM_EAGER                ? c->eager
+         : param == CRUM_PARAM_DIFF_NONTEMPORAL ? c->diff_nt
+         : param == CRUM_PARAM_PACK_NT_STORE    ? c->pack_nt
+                                                : c->pack_pf) = v != 0;
         return CRUM_OK;
     }
     if (param == CRUM_PARAM_CHUNK_GROWTH) {
@@ -530,6 +532,7 @@ int crum_ctx_get_param(crum_ctx* c, int param, uint64_t* v)
     case CRUM_PARAM_DIRECT_BYTES: *v = c->direct_bytes; return CRUM_OK;
     case CRUM_PARAM_CHUNK_GROWTH: *v = c->chunk_growth; return CRUM_OK;
     case CRUM_PARAM_PACK_NT_STORE: *v = c->pack_nt ? 1 : 0; return CRUM_OK;
+    case CRUM_PARAM_PACK_PREFETCH: *v = c->pack_pf ? 1 : 0; return CRUM_OK;
     default: return CRUM_EINVAL;
     }
 }
@@ -731,7 +734,7 @@ static int snapshot_impl(crum_ctx* c, const crum_region* regions, uint32_t n_reg
             CRUM_TRY(launch_pack(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                  np_shift, pc_shift, d_flags, himg, d_crcs, d_partials,
                                  c->d_tabs, d_glob, c->shape.pack_blocks, c->pack_depth,
-                                 c->crc_variant, stream, c->pack_nt));
+                                 c->crc_variant, stream, ctx_pack_flags(c)));
             CRUM_TRY(launch_finalize(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                      np_shift, pc_shift, d_partials, d_crcs, himg, d_glob,
                                      c->d_tabs, stream));
@@ -776,7 +779,7 @@ static int snapshot_impl(crum_ctx* c, const crum_region* regions, uint32_t n_reg
                 CRUM_TRY(launch_pack(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                      np_shift, pc_shift, d_flags, staging, d_crcs,
                                      d_partials, c->d_tabs, d_glob, c->shape.pack_blocks,
-                                     c->pack_depth, c->crc_variant, stream, c->pack_nt));
+                                     c->pack_depth, c->crc_variant, stream, ctx_pack_flags(c)));
                 CRUM_TRY(launch_finalize(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                          np_shift, pc_shift, d_partials, d_crcs, staging, d_glob,
                                          c->d_tabs, stream));
@@ -849,7 +852,7 @@ static int snapshot_impl(crum_ctx* c, const crum_region* regions, uint32_t n_reg
                 CRUM_TRY(launch_pack(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                      np_shift, pc_shift, d_flags, staging, d_crcs,
                                      d_partials, c->d_tabs, d_glob, c->shape.pack_blocks,
-                                     c->pack_depth, c->crc_variant, stream, c->pack_nt));
+                                     c->pack_depth, c->crc_variant, stream, ctx_pack_flags(c)));
                 CRUM_TRY(launch_finalize(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                          np_shift, pc_shift, d_partials, d_crcs, staging, d_glob,
                                          c->d_tabs, stream));
@@ -1032,7 +1035,7 @@ int crum_restore(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
         CRUM_TRY(launch_pack(kModeVerify, d_regs, n_regions, d_reqs, d_out, d_list, sr, np_shift,
                              pc_shift, nullptr, staging, d_crcs, d_partials, c->d_tabs,
                              d_glob, c->shape.pack_blocks, c->pack_depth, c->crc_variant,
-                             stream));
+                             stream, ctx_pack_flags(c)));
         CRUM_TRY(launch_finalize(kModeVerify, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                  np_shift, pc_shift, d_partials, d_crcs, staging, d_glob,
                                  c->d_tabs, stream));

@@ -147,7 +147,8 @@ hipError_t launch_list(const uint64_t* bitmap, const uint32_t* prefix, uint64_t 
 // lookups between byte and nibble tables.  Pack updates the shadows of regions whose flags bit 0
 // is set.  unit_flags (pack only, may be null): the diff's per-unit flags of
 // the same page space; units flagged clean are then read from the shadow.
-// nt_store (pack only): write the image with non-temporal stores.
+// nt_store: bit 0 (pack only) writes the image with non-temporal stores;
+// bit 1 issues each lane's next loads before folding the current ones.
 hipError_t launch_pack(int mode, const DevRegion* regs, uint32_t n_regs, const DevRequest* reqs,
                        const DevReqOut* out, const uint32_t* list, SlotRange range,
                        uint32_t np_shift, uint32_t piece_shift, const uint8_t* unit_flags,

@@ -354,11 +354,66 @@ __device__ __forceinline__ uint32_t piece_steps(const PieceSrc& src, gv4 __restr
     return s;
 }
 
+// As piece_steps, with the loads of the next U steps issued before the
+// stores and CRC of the current ones, so a wave keeps page loads in flight
+// while it works through its LDS table lookups.
+template <int STORE, int U, int V>
+__device__ __forceinline__ uint32_t piece_steps_pf(const PieceSrc& src, gv4 __restrict__ dst,
+                                                   gv4 __restrict__ sh, uint32_t* t_io,
+                                                   uint32_t steps, uint32_t lane,
+                                                   const uint32_t* __restrict__ lds, uint32_t s)
+{
+    uint32_t t = *t_io;
+    if (t + U > steps)
+        return s;
+    u32x4 w[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        w[u] = src.at(t + u)[(t + u) * 64 + lane];
+    for (;;) {
+        const bool more = t + 2 * U <= steps;
+        u32x4 nx[U];
+        if (more) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                nx[u] = src.at(t + U + u)[(t + U + u) * 64 + lane];
+        }
+        if (STORE) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (STORE == 2)
+                    __builtin_nontemporal_store(w[u], dst + (t + u) * 64 + lane);
+                else
+                    dst[(t + u) * 64 + lane] = w[u];
+            }
+            if (sh) {
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (src.is_dirty(t + u))
+                        sh[(t + u) * 64 + lane] = w[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            s = shift1k_v<V>(lds, s) ^
+                word_crc_v<V>(lds, make_uint4(w[u].x, w[u].y, w[u].z, w[u].w));
+        t += U;
+        if (!more)
+            break;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            w[u] = nx[u];
+    }
+    *t_io = t;
+    return s;
+}
+
 // Raw (zero-initialised) CRC of `steps` KiB, copied to dst (and to the shadow
 // sh, dirty units only) when STORE.  DEPTH: 16-byte loads each lane issues
-// before it folds them into its CRC.  All lanes return the same value.
+// before it folds them into its CRC; PF: the next DEPTH loads are issued
+// before the current ones are folded.  All lanes return the same value.
 // gz: z[0] of the shift tables in global memory (the butterfly's shifts).
-template <int STORE, int DEPTH, int V>
+template <int STORE, int DEPTH, int V, bool PF>
 __device__ __forceinline__ uint32_t wave_piece_crc(const PieceSrc& src, gv4 __restrict__ dst,
                                                    gv4 __restrict__ sh, uint32_t steps,
                                                    uint32_t lane,
@@ -367,7 +422,10 @@ __device__ __forceinline__ uint32_t wave_piece_crc(const PieceSrc& src, gv4 __re
 {
     uint32_t s = 0;
     uint32_t t = 0;
-    s = piece_steps<STORE, DEPTH, V>(src, dst, sh, &t, steps, lane, lds, s);
+    if (PF)
+        s = piece_steps_pf<STORE, DEPTH, V>(src, dst, sh, &t, steps, lane, lds, s);
+    else
+        s = piece_steps<STORE, DEPTH, V>(src, dst, sh, &t, steps, lane, lds, s);
     if (DEPTH > 4)
         s = piece_steps<STORE, 4, V>(src, dst, sh, &t, steps, lane, lds, s);
     s = piece_steps<STORE, 1, V>(src, dst, sh, &t, steps, lane, lds, s);
@@ -810,13 +868,23 @@ __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs
             gv4 sh = ((R.flags & 1u) && R.shadow)
                             ? (gv4)(R.shadow + page_off + piece_off)
                             : nullptr;
-            raw = nt_store ? wave_piece_crc<2, DEPTH, V>(src, (gv4)slot_ptr, sh, steps, lane,
-                                                         lds, gz)
-                           : wave_piece_crc<1, DEPTH, V>(src, (gv4)slot_ptr, sh, steps, lane,
-                                                         lds, gz);
+            if (nt_store & 2u)
+                raw = (nt_store & 1u) ? wave_piece_crc<2, DEPTH, V, true>(
+                                            src, (gv4)slot_ptr, sh, steps, lane, lds, gz)
+                                      : wave_piece_crc<1, DEPTH, V, true>(
+                                            src, (gv4)slot_ptr, sh, steps, lane, lds, gz);
+            else
+                raw = (nt_store & 1u) ? wave_piece_crc<2, DEPTH, V, false>(
+                                            src, (gv4)slot_ptr, sh, steps, lane, lds, gz)
+                                      : wave_piece_crc<1, DEPTH, V, false>(
+                                            src, (gv4)slot_ptr, sh, steps, lane, lds, gz);
         } else {
             const PieceSrc src{(gcv4)slot_ptr, nullptr, ~0u, 0};
-            raw = wave_piece_crc<0, DEPTH, V>(src, nullptr, nullptr, steps, lane, lds, gz);
+            raw = (nt_store & 2u)
+                      ? wave_piece_crc<0, DEPTH, V, true>(src, nullptr, nullptr, steps, lane, lds,
+                                                          gz)
+                      : wave_piece_crc<0, DEPTH, V, false>(src, nullptr, nullptr, steps, lane,
+                                                           lds, gz);
         }
         if (lane != 0)
             continue;
@@ -914,11 +982,11 @@ hipError_t launch_pack(int mode, const DevRegion* regs, uint32_t n_regs, const D
     if (mode == kModePack)
         launch_pack_mode<kModePack>(grid, depth, variant, s, regs, n_regs, reqs, out, list,
                                     range, np_shift, piece_shift, unit_flags, staging, crc_out,
-                                    partials, tabs, glob, nt_store ? 1u : 0u);
+                                    partials, tabs, glob, (uint32_t)nt_store);
     else
         launch_pack_mode<kModeVerify>(grid, depth, variant, s, regs, n_regs, reqs, out, list,
                                       range, np_shift, piece_shift, nullptr, staging, crc_out,
-                                      partials, tabs, glob, 0u);
+                                      partials, tabs, glob, (uint32_t)nt_store & 2u);
     return hipGetLastError();
 }
 

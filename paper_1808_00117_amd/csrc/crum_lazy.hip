@@ -52,7 +52,7 @@ struct crum_lazy {
     uint32_t flags = 0;
     uint64_t small_bytes = 0;
     uint32_t pc_shift = 0, np_shift = 0;
-    int pack_blocks = 0, depth = 4, variant = kCrcVariantAuto;
+    int pack_blocks = 0, depth = 4, variant = kCrcVariantAuto, pack_flags = 0;
     std::vector<uint64_t> bitmap;   // image bitmap, W words
     std::vector<uint64_t> prefix;   // slots before word w
     std::vector<uint64_t> fetched;  // bit per page: its fetch has been enqueued
@@ -159,7 +159,7 @@ hipError_t run_kernels(crum_lazy* z, uint64_t k0, uint64_t k1, uint8_t* src, hip
         const SlotRange sr{k0, k1, nullptr, 0, n};
         e = launch_pack(kModeVerify, regs, nr, req, out, list, sr, nps, pcs,
                         nullptr, src, crcs, partials, ctx_tables(z->ctx), glob,
-                        z->pack_blocks, z->depth, z->variant, s);
+                        z->pack_blocks, z->depth, z->variant, s, z->pack_flags & 2);
         if (e != hipSuccess)
             return e;
         e = launch_finalize(kModeVerify, regs, nr, req, out, list, sr, nps, pcs,
@@ -338,6 +338,7 @@ int crum_lazy_open(crum_ctx* c, const crum_region* regions, uint32_t n_regions,
     z->np_shift = I.ps > z->pc_shift ? I.ps - z->pc_shift : 0;
     z->pack_blocks = ctx_shape(c).pack_blocks;
     z->depth = ctx_pack_depth(c);
+    z->pack_flags = ctx_pack_flags(c);
     z->variant = ctx_crc_variant(c);
     z->bitmap = std::move(bm);
     z->prefix = std::move(prefix);

@@ -243,7 +243,7 @@ int crum_snapshot_noalloc(crum_ctx* c, const crum_region* regions, uint32_t n_re
             CRUM_TRY_C(launch_pack(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                    np_shift, pc_shift, d_flags, staging, d_crcs, d_partials,
                                    c->d_tabs, d_glob, c->shape.pack_blocks, c->pack_depth,
-                                   c->crc_variant, stream, c->pack_nt));
+                                   c->crc_variant, stream, ctx_pack_flags(c)));
             CRUM_TRY_C(launch_finalize(kModePack, d_regs, n_regions, d_reqs, d_out, d_list, sr,
                                        np_shift, pc_shift, d_partials, d_crcs, staging, d_glob,
                                        c->d_tabs, stream));

@@ -307,7 +307,7 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
             e = launch_pack(kModePack, d_regs, p->n_regs, d_reqs, d_out, d_list, sr, np_shift,
                             pc_shift, d_flags, p->staging, d_crcs, d_part, tabs, d_glob,
                             shape.pack_blocks, ctx_pack_depth(c), ctx_crc_variant(c), s,
-                            ctx_pack_nt(c));
+                            ctx_pack_flags(c));
         if (e == hipSuccess)
             e = launch_finalize(kModePack, d_regs, p->n_regs, d_reqs, d_out, d_list, sr, np_shift,
                                 pc_shift, d_part, d_crcs, p->staging, d_glob, tabs, s);

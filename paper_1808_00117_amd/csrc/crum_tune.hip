@@ -188,6 +188,7 @@ int param_id(const std::string& name)
         {"direct_bytes", CRUM_PARAM_DIRECT_BYTES},
         {"chunk_growth", CRUM_PARAM_CHUNK_GROWTH},
         {"pack_nt_store", CRUM_PARAM_PACK_NT_STORE},
+        {"pack_prefetch", CRUM_PARAM_PACK_PREFETCH},
     };
     for (const auto& n : names)
         if (name == n.first)

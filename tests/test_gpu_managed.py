@@ -62,4 +62,14 @@ def test_managed_parity(P, n_pages, device_frac):
         assert np.array_equal(himg.numpy(st.image_bytes), img_o)
     # the host still sees the bytes it and the device wrote
     assert np.array_equal(cur.numpy(0, N), host_cur)
+    # the runtime's residency report of every page (recorded, not asserted:
+    # on devices without managed-memory support the allocation is host memory
+    # and the report carries no location)
+    locs = {}
+    for p in range(n_pages):
+        rc, loc = cur.last_prefetch_location(p * P, P)
+        kind = "device" if p in set(int(x) for x in dev_pages) else "host"
+        locs.setdefault(kind, {}).setdefault(f"rc{rc}:loc{loc}", 0)
+        locs[kind][f"rc{rc}:loc{loc}"] += 1
+    log(f"[managed] last prefetch location per page kind: {locs}")
     crum.crum_ctx_destroy(ctx)

@@ -81,7 +81,14 @@ def test_trace_summary_reports_timed_drain_copies(tmp_path):
               ["Direction", "Start_Timestamp", "End_Timestamp", "Size"], copies)
     out = bench.trace_summary(str(tmp_path), 2)
     assert "k_pack (snapshot pack) launches in the timed snapshots: 2" in out
-    assert "2 copies, summed duration 0.002 ms, 2097152 bytes, 1048.58 GB/s" in out
+    assert "2 copies, summed duration 0.002 ms" in out
+    assert "2097152 bytes (from the trace): 1048.58 GB/s" in out
+    # a trace without sizes: the rate comes from the images' bytes
+    write_csv(tmp_path / "run_memory_copy_trace.csv",
+              ["Kind", "Direction", "Start_Timestamp", "End_Timestamp"],
+              [("MEMORY_COPY", d, a, b) for d, a, b, _ in copies])
+    out = bench.trace_summary(str(tmp_path), 2, image_bytes=1 << 20)
+    assert "2097152 bytes (2 images of 1048576 bytes)" in out
 
 
 def test_kernel_hash_ignores_comments(tmp_path, monkeypatch):
