@@ -58,6 +58,7 @@ def hip():
             "hipMemAdvise": [V, S, I, I],
             "hipMemRangeGetAttribute": [V, S, I, V, S],
             "hipPointerGetAttributes": [V, V],
+            "hipGetLastError": [],
         }
         for name, args in sigs.items():
             f = getattr(h, name)
@@ -138,11 +139,17 @@ class ManagedBuffer:
         return hip().hipMemPrefetchAsync(self.ptr + offset, nbytes, device, stream)
 
     def last_prefetch_location(self, offset: int, nbytes: int):
+        """(HIP status, location) of hipMemRangeGetAttribute(LastPrefetchLocation).
+        The query can leave an error in the runtime's last-error slot, which a
+        later launch check would report as its own: the slot is read and
+        cleared here, and a nonzero value is returned as the status when the
+        call itself reported success."""
         v = ctypes.c_int(-99)
         rc = hip().hipMemRangeGetAttribute(ctypes.byref(v), 4,
                                            hipMemRangeAttributeLastPrefetchLocation,
                                            self.ptr + offset, nbytes)
-        return rc, v.value
+        last = hip().hipGetLastError()
+        return (rc or last), v.value
 
     def numpy(self, offset: int, n: int):
         import numpy as np
