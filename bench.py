@@ -532,7 +532,7 @@ def percentile(v, q):
     return v[min(len(v) - 1, int(round(q * (len(v) - 1))))]
 
 
-def bench_batched(args) -> dict:
+def bench_batched(args, keep: bool = False):
     """Batched workload: 256 requests (1-32 allocations each, request totals
     log-uniform 1 MiB-2 GiB, 4 KiB or 64 KiB pages, dirty fraction U(1%, 50%)
     in runs of mean 16) snapshotted by one plan launch (captured graphs, one
@@ -541,7 +541,10 @@ def bench_batched(args) -> dict:
     Three plans are timed: the grouped plan (tuned shapes, caller's order),
     the same plan smallest request first, and a one-graph plan (a single group
     holding all 256 requests: one persistent diff, one drain).  Returns the
-    result dict."""
+    result dict; with `keep`, (result, release) where release() frees the
+    device and pinned buffers later (freeing some 160 GB of device memory
+    starts driver background work that slows HBM-bound kernels for a while,
+    so a leg measured next keeps them allocated)."""
     import numpy as np
 
     import paper_1808_00117_amd as crum
@@ -764,13 +767,18 @@ def bench_batched(args) -> dict:
     }
     crum.crum_ctx_destroy(ctx)
     crum.crum_ctx_destroy(pctx)
-    for pr in pairs:
-        for c, sh in pr:
-            c.free()
-            if sh:
-                sh.free()
-    for b in (staging, h_images, status, pstage, pstatus):
-        b.free()
+
+    def release():
+        for pr in pairs:
+            for c, sh in pr:
+                c.free()
+                if sh:
+                    sh.free()
+        for b in (staging, h_images, status, pstage, pstatus):
+            b.free()
+    if keep:
+        return result, release
+    release()
     return result
 
 
@@ -787,10 +795,12 @@ def bench_headline(args):
     snapshots), the drain against the host link, the pack, verify and
     scatter rates, and a verified restore; then the CPU oracle on one thread
     and on all threads.  One JSON line."""
-    b = bench_batched(args)
+    b, release = bench_batched(args, keep=True)
     log(f"[bench] batched leg: {b['value']} GB/s, p99 {b['batched']['latency_ms']['p99']} ms "
         f"vs plain {b['plain']['latency_ms']['p99']} ms")
+    # the batched leg's buffers stay allocated until the second leg is done
     m = bench_many(argparse.Namespace(**dict(vars(args), config="many")), with_cpu=False)
+    release()
     cpu = None
     if args.cpu_seconds > 0:
         from synth import scenarios as sc
