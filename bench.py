@@ -532,7 +532,7 @@ def percentile(v, q):
     return v[min(len(v) - 1, int(round(q * (len(v) - 1))))]
 
 
-def bench_batched(args, keep: bool = False):
+def bench_batched(args) -> dict:
     """Batched workload: 256 requests (1-32 allocations each, request totals
     log-uniform 1 MiB-2 GiB, 4 KiB or 64 KiB pages, dirty fraction U(1%, 50%)
     in runs of mean 16) snapshotted by one plan launch (captured graphs, one
@@ -541,10 +541,7 @@ def bench_batched(args, keep: bool = False):
     Three plans are timed: the grouped plan (tuned shapes, caller's order),
     the same plan smallest request first, and a one-graph plan (a single group
     holding all 256 requests: one persistent diff, one drain).  Returns the
-    result dict; with `keep`, (result, release) where release() frees the
-    device and pinned buffers later (freeing some 160 GB of device memory
-    starts driver background work that slows HBM-bound kernels for a while,
-    so a leg measured next keeps them allocated)."""
+    result dict."""
     import numpy as np
 
     import paper_1808_00117_amd as crum
@@ -768,18 +765,37 @@ def bench_batched(args, keep: bool = False):
     crum.crum_ctx_destroy(ctx)
     crum.crum_ctx_destroy(pctx)
 
-    def release():
-        for pr in pairs:
-            for c, sh in pr:
-                c.free()
-                if sh:
-                    sh.free()
-        for b in (staging, h_images, status, pstage, pstatus):
-            b.free()
-    if keep:
-        return result, release
-    release()
+    for pr in pairs:
+        for c, sh in pr:
+            c.free()
+            if sh:
+                sh.free()
+    for b in (staging, h_images, status, pstage, pstatus):
+        b.free()
     return result
+
+
+def run_leg(args, config: str) -> dict:
+    """Run `bench.py --config <config>` with this run's steps, warmup and
+    parameters in a child process (no CPU baseline there) and return its
+    JSON line."""
+    import subprocess
+    cmd = [sys.executable, "-u", os.path.abspath(__file__), "--config", config,
+           "--steps", str(args.steps), "--warmup", str(args.warmup), "--cpu-seconds", "0"]
+    for kv in args.param:
+        cmd += ["--param", kv]
+    if args.tune_cache:
+        cmd += ["--tune-cache", args.tune_cache]
+    if args.no_corunner:
+        cmd.append("--no-corunner")
+    log(f"[bench] leg: {' '.join(cmd[2:])}")
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True)
+    if r.returncode != 0:
+        raise SystemExit(f"bench leg {config} failed with status {r.returncode}")
+    lines = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
+    if not lines:
+        raise SystemExit(f"bench leg {config} printed no result")
+    return json.loads(lines[-1])
 
 
 HEADLINE_METRIC = ("snapshot GB/s (diff+CRC+compact+drain) and p99 latency, batched vs plain")
@@ -794,13 +810,17 @@ def bench_headline(args):
     the diff kernel's roofline (HIP events around each launch over its timed
     snapshots), the drain against the host link, the pack, verify and
     scatter rates, and a verified restore; then the CPU oracle on one thread
-    and on all threads.  One JSON line."""
-    b, release = bench_batched(args, keep=True)
+    and on all threads.  The two GPU legs run as child processes of this
+    one (this process does not use the GPU).  One JSON line."""
+    # Each leg runs in a process of its own: in one process, the streams the
+    # first leg leaves behind change how the second leg's snapshot and
+    # co-runner streams share the device's hardware queues (the co-runner's
+    # kernels then land between a diff launch's timing events), and the
+    # first leg's 160 GB of buffers would be freed or held in its way.
+    b = run_leg(args, "batched")
     log(f"[bench] batched leg: {b['value']} GB/s, p99 {b['batched']['latency_ms']['p99']} ms "
         f"vs plain {b['plain']['latency_ms']['p99']} ms")
-    # the batched leg's buffers stay allocated until the second leg is done
-    m = bench_many(argparse.Namespace(**dict(vars(args), config="many")), with_cpu=False)
-    release()
+    m = run_leg(args, "many")
     cpu = None
     if args.cpu_seconds > 0:
         from synth import scenarios as sc
