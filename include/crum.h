@@ -477,7 +477,9 @@ int crum_ctx_get_param(crum_ctx* ctx, int param, uint64_t* value);
 
 /* Per-kernel timing, for measurement.  The context brackets each launch of
  * the selected kernel classes (0 diff, 1 pack, 2 drain copies,
- * 3 scan/bitmap/list, 4 header, 5 verify, 6 scatter) with timing events:
+ * 3 scan/bitmap/list, 4 header, 5 verify, 6 scatter; the pack and verify
+ * classes time their k_pack launches only, not the k_finalize that combines
+ * the CRCs of pages larger than one piece) with timing events:
  * `classes` is a bit mask (bit c selects class c), 0 turns timing off and a
  * negative value selects every class.  Each event record costs host time, so
  * short snapshots are timed with few classes.  crum_ctx_timing returns, for
