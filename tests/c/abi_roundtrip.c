@@ -2,8 +2,10 @@
  * (one with a shadow, one without), a snapshot with the image in pinned
  * memory, a verified restore into fresh buffers holding the shadow's bytes,
  * an on-demand restore of the same image (one touch, then finish), then a
- * snapshot with shadow update and one more that must find nothing dirty.
- * Prints one line and exits 0 when every check holds. */
+ * snapshot with shadow update and one more that must find nothing dirty,
+ * then host write tracking over a managed region with a tracked snapshot and
+ * the allocation-free snapshot of the same region.  Prints one line and
+ * exits 0 when every check holds. */
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -155,6 +157,54 @@ int main(void)
     HIPOK(hipStreamSynchronize(s));
     if (rc != CRUM_OK || st->code != CRUM_OK || st->n_dirty != 0)
         return fail("snapshot after shadow update", (long)st->n_dirty);
+
+    /* host write tracking: a tracker's view over a managed region of N0
+     * pages; the first flush (every page of a new view is dirty) fills the
+     * region with region 0's bytes, which sh0 now holds too (shadow updated
+     * above); then writes to pages 5 and 17 through the view fault once each
+     * and are the only candidates of the tracked snapshot, which finds
+     * exactly them; the allocation-free entry point gives the same image */
+    void* man = NULL;
+    HIPOK(hipMallocManaged(&man, b0, hipMemAttachGlobal));
+    crum_track* tr = NULL;
+    rc = crum_track_create(b0, PAGE, &tr);
+    if (rc != CRUM_OK)
+        return fail("crum_track_create", rc);
+    uint8_t* view = (uint8_t*)crum_track_view(tr);
+    memcpy(view, h_cur0, b0);
+    uint64_t n_flushed = 0;
+    rc = crum_track_flush(tr, man, 2, &n_flushed);
+    if (rc != CRUM_OK || n_flushed != N0)
+        return fail("first flush", (long)n_flushed);
+    uint64_t cand[1];
+    if (crum_track_pending(tr, cand, 1, 1) != CRUM_OK || cand[0] != (1ull << N0) - 1)
+        return fail("pending after the first flush", 0);
+    view[5u * PAGE + 7u] ^= 0x01;
+    view[17u * PAGE] ^= 0x02;
+    view[17u * PAGE + 1u] ^= 0x04;
+    crum_track_info ti;
+    if (crum_track_stats(tr, &ti) != CRUM_OK || ti.faults != 2 || ti.dirty_pages != 2)
+        return fail("write faults", (long)ti.faults);
+    rc = crum_track_flush(tr, man, 1, &n_flushed);
+    if (rc != CRUM_OK || n_flushed != 2 || crum_track_pending(tr, cand, 1, 1) != CRUM_OK ||
+        cand[0] != ((1ull << 5) | (1ull << 17)))
+        return fail("flush of the written pages", (long)n_flushed);
+    crum_region mreg[1] = {{man, sh0, b0, 73}};
+    rc = crum_snapshot_tracked(ctx, mreg, 1, PAGE, 0, 12, cand, 1, staging, cap, h_image, cap, s,
+                               st);
+    HIPOK(hipStreamSynchronize(s));
+    if (rc != CRUM_OK || st->code != CRUM_OK || st->n_dirty != 2)
+        return fail("tracked snapshot", (long)st->n_dirty);
+    const uint64_t tracked_bytes = st->image_bytes;
+    memcpy(h_back, h_image, tracked_bytes < b0 ? tracked_bytes : b0);
+    rc = crum_snapshot_noalloc(ctx, mreg, 1, PAGE, 0, 12, staging, cap, h_image, cap, s, st);
+    HIPOK(hipStreamSynchronize(s));
+    if (rc != CRUM_OK || st->code != CRUM_OK || st->n_dirty != 2 ||
+        st->image_bytes != tracked_bytes || tracked_bytes > b0 ||
+        memcmp(h_back, h_image, tracked_bytes) != 0)
+        return fail("allocation-free snapshot of the managed region", rc);
+    crum_track_destroy(tr);
+    HIPOK(hipFree(man));
 
     crum_ctx_destroy(ctx);
     HIPOK(hipStreamDestroy(s));

@@ -148,7 +148,9 @@ def test_many_allocs_16gib():
 @pytest.mark.timeout(900)
 def test_managed_32gib():
     """The 32 GiB managed workload, 70 % of pages written by host threads and
-    30 % prefetched and written by a kernel."""
+    30 % prefetched and written by a kernel; then the same workload with the
+    host writes tracked (the tracked snapshot's image against the same oracle
+    image)."""
     import bench
     import paper_1808_00117_amd as crum
     import paper_1808_00117_amd.hip as H
@@ -188,7 +190,17 @@ def test_managed_32gib():
         assert st.code == 0 and st.n_dirty == D and st.image_bytes == ib, st
         check_image(himg.numpy(ib), scn, 24, np.random.default_rng(32), seq=3)
         log("[fullsize] managed: oracle image (streamed)")
-        assert_same_image(himg.numpy(ib), oracle_image(scn, 3), "managed image vs oracle")
+        want = oracle_image(scn, 3)
+        assert_same_image(himg.numpy(ib), want, "managed image vs oracle")
+        # host write tracking (Algorithm 1): host pages written through a
+        # tracker's view and flushed, the snapshot reading only the flushed
+        # pages and the device pages; its image must be the oracle's too
+        import argparse
+        log("[fullsize] managed: tracked snapshot")
+        tr = bench.managed_tracked_leg(argparse.Namespace(steps=1, warmup=0), scn, cur, sh,
+                                       table, ctx, staging, himg, cap, status, s, want, 0.0)
+        assert tr["same_image_as_untracked"] and tr["candidate_pages"] < G, tr
+        assert_same_image(himg.numpy(ib), want, "tracked managed image vs oracle")
     finally:
         crum.crum_ctx_destroy(ctx)
         cur.free()
