@@ -636,7 +636,8 @@ def bench_batched(args) -> dict:
     def timed(plan):
         """Warm-up and timed launches of a plan: makespans, per-request
         latencies (launch start to the end of the request's group drain) and
-        the last statuses."""
+        the last statuses.  The context's timing sums restart after the
+        warm-up launches."""
         order, gr = plan.order(), plan.groups()
         group_of = np.zeros(len(reqs), np.int64)
         for g in range(len(gr) - 1):
@@ -644,6 +645,7 @@ def bench_batched(args) -> dict:
                 group_of[order[pos]] = g
         for _ in range(args.warmup):
             launch(plan)
+        crum.crum_ctx_timing_reset(ctx)
         sts = crum.read_request_statuses(status.ptr, len(reqs))
         for q, (code, _, D, G, ib, off) in enumerate(sts):
             assert code == 0 and D == reqs[q].n_dirty and ib == sizes[q], (q, sts[q])
@@ -654,8 +656,13 @@ def bench_batched(args) -> dict:
             lat.extend(gt[g] for g in group_of)
         return mk, lat, sts, len(gr) - 1
 
+    # the grouped plan with its diff launches timed (each group's diff
+    # kernel records the device wall clock at its start and end)
+    crum.crum_ctx_set_timing(ctx, crum.TIMING_DIFF)
     plan = make_plan()
+    crum.crum_ctx_set_timing(ctx, 0)
     mk, lat_b, sts, n_groups = timed(plan)
+    n_pd, pd_ms = crum.crum_ctx_timing(ctx, 0)
     offsets = [st[5] for st in sts]
     batched_image = h_images.numpy(cap)[: max(o + b for o, b in zip(offsets, sizes))].copy()
     plan.destroy()
@@ -715,6 +722,16 @@ def bench_batched(args) -> dict:
                for o, b in zip(offsets, sizes))
     assert same, "batched and plain images differ"
     mk_ms = 1e3 * statistics.median(mk)
+    # the plan's diff bytes per launch: both copies of every region with a
+    # shadow (regions without one are flagged without loads) and one flag
+    # byte per diff unit
+    us_max = crum.crum_ctx_get_param(ctx, crum.CRUM_PARAM_DIFF_UNIT_SHIFT)
+    plan_diff_bytes = 0
+    for r in reqs:
+        us = min(r.page_size.bit_length() - 1, us_max)
+        for g in r.regions:
+            plan_diff_bytes += (2 * g.nbytes if g.has_shadow else 0) + (g.nbytes >> us)
+    pd_gbs = plan_diff_bytes * args.steps / (pd_ms * 1e-3) / 1e9 if pd_ms > 0 else None
     result = {
         "metric": "snapshot GB/s (diff+CRC+compact+drain), batched vs plain",
         "value": round(N / (statistics.median(mk)) / 1e9, 2),
@@ -741,7 +758,18 @@ def bench_batched(args) -> dict:
                     "makespans_ms": [round(1e3 * v, 1) for v in mk],
                     "latency_ms": {"p50": round(percentile(lat_b, 0.5), 2),
                                    "p99": round(percentile(lat_b, 0.99), 2)},
-                    "drain_gbs": round(sum(sizes) / statistics.median(mk) / 1e9, 2)},
+                    "drain_gbs": round(sum(sizes) / statistics.median(mk) / 1e9, 2),
+                    "diff_roofline": {
+                        "kernel": "k_diff", "bound": "hbm",
+                        "achieved": round(pd_gbs, 1) if pd_gbs else None,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(pd_gbs / HBM_PEAK_GBS, 4) if pd_gbs else None,
+                        "launches": n_pd,
+                        "avg_launch_ms": round(pd_ms / max(n_pd, 1), 4),
+                        "algorithmic_bytes_per_step": plan_diff_bytes,
+                        "what": "the plan's persistent diff launches (one per group), "
+                                "timed by the device wall clock the diff kernel records at "
+                                "its start and end, summed over the timed launches"}},
         "batched_smallest_first": {
             "makespan_ms": round(1e3 * statistics.median(mk_s), 2),
             "gbs": round(N / statistics.median(mk_s) / 1e9, 2),

@@ -484,7 +484,11 @@ int crum_ctx_get_param(crum_ctx* ctx, int param, uint64_t* value);
  * negative value selects every class.  Each event record costs host time, so
  * short snapshots are timed with few classes.  crum_ctx_timing returns, for
  * class `which`, the number of launches and the summed duration in
- * milliseconds since the last reset; it waits for the recorded events. */
+ * milliseconds since the last reset; it waits for the recorded events.
+ * A plan created while the diff class is timed has each group's diff kernel
+ * write the device's constant-rate wall clock at its start and end; each
+ * launch of that plan adds those durations to the diff class and returns
+ * only after the plan's drains have ended. */
 int crum_ctx_set_timing(crum_ctx* ctx, int classes);
 int crum_ctx_timing(crum_ctx* ctx, int which, uint64_t* launches, double* total_ms);
 int crum_ctx_timing_reset(crum_ctx* ctx);

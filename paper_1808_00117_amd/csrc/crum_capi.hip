@@ -557,6 +557,10 @@ int crum_ctx_timing_reset(crum_ctx* c)
         v.clear();
     }
     c->pool_used = 0;
+    for (int k = 0; k < kTimingClasses; ++k) {
+        c->extra_n[k] = 0;
+        c->extra_ms[k] = 0;
+    }
     return CRUM_OK;
 }
 
@@ -573,8 +577,8 @@ int crum_ctx_timing(crum_ctx* c, int which, uint64_t* launches, double* total_ms
             return CRUM_EHIP;
         tot += ms;
     }
-    *launches = c->spans[which].size();
-    *total_ms = tot;
+    *launches = c->spans[which].size() + c->extra_n[which];
+    *total_ms = tot + c->extra_ms[which];
     return CRUM_OK;
 }
 

@@ -121,9 +121,13 @@ struct SlotRange {
 void build_crc_tables(CrcTables* host);
 // cand (may be null): bitmap over global pages; pages whose bit is clear are
 // flagged clean without being read (they are known to equal their shadow).
+// stamp (may be null): two words, the wall clock at the launch's start and
+// the latest end of its workgroups (stamp[1] must start below any clock
+// value, e.g. zeroed once).
 hipError_t launch_diff(const DevRegion* regs, uint32_t n_regs, uint64_t u0, uint64_t u1,
                        uint8_t* unit_flags, int blocks, int nontemporal, int prio,
-                       hipStream_t s, const uint64_t* cand = nullptr);
+                       hipStream_t s, const uint64_t* cand = nullptr,
+                       uint64_t* stamp = nullptr);
 hipError_t launch_bitmap(const DevRegion* regs, uint32_t n_regs, uint64_t w0, uint64_t w1,
                          const uint8_t* unit_flags, uint64_t* bitmap, hipStream_t s);
 // Scans words [w0, w1) continuing glob->running; writes the new running total

@@ -174,6 +174,9 @@ struct crum_ctx {
     uint8_t* na_scratch = nullptr;
     uint8_t* na_pin = nullptr;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> spans[crum::kTimingClasses];
+    // launches timed elsewhere (inside a plan's graphs), already summed
+    uint64_t extra_n[crum::kTimingClasses] = {};
+    double extra_ms[crum::kTimingClasses] = {};
 };
 
 
@@ -197,6 +200,12 @@ inline int ctx_pack_depth(const crum_ctx* c) { return c->pack_depth; }
 inline int ctx_diff_prio(const crum_ctx* c) { return c->diff_prio; }
 inline int ctx_crc_variant(const crum_ctx* c) { return c->crc_variant; }
 inline int ctx_plan_order(const crum_ctx* c) { return c->plan_order; }
+inline bool ctx_times(const crum_ctx* c, int cls) { return (c->timing_mask >> cls) & 1u; }
+inline void ctx_add_timing(crum_ctx* c, int cls, double ms)
+{
+    c->extra_n[cls] += 1;
+    c->extra_ms[cls] += ms;
+}
 inline uint32_t ctx_chunk_growth(const crum_ctx* c) { return c->chunk_growth; }
 inline int ctx_pack_nt(const crum_ctx* c) { return c->pack_nt ? 1 : 0; }
 // launch_pack's flag bits: 1 non-temporal image stores, 2 prefetching loop

@@ -485,12 +485,19 @@ __device__ __forceinline__ uint32_t xor_or(gcv4 __restrict__ a, gcv4 __restrict_
 // cand (may be null): a bitmap over global pages from host write tracking;
 // a page whose bit is clear is known to equal its shadow, so its units are
 // flagged clean without reading either copy.
+// stamp (may be null): stamp[0] gets the constant-rate wall clock when
+// workgroup 0 starts (the first one dispatched), stamp[1] the largest clock
+// at which a workgroup ends.  stamp[1] needs no reset between launches: a
+// later launch's clocks exceed every earlier one's.
 template <bool NT>
 __global__ __launch_bounds__(256) void k_diff(const DevRegion* __restrict__ regs,
                                               uint32_t n_regs, uint64_t u0, uint64_t u1,
                                               uint8_t* __restrict__ unit_flags, uint32_t prio,
-                                              const uint64_t* __restrict__ cand)
+                                              const uint64_t* __restrict__ cand,
+                                              uint64_t* __restrict__ stamp)
 {
+    if (stamp && blockIdx.x == 0 && threadIdx.x == 0)
+        stamp[0] = wall_clock64();
     if (prio == 1)
         __builtin_amdgcn_s_setprio(1);
     else if (prio == 2)
@@ -531,11 +538,17 @@ __global__ __launch_bounds__(256) void k_diff(const DevRegion* __restrict__ regs
         if (lane == 0)
             unit_flags[u] = m != 0;
     }
+    if (stamp) {
+        __syncthreads();
+        if (threadIdx.x == 0)
+            atomicMax(reinterpret_cast<unsigned long long*>(stamp + 1),
+                      (unsigned long long)wall_clock64());
+    }
 }
 
 hipError_t launch_diff(const DevRegion* regs, uint32_t n_regs, uint64_t u0, uint64_t u1,
                        uint8_t* unit_flags, int blocks, int nontemporal, int prio,
-                       hipStream_t s, const uint64_t* cand)
+                       hipStream_t s, const uint64_t* cand, uint64_t* stamp)
 {
     if (u1 <= u0)
         return hipSuccess;
@@ -543,10 +556,10 @@ hipError_t launch_diff(const DevRegion* regs, uint32_t n_regs, uint64_t u0, uint
     const uint64_t nb = need < (uint64_t)blocks ? need : (uint64_t)blocks;
     if (nontemporal)
         hipLaunchKernelGGL(k_diff<true>, dim3((unsigned)nb), dim3(256), 0, s, regs, n_regs, u0,
-                           u1, unit_flags, (uint32_t)prio, cand);
+                           u1, unit_flags, (uint32_t)prio, cand, stamp);
     else
         hipLaunchKernelGGL(k_diff<false>, dim3((unsigned)nb), dim3(256), 0, s, regs, n_regs, u0,
-                           u1, unit_flags, (uint32_t)prio, cand);
+                           u1, unit_flags, (uint32_t)prio, cand, stamp);
     return hipGetLastError();
 }
 

@@ -40,6 +40,14 @@ struct crum_plan {
     hipEvent_t t_start = nullptr;
     std::vector<hipEvent_t> t_group;
     bool timed = false;
+    // with the context timing its diff class at plan creation: each group's
+    // diff launch writes its start and end wall clock to d_stamp (2 words per
+    // group); a launch copies them after h_rb and adds the durations to the
+    // context's diff timing
+    uint64_t* d_stamp = nullptr;
+    std::vector<uint64_t> diff_units;  // diff units of each group (0: no diff launch)
+    bool diff_timed = false;
+    double clock_khz = 0;
 };
 
 namespace {
@@ -237,19 +245,20 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
     const size_t o_bounds = take(8 * std::max<size_t>(n_groups, 1));
     const size_t o_status = take(40ull * std::max<uint32_t>(n_reqs, 1));
     const size_t o_order = take(4ull * std::max<uint32_t>(n_reqs, 1));
+    const size_t o_stamp = take(16 * std::max<size_t>(n_groups, 1));
+    const size_t rb_bytes = 24 * std::max<size_t>(n_groups, 1);  // ends, then stamps
     DeviceGuardC g(ctx_device(c));
     auto fail = [&](int code) {
         plan_free(p);
         return code;
     };
     if (hipMalloc(reinterpret_cast<void**>(&p->d_mem), off) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&p->h_rb), 8 * std::max<size_t>(n_groups, 1), 0) !=
-            hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&p->h_rb), rb_bytes, 0) != hipSuccess ||
         hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_done, hipEventDisableTiming) != hipSuccess ||
         hipEventCreate(&p->t_start) != hipSuccess)
         return fail(CRUM_EHIP);
-    std::memset(p->h_rb, 0, 8 * std::max<size_t>(n_groups, 1));
+    std::memset(p->h_rb, 0, rb_bytes);
     uint8_t* M = p->d_mem;
     if (hipMemcpy(M + o_regs, dregs.data(), sizeof(DevRegion) * dregs.size(),
                   hipMemcpyHostToDevice) != hipSuccess ||
@@ -274,6 +283,16 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
     p->d_status = M + o_status;
     const LaunchShape shape = ctx_shape(c);
     const CrcTables* tabs = ctx_tables(c);
+    p->diff_timed = ctx_times(c, kTDiff);
+    if (p->diff_timed) {
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx_device(c)) !=
+                hipSuccess ||
+            khz <= 0 || hipMemset(M + o_stamp, 0, 16 * std::max<size_t>(n_groups, 1)) != hipSuccess)
+            return fail(CRUM_EHIP);
+        p->clock_khz = khz;
+        p->d_stamp = reinterpret_cast<uint64_t*>(M + o_stamp);
+    }
 
     // ---- capture one graph per group
     for (size_t gi = 0; gi < n_groups; ++gi) {
@@ -281,6 +300,7 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
         const uint64_t w0 = q0 < n_reqs ? dreq[q0].first_word : W;
         const uint64_t w1 = q1 < n_reqs ? dreq[q1].first_word : W;
         const uint64_t u0 = req_unit0[q0], u1 = req_unit0[q1];
+        p->diff_units.push_back(u1 - u0);
         uint32_t hdr_blocks = 1;
         for (uint32_t q = q0; q < q1; ++q)
             hdr_blocks = std::max(hdr_blocks, header_blocks(dreq[q].n_regions, dreq[q].n_words,
@@ -293,7 +313,8 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
             e = launch_plan_init(d_glob, s);
         if (e == hipSuccess)
             e = launch_diff(d_regs, p->n_regs, u0, u1, d_flags, shape.diff_blocks,
-                            ctx_diff_nt(c), ctx_diff_prio(c), s);
+                            ctx_diff_nt(c), ctx_diff_prio(c), s, nullptr,
+                            p->d_stamp ? p->d_stamp + 2 * gi : nullptr);
         if (e == hipSuccess)
             e = launch_bitmap(d_regs, p->n_regs, w0, w1, d_flags, d_bitmap, s);
         if (e == hipSuccess)
@@ -378,9 +399,21 @@ int crum_plan_launch(crum_plan* p, void* stream_, crum_request_status* h_status)
     if (p->n_reqs)
         CRUM_TRY_C(hipMemcpyAsync(h_status, p->d_status, 40ull * p->n_reqs,
                                   hipMemcpyDeviceToHost, side));
+    uint64_t* h_stamp = reinterpret_cast<uint64_t*>(p->h_rb + 8 * n_groups);
+    if (p->diff_timed)
+        CRUM_TRY_C(hipMemcpyAsync(h_stamp, p->d_stamp, 16 * n_groups, hipMemcpyDeviceToHost,
+                                  side));
     CRUM_TRY_C(hipEventRecord(p->ev_done, side));
     CRUM_TRY_C(hipStreamWaitEvent(stream, p->ev_done, 0));
     p->timed = true;
+    if (p->diff_timed) {
+        // a plan that times its diff launches returns after its drains end
+        CRUM_TRY_C(hipEventSynchronize(p->ev_done));
+        for (size_t gi = 0; gi < n_groups; ++gi)
+            if (p->diff_units[gi] && h_stamp[2 * gi + 1] > h_stamp[2 * gi])
+                ctx_add_timing(c, kTDiff,
+                               (double)(h_stamp[2 * gi + 1] - h_stamp[2 * gi]) / p->clock_khz);
+    }
     return CRUM_OK;
 }
 

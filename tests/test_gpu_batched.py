@@ -120,6 +120,31 @@ def test_batched_many_groups(ctx):
             assert np.array_equal(img, oracle.snapshot(regs, P, seq=seq)[1]), q
 
 
+def test_timed_plan_counts_diff_launches_and_keeps_images(ctx):
+    """A plan created while the diff class is timed has each group's diff
+    kernel record its start and end clock: one timed diff per group that
+    scans anything, per launch, and the same images."""
+    import paper_1808_00117_amd as crum
+    host = make_requests(12, 30, max_regions=3)
+    log("[batched] 30 requests, one group per request, diff launches timed")
+    crum.crum_ctx_timing_reset(ctx.ctx)
+    crum.crum_ctx_set_timing(ctx.ctx, crum.TIMING_DIFF)
+    try:
+        dev, results, groups = run_plan(ctx, host, launches=3, small_groups=True)
+        n, ms = crum.crum_ctx_timing(ctx.ctx, 0)
+    finally:
+        crum.crum_ctx_set_timing(ctx.ctx, 0)
+        crum.crum_ctx_timing_reset(ctx.ctx)
+    nonempty = sum(1 for regs, _, _ in host if sum(c.size for c, _, _ in regs) > 0)
+    assert n == 3 * nonempty, (n, nonempty, len(groups) - 1)
+    assert ms > 0
+    for sts, imgs in results:
+        for q, ((code, *_), img) in enumerate(zip(sts, imgs)):
+            regs, P, seq = host[q]
+            assert code == 0
+            assert np.array_equal(img, oracle.snapshot(regs, P, seq=seq)[1]), q
+
+
 def test_batched_update_shadow(ctx):
     import torch
     host = make_requests(3, 10, max_regions=2, page_sizes=(4 * KiB,))
