@@ -1576,7 +1576,7 @@ def managed_tracked_leg(args, scn, cur, sh, table, ctx, staging, himg, cap, stat
 
         def snap():
             rc = crum.crum_snapshot_tracked(ctx, table, P, 0, 3, cand, staging.ptr, cap,
-                                            himg.ptr, cap, s1.handle, status.ptr)
+                                            himg.ptr, himg.nbytes, s1.handle, status.ptr)
             assert rc == 0, rc
             s1.synchronize()
             st = crum.read_status(status.ptr)
