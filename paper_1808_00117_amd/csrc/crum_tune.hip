@@ -33,6 +33,8 @@ struct Reader {
     const char* p;
     const char* end;
     bool ok = true;
+    int depth = 0;  // nesting of skipped values, bounded so that input cannot exhaust the stack
+    static constexpr int kMaxDepth = 64;
 
     void ws()
     {
@@ -110,25 +112,13 @@ struct Reader {
         ws();
         if (p >= end)
             return ok = false;
-        if (*p == '{') {
-            ++p;
-            if (eat('}'))
-                return true;
-            do {
-                if (!str(nullptr) || !eat(':') || !skip())
-                    return ok = false;
-            } while (eat(','));
-            return eat('}') || (ok = false);
-        }
-        if (*p == '[') {
-            ++p;
-            if (eat(']'))
-                return true;
-            do {
-                if (!skip())
-                    return ok = false;
-            } while (eat(','));
-            return eat(']') || (ok = false);
+        if (*p == '{' || *p == '[') {
+            if (depth >= kMaxDepth)
+                return ok = false;
+            ++depth;
+            const bool r = skip_container();
+            --depth;
+            return r;
         }
         if (*p == '"')
             return str(nullptr);
@@ -141,6 +131,26 @@ struct Reader {
         uint64_t v;
         bool i;
         return num(&v, &i);
+    }
+    // an object or array (at *p)
+    bool skip_container()
+    {
+        if (*p++ == '{') {
+            if (eat('}'))
+                return true;
+            do {
+                if (!str(nullptr) || !eat(':') || !skip())
+                    return ok = false;
+            } while (eat(','));
+            return eat('}') || (ok = false);
+        }
+        if (eat(']'))
+            return true;
+        do {
+            if (!skip())
+                return ok = false;
+        } while (eat(','));
+        return eat(']') || (ok = false);
     }
     // {"name": integer, ...}: integer members only
     bool int_members(std::vector<std::pair<std::string, uint64_t>>* out)

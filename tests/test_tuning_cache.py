@@ -48,3 +48,38 @@ def test_malformed_and_missing_files(tmp_path):
     p = tmp_path / "empty.json"
     p.write_text("{}")
     assert crum.crum_tuning_check(str(p), KEY) == (crum.CRUM_OK, 0)
+
+
+FUZZ = r"""
+import os, random, sys
+sys.path.insert(0, sys.argv[1])
+import paper_1808_00117_amd as crum
+KEY, src, tmp = sys.argv[2], open(sys.argv[3], "rb").read(), sys.argv[4]
+rng = random.Random(7)
+cases = [src[:n] for n in range(0, len(src), max(1, len(src) // 300))]
+for _ in range(300):
+    b = bytearray(src)
+    for _ in range(rng.randint(1, 8)):
+        b[rng.randrange(len(b))] = rng.choice(b'{}[]",:-.e0123456789 x\\')
+    cases.append(bytes(b))
+cases += [b"[" * 100000, b'{"a":' * 50000, b'{"' + KEY.encode() + b'":' + b"[" * 70 + b"]" * 70 + b"}"]
+for i, c in enumerate(cases):
+    with open(tmp, "wb") as f:
+        f.write(c)
+    rc, n = crum.crum_tuning_check(tmp, KEY)
+    assert rc in (crum.CRUM_OK, crum.CRUM_EINVAL), (i, rc)
+print("fuzz ok", len(cases))
+"""
+
+
+def test_reader_survives_truncated_mutated_and_deep_input(tmp_path):
+    """Every prefix of the committed cache, random byte mutations of it and
+    deeply nested values come back as OK or EINVAL: the reader neither
+    crashes nor recurses without bound (run in a child process, so a crash
+    fails this test instead of ending the run)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", FUZZ, root, KEY, autotune.DEFAULT_CACHE,
+                        str(tmp_path / "f.json")], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and "fuzz ok" in r.stdout, r.stdout + r.stderr
