@@ -1957,7 +1957,8 @@ def bench_many(args, with_cpu: bool = True) -> dict:
                       if cap <= crum.crum_ctx_get_param(ctx, crum.CRUM_PARAM_DIRECT_BYTES)
                       else "chunk-pipelined" if N > crum.crum_ctx_get_param(
                           ctx, crum.CRUM_PARAM_CHUNK_BYTES)
-                      else "diff-first (the pages make one chunk)"),
+                      else "chunked, one chunk (the whole image drained in one copy "
+                           "behind the header)"),
             "co_runner": (f"fp32 SAXPY 4096x4096: graphs of {PASSES} single-pass kernels "
                           f"issued continuously on a second stream by a second host thread "
                           f"({sax_graphs[0]} graphs during the timed steps)") if corun_on else None,

@@ -133,12 +133,11 @@ int crum_image_bytes(uint32_t n_regions, uint64_t total_pages, uint64_t n_dirty,
  * layout above, and the drain of the image to h_image on the context's side
  * stream; `stream` is made to wait for the drain.  The calling thread blocks
  * only on small device-to-host reads of dirty counts.  Two orders give the
- * same image: when both capacities hold an image with every page dirty, the
- * pages span more than one chunk and CRUM_PARAM_EAGER is 1, the page space is
- * processed in chunks and each chunk is drained while later chunks are
- * diffed; otherwise the whole diff
- * and the capacity check run first, then pack chunks with their drain behind
- * them.  A third order applies when an image with every page dirty is at most
+ * same image: when both capacities hold an image with every page dirty and
+ * CRUM_PARAM_EAGER is 1, the page space is processed in chunks and each chunk
+ * is drained while later chunks are diffed (an image of one chunk is drained
+ * in one copy behind the header); otherwise the whole diff and the capacity
+ * check run first, then pack chunks with their drain behind them.  A third order applies when an image with every page dirty is at most
  * CRUM_PARAM_DIRECT_BYTES and h_image is host memory the device maps at the
  * same address (hipHostMalloc): the pack and header kernels write the image
  * straight into h_image, d_staging is not written, and the calling thread
@@ -420,8 +419,7 @@ void crum_server_destroy(crum_server* server);
  *   (128 MiB / 4 GiB); chunks grow by CRUM_PARAM_CHUNK_GROWTH up to the maximum.
  * CRUM_PARAM_EAGER: 1 pipelines the snapshot by chunks whenever the staging
  *   and host capacities hold an image with every page dirty (so ENOSPC is
- *   impossible) and the pages span more than one chunk; 0 always runs the
- *   whole diff first (1).
+ *   impossible); 0 always runs the whole diff first (1).
  * CRUM_PARAM_DRAIN_CHUNK_BYTES: first pack/drain chunk of the non-pipelined
  *   order (8 MiB, doubling up to 256 MiB).
  * CRUM_PARAM_DIFF_UNIT_SHIFT: log2 of the largest diff unit, 12..14 (14):

@@ -651,8 +651,6 @@ static int snapshot_impl(crum_ctx* c, const crum_region* regions, uint32_t n_reg
             chunk_bytes = std::min<uint64_t>(chunk_bytes * c->chunk_growth,
                                              std::max(c->chunk_max_bytes, c->chunk_bytes));
         }
-        if (cuts.size() == 2)
-            eager = false;
     } else {
         cuts.push_back(G);
     }
@@ -792,13 +790,21 @@ static int snapshot_impl(crum_ctx* c, const crum_region* regions, uint32_t n_reg
             }
             CRUM_TRY(hipEventRecord(c->ev_chunk[ci], stream));
         }
-        // ---- drain each chunk as soon as its count is known
+        // the header takes its sizes from the device, so it follows the last
+        // pack without waiting for the host
+        {
+            Span sp(c, kTHeader, stream);
+            CRUM_TRY(launch_header(d_regs, d_reqs, 0, 1, hdr_blocks, d_out, d_bitmap, d_crcs,
+                                   staging, capacity, c->d_tabs, stream));
+        }
+        // ---- drain each chunk as soon as its count is known (one chunk: the
+        // whole image in one copy behind the header, below)
         uint64_t prev = 0;
         for (size_t ci = 0; ci < n_chunks; ++ci) {
             CRUM_TRY(hipEventSynchronize(c->ev_cnt[ci]));
             uint64_t cnt;
             std::memcpy(&cnt, rb + 128 + 8 * ci, 8);
-            if (himg && cnt > prev) {
+            if (himg && cnt > prev && n_chunks > 1) {
                 CRUM_TRY(hipStreamWaitEvent(c->side, c->ev_chunk[ci], 0));
                 const uint64_t off = data_off + (prev << ps);
                 Span sp(c, kTDrain, c->side);
@@ -880,8 +886,9 @@ static int snapshot_impl(crum_ctx* c, const crum_region* regions, uint32_t n_reg
         }
     }
 
-    // ---- header (with the CRC array), then the prefix and tail of the drain
-    {
+    // ---- header (with the CRC array; already enqueued in the chunked order),
+    // then the prefix and tail of the drain
+    if (!eager) {
         Span sp(c, kTHeader, stream);
         CRUM_TRY(launch_header(d_regs, d_reqs, 0, 1, hdr_blocks, d_out, d_bitmap, d_crcs,
                                staging, capacity, c->d_tabs, stream));
@@ -891,10 +898,14 @@ static int snapshot_impl(crum_ctx* c, const crum_region* regions, uint32_t n_reg
         CRUM_TRY(hipStreamWaitEvent(c->side, c->ev_hdr, 0));
         const uint64_t tail = data_off + (D << ps);
         Span sp(c, kTDrain, c->side);
-        CRUM_TRY(hipMemcpyAsync(himg, staging, data_off, hipMemcpyDeviceToHost, c->side));
-        if (image_bytes > tail)
-            CRUM_TRY(hipMemcpyAsync(himg + tail, staging + tail, image_bytes - tail,
-                                    hipMemcpyDeviceToHost, c->side));
+        if (eager && n_chunks == 1) {
+            CRUM_TRY(hipMemcpyAsync(himg, staging, image_bytes, hipMemcpyDeviceToHost, c->side));
+        } else {
+            CRUM_TRY(hipMemcpyAsync(himg, staging, data_off, hipMemcpyDeviceToHost, c->side));
+            if (image_bytes > tail)
+                CRUM_TRY(hipMemcpyAsync(himg + tail, staging + tail, image_bytes - tail,
+                                        hipMemcpyDeviceToHost, c->side));
+        }
         sp.end();
         CRUM_TRY(hipMemcpyAsync(h_status, d_out, sizeof(crum_status), hipMemcpyDeviceToHost,
                                 c->side));

@@ -826,7 +826,9 @@ __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs
     uint64_t slot0, slot1;
     slot_range(sr, &slot0, &slot1);
     const uint64_t n_items = (slot1 - slot0) << np_shift;
-    if (n_items == 0)
+    // a grid sized for the most slots the launch could get: workgroups past
+    // the items leave before staging their tables
+    if ((uint64_t)blockIdx.x * 4 >= n_items)
         return;
     load_pack_tables(lds, tabs);
     const uint32_t* gz = &tabs->z[0][0][0];

@@ -20,8 +20,8 @@ def snap():
     crum.lib()  # the HIP library must be present; no fallback exists
     from paper_1808_00117_amd.api import Snapshotter
     s = Snapshotter(0)
-    # the staging orders (pipelined and diff-first); the direct order that
-    # small images take by default has its own context below
+    # the staging orders (chunked and diff-first); the opt-in direct order
+    # has its own context below
     crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_DIRECT_BYTES, 0)
     yield s
     s.close()
