@@ -757,3 +757,58 @@ def test_restore_parity_property(snap):
                 assert np.array_equal(s.cpu().numpy(), hs)
 
     run()
+
+
+def test_restore_corruption_property(snap):
+    """Drawn images with one to three bytes changed anywhere (header, region
+    table, bitmap, pads, packed pages, CRC array), restored with verification
+    into buffers holding their old bytes: the restore succeeds exactly when
+    the oracle's does; a change inside the packed pages alone is CRUM_ECRC at
+    the oracle's lowest bad slot; any refused image leaves every region
+    unchanged; an accepted one gives the oracle's bytes.  Derandomized."""
+    import torch
+    from hypothesis import HealthCheck, given, settings
+    from hypothesis import strategies as st
+
+    @settings(max_examples=40, deadline=None, derandomize=True,
+              suppress_health_check=list(HealthCheck))
+    @given(counts=st.lists(st.integers(1, 90), min_size=1, max_size=4),
+           pshift=st.sampled_from([12, 14, 16]),
+           density=st.sampled_from([0.05, 0.3, 1.0]),
+           where=st.sampled_from(["meta", "pages", "crcs", "any"]),
+           n_bytes=st.integers(1, 3),
+           seed=st.integers(0, 2**31 - 1))
+    def run(counts, pshift, density, where, n_bytes, seed):
+        P = 1 << pshift
+        rng = np.random.default_rng(seed)
+        G = sum(counts)
+        dirty = {g for g in range(G) if rng.random() < density} or {int(rng.integers(0, G))}
+        host = host_case(tuple(counts), P, dirty, seed=seed)
+        st_o, img, _ = oracle.snapshot(host, P, seq=seed & 0xFF)
+        assert st_o.code == oracle.OK
+        data_off = oracle.prefix_bytes(len(counts), G)
+        tail = data_off + st_o.n_dirty * P
+        span = {"meta": (0, data_off), "pages": (data_off, tail),
+                "crcs": (tail, img.size), "any": (0, img.size)}[where]
+        bad = img.copy()
+        for pos in rng.choice(np.arange(span[0], span[1]), size=n_bytes, replace=False):
+            bad[pos] ^= np.uint8(1 + rng.integers(0, 255))
+        old = [(sh.copy(), rid) for _, sh, rid in host]
+        tgt = [(c.copy(), None, rid) for c, rid in old]
+        res = oracle.restore(tgt, bad, oracle.VERIFY)
+        dev = upload([(c, None, rid) for c, rid in old])
+        staging = torch.empty(max(bad.size, 16), dtype=torch.uint8, device="cuda")
+        rc, stg = snap.restore(dev, torch.from_numpy(bad).pin_memory(), bad.size, staging,
+                               flags=oracle.VERIFY)
+        assert (stg.code == 0) == (res.code == oracle.OK), (where, stg, res)
+        if where == "pages":
+            assert res.code == oracle.ECRC and stg.code == res.code, (stg, res)
+            assert stg.first_bad == res.first_bad, (stg, res)
+        if res.code == oracle.OK:
+            for (c, _, _), (hc, _, _) in zip(dev, tgt):
+                assert np.array_equal(c.cpu().numpy(), hc)
+        else:
+            for (c, _, _), (hc, _) in zip(dev, old):
+                assert np.array_equal(c.cpu().numpy(), hc)
+
+    run()
