@@ -72,6 +72,9 @@ def parse_args():
     ap.add_argument("--tune-cache", default=None,
                     help="tuning cache path (default: the package's tuning_cache.json)")
     ap.add_argument("--no-corunner", action="store_true")
+    ap.add_argument("--seed-base", type=int, default=1000,
+                    help="configuration k draws its scenario with seed SEED_BASE + k (1000: "
+                         "the reported inputs; 2000 and 3000: variance runs)")
     ap.add_argument("--param", action="append", default=[], metavar="NAME=VALUE",
                     help="set a context parameter (names as in autotune.PARAMS)")
     ap.add_argument("--diff-prio", type=int, default=None,
@@ -550,7 +553,7 @@ def bench_batched(args) -> dict:
     from synth import scenarios as sc
 
     crum.lib()
-    reqs = sc.batched(seed=1004, n_requests=args.requests)
+    reqs = sc.batched(seed=args.seed_base + 4, n_requests=args.requests)
     N = sum(r.total_bytes for r in reqs)
     Dsum = sum(r.n_dirty for r in reqs)
     log(f"[batched] {len(reqs)} requests, {N / 1e9:.1f} GB scanned, "
@@ -816,6 +819,8 @@ def run_leg(args, config: str) -> dict:
         cmd += ["--tune-cache", args.tune_cache]
     if args.no_corunner:
         cmd.append("--no-corunner")
+    if args.seed_base != 1000:
+        cmd += ["--seed-base", str(args.seed_base)]
     log(f"[bench] leg: {' '.join(cmd[2:])}")
     r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True)
     if r.returncode != 0:
@@ -853,7 +858,8 @@ def bench_headline(args):
     if args.cpu_seconds > 0:
         from synth import scenarios as sc
         log("[bench] CPU oracle baseline ...")
-        cpu = cpu_baseline(sc.many_allocs(), args.cpu_seconds, args.cpu_threads)
+        cpu = cpu_baseline(sc.many_allocs(seed=args.seed_base + 2), args.cpu_seconds,
+                           args.cpu_threads)
     bat, pl = b["batched"], b["plain"]
     roof = dict(m["roofline"])
     roof["workload"] = ("the 16 GiB many-allocations snapshot (64 regions, 64 KiB pages) "
@@ -912,8 +918,8 @@ def bench_served(args):
 
     crum.lib()
     P = 64 * 1024
-    sizes = sc.served_clients()
-    trace = sc.served_trace(duration=args.duration, rate=args.rate)
+    sizes = sc.served_clients(seed=args.seed_base + 5)
+    trace = sc.served_trace(seed=args.seed_base + 5, duration=args.duration, rate=args.rate)
     warm = min(5.0, args.duration / 6)
     # offered device-to-host load: expected dirty bytes of the snapshots per second
     offered = sum(sizes[c] * f for t, c, k, f in trace if k == 1) / args.duration
@@ -929,7 +935,7 @@ def bench_served(args):
 
     def reset_state():
         for i, (c, s, n) in enumerate(zip(cur, sh, sizes)):
-            synth.fill_dev(c.ptr, n, 1005, i, 0, 0)
+            synth.fill_dev(c.ptr, n, args.seed_base + 5, i, 0, 0)
             H.memcpy_dtod(s.ptr, c.ptr, n)
         H.device_synchronize()
 
@@ -1040,7 +1046,7 @@ def bench_persist(args):
     from synth import scenarios as sc
 
     crum.lib()
-    scn = sc.many_allocs()
+    scn = sc.many_allocs(seed=args.seed_base + 2)
     P, N, D, G, R = scn.page_size, scn.total_bytes, scn.n_dirty, scn.total_pages, len(scn.regions)
     pairs = materialize_raw(scn, H)
     table = crum.region_table([(c.ptr, s.ptr if s else 0, r.nbytes, r.id)
@@ -1184,7 +1190,7 @@ def bench_lazy(args):
     from synth import scenarios as sc
 
     crum.lib()
-    scn = sc.many_allocs()
+    scn = sc.many_allocs(seed=args.seed_base + 2)
     P, N, D, G, R = scn.page_size, scn.total_bytes, scn.n_dirty, scn.total_pages, len(scn.regions)
     pairs = materialize_raw(scn, H)
     table = crum.region_table([(c.ptr, s.ptr, r.nbytes, r.id)
@@ -1390,7 +1396,7 @@ def bench_managed(args):
     from synth import scenarios as sc
 
     crum.lib()
-    scn = sc.managed()
+    scn = sc.managed(seed=args.seed_base + 3)
     r = scn.regions[0]
     P, G, N, D = scn.page_size, scn.total_pages, scn.total_bytes, scn.n_dirty
     dev_pages = scn.meta["device_pages"]
@@ -1665,12 +1671,12 @@ def bench_many(args, with_cpu: bool = True) -> dict:
         raise RuntimeError("bench.py needs a GPU")
 
     if args.config == "many":
-        scn = sc.many_allocs()
+        scn = sc.many_allocs(seed=args.seed_base + 2)
         workload = "many_allocs"
         wl_name = "64 allocations log-uniform 4KiB-1GiB scaled to 16 GiB, 64 KiB pages, " \
                   "clustered dirty runs (p_start 0.003, mean 32)"
     else:
-        scn = sc.plain()
+        scn = sc.plain(seed=args.seed_base + 1)
         workload = "plain"
         wl_name = "one 64 MiB allocation, 4 KiB pages, 5% of pages dirty"
         if args.cold:
