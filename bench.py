@@ -94,6 +94,9 @@ def parse_args():
                     help="run a 1 GiB plain copy kernel first (counter calibration)")
     ap.add_argument("--trace-summary", metavar="DIR",
                     help="summarise a rocprofv3 --kernel-trace --stats run of this script")
+    ap.add_argument("--plan-groups", type=int, default=0,
+                    help="with --trace-summary of a --config batched run: the grouped "
+                         "plan's group count (its first launches' diffs are summarised)")
     ap.add_argument("--image-bytes", type=int, default=0,
                     help="--trace-summary: bytes of one timed snapshot's image, for the drain "
                          "rate when the copy trace carries no sizes")
@@ -196,11 +199,15 @@ def pmc_table(d: str, kernels=("k_pack<0", "k_pack<1", "k_diff", "k_scatter")) -
     return "\n".join(out)
 
 
-def trace_summary(d: str, steps: int, image_bytes: int = 0) -> str:
+def trace_summary(d: str, steps: int, image_bytes: int = 0, plan_groups: int = 0,
+                  warmup: int = 0) -> str:
     """Markdown summary of a rocprofv3 kernel-trace run of this script: the
     per-kernel stats table, and the k_diff launches of the last `steps`
     snapshots (the timed region), which is what the bench's avg_launch_ms
-    covers."""
+    covers.  With plan_groups (a `--config batched` run without --tune): the
+    first plan_groups * (warmup + steps) k_diff launches of the run are the
+    grouped plan's, the last plan_groups * steps of them its timed launches,
+    which is what the batched block's diff_roofline covers."""
     import csv
     import glob
 
@@ -232,6 +239,16 @@ def trace_summary(d: str, steps: int, image_bytes: int = 0) -> str:
                       for r in rows if "k_diff" in r["Kernel_Name"])
         heads = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
                        for r in rows if "k_header" in r["Kernel_Name"])
+        if plan_groups:
+            n0, n1 = plan_groups * warmup, plan_groups * (warmup + steps)
+            if len(diff) >= n1:
+                sel = diff[n0:n1]
+                avg = statistics.mean(b - a for a, b in sel) / 1e6
+                out.append("")
+                out.append(f"k_diff launches of the grouped plan's {steps} timed launches "
+                           f"({plan_groups} groups each): {len(sel)}, average duration "
+                           f"{avg:.4f} ms, summed {sum(b - a for a, b in sel) / 1e6:.3f} ms")
+            return "\n".join(out)
         if diff and len(heads) >= steps:
             t0 = heads[-steps - 1][0] if len(heads) > steps else 0
             sel = [(a, b) for a, b in diff if a > t0]
@@ -1627,7 +1644,8 @@ def main():
         print(json.dumps(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], wl), indent=1))
         return
     if args.trace_summary:
-        print(trace_summary(args.trace_summary, args.steps, args.image_bytes))
+        print(trace_summary(args.trace_summary, args.steps, args.image_bytes, args.plan_groups,
+                            args.warmup))
         return
     if args.pmc_table:
         print(pmc_table(args.pmc_table))
