@@ -385,7 +385,7 @@ def settle_copy_engines(H, dev_ptr: int, host_ptr: int, nbytes: int = 256 << 20,
     """Wait until device-to-host copies run at a steady rate.  Shortly after
     a process allocates (or another process frees) tens of GB of device
     memory, pinned copies on this system run at about half rate for a few
-    seconds (the copy engines are shared with the driver's background work),
+    seconds (the copy engines are shared with the kernel driver's background work),
     then at full rate for good.  Repeats a `nbytes` copy until three in a row
     are within 3 % of the best rate seen and above 45 GB/s, or `limit_s`."""
     s = H.Stream()
@@ -1651,9 +1651,9 @@ def main():
         print(pmc_table(args.pmc_table))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: the snapshot path has no cross-GPU step, and "
-              "multi-GPU runs are not part of this build (each GPU would snapshot its own "
-              "regions independently).", file=sys.stderr)
+        print("bench.py measures one GPU: the snapshot path has no cross-GPU step and "
+              "is measured on one device only (each GPU would snapshot its own regions "
+              "independently).", file=sys.stderr)
         sys.exit(2)
     if args.config == "headline":
         return bench_headline(args)
