@@ -91,6 +91,22 @@ def test_trace_summary_reports_timed_drain_copies(tmp_path):
     assert "2097152 bytes (2 images of 1048576 bytes)" in out
 
 
+def test_trace_summary_of_the_grouped_plan(tmp_path):
+    """With the plan's group count, the k_diff launches of its warm-up
+    launches are skipped and those of its timed launches averaged; later
+    launches (the other plans, the plain snapshots) are left out."""
+    hdr = ["Kernel_Name", "Start_Timestamp", "End_Timestamp"]
+    rows = []
+    t = 0
+    for launch, dur in enumerate([1000, 4000, 4000, 9000]):  # warm-up, 2 timed, later
+        for _ in range(3):  # 3 groups
+            rows.append(("void crum::k_diff<true>(...)", t, t + dur))
+            t += 10000
+    write_csv(tmp_path / "run_kernel_trace.csv", hdr, rows)
+    out = bench.trace_summary(str(tmp_path), 2, plan_groups=3, warmup=1)
+    assert "timed launches (3 groups each): 6, average duration 0.0040 ms" in out
+
+
 def test_kernel_hash_ignores_comments(tmp_path, monkeypatch):
     src = tmp_path / "paper_1808_00117_amd" / "csrc"
     src.mkdir(parents=True)
