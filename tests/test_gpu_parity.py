@@ -812,3 +812,28 @@ def test_restore_corruption_property(snap):
                 assert np.array_equal(c.cpu().numpy(), hc)
 
     run()
+
+
+@pytest.mark.parametrize("P,counts,dirty", [(64 * MiB, (3,), {0, 2}), (1 << 30, (1,), {0})],
+                         ids=["p64m", "p1g"])
+def test_largest_page_sizes(snap, P, counts, dirty):
+    """Pages of 64 MiB and of 1 GiB (the largest page size accepted): 4096 and
+    65 536 pieces per page combined by k_finalize, 4096 and 65 536 diff units
+    per bitmap bit; image equal to the oracle's in both staging orders, and a
+    verified restore of it."""
+    import torch
+    log(f"[parity] page size {P >> 20} MiB, {counts[0]} pages, dirty {sorted(dirty)}")
+    rng = np.random.default_rng(77)
+    cur = np.frombuffer(rng.bytes(counts[0] * P), dtype=np.uint8).copy()
+    sh = cur.copy()
+    for g in dirty:  # one changed byte per dirty page, at a drawn offset
+        sh[g * P + int(rng.integers(0, P))] ^= np.uint8(1 + rng.integers(0, 255))
+    host = [(cur, sh, 4242)]
+    dev, img = check_parity(snap, host, P)
+    targets = [(sh.clone(), None, rid) for _, sh, rid in dev]
+    staging = torch.empty(img.size, dtype=torch.uint8, device="cuda")
+    rc, st = snap.restore(targets, torch.from_numpy(img).pin_memory(), img.size, staging,
+                          flags=oracle.VERIFY)
+    assert rc == 0 and st.code == 0 and st.n_dirty == len(dirty), st
+    for (t, _, _), (c, _, _) in zip(targets, dev):
+        assert torch.equal(t, c)
