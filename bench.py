@@ -882,8 +882,8 @@ def bench_headline(args):
     roof["workload"] = ("the 16 GiB many-allocations snapshot (64 regions, 64 KiB pages) "
                         "beside the SAXPY co-runner: its own timed snapshots in this run")
     many = {k: m[k] for k in ("value", "unit", "ms_per_step", "latency_ms", "config", "restore",
-                              "roofline_alone", "drain", "pack", "header", "breakdown_timed",
-                              "overlap")}
+                              "roofline_alone", "drain", "pack", "diff_and_crc", "header",
+                              "breakdown_timed", "overlap")}
     many["metric"] = m["metric"]
     many["steps"] = m["steps"]
     result = {
@@ -914,6 +914,7 @@ def bench_headline(args):
         "roofline": roof,
         "drain": m["drain"],
         "pack": m["pack"],
+        "diff_and_crc": m["diff_and_crc"],
         "many_allocs": many,
         "cpu_baseline": cpu,
     }
@@ -1907,6 +1908,10 @@ def bench_many(args, with_cpu: bool = True) -> dict:
     pack_bytes = 2 * D * P + 4 * D
     pack_gbs = pack_bytes * n_breakdown / (pack_ms * 1e-3) / 1e9
     n_hd, header_ms = timing["header"]
+    # the two HBM-bound kernels of the path together: diff and pack (with its
+    # CRC) bytes of one snapshot over their summed time per snapshot
+    dc_ms = diff_ms / args.steps + pack_ms / n_breakdown
+    dc_gbs = (diff_bytes_step + pack_bytes) / (dc_ms * 1e-3) / 1e9
     sax_with = None
     if sax_graphs[0]:
         sax_with = sax_bytes_per_pass * PASSES * sax_graphs[0] / (sax_time[0] * 1e-3) / 1e9
@@ -2026,6 +2031,13 @@ def bench_many(args, with_cpu: bool = True) -> dict:
                  "algorithmic_bytes_per_step": pack_bytes,
                  "what": None if drain_gbs else "direct order: the pack's stores cross the "
                                                 "host link into the pinned image"},
+        "diff_and_crc": {"achieved": round(dc_gbs, 1), "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                         "frac": round(dc_gbs / HBM_PEAK_GBS, 4),
+                         "ms_per_snapshot": round(dc_ms, 4),
+                         "algorithmic_bytes_per_step": diff_bytes_step + pack_bytes,
+                         "what": "k_diff and k_pack (copy + CRC-32C) together: both kernels' "
+                                 "algorithmic bytes of one snapshot over their summed launch "
+                                 "durations per snapshot"},
         "header": {"avg_launch_ms": round(header_ms / max(n_hd, 1), 4)},
         "breakdown_timed": "in the timed steps" if breakdown_in_timed else
                            f"separate pass of {n_breakdown} snapshots after the timed steps",
