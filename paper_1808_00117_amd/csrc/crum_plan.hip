@@ -208,7 +208,7 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
     const uint64_t capacity = h_images ? std::min(staging_bytes, h_images_bytes) : staging_bytes;
 
     // ---- groups of whole requests: scanned bytes start at CHUNK_BYTES and
-    // double up to CHUNK_MAX_BYTES
+    // grow by CHUNK_GROWTH per group up to CHUNK_MAX_BYTES
     p->group_q.push_back(0);
     {
         uint64_t target = ctx_chunk_bytes(c), acc = 0;
