@@ -301,7 +301,10 @@ def test_persist_16gib_image(tmp_path):
     ib = crum.crum_image_bytes(R, G, D, P)
     cap = crum.crum_image_bytes(R, G, G, P)
     staging = H.DeviceBuffer(cap)
-    bufs = [H.PinnedBuffer(cap), H.PinnedBuffer(cap)]
+    # the first image in a buffer for the worst case (the pipelined order),
+    # the second in one of its exact size (the diff-first order): less
+    # pinned memory, which is a host-wide resource
+    bufs = [H.PinnedBuffer(cap), H.PinnedBuffer(ib)]
     status = H.PinnedBuffer(64)
     ctx = crum.crum_ctx_create(0)
     s = H.Stream()
@@ -310,7 +313,7 @@ def test_persist_16gib_image(tmp_path):
         tickets = []
         for i in range(2):
             assert crum.crum_snapshot(ctx, table, P, 0, 20 + i, staging.ptr, cap, bufs[i].ptr,
-                                      cap, s.handle, status.ptr) == 0
+                                      bufs[i].nbytes, s.handle, status.ptr) == 0
             s.synchronize()
             assert crum.read_status(status.ptr).code == 0
             tickets.append(w.submit(str(tmp_path / f"ckpt{i}.crum"), bufs[i].ptr, ib))
@@ -328,6 +331,8 @@ def test_persist_16gib_image(tmp_path):
             c.free()
             sh.free()
         staging.free()
+        for b in bufs:
+            b.free()
         for b in bufs:
             b.free()
 
