@@ -777,6 +777,7 @@ def bench_batched(args) -> dict:
                     "groups": n_groups,
                     "makespans_ms": [round(1e3 * v, 1) for v in mk],
                     "latency_ms": {"p50": round(percentile(lat_b, 0.5), 2),
+                                   "p90": round(percentile(lat_b, 0.9), 2),
                                    "p99": round(percentile(lat_b, 0.99), 2)},
                     "drain_gbs": round(sum(sizes) / statistics.median(mk) / 1e9, 2),
                     "diff_roofline": {
@@ -794,12 +795,14 @@ def bench_batched(args) -> dict:
             "makespan_ms": round(1e3 * statistics.median(mk_s), 2),
             "gbs": round(N / statistics.median(mk_s) / 1e9, 2),
             "latency_ms": {"p50": round(percentile(lat_s, 0.5), 2),
+                           "p90": round(percentile(lat_s, 0.9), 2),
                            "p99": round(percentile(lat_s, 0.99), 2)},
             "groups": n_groups_s, "same_images": same_s},
         "batched_one_graph": {
             "makespan_ms": round(1e3 * statistics.median(mk_1), 2),
             "gbs": round(N / statistics.median(mk_1) / 1e9, 2),
             "latency_ms": {"p50": round(percentile(lat_1, 0.5), 2),
+                           "p90": round(percentile(lat_1, 0.9), 2),
                            "p99": round(percentile(lat_1, 0.99), 2)},
             "groups": n_groups_1, "same_images": same_1,
             "what": "all 256 requests in one captured graph (one persistent diff, one "
@@ -807,6 +810,7 @@ def bench_batched(args) -> dict:
         "plain": {"makespan_ms": round(1e3 * t_plain, 2),
                   "gbs": round(N / t_plain / 1e9, 2),
                   "latency_ms": {"p50": round(1e3 * percentile(lat_p, 0.5), 2),
+                                 "p90": round(1e3 * percentile(lat_p, 0.9), 2),
                                  "p99": round(1e3 * percentile(lat_p, 0.99), 2)}},
         "bit_exact_vs_plain": same,
     }
@@ -1004,6 +1008,7 @@ def bench_served(args):
         drained = sum(d["image_bytes"] for d in snaps)
         return {"slots": n_slots, "requests": len(win),
                 "latency_ms": {"p50": round(percentile(lat, 0.5), 2),
+                               "p90": round(percentile(lat, 0.9), 2),
                                "p99": round(percentile(lat, 0.99), 2)},
                 "snapshot_gbs": round(scanned / span / 1e9, 2),
                 "drain_gbs": round(drained / span / 1e9, 2),
