@@ -401,3 +401,65 @@ def test_tuning_cache_class_shapes_apply_and_explicit_params_win(tmp_path):
             assert np.array_equal(res2[0][1][q], res[0][1][q]), q
     finally:
         s.close()
+
+
+def test_batched_shadow_and_capacity_property(ctx):
+    """Drawn request sets with drawn shadow-update flags, a drawn staging
+    capacity (from too small for anything to room for every image) and the
+    caller's or smallest-first order, one request per group: in processing
+    order the statuses are OK for a run of groups whose images fit and
+    ENOSPC from the first group that does not fit on; every OK image is the
+    oracle's; a request that was packed with the flag has its shadows updated,
+    every other request's shadows are unchanged.  Derandomized."""
+    import torch
+    import paper_1808_00117_amd as crum
+    from hypothesis import HealthCheck, given, settings
+    from hypothesis import strategies as st
+
+    @settings(max_examples=15, deadline=None, derandomize=True,
+              suppress_health_check=list(HealthCheck))
+    @given(seed=st.integers(0, 2**31 - 1), n=st.integers(1, 10),
+           room=st.sampled_from([0.0, 0.3, 0.6, 1.0]), order=st.sampled_from([0, 1]),
+           flag_seed=st.integers(0, 2**31 - 1))
+    def run(seed, n, room, order, flag_seed):
+        host = make_requests(seed, n, max_regions=3, page_sizes=(4 * KiB, 64 * KiB))
+        frng = np.random.default_rng(flag_seed)
+        flags = [int(frng.integers(0, 2)) for _ in range(n)]
+        imgs = [oracle.snapshot(r, P, seq=s)[1] for r, P, s in host]
+        aligned = [((im.size + 4095) // 4096) * 4096 for im in imgs]
+        scanned = [sum(c.size for c, _, _ in r) for r, _, _ in host]
+        proc = sorted(range(n), key=lambda q: scanned[q]) if order else list(range(n))
+        cap = max(16, int(room * sum(aligned)))
+        dev = [upload(regs) for regs, _, _ in host]
+        before = [[None if s is None else s.clone() for _, s, _ in d] for d in dev]
+        crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_PLAN_ORDER, order)
+        try:
+            dev, results, groups = run_plan(ctx, host, flags=flags, staging_bytes=cap,
+                                            small_groups=True, dev=dev)
+        finally:
+            crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_PLAN_ORDER, 0)
+        sts, got = results[0]
+        codes = [sts[q][0] for q in proc]
+        assert set(codes) <= {0, -2}, codes
+        k = codes.index(-2) if -2 in codes else n
+        assert all(c == -2 for c in codes[k:]), codes
+        used = sum(aligned[q] for q in proc[:k])
+        assert used <= cap
+        if k < n:  # the group holding the first refused request does not fit
+            g = max(i for i in range(len(groups) - 1) if groups[i] <= k)
+            assert groups[g] == k, (groups, k)
+            need = sum(aligned[proc[i]] for i in range(groups[g], groups[g + 1]))
+            assert used + need > cap, (used, need, cap)
+        for q in range(n):
+            ok = sts[q][0] == 0
+            if ok:
+                assert np.array_equal(got[q], imgs[q]), q
+            for (c, s, _), b in zip(dev[q], before[q]):
+                if s is None:
+                    continue
+                if ok and flags[q]:
+                    assert torch.equal(s, c), q
+                else:
+                    assert torch.equal(s, b), q
+
+    run()
