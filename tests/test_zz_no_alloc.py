@@ -134,3 +134,53 @@ def test_noalloc_refuses_inputs_beyond_its_scratch():
         torch.cuda.synchronize()
     finally:
         crum.crum_ctx_destroy(ctx)
+
+
+def test_noalloc_property():
+    """Drawn region tables (zero-length regions, regions without a shadow,
+    ragged bitmap words), page sizes and the shadow-update flag, called in a
+    row on one context: each image is the oracle's byte for byte, and with
+    the flag the shadows then equal the current bytes.  Derandomized."""
+    import torch
+    from hypothesis import HealthCheck, given, settings
+    from hypothesis import strategies as st
+
+    import paper_1808_00117_amd as crum
+    from paper_1808_00117_amd.api import regions_of
+    ctx = crum.crum_ctx_create(0)
+    try:
+        @settings(max_examples=12, deadline=None, derandomize=True,
+                  suppress_health_check=list(HealthCheck))
+        @given(counts=st.lists(st.integers(0, 140), min_size=0, max_size=5),
+               pshift=st.sampled_from([12, 14, 16, 18]),
+               frac=st.sampled_from([0.0, 0.1, 0.5, 1.0]),
+               nulls=st.sets(st.integers(0, 4), max_size=2),
+               update=st.booleans(), seed=st.integers(0, 2**31 - 1))
+        def one(counts, pshift, frac, nulls, update, seed):
+            P = 1 << pshift
+            host = host_case(tuple(counts), P, frac, seed, tuple(nulls))
+            st_o, img_o, _ = oracle.snapshot(host, P, seq=seed & 0xFF)
+            dev = upload(host)
+            cap = max(image_capacity(dev, P), 4096)
+            staging = torch.empty(cap, dtype=torch.uint8, device="cuda")
+            h = torch.zeros(cap, dtype=torch.uint8, pin_memory=True)
+            status = torch.zeros(64, dtype=torch.uint8, pin_memory=True)
+            rc = crum.crum_snapshot_noalloc(ctx, regions_of(dev), P,
+                                            crum.CRUM_UPDATE_SHADOW if update else 0,
+                                            seed & 0xFF, staging.data_ptr(), cap, h.data_ptr(),
+                                            cap, torch.cuda.current_stream().cuda_stream,
+                                            status.data_ptr())
+            assert rc == crum.CRUM_OK, rc
+            torch.cuda.synchronize()
+            s = crum.read_status(status.data_ptr())
+            assert s.code == 0 and s.n_dirty == st_o.n_dirty and \
+                s.image_bytes == st_o.image_bytes, s
+            assert np.array_equal(h[: s.image_bytes].numpy(), img_o)
+            if update:
+                for c, sh, _ in dev:
+                    if sh is not None:
+                        assert torch.equal(c, sh)
+
+        one()
+    finally:
+        crum.crum_ctx_destroy(ctx)
