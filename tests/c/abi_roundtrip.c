@@ -4,12 +4,17 @@
  * an on-demand restore of the same image (one touch, then finish), then a
  * snapshot with shadow update and one more that must find nothing dirty,
  * then host write tracking over a managed region with a tracked snapshot and
- * the allocation-free snapshot of the same region.  Prints one line and
- * exits 0 when every check holds. */
+ * the allocation-free snapshot of the same region.  In between, a plan of
+ * the two regions as two requests is launched twice and each request's
+ * image compared with the plain snapshot's, and one of them is persisted
+ * to a file by the writer and read back.  Prints one line and exits 0 when
+ * every check holds. */
+#define _POSIX_C_SOURCE 200809L
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <unistd.h>
 
 #include <hip/hip_runtime_api.h>
 
@@ -112,6 +117,81 @@ int main(void)
     rc = crum_restore(ctx, targets, 2, h_image, image_bytes, CRUM_VERIFY, staging, cap, s, st);
     if (rc != CRUM_EMISMATCH || st->code != CRUM_EMISMATCH)
         return fail("restore with a wrong id", rc);
+
+    /* a plan: region 0 and region 1 as two requests (caller's order), two
+     * launches; each image equals the plain snapshot of that region alone */
+    {
+        uint64_t cap0 = 0, cap1 = 0;
+        if (crum_image_bytes(1, N0, N0, PAGE, &cap0) != CRUM_OK ||
+            crum_image_bytes(1, N1, N1, PAGE, &cap1) != CRUM_OK)
+            return fail("crum_image_bytes (plan)", 0);
+        const uint64_t pcap = (cap0 + 4095) / 4096 * 4096 + (cap1 + 4095) / 4096 * 4096;
+        void *pstage = NULL, *h_plan = NULL, *h_one = NULL;
+        crum_request_status* pst = NULL;
+        HIPOK(hipMalloc(&pstage, pcap));
+        HIPOK(hipHostMalloc(&h_plan, pcap, 0));
+        HIPOK(hipHostMalloc(&h_one, cap0 > cap1 ? cap0 : cap1, 0));
+        HIPOK(hipHostMalloc((void**)&pst, 2 * sizeof(*pst), 0));
+        crum_request reqs[2] = {{&regs[0], 1, PAGE, 0, 0, 31}, {&regs[1], 1, PAGE, 0, 0, 32}};
+        crum_plan* plan = NULL;
+        rc = crum_plan_create(ctx, reqs, 2, pstage, pcap, h_plan, pcap, &plan);
+        if (rc != CRUM_OK)
+            return fail("crum_plan_create", rc);
+        for (int launch = 0; launch < 2; ++launch) {
+            memset(pst, 0, 2 * sizeof(*pst));
+            rc = crum_plan_launch(plan, s, pst);
+            HIPOK(hipStreamSynchronize(s));
+            if (rc != CRUM_OK || pst[0].status.code != CRUM_OK ||
+                pst[1].status.code != CRUM_OK || pst[0].status.n_dirty != n_changed ||
+                pst[1].status.n_dirty != N1 || pst[1].image_offset % 4096 != 0)
+                return fail("crum_plan_launch", rc);
+        }
+        uint32_t n_groups = 0;
+        if (crum_plan_groups(plan, &n_groups, NULL, 0) != CRUM_OK || n_groups < 1)
+            return fail("crum_plan_groups", (long)n_groups);
+        for (unsigned q = 0; q < 2; ++q) {
+            rc = crum_snapshot(ctx, &regs[q], 1, PAGE, 0, 31 + q, staging, cap, h_one,
+                               q ? cap1 : cap0, s, st);
+            HIPOK(hipStreamSynchronize(s));
+            if (rc != CRUM_OK || st->code != CRUM_OK ||
+                st->image_bytes != pst[q].status.image_bytes ||
+                memcmp((const uint8_t*)h_plan + pst[q].image_offset, h_one, st->image_bytes))
+                return fail("plan image vs plain snapshot", (long)q);
+        }
+        crum_plan_destroy(plan);
+
+        /* the writer persists request 0's image; the file reads back equal */
+        char path[] = "/tmp/crum_abi_XXXXXX";
+        const int fd = mkstemp(path);
+        if (fd < 0)
+            return fail("mkstemp", 0);
+        close(fd);
+        crum_writer* wr = NULL;
+        uint64_t ticket = 0;
+        crum_write_status ws;
+        const uint64_t ib0 = pst[0].status.image_bytes;
+        if (crum_writer_create(2, 1u << 20, 0, &wr) != CRUM_OK ||
+            crum_writer_submit(wr, path, (const uint8_t*)h_plan + pst[0].image_offset, ib0,
+                               &ticket) != CRUM_OK ||
+            crum_writer_poll(wr, ticket, 1, &ws) != CRUM_OK || ws.code != CRUM_OK ||
+            ws.bytes != ib0)
+            return fail("crum_writer", 0);
+        crum_writer_destroy(wr);
+        FILE* f = fopen(path, "rb");
+        uint8_t* back = malloc(ib0 + 1);
+        if (!f || !back)
+            return fail("read back the file", 0);
+        const size_t got = fread(back, 1, ib0 + 1, f);
+        fclose(f);
+        unlink(path);
+        if (got != ib0 || memcmp(back, (const uint8_t*)h_plan + pst[0].image_offset, ib0))
+            return fail("file equals the image", (long)got);
+        free(back);
+        HIPOK(hipFree(pstage));
+        HIPOK(hipHostFree(h_plan));
+        HIPOK(hipHostFree(h_one));
+        HIPOK(hipHostFree(pst));
+    }
 
     /* on-demand restore of the same image into buffers holding old bytes:
      * one touch of region 0's page 3 (dirty) fetches exactly that page, then

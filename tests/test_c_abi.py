@@ -1,7 +1,9 @@
 """The boundary used from C: a C99 program that includes only crum.h and the
 HIP runtime API compiles warning-free and links against libcrum.so (CPU), and
-on the GPU takes a snapshot, restores it with verification, and finds nothing
-dirty after a shadow update (tests/c/abi_roundtrip.c)."""
+on the GPU takes a snapshot, restores it with verification, runs a plan of two
+requests and persists an image with the writer, restores on demand, finds
+nothing dirty after a shadow update, and snapshots a tracked managed region
+with and without allocation (tests/c/abi_roundtrip.c)."""
 import os
 import subprocess
 
