@@ -7,8 +7,10 @@
  * the allocation-free snapshot of the same region.  In between, a plan of
  * the two regions as two requests is launched twice and each request's
  * image compared with the plain snapshot's, and one of them is persisted
- * to a file by the writer and read back.  Prints one line and exits 0 when
- * every check holds. */
+ * to a file by the writer and read back; at the end a serving loop with one
+ * client snapshots, repairs a clobbered page by a restore request and finds
+ * nothing changed after it.  Prints one line and exits 0 when every check
+ * holds. */
 #define _POSIX_C_SOURCE 200809L
 #include <stdint.h>
 #include <stdio.h>
@@ -285,6 +287,53 @@ int main(void)
         return fail("allocation-free snapshot of the managed region", rc);
     crum_track_destroy(tr);
     HIPOK(hipFree(man));
+
+    /* the serving loop: one client (fresh copies of region 0's bytes and old
+     * shadow), two slots; a snapshot finds the changed pages, a restore
+     * after clobbering a changed page repairs it, and a second snapshot then
+     * finds nothing */
+    {
+        void *scur = NULL, *ssh = NULL;
+        HIPOK(hipMalloc(&scur, b0));
+        HIPOK(hipMalloc(&ssh, b0));
+        HIPOK(hipMemcpy(scur, h_cur0, b0, hipMemcpyHostToDevice));
+        HIPOK(hipMemcpy(ssh, h_sh0, b0, hipMemcpyHostToDevice));
+        crum_region sreg[1] = {{scur, ssh, b0, 74}};
+        crum_client cl[1] = {{sreg, 1, PAGE}};
+        crum_server* srv = NULL;
+        rc = crum_server_create(0, cl, 1, 2, 16u << 20, &srv);
+        if (rc != CRUM_OK)
+            return fail("crum_server_create", rc);
+        crum_server_completion done[2];
+        uint32_t n_done = 0;
+        uint64_t id = 0;
+        uint64_t want = 0;
+        if (crum_image_bytes(1, N0, n_changed, PAGE, &want) != CRUM_OK)
+            return fail("crum_image_bytes (server)", 0);
+        if (crum_server_submit(srv, 0, CRUM_REQ_SNAPSHOT, 1, &id) != CRUM_OK ||
+            crum_server_poll(srv, done, 2, &n_done, 1) != CRUM_OK || n_done != 1 ||
+            done[0].code != CRUM_OK || done[0].n_dirty != n_changed ||
+            done[0].image_bytes != want)
+            return fail("served snapshot", (long)done[0].n_dirty);
+        const void* img_ptr = NULL;
+        uint64_t img_len = 0;
+        if (crum_server_latest_image(srv, 0, &img_ptr, &img_len) != CRUM_OK || img_len != want)
+            return fail("crum_server_latest_image", (long)img_len);
+        HIPOK(hipMemset((uint8_t*)scur + 3u * PAGE, 0xee, PAGE)); /* page 3 changed */
+        HIPOK(hipDeviceSynchronize()); /* the workers' streams do not wait for it */
+        if (crum_server_submit(srv, 0, CRUM_REQ_RESTORE, 2, &id) != CRUM_OK ||
+            crum_server_submit(srv, 0, CRUM_REQ_SNAPSHOT, 3, &id) != CRUM_OK ||
+            crum_server_poll(srv, done, 2, &n_done, 1) != CRUM_OK || n_done != 2 ||
+            done[0].tag != 2 || done[0].code != CRUM_OK || done[1].tag != 3 ||
+            done[1].code != CRUM_OK || done[1].n_dirty != 0)
+            return fail("served restore, then snapshot", (long)done[1].n_dirty);
+        crum_server_destroy(srv);
+        HIPOK(hipMemcpy(h_back, scur, b0, hipMemcpyDeviceToHost));
+        if (memcmp(h_back, h_cur0, b0) != 0)
+            return fail("served restore repaired the page", 0);
+        HIPOK(hipFree(scur));
+        HIPOK(hipFree(ssh));
+    }
 
     crum_ctx_destroy(ctx);
     HIPOK(hipStreamDestroy(s));

@@ -2,8 +2,8 @@
 HIP runtime API compiles warning-free and links against libcrum.so (CPU), and
 on the GPU takes a snapshot, restores it with verification, runs a plan of two
 requests and persists an image with the writer, restores on demand, finds
-nothing dirty after a shadow update, and snapshots a tracked managed region
-with and without allocation (tests/c/abi_roundtrip.c)."""
+nothing dirty after a shadow update, snapshots a tracked managed region with
+and without allocation, and drives the serving loop (tests/c/abi_roundtrip.c)."""
 import os
 import subprocess
 
