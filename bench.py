@@ -679,7 +679,9 @@ def bench_batched(args) -> dict:
     # the grouped plan with its diff launches timed (each group's diff
     # kernel records the device wall clock at its start and end)
     crum.crum_ctx_set_timing(ctx, crum.TIMING_DIFF)
+    t_create = time.perf_counter()
     plan = make_plan()
+    create_ms = 1e3 * (time.perf_counter() - t_create)
     crum.crum_ctx_set_timing(ctx, 0)
     mk, lat_b, sts, n_groups = timed(plan)
     n_pd, pd_ms = crum.crum_ctx_timing(ctx, 0)
@@ -775,6 +777,7 @@ def bench_batched(args) -> dict:
         "batched": {"makespan_ms": round(mk_ms, 2),
                     "gbs": round(N / statistics.median(mk) / 1e9, 2),
                     "groups": n_groups,
+                    "plan_create_ms": round(create_ms, 1),
                     "makespans_ms": [round(1e3 * v, 1) for v in mk],
                     "latency_ms": {"p50": round(percentile(lat_b, 0.5), 2),
                                    "p90": round(percentile(lat_b, 0.9), 2),
