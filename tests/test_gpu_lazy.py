@@ -60,6 +60,7 @@ class Session:
         self.crum, self.P, self.regs = crum, P, regs
         self.targets = [to_dev(old) for _, old, _ in regs]
         self.shadows = [torch.zeros_like(t) for t in self.targets] if shadows else None
+        torch.cuda.synchronize()  # the session's stream does not wait for torch's
         table = [(t.data_ptr(), self.shadows[i].data_ptr() if shadows else 0, t.numel(), rid)
                  for i, (t, (_, _, rid)) in enumerate(zip(self.targets, regs))]
         self.img = img if image is None else image
