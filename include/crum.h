@@ -448,7 +448,10 @@ void crum_server_destroy(crum_server* server);
  * CRUM_PARAM_PACK_NT_STORE: 1 writes the image with non-temporal stores in
  *   the pack kernel (0).
  * CRUM_PARAM_PACK_PREFETCH: 1 makes each lane of the pack and verify kernels
- *   issue its next loads before folding the current ones into its CRC (0).
+ *   issue its next loads before folding the current ones into its CRC (0);
+ *   it applies with cached loads only (CRUM_PARAM_PACK_NT_LOAD 0).
+ * CRUM_PARAM_PACK_NT_LOAD: 1 reads the pages in the pack and verify kernels
+ *   with non-temporal loads, which are not kept in the caches (1).
  * Values of 0 are rejected (CRUM_EINVAL) except for the on/off switches,
  * the priority and the direct-order size. */
 enum {
@@ -468,7 +471,8 @@ enum {
     CRUM_PARAM_DIRECT_BYTES = 14,
     CRUM_PARAM_CHUNK_GROWTH = 15,
     CRUM_PARAM_PACK_NT_STORE = 16,
-    CRUM_PARAM_PACK_PREFETCH = 17
+    CRUM_PARAM_PACK_PREFETCH = 17,
+    CRUM_PARAM_PACK_NT_LOAD = 18
 };
 int crum_ctx_set_param(crum_ctx* ctx, int param, uint64_t value);
 int crum_ctx_get_param(crum_ctx* ctx, int param, uint64_t* value);

@@ -42,6 +42,7 @@ PARAMS = {
     "chunk_growth": C.CRUM_PARAM_CHUNK_GROWTH,
     "pack_nt_store": C.CRUM_PARAM_PACK_NT_STORE,
     "pack_prefetch": C.CRUM_PARAM_PACK_PREFETCH,
+    "pack_nt_load": C.CRUM_PARAM_PACK_NT_LOAD,
     "eager": C.CRUM_PARAM_EAGER,
 }
 

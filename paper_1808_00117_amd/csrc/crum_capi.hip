@@ -380,12 +380,14 @@ int set_param_raw(crum_ctx* c, int param, uint64_t v)
     if (!c)
         return CRUM_EINVAL;
     if (param == CRUM_PARAM_EAGER || param == CRUM_PARAM_DIFF_NONTEMPORAL ||
-        param == CRUM_PARAM_PACK_NT_STORE || param == CRUM_PARAM_PACK_PREFETCH) {
+        param == CRUM_PARAM_PACK_NT_STORE || param == CRUM_PARAM_PACK_PREFETCH ||
+        param == CRUM_PARAM_PACK_NT_LOAD) {
         if (v > 1)
             return CRUM_EINVAL;
         (param == CRUM_PARAM_EAGER                ? c->eager
          : param == CRUM_PARAM_DIFF_NONTEMPORAL ? c->diff_nt
          : param == CRUM_PARAM_PACK_NT_STORE    ? c->pack_nt
+         : param == CRUM_PARAM_PACK_NT_LOAD     ? c->pack_ntl
                                                 : c->pack_pf) = v != 0;
         return CRUM_OK;
     }
@@ -533,6 +535,7 @@ int crum_ctx_get_param(crum_ctx* c, int param, uint64_t* v)
     case CRUM_PARAM_CHUNK_GROWTH: *v = c->chunk_growth; return CRUM_OK;
     case CRUM_PARAM_PACK_NT_STORE: *v = c->pack_nt ? 1 : 0; return CRUM_OK;
     case CRUM_PARAM_PACK_PREFETCH: *v = c->pack_pf ? 1 : 0; return CRUM_OK;
+    case CRUM_PARAM_PACK_NT_LOAD: *v = c->pack_ntl ? 1 : 0; return CRUM_OK;
     default: return CRUM_EINVAL;
     }
 }

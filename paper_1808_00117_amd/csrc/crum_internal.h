@@ -153,6 +153,7 @@ struct crum_ctx {
     uint64_t direct_bytes = 0;  // opt-in: worst-case images up to this size go straight to the host
     uint32_t chunk_growth = 4;  // growth factor of pipelined chunks and plan groups
     bool pack_nt = false;       // non-temporal image stores in the pack
+    bool pack_ntl = true;       // pack/verify: non-temporal page loads
     bool pack_pf = false;       // pack/verify: next loads issued before folding the current
     // tuned shapes per workload class (crum_ctx_create's tuning cache), applied
     // to a call's parameters that crum_ctx_set_param has not set
@@ -209,7 +210,12 @@ inline void ctx_add_timing(crum_ctx* c, int cls, double ms)
 inline uint32_t ctx_chunk_growth(const crum_ctx* c) { return c->chunk_growth; }
 inline int ctx_pack_nt(const crum_ctx* c) { return c->pack_nt ? 1 : 0; }
 // launch_pack's flag bits: 1 non-temporal image stores, 2 prefetching loop
-inline int ctx_pack_flags(const crum_ctx* c) { return (c->pack_nt ? 1 : 0) | (c->pack_pf ? 2 : 0); }
+// bit 0: non-temporal image stores; bit 1: next loads issued early (cached
+// loads only); bit 2: non-temporal page loads
+inline int ctx_pack_flags(const crum_ctx* c)
+{
+    return (c->pack_nt ? 1 : 0) | (c->pack_pf ? 2 : 0) | (c->pack_ntl ? 4 : 0);
+}
 
 // Applies the context's tuned shapes for one call's workload class, for the
 // duration of the call (a context is used by one thread at a time), to the

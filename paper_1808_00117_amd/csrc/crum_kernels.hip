@@ -317,7 +317,15 @@ struct PieceSrc {
 // lds: the pack layout (kPackLdsWords); V: the CRC step variant.  STORE: 0
 // reads only (verify), 1 copies into dst, 2 copies with non-temporal stores
 // (the image is streamed out and not read again by the kernels).
-template <int STORE, int U, int V>
+template <int LD>
+__device__ __forceinline__ u32x4 piece_load(gcv4 p)
+{
+    if (LD)
+        return __builtin_nontemporal_load(p);
+    return *p;
+}
+
+template <int STORE, int U, int V, int LD = 0>
 __device__ __forceinline__ uint32_t piece_steps(const PieceSrc& src, gv4 __restrict__ dst,
                                                 gv4 __restrict__ sh, uint32_t* t_io,
                                                 uint32_t steps, uint32_t lane,
@@ -328,7 +336,7 @@ __device__ __forceinline__ uint32_t piece_steps(const PieceSrc& src, gv4 __restr
         u32x4 w[U];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            w[u] = src.at(t + u)[(t + u) * 64 + lane];
+            w[u] = piece_load<LD>(src.at(t + u) + (t + u) * 64 + lane);
         if (STORE) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -357,7 +365,7 @@ __device__ __forceinline__ uint32_t piece_steps(const PieceSrc& src, gv4 __restr
 // As piece_steps, with the loads of the next U steps issued before the
 // stores and CRC of the current ones, so a wave keeps page loads in flight
 // while it works through its LDS table lookups.
-template <int STORE, int U, int V>
+template <int STORE, int U, int V, int LD = 0>
 __device__ __forceinline__ uint32_t piece_steps_pf(const PieceSrc& src, gv4 __restrict__ dst,
                                                    gv4 __restrict__ sh, uint32_t* t_io,
                                                    uint32_t steps, uint32_t lane,
@@ -369,14 +377,14 @@ __device__ __forceinline__ uint32_t piece_steps_pf(const PieceSrc& src, gv4 __re
     u32x4 w[U];
 #pragma unroll
     for (int u = 0; u < U; ++u)
-        w[u] = src.at(t + u)[(t + u) * 64 + lane];
+        w[u] = piece_load<LD>(src.at(t + u) + (t + u) * 64 + lane);
     for (;;) {
         const bool more = t + 2 * U <= steps;
         u32x4 nx[U];
         if (more) {
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                nx[u] = src.at(t + U + u)[(t + U + u) * 64 + lane];
+                nx[u] = piece_load<LD>(src.at(t + U + u) + (t + U + u) * 64 + lane);
         }
         if (STORE) {
 #pragma unroll
@@ -413,7 +421,7 @@ __device__ __forceinline__ uint32_t piece_steps_pf(const PieceSrc& src, gv4 __re
 // before it folds them into its CRC; PF: the next DEPTH loads are issued
 // before the current ones are folded.  All lanes return the same value.
 // gz: z[0] of the shift tables in global memory (the butterfly's shifts).
-template <int STORE, int DEPTH, int V, bool PF>
+template <int STORE, int DEPTH, int V, bool PF, int LD = 0>
 __device__ __forceinline__ uint32_t wave_piece_crc(const PieceSrc& src, gv4 __restrict__ dst,
                                                    gv4 __restrict__ sh, uint32_t steps,
                                                    uint32_t lane,
@@ -423,12 +431,12 @@ __device__ __forceinline__ uint32_t wave_piece_crc(const PieceSrc& src, gv4 __re
     uint32_t s = 0;
     uint32_t t = 0;
     if (PF)
-        s = piece_steps_pf<STORE, DEPTH, V>(src, dst, sh, &t, steps, lane, lds, s);
+        s = piece_steps_pf<STORE, DEPTH, V, LD>(src, dst, sh, &t, steps, lane, lds, s);
     else
-        s = piece_steps<STORE, DEPTH, V>(src, dst, sh, &t, steps, lane, lds, s);
+        s = piece_steps<STORE, DEPTH, V, LD>(src, dst, sh, &t, steps, lane, lds, s);
     if (DEPTH > 4)
-        s = piece_steps<STORE, 4, V>(src, dst, sh, &t, steps, lane, lds, s);
-    s = piece_steps<STORE, 1, V>(src, dst, sh, &t, steps, lane, lds, s);
+        s = piece_steps<STORE, 4, V, LD>(src, dst, sh, &t, steps, lane, lds, s);
+    s = piece_steps<STORE, 1, V, LD>(src, dst, sh, &t, steps, lane, lds, s);
     return lane_combine_z(lds, gz, s, lane);
 }
 
@@ -883,7 +891,12 @@ __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs
             gv4 sh = ((R.flags & 1u) && R.shadow)
                             ? (gv4)(R.shadow + page_off + piece_off)
                             : nullptr;
-            if (nt_store & 2u)
+            if (nt_store & 4u)
+                raw = (nt_store & 1u) ? wave_piece_crc<2, DEPTH, V, false, 1>(
+                                            src, (gv4)slot_ptr, sh, steps, lane, lds, gz)
+                                      : wave_piece_crc<1, DEPTH, V, false, 1>(
+                                            src, (gv4)slot_ptr, sh, steps, lane, lds, gz);
+            else if (nt_store & 2u)
                 raw = (nt_store & 1u) ? wave_piece_crc<2, DEPTH, V, true>(
                                             src, (gv4)slot_ptr, sh, steps, lane, lds, gz)
                                       : wave_piece_crc<1, DEPTH, V, true>(
@@ -895,7 +908,10 @@ __global__ __launch_bounds__(256) void k_pack(const DevRegion* __restrict__ regs
                                             src, (gv4)slot_ptr, sh, steps, lane, lds, gz);
         } else {
             const PieceSrc src{(gcv4)slot_ptr, nullptr, ~0u, 0};
-            raw = (nt_store & 2u)
+            raw = (nt_store & 4u)
+                      ? wave_piece_crc<0, DEPTH, V, false, 1>(src, nullptr, nullptr, steps, lane,
+                                                              lds, gz)
+                  : (nt_store & 2u)
                       ? wave_piece_crc<0, DEPTH, V, true>(src, nullptr, nullptr, steps, lane, lds,
                                                           gz)
                       : wave_piece_crc<0, DEPTH, V, false>(src, nullptr, nullptr, steps, lane,
@@ -1001,7 +1017,7 @@ hipError_t launch_pack(int mode, const DevRegion* regs, uint32_t n_regs, const D
     else
         launch_pack_mode<kModeVerify>(grid, depth, variant, s, regs, n_regs, reqs, out, list,
                                       range, np_shift, piece_shift, nullptr, staging, crc_out,
-                                      partials, tabs, glob, (uint32_t)nt_store & 2u);
+                                      partials, tabs, glob, (uint32_t)nt_store & 6u);
     return hipGetLastError();
 }
 

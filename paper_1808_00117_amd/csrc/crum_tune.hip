@@ -199,6 +199,7 @@ int param_id(const std::string& name)
         {"chunk_growth", CRUM_PARAM_CHUNK_GROWTH},
         {"pack_nt_store", CRUM_PARAM_PACK_NT_STORE},
         {"pack_prefetch", CRUM_PARAM_PACK_PREFETCH},
+        {"pack_nt_load", CRUM_PARAM_PACK_NT_LOAD},
     };
     for (const auto& n : names)
         if (name == n.first)

@@ -570,20 +570,21 @@ def test_diff_variants(unit_shift, nt):
         s.close()
 
 
-@pytest.mark.parametrize("piece_shift,depth,crc_variant,nt,pf",
-                         [(12, 16, 1, 0, 0), (13, 4, 2, 0, 1), (14, 8, 3, 1, 0),
-                          (16, 16, 4, 0, 1), (16, 4, 5, 1, 1), (16, 8, 0, 0, 0),
-                          (16, 4, 6, 0, 0), (14, 4, 6, 1, 1), (14, 16, 0, 0, 1)])
-def test_pack_variants(piece_shift, depth, crc_variant, nt, pf):
-    """Every pack piece size, load depth, CRC step variant, store kind and
-    load order gives the oracle's image, and the restore (verify + scatter
-    over the same pieces) reproduces memory; a page corrupted in the image is
-    still rejected with its slot."""
+@pytest.mark.parametrize("piece_shift,depth,crc_variant,nt,pf,ntl",
+                         [(12, 16, 1, 0, 0, 1), (13, 4, 2, 0, 1, 0), (14, 8, 3, 1, 0, 1),
+                          (16, 16, 4, 0, 1, 0), (16, 4, 5, 1, 1, 0), (16, 8, 0, 0, 0, 0),
+                          (16, 4, 6, 0, 0, 1), (14, 4, 6, 1, 1, 0), (14, 16, 0, 0, 1, 0),
+                          (14, 8, 6, 1, 0, 1), (13, 16, 3, 0, 0, 1)])
+def test_pack_variants(piece_shift, depth, crc_variant, nt, pf, ntl):
+    """Every pack piece size, load depth, CRC step variant, store kind, load
+    kind and load order gives the oracle's image, and the restore (verify +
+    scatter over the same pieces) reproduces memory; a page corrupted in the
+    image is still rejected with its slot."""
     import torch
     import paper_1808_00117_amd as crum
     from paper_1808_00117_amd.api import Snapshotter
     log(f"[pack] piece_shift={piece_shift} depth={depth} crc_variant={crc_variant} "
-        f"nt_store={nt} prefetch={pf}")
+        f"nt_store={nt} prefetch={pf} nt_load={ntl}")
     s = Snapshotter(0)
     try:
         crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_PIECE_SHIFT, piece_shift)
@@ -591,6 +592,8 @@ def test_pack_variants(piece_shift, depth, crc_variant, nt, pf):
         crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_CRC_VARIANT, crc_variant)
         crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_PACK_NT_STORE, nt)
         crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_PACK_PREFETCH, pf)
+        crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_PACK_NT_LOAD, ntl)
+        assert crum.crum_ctx_get_param(s.ctx, crum.CRUM_PARAM_PACK_NT_LOAD) == ntl
         assert crum.crum_ctx_get_param(s.ctx, crum.CRUM_PARAM_CRC_VARIANT) == crc_variant
         crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_PACK_BLOCKS, 5)
         assert crum.crum_ctx_get_param(s.ctx, crum.CRUM_PARAM_PIECE_SHIFT) == piece_shift
