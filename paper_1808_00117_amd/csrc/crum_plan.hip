@@ -301,10 +301,13 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
         const uint64_t w1 = q1 < n_reqs ? dreq[q1].first_word : W;
         const uint64_t u0 = req_unit0[q0], u1 = req_unit0[q1];
         p->diff_units.push_back(u1 - u0);
-        uint32_t hdr_blocks = 1;
-        for (uint32_t q = q0; q < q1; ++q)
+        uint32_t hdr_blocks = 1, min_us = 64;
+        for (uint32_t q = q0; q < q1; ++q) {
             hdr_blocks = std::max(hdr_blocks, header_blocks(dreq[q].n_regions, dreq[q].n_words,
                                                             dreq[q].n_pages));
+            if (dreq[q].n_regions)
+                min_us = std::min(min_us, dregs[dreq[q].first_region].unit_shift);
+        }
         hipStream_t s = p->cap_stream;
         if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return fail(CRUM_EHIP);
@@ -314,7 +317,8 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
         if (e == hipSuccess)
             e = launch_diff(d_regs, p->n_regs, u0, u1, d_flags, shape.diff_blocks,
                             ctx_diff_nt(c), ctx_diff_prio(c), s, nullptr,
-                            p->d_stamp ? p->d_stamp + 2 * gi : nullptr);
+                            p->d_stamp ? p->d_stamp + 2 * gi : nullptr,
+                            ctx_diff_quad(c, min_us, u1 - u0));
         if (e == hipSuccess)
             e = launch_bitmap(d_regs, p->n_regs, w0, w1, d_flags, d_bitmap, s);
         if (e == hipSuccess)
