@@ -50,7 +50,7 @@ def parse_args():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="headline",
                     choices=["headline", "many", "plain", "batched", "served", "managed",
-                             "persist", "lazy"],
+                             "persist", "lazy", "diff_sizes"],
                     help="headline (default): the batched 256-request workload, batched vs "
                          "plain, then the 16 GiB many-allocations snapshot beside its "
                          "co-runner (diff roofline, drain, pack, restore) and the CPU oracle")
@@ -1198,6 +1198,70 @@ def bench_persist(args):
     print(json.dumps(result), flush=True)
 
 
+def bench_diff_sizes(args):
+    """The diff kernel alone by launch size, page size and units per wave:
+    one 8 GiB region pair (current and shadow, equal, so nothing is dirty),
+    snapshotted in the diff-first order (one diff launch per snapshot) over
+    its first 256 MiB, 1, 2 and 4 GiB and the whole 8 GiB, with 4 KiB and
+    64 KiB pages, CRUM_PARAM_DIFF_QUAD 0 and 1 (four units per wave; with
+    64 KiB pages the units are 16 KiB and the mode changes only the grouping).
+    A 5 s pause after the allocation lets the copy engines and HBM settle.
+    One JSON line per case: event-timed average launch and the HBM rate of
+    its algorithmic bytes (2 x span + one flag byte per unit)."""
+    import paper_1808_00117_amd as crum
+    import paper_1808_00117_amd.hip as H
+    import synth
+
+    N = 8 << 30
+    cur, sh = H.DeviceBuffer(N), H.DeviceBuffer(N)
+    synth.fill_dev(cur.ptr, N, args.seed_base + 11, 0, 0, 0)
+    H.memcpy_dtod(sh.ptr, cur.ptr, N)
+    H.device_synchronize()
+    time.sleep(5)
+    s = H.Stream()
+    status = H.PinnedBuffer(64)
+    reps = max(3, args.steps // 4)
+    try:
+        for span in (256 << 20, 1 << 30, 2 << 30, 4 << 30, N):
+            table = crum.region_table([(cur.ptr, sh.ptr, span, 1)])
+            for P in (4096, 65536):
+                cap = crum.crum_image_prefix_bytes(1, span // P) + 4096
+                staging = H.DeviceBuffer(cap)
+                for quad in (0, 1):
+                    ctx = crum.crum_ctx_create(0)
+                    try:
+                        crum.crum_ctx_set_param(ctx, crum.CRUM_PARAM_EAGER, 0)
+                        crum.crum_ctx_set_param(ctx, crum.CRUM_PARAM_DIFF_QUAD, quad)
+
+                        def snap():
+                            rc = crum.crum_snapshot(ctx, table, P, 0, 1, staging.ptr, cap, 0, 0,
+                                                    s.handle, status.ptr)
+                            s.synchronize()
+                            st = crum.read_status(status.ptr)
+                            if rc != 0 or st.code != 0 or st.n_dirty != 0:
+                                raise RuntimeError(f"diff_sizes: rc {rc}, {st}")
+                        for _ in range(3):
+                            snap()
+                        crum.crum_ctx_timing_reset(ctx)
+                        crum.crum_ctx_set_timing(ctx, crum.TIMING_DIFF)
+                        for _ in range(reps):
+                            snap()
+                        n, ms = crum.crum_ctx_timing(ctx, 0)
+                    finally:
+                        crum.crum_ctx_destroy(ctx)
+                    unit = min(P, 1 << 14)
+                    gbs = (2 * span + span // unit) * n / (ms * 1e-3) / 1e9
+                    print(json.dumps({"config": "diff_sizes", "span_bytes": span, "page": P,
+                                      "unit": unit, "diff_quad": quad, "launches": n,
+                                      "avg_launch_ms": round(ms / n, 4),
+                                      "achieved_gbs": round(gbs, 1),
+                                      "frac": round(gbs / 8000, 4)}), flush=True)
+                staging.free()
+    finally:
+        cur.free()
+        sh.free()
+
+
 def bench_lazy(args):
     """On-demand restore of the 16 GiB many-allocations image (section 4.2's
     read-fault readahead, with touches announced by the caller) against the
@@ -1677,6 +1741,8 @@ def main():
         return bench_persist(args)
     if args.config == "lazy":
         return bench_lazy(args)
+    if args.config == "diff_sizes":
+        return bench_diff_sizes(args)
     print(json.dumps(bench_many(args)), flush=True)
 
 
