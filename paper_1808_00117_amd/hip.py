@@ -69,7 +69,12 @@ def hip():
 
 
 def check(rc: int, what: str) -> None:
+    """Raise on a failed HIP call.  HIP also keeps the failure as the calling
+    thread's last error, which the next launch check (hipGetLastError, as in
+    libcrum's kernel launchers) would report as its own; a caller that goes on
+    after catching this error must not see it there, so it is cleared here."""
     if rc != 0:
+        hip().hipGetLastError()
         raise RuntimeError(f"{what} failed with hipError {rc}")
 
 
