@@ -1202,9 +1202,9 @@ def bench_diff_sizes(args):
     """The diff kernel alone by launch size, page size and units per wave:
     one 8 GiB region pair (current and shadow, equal, so nothing is dirty),
     snapshotted in the diff-first order (one diff launch per snapshot) over
-    its first 256 MiB, 1, 2 and 4 GiB and the whole 8 GiB, with 4 KiB and
-    64 KiB pages, CRUM_PARAM_DIFF_QUAD 0 and 1 (four units per wave; with
-    64 KiB pages the units are 16 KiB and the mode changes only the grouping).
+    its first 64 and 256 MiB, 1, 2 and 4 GiB and the whole 8 GiB, with 4 KiB and
+    64 KiB pages, CRUM_PARAM_DIFF_GROUP 1, 2 and 4 (4 KiB units per wave; with
+    64 KiB pages the units are 16 KiB and one per wave whatever the group).
     A 5 s pause after the allocation lets the copy engines and HBM settle.
     One JSON line per case: event-timed average launch and the HBM rate of
     its algorithmic bytes (2 x span + one flag byte per unit)."""
@@ -1222,16 +1222,16 @@ def bench_diff_sizes(args):
     status = H.PinnedBuffer(64)
     reps = max(3, args.steps // 4)
     try:
-        for span in (256 << 20, 1 << 30, 2 << 30, 4 << 30, N):
+        for span in (64 << 20, 256 << 20, 1 << 30, 2 << 30, 4 << 30, N):
             table = crum.region_table([(cur.ptr, sh.ptr, span, 1)])
             for P in (4096, 65536):
                 cap = crum.crum_image_prefix_bytes(1, span // P) + 4096
                 staging = H.DeviceBuffer(cap)
-                for quad in (0, 1):
+                for group in ((1, 2, 4) if P == 4096 else (1,)):
                     ctx = crum.crum_ctx_create(0)
                     try:
                         crum.crum_ctx_set_param(ctx, crum.CRUM_PARAM_EAGER, 0)
-                        crum.crum_ctx_set_param(ctx, crum.CRUM_PARAM_DIFF_QUAD, quad)
+                        crum.crum_ctx_set_param(ctx, crum.CRUM_PARAM_DIFF_GROUP, group)
 
                         def snap():
                             rc = crum.crum_snapshot(ctx, table, P, 0, 1, staging.ptr, cap, 0, 0,
@@ -1252,7 +1252,7 @@ def bench_diff_sizes(args):
                     unit = min(P, 1 << 14)
                     gbs = (2 * span + span // unit) * n / (ms * 1e-3) / 1e9
                     print(json.dumps({"config": "diff_sizes", "span_bytes": span, "page": P,
-                                      "unit": unit, "diff_quad": quad, "launches": n,
+                                      "unit": unit, "diff_group": group, "launches": n,
                                       "avg_launch_ms": round(ms / n, 4),
                                       "achieved_gbs": round(gbs, 1),
                                       "frac": round(gbs / 8000, 4)}), flush=True)

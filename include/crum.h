@@ -82,7 +82,9 @@ enum {
     CRUM_ENOSPC = -2,    /* image larger than the staging or host capacity */
     CRUM_ECRC = -3,      /* a packed page failed CRC verification */
     CRUM_EFORMAT = -4,   /* image header, table, bitmap, pads or checksums invalid */
-    CRUM_EHIP = -5,      /* a HIP runtime call failed */
+    CRUM_EHIP = -5,      /* a HIP runtime call failed (kernel launches are checked with
+                            hipGetLastError, so a failure of the caller's own that is
+                            still pending in the calling thread shows here too) */
     CRUM_EMISMATCH = -6  /* restore table differs from the image (count, len, id) */
 };
 
@@ -452,16 +454,12 @@ void crum_server_destroy(crum_server* server);
  *   it applies with cached loads only (CRUM_PARAM_PACK_NT_LOAD 0).
  * CRUM_PARAM_PACK_NT_LOAD: 1 reads the pages in the pack and verify kernels
  *   with non-temporal loads, which are not kept in the caches (1).
- * CRUM_PARAM_DIFF_QUAD: 1 gives each wave of the diff kernel four consecutive
- *   diff units, so that four 4 KiB units of one region are read as one 16 KiB
- *   span with as many loads in flight as a 16 KiB unit; 0 gives each wave one
- *   unit; 2 takes 1 for a diff launch of at least 2^18 units whose smallest
- *   unit is 4 KiB (1 GiB of 4 KiB pages) and 0 otherwise; values above 2 are
- *   rejected (0).  Four units per wave lifted 8 GiB launches of 4 KiB units
- *   from 0.76 to 0.835 of HBM peak on devices where one unit per wave stays
- *   near 0.76, and cost 4-7 % at 1-8 GiB on devices where it reaches 0.86.
+ * CRUM_PARAM_DIFF_GROUP: 4 KiB diff units per wave of the diff kernel, 1, 2
+ *   or 4, for launches whose smallest unit is 4 KiB: 2 or 4 units of one
+ *   region are read as one span with 8 or 16 loads per array in flight per
+ *   lane (16 KiB units always have 16); other values are rejected (2).
  * Values of 0 are rejected (CRUM_EINVAL) except for the on/off switches,
- * the diff quad mode, the priority and the direct-order size. */
+ * the priority and the direct-order size. */
 enum {
     CRUM_PARAM_DIFF_BLOCKS = 1,
     CRUM_PARAM_PACK_BLOCKS = 2,
@@ -481,7 +479,7 @@ enum {
     CRUM_PARAM_PACK_NT_STORE = 16,
     CRUM_PARAM_PACK_PREFETCH = 17,
     CRUM_PARAM_PACK_NT_LOAD = 18,
-    CRUM_PARAM_DIFF_QUAD = 19
+    CRUM_PARAM_DIFF_GROUP = 19
 };
 int crum_ctx_set_param(crum_ctx* ctx, int param, uint64_t value);
 int crum_ctx_get_param(crum_ctx* ctx, int param, uint64_t* value);

@@ -29,7 +29,7 @@ CRUM_PARAM_PIECE_SHIFT, CRUM_PARAM_PACK_DEPTH, CRUM_PARAM_DIFF_PRIORITY = 9, 10,
 CRUM_PARAM_CRC_VARIANT, CRUM_PARAM_PLAN_ORDER = 12, 13
 CRUM_PARAM_DIRECT_BYTES = 14
 CRUM_PARAM_CHUNK_GROWTH, CRUM_PARAM_PACK_NT_STORE, CRUM_PARAM_PACK_PREFETCH = 15, 16, 17
-CRUM_PARAM_PACK_NT_LOAD, CRUM_PARAM_DIFF_QUAD = 18, 19
+CRUM_PARAM_PACK_NT_LOAD, CRUM_PARAM_DIFF_GROUP = 18, 19
 
 CODE_NAMES = {0: "CRUM_OK", -1: "CRUM_EINVAL", -2: "CRUM_ENOSPC", -3: "CRUM_ECRC",
               -4: "CRUM_EFORMAT", -5: "CRUM_EHIP", -6: "CRUM_EMISMATCH", -7: "CRUM_EIO",

@@ -43,7 +43,7 @@ PARAMS = {
     "pack_nt_store": C.CRUM_PARAM_PACK_NT_STORE,
     "pack_prefetch": C.CRUM_PARAM_PACK_PREFETCH,
     "pack_nt_load": C.CRUM_PARAM_PACK_NT_LOAD,
-    "diff_quad": C.CRUM_PARAM_DIFF_QUAD,
+    "diff_group": C.CRUM_PARAM_DIFF_GROUP,
     "eager": C.CRUM_PARAM_EAGER,
 }
 

@@ -391,10 +391,10 @@ int set_param_raw(crum_ctx* c, int param, uint64_t v)
                                                 : c->pack_pf) = v != 0;
         return CRUM_OK;
     }
-    if (param == CRUM_PARAM_DIFF_QUAD) {
-        if (v > 2)
+    if (param == CRUM_PARAM_DIFF_GROUP) {
+        if (v != 1 && v != 2 && v != 4)
             return CRUM_EINVAL;
-        c->diff_quad = (uint8_t)v;
+        c->diff_group = (uint8_t)v;
         return CRUM_OK;
     }
     if (param == CRUM_PARAM_CHUNK_GROWTH) {
@@ -542,7 +542,7 @@ int crum_ctx_get_param(crum_ctx* c, int param, uint64_t* v)
     case CRUM_PARAM_PACK_NT_STORE: *v = c->pack_nt ? 1 : 0; return CRUM_OK;
     case CRUM_PARAM_PACK_PREFETCH: *v = c->pack_pf ? 1 : 0; return CRUM_OK;
     case CRUM_PARAM_PACK_NT_LOAD: *v = c->pack_ntl ? 1 : 0; return CRUM_OK;
-    case CRUM_PARAM_DIFF_QUAD: *v = c->diff_quad; return CRUM_OK;
+    case CRUM_PARAM_DIFF_GROUP: *v = c->diff_group; return CRUM_OK;
     default: return CRUM_EINVAL;
     }
 }
@@ -733,7 +733,7 @@ static int snapshot_impl(crum_ctx* c, const crum_region* regions, uint32_t n_reg
             Span sp(c, kTDiff, stream);
             CRUM_TRY(launch_diff(d_regs, n_regions, 0, n_units, d_flags, c->shape.diff_blocks,
                                  c->diff_nt, c->diff_prio, stream, d_cand, nullptr,
-                                 ctx_diff_quad(c, us, n_units)));
+                                 ctx_diff_group(c, us)));
         }
         {
             Span sp(c, kTScan, stream);
@@ -776,7 +776,7 @@ static int snapshot_impl(crum_ctx* c, const crum_region* regions, uint32_t n_reg
                 CRUM_TRY(launch_diff(d_regs, n_regions, g0 << (ps - us), g1 << (ps - us), d_flags,
                                      c->shape.diff_blocks, c->diff_nt, c->diff_prio, stream,
                                      d_cand, nullptr,
-                                     ctx_diff_quad(c, us, (g1 - g0) << (ps - us))));
+                                     ctx_diff_group(c, us)));
             }
             {
                 Span sp(c, kTScan, stream);
@@ -833,7 +833,7 @@ static int snapshot_impl(crum_ctx* c, const crum_region* regions, uint32_t n_reg
             Span sp(c, kTDiff, stream);
             CRUM_TRY(launch_diff(d_regs, n_regions, 0, n_units, d_flags, c->shape.diff_blocks,
                                  c->diff_nt, c->diff_prio, stream, d_cand, nullptr,
-                                 ctx_diff_quad(c, us, n_units)));
+                                 ctx_diff_group(c, us)));
         }
         {
             Span sp(c, kTScan, stream);

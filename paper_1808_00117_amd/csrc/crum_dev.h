@@ -124,12 +124,12 @@ void build_crc_tables(CrcTables* host);
 // stamp (may be null): two words, the wall clock at the launch's start and
 // the latest end of its workgroups (stamp[1] must start below any clock
 // value, e.g. zeroed once).
-// quad != 0: each wave takes four consecutive units (four 4 KiB units of a
-// region as one 16 KiB span).
+// group 2 or 4: each wave takes that many consecutive units (as many 4 KiB
+// units of a region read as one span); other values: one unit per wave.
 hipError_t launch_diff(const DevRegion* regs, uint32_t n_regs, uint64_t u0, uint64_t u1,
                        uint8_t* unit_flags, int blocks, int nontemporal, int prio,
                        hipStream_t s, const uint64_t* cand = nullptr,
-                       uint64_t* stamp = nullptr, int quad = 0);
+                       uint64_t* stamp = nullptr, int group = 1);
 hipError_t launch_bitmap(const DevRegion* regs, uint32_t n_regs, uint64_t w0, uint64_t w1,
                          const uint8_t* unit_flags, uint64_t* bitmap, hipStream_t s);
 // Scans words [w0, w1) continuing glob->running; writes the new running total

@@ -154,7 +154,7 @@ struct crum_ctx {
     uint32_t chunk_growth = 4;  // growth factor of pipelined chunks and plan groups
     bool pack_nt = false;       // non-temporal image stores in the pack
     bool pack_ntl = true;       // pack/verify: non-temporal page loads
-    uint8_t diff_quad = 0;      // diff: four units per wave (0 off, 1 on, 2 large 4 KiB launches)
+    uint8_t diff_group = 2;     // diff: 4 KiB units per wave (1, 2 or 4)
     bool pack_pf = false;       // pack/verify: next loads issued before folding the current
     // tuned shapes per workload class (crum_ctx_create's tuning cache), applied
     // to a call's parameters that crum_ctx_set_param has not set
@@ -213,14 +213,11 @@ inline int ctx_pack_nt(const crum_ctx* c) { return c->pack_nt ? 1 : 0; }
 // launch_pack's flag bits: 1 non-temporal image stores, 2 prefetching loop
 // bit 0: non-temporal image stores; bit 1: next loads issued early (cached
 // loads only); bit 2: non-temporal page loads
-// Four units per wave for a diff launch over n_units units whose smallest
-// unit is 1 << min_us bytes: always (mode 1), or for launches of at least
-// 2^18 units of 4 KiB (1 GiB; mode 2).
-inline int ctx_diff_quad(const crum_ctx* c, uint32_t min_us, uint64_t n_units)
+// Units per wave of a diff launch whose smallest unit is 1 << min_us bytes:
+// the context's group for 4 KiB units, else one.
+inline int ctx_diff_group(const crum_ctx* c, uint32_t min_us)
 {
-    return c->diff_quad == 1 || (c->diff_quad == 2 && min_us == 12 && n_units >= (1ull << 18))
-               ? 1
-               : 0;
+    return min_us == 12 ? c->diff_group : 1;
 }
 inline int ctx_pack_flags(const crum_ctx* c)
 {

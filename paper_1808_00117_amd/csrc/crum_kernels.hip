@@ -486,16 +486,15 @@ __device__ __forceinline__ uint32_t xor_or(gcv4 __restrict__ a, gcv4 __restrict_
     return x.x | x.y | x.z | x.w;
 }
 
-// Four consecutive 4 KiB units read as one 16 KiB span: 16 loads per array
-// in flight per lane (as for one 16 KiB unit), x[k] = OR of (a ^ b) over
-// unit k's four loads.
-template <bool NT>
-__device__ __forceinline__ void xor_or_quad(gcv4 __restrict__ a, gcv4 __restrict__ b,
-                                            uint32_t* x)
+// G consecutive 4 KiB units read as one span of G * 4 KiB: 4G loads per
+// array in flight per lane, x[k] = OR of (a ^ b) over unit k's four loads.
+template <int G, bool NT>
+__device__ __forceinline__ void xor_or_group(gcv4 __restrict__ a, gcv4 __restrict__ b,
+                                             uint32_t* x)
 {
-    u32x4 va[16], vb[16];
+    u32x4 va[4 * G], vb[4 * G];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
+    for (int j = 0; j < 4 * G; ++j) {
         if (NT) {
             va[j] = __builtin_nontemporal_load(a + j * 64);
             vb[j] = __builtin_nontemporal_load(b + j * 64);
@@ -505,7 +504,7 @@ __device__ __forceinline__ void xor_or_quad(gcv4 __restrict__ a, gcv4 __restrict
         }
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < G; ++k) {
         u32x4 o = va[4 * k] ^ vb[4 * k];
 #pragma unroll
         for (int j = 1; j < 4; ++j)
@@ -550,11 +549,11 @@ __device__ __forceinline__ void diff_unit(const DevRegion* __restrict__ regs, ui
 }
 
 // Diff of global units [u0, u1); unit_flags[u] = 1 when any byte of the unit
-// differs from the shadow (or the region has none).  QUAD false: one wave per
-// unit.  QUAD true: one wave per four consecutive units (from u0); four 4 KiB
+// differs from the shadow (or the region has none).  G = 1: one wave per
+// unit.  G = 2 or 4: one wave per G consecutive units (from u0); G 4 KiB
 // units of one region with a shadow, all candidates when a candidate set is
-// given, are read as one 16 KiB span, so a wave keeps as many loads in flight
-// as for a 16 KiB unit; other groups of four are done one unit at a time.
+// given, are read as one span of G * 4 KiB, so a wave keeps 4G loads per
+// array in flight; other groups are done one unit at a time.
 // prio 1..3 raises the waves' issue priority on their compute unit above
 // that of co-running kernels' waves (0 leaves it at the default).
 // cand (may be null): a bitmap over global pages from host write tracking;
@@ -564,7 +563,7 @@ __device__ __forceinline__ void diff_unit(const DevRegion* __restrict__ regs, ui
 // workgroup 0 starts (the first one dispatched), stamp[1] the largest clock
 // at which a workgroup ends.  stamp[1] needs no reset between launches: a
 // later launch's clocks exceed every earlier one's.
-template <bool NT, bool QUAD>
+template <bool NT, int G>
 __global__ __launch_bounds__(256) void k_diff(const DevRegion* __restrict__ regs,
                                               uint32_t n_regs, uint64_t u0, uint64_t u1,
                                               uint8_t* __restrict__ unit_flags, uint32_t prio,
@@ -585,19 +584,19 @@ __global__ __launch_bounds__(256) void k_diff(const DevRegion* __restrict__ regs
     const uint64_t n_waves = (uint64_t)gridDim.x * 4;
     uint32_t r = 0;
     uint64_t r_lo = 1, r_hi = 0;
-    if (!QUAD) {
+    if (G == 1) {
         for (uint64_t u = u0 + wave; u < u1; u += n_waves)
             diff_unit<NT>(regs, n_regs, u, unit_flags, cand, lane, r, r_lo, r_hi);
     } else {
-        for (uint64_t base = u0 + 4 * wave; base < u1; base += 4 * n_waves) {
-            const uint64_t end = base + 4 < u1 ? base + 4 : u1;
+        for (uint64_t base = u0 + G * wave; base < u1; base += G * n_waves) {
+            const uint64_t end = base + G < u1 ? base + G : u1;
             if (base < r_lo || base >= r_hi) {
                 r = find_region<4>(regs, n_regs, base);
                 r_lo = regs[r].first_unit;
                 r_hi = r_lo + (regs[r].len >> regs[r].unit_shift);
             }
             const DevRegion& R = regs[r];
-            bool fused = end == base + 4 && base + 4 <= r_hi && R.unit_shift == 12 &&
+            bool fused = end == base + G && base + G <= r_hi && R.unit_shift == 12 &&
                          R.shadow != nullptr;
             if (fused && cand) {
                 const uint32_t sh = R.page_shift - 12;
@@ -608,10 +607,11 @@ __global__ __launch_bounds__(256) void k_diff(const DevRegion* __restrict__ regs
             }
             if (fused) {
                 const uint64_t off = (base - R.first_unit) << 12;
-                uint32_t x[4];
-                xor_or_quad<NT>((gcv4)(R.cur + off) + lane, (gcv4)(R.shadow + off) + lane, x);
+                uint32_t x[G];
+                xor_or_group<G, NT>((gcv4)(R.cur + off) + lane, (gcv4)(R.shadow + off) + lane,
+                                    x);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
+                for (int k = 0; k < G; ++k) {
                     const uint64_t m = __ballot(x[k] != 0);
                     if (lane == 0)
                         unit_flags[base + k] = m != 0;
@@ -632,26 +632,31 @@ __global__ __launch_bounds__(256) void k_diff(const DevRegion* __restrict__ regs
 
 hipError_t launch_diff(const DevRegion* regs, uint32_t n_regs, uint64_t u0, uint64_t u1,
                        uint8_t* unit_flags, int blocks, int nontemporal, int prio,
-                       hipStream_t s, const uint64_t* cand, uint64_t* stamp, int quad)
+                       hipStream_t s, const uint64_t* cand, uint64_t* stamp, int group)
 {
     if (u1 <= u0)
         return hipSuccess;
-    const uint64_t per_wave = quad ? 4 : 1;
-    const uint64_t need = ((u1 - u0 + per_wave - 1) / per_wave + 3) / 4;
+    if (group != 2 && group != 4)
+        group = 1;
+    const uint64_t need = ((u1 - u0 + group - 1) / group + 3) / 4;
     const uint64_t nb = need < (uint64_t)blocks ? need : (uint64_t)blocks;
-#define CRUM_DIFF(NTV, QV)                                                                   \
-    hipLaunchKernelGGL((k_diff<NTV, QV>), dim3((unsigned)nb), dim3(256), 0, s, regs, n_regs, \
+#define CRUM_DIFF(NTV, GV)                                                                   \
+    hipLaunchKernelGGL((k_diff<NTV, GV>), dim3((unsigned)nb), dim3(256), 0, s, regs, n_regs, \
                        u0, u1, unit_flags, (uint32_t)prio, cand, stamp)
     if (nontemporal) {
-        if (quad)
-            CRUM_DIFF(true, true);
+        if (group == 4)
+            CRUM_DIFF(true, 4);
+        else if (group == 2)
+            CRUM_DIFF(true, 2);
         else
-            CRUM_DIFF(true, false);
+            CRUM_DIFF(true, 1);
     } else {
-        if (quad)
-            CRUM_DIFF(false, true);
+        if (group == 4)
+            CRUM_DIFF(false, 4);
+        else if (group == 2)
+            CRUM_DIFF(false, 2);
         else
-            CRUM_DIFF(false, false);
+            CRUM_DIFF(false, 1);
     }
 #undef CRUM_DIFF
     return hipGetLastError();

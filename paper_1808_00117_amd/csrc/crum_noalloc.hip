@@ -226,7 +226,7 @@ int crum_snapshot_noalloc(crum_ctx* c, const crum_region* regions, uint32_t n_re
     CRUM_TRY_C(hipEventRecord(c->ev_upload, stream));
     CRUM_TRY_C(launch_diff(d_regs, n_regions, 0, n_units, d_flags, c->shape.diff_blocks,
                            c->diff_nt, c->diff_prio, stream, nullptr, nullptr,
-                           ctx_diff_quad(c, us, n_units)));
+                           ctx_diff_group(c, us)));
     CRUM_TRY_C(launch_bitmap(d_regs, n_regions, 0, W, d_flags, d_bitmap, stream));
     CRUM_TRY_C(launch_scan(d_bitmap, 0, W, W, d_prefix, d_bounds, 1, d_reqs, 0, 1, d_out, d_glob,
                            capacity, 0, nullptr, stream));

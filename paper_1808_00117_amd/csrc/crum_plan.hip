@@ -318,7 +318,7 @@ int crum_plan_create(crum_ctx* c, const crum_request* reqs, uint32_t n_reqs, voi
             e = launch_diff(d_regs, p->n_regs, u0, u1, d_flags, shape.diff_blocks,
                             ctx_diff_nt(c), ctx_diff_prio(c), s, nullptr,
                             p->d_stamp ? p->d_stamp + 2 * gi : nullptr,
-                            ctx_diff_quad(c, min_us, u1 - u0));
+                            ctx_diff_group(c, min_us));
         if (e == hipSuccess)
             e = launch_bitmap(d_regs, p->n_regs, w0, w1, d_flags, d_bitmap, s);
         if (e == hipSuccess)

@@ -200,7 +200,7 @@ int param_id(const std::string& name)
         {"pack_nt_store", CRUM_PARAM_PACK_NT_STORE},
         {"pack_prefetch", CRUM_PARAM_PACK_PREFETCH},
         {"pack_nt_load", CRUM_PARAM_PACK_NT_LOAD},
-        {"diff_quad", CRUM_PARAM_DIFF_QUAD},
+        {"diff_group", CRUM_PARAM_DIFF_GROUP},
     };
     for (const auto& n : names)
         if (name == n.first)

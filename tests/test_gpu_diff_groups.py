@@ -1,10 +1,10 @@
-"""GPU parity of the diff kernel's four-units-per-wave mode at the size where
-the default takes it (launches of at least 2^18 units of 4 KiB): two regions
-of 1 GiB and 1 GiB + 12 KiB with 4 KiB pages (the second ends in a group of
-three units, done one at a time), dirty pages planted at region starts and
-ends and inside, snapshotted in the pipelined order (staging for the worst
-case: chunk launches below and above the size) and in the diff-first order,
-with the mode off, on and at its default; every image equals the oracle's."""
+"""GPU parity of the diff kernel with 1, 2 and 4 units of 4 KiB per wave at
+full size: two regions of 1 GiB and 1 GiB + 12 KiB with 4 KiB pages (the
+second ends in a group of three units, done one at a time by groups of two
+or four), dirty pages planted at region starts and ends and inside,
+snapshotted in the pipelined order (staging for the worst case: chunk
+launches of 128 MiB to 1.4 GiB) and in the diff-first order; every image
+equals the oracle's."""
 import numpy as np
 import pytest
 
@@ -17,7 +17,7 @@ KiB, GiB = 1 << 10, 1 << 30
 P = 4 * KiB
 
 
-def test_quad_mode_full_size():
+def test_diff_groups_full_size():
     import torch
 
     import paper_1808_00117_amd as crum
@@ -49,9 +49,9 @@ def test_quad_mode_full_size():
         h = torch.empty(worst, dtype=torch.uint8, pin_memory=True)
         for cap in (worst, st_o.image_bytes):
             staging = torch.empty(cap, dtype=torch.uint8, device="cuda")
-            for quad in (0, 1, 2):
-                log(f"[quad] cap={cap} quad={quad}")
-                crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_DIFF_QUAD, quad)
+            for group in (1, 2, 4):
+                log(f"[diff group] cap={cap} group={group}")
+                crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_DIFF_GROUP, group)
                 rc = crum.crum_snapshot(s.ctx, regions_of(dev), P, 0, 9, staging.data_ptr(),
                                         cap, h.data_ptr(), worst,
                                         torch.cuda.current_stream().cuda_stream,
@@ -61,7 +61,7 @@ def test_quad_mode_full_size():
                 st = s.status()
                 assert st.code == 0 and st.n_dirty == st_o.n_dirty, st
                 assert st.image_bytes == st_o.image_bytes
-                assert np.array_equal(h[: st.image_bytes].numpy(), img_o), (cap, quad)
+                assert np.array_equal(h[: st.image_bytes].numpy(), img_o), (cap, group)
             del staging
     finally:
         s.close()

@@ -551,10 +551,10 @@ def test_param_api(snap):
 
 @pytest.mark.parametrize("unit_shift", [12, 13, 14])
 @pytest.mark.parametrize("nt", [0, 1])
-@pytest.mark.parametrize("quad", [0, 1])
-def test_diff_variants(unit_shift, nt, quad):
-    """Every diff unit size, load kind and units-per-wave mode gives the
-    oracle's image (regions of 37 and 9 pages leave groups of four units that
+@pytest.mark.parametrize("group", [1, 2, 4])
+def test_diff_variants(unit_shift, nt, group):
+    """Every diff unit size, load kind and number of units per wave gives the
+    oracle's image (regions of 37 and 9 pages leave groups of units that
     straddle two regions)."""
     import paper_1808_00117_amd as crum
     from paper_1808_00117_amd.api import Snapshotter
@@ -563,7 +563,7 @@ def test_diff_variants(unit_shift, nt, quad):
         crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_DIFF_UNIT_SHIFT, unit_shift)
         crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_DIFF_NONTEMPORAL, nt)
         crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_DIFF_BLOCKS, 7)
-        crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_DIFF_QUAD, quad)
+        crum.crum_ctx_set_param(s.ctx, crum.CRUM_PARAM_DIFF_GROUP, group)
         for P, counts in [(4 * KiB, (37, 70)), (8 * KiB, (9, 60)), (32 * KiB, (13, 5)),
                           (64 * KiB, (6,))]:
             G = sum(counts)

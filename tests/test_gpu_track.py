@@ -76,22 +76,22 @@ def test_candidate_supersets_give_the_oracle_image(ctx, seed):
     W = (G + 63) // 64
     extra = set(int(x) for x in rng.choice(G, size=G // 4, replace=False))
     import paper_1808_00117_amd as crum
-    q0 = crum.crum_ctx_get_param(ctx.ctx, crum.CRUM_PARAM_DIFF_QUAD)
+    q0 = crum.crum_ctx_get_param(ctx.ctx, crum.CRUM_PARAM_DIFF_GROUP)
     try:
-        for quad in (0, 1):
-            crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_DIFF_QUAD, quad)
+        for group in (1, 2, 4):
+            crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_DIFF_GROUP, group)
             for name, pages in (("exact", dirty), ("superset", dirty | extra),
                                 ("all", range(G))):
                 cand = np.zeros(W + int(rng.integers(0, 3)), np.uint64)
                 set_bits(cand, pages)
                 for cap in (image_capacity(dev, P), st_o.image_bytes):
                     log(f"[track] seed {seed} P={P} G={G} D={st_o.n_dirty} {name} "
-                        f"cap={cap} quad={quad}")
+                        f"cap={cap} group={group}")
                     st, img = tracked(ctx, dev, P, cand, cap)
                     assert st.n_dirty == st_o.n_dirty
-                    assert np.array_equal(img, img_o), (name, cap, quad)
+                    assert np.array_equal(img, img_o), (name, cap, group)
     finally:
-        crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_DIFF_QUAD, q0)
+        crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_DIFF_GROUP, q0)
 
 
 def test_pages_outside_the_set_are_not_read(ctx):
@@ -108,17 +108,17 @@ def test_pages_outside_the_set_are_not_read(ctx):
     cand = np.zeros(4, np.uint64)
     set_bits(cand, [3, 51, 100])
     import paper_1808_00117_amd as crum
-    q0 = crum.crum_ctx_get_param(ctx.ctx, crum.CRUM_PARAM_DIFF_QUAD)
+    q0 = crum.crum_ctx_get_param(ctx.ctx, crum.CRUM_PARAM_DIFF_GROUP)
     try:
-        for quad in (0, 1):
-            crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_DIFF_QUAD, quad)
+        for group in (1, 2, 4):
+            crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_DIFF_GROUP, group)
             st, img = tracked(ctx, dev, P, cand, image_capacity(dev, P))
             assert st.n_dirty == 2
             bm = np.frombuffer(img[96:96 + 32].tobytes(), np.uint64)
             bits = np.flatnonzero(np.unpackbits(bm.view(np.uint8), bitorder="little"))
-            assert list(bits) == [3, 51], quad
+            assert list(bits) == [3, 51], group
     finally:
-        crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_DIFF_QUAD, q0)
+        crum.crum_ctx_set_param(ctx.ctx, crum.CRUM_PARAM_DIFF_GROUP, q0)
 
 
 def test_short_candidate_bitmap_is_einval(ctx):
